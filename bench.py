@@ -1,0 +1,167 @@
+"""Benchmark of the fused D2Q9 TRT-VP step on one MI355X.
+
+One step = one pass of the whole hot path over the large single domain
+(8192 x 4096 nodes, two counter-rotating cylinders, a tandem pair and a NACA-0012
+airfoil, Re = 200, U = 0.04): the fused pull-stream / moments / penalization /
+TRT-collision kernel plus the per-body force and global mass reduction of every
+step. Inputs are synthetic and resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS (10^6 lattice-node updates per second, all nodes
+counted), the HBM roofline fraction of the step kernel from algorithmic bytes
+(9 loads + 9 stores + 1 mask byte per node) and HIP-event timing on the
+solver's stream, and the FP64 CPU oracle timed on the host's cores on a bounded
+sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16|bf16|f64]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "MLUPS + % of HBM peak, plain vs batched/FP16; p50/p99 solve latency"
+BYTES_PER_NODE = {"f64": 145, "f32": 73, "f16": 37, "bf16": 37}
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("lbvp_kernels.hip", "lbvp_internal.h"):
+        with open(os.path.join(ROOT, "paper_1901_08766_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(storage: str, nodes: int):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    entry = c.get("per_storage", {}).get(storage)
+    if not entry or entry.get("nodes") != nodes:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def time_gpu(storage: str, steps: int, warmup: int, prob):
+    import torch
+    from paper_1901_08766_amd import lbvp
+
+    solver = lbvp.Solver(prob, storage=storage, force_every=1, force_capacity=steps + warmup + 16)
+    stream = solver.stream
+    solver.step(warmup)
+    solver.synchronize()
+    solver.forces()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    solver.step(steps)
+    stop.record(stream)
+    stop.synchronize()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    forces, mass, _ = solver.forces()
+    ok = bool((mass == mass).all()) and len(mass) == steps
+    solver.close()
+    torch.cuda.empty_cache()
+    return ms / steps, ok
+
+
+def cpu_baseline(prob, budget_s: float = 15.0):
+    """The FP64 oracle on this host's cores, on the same domain, for as many
+    whole steps as fit in about ``budget_s`` seconds (at least one)."""
+    from oracle import ref
+
+    r = ref.RefSolver(prob)
+    t0 = time.perf_counter()
+    r.step(1)
+    one = time.perf_counter() - t0
+    n_more = max(0, int(budget_s / max(one, 1e-9)) - 1)
+    t1 = time.perf_counter()
+    if n_more:
+        r.step(n_more)
+    total = one + (time.perf_counter() - t1)
+    steps = 1 + n_more
+    r.close()
+    mlups = prob.nx * prob.ny * steps / total / 1e6
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": ref.num_threads(), "kind": "oracle",
+            "sample": f"{steps} FP64 steps of the full {prob.nx}x{prob.ny} domain ({total:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_NODE))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--variants", default="f16,bf16",
+                    help="other storage types to time as extra fields ('' for none)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only: the single-domain step has "
+                                   "no multi-GPU path in this build (--gpus must be 1)"}))
+        sys.exit(2)
+
+    from paper_1901_08766_amd import inputs
+
+    prob = inputs.large_domain()
+    nodes = prob.nx * prob.ny
+    print(f"# workload {prob.name}: {nodes} nodes, {prob.n_bodies} bodies, storage {a.storage}", file=sys.stderr,
+          flush=True)
+    ms, ok = time_gpu(a.storage, a.steps, a.warmup, prob)
+    if not ok:
+        raise SystemExit("non-finite mass during the timed run")
+    mlups = nodes / (ms * 1e-3) / 1e6
+    alg_bytes = BYTES_PER_NODE[a.storage] * nodes
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    extra = {}
+    for v in [s for s in a.variants.split(",") if s and s != a.storage]:
+        vms, vok = time_gpu(v, a.steps, a.warmup, prob)
+        vb = BYTES_PER_NODE[v] * nodes / (vms * 1e-3) / 1e9
+        extra[v] = {"MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
+                    "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok}
+        print(f"# {v}: {extra[v]}", file=sys.stderr, flush=True)
+    traffic = measured_traffic(a.storage, nodes)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": a.storage,
+        "data": "synthetic",
+        "config": {"workload": f"large single domain {prob.nx}x{prob.ny}, 5 bodies (counter-rotating pair, "
+                               f"tandem pair, NACA-0012), Re=200, U=0.04",
+                   "nx": prob.nx, "ny": prob.ny, "storage": a.storage, "layout": "two-lattice pull",
+                   "force_every": 1},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic},
+        "variants": extra,
+    }
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(prob, a.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

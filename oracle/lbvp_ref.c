@@ -311,7 +311,8 @@ int lbvp_ref_step(ref_ctx *c, int64_t n_steps, double *forces, double *mass)
     for (int64_t s = 0; s < n_steps; ++s) {
         const double *g = c->g;
         double *gn = c->g_next;
-#pragma omp parallel for schedule(static)
+        /* rows in parallel only when the grid is big enough to pay for the fork */
+#pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= 65536)
         for (int j = 0; j < ny; ++j) {
             double *rf = c->row_force + (int64_t)2 * nb * j;
             for (int k = 0; k < 2 * nb; ++k) rf[k] = 0.0;

@@ -1,0 +1,574 @@
+// lbvp_api.hip -- host side of the C ABI declared in include/lbvp.h.
+//
+// A context owns (or borrows) one device arena holding, in order: the two
+// population lattices, the mask, the body table, the field planes, the force
+// and mass reduction partials and their index tables, the force ring and a
+// staging area for host<->device conversions. Every launch goes to the
+// context's stream; only lbvp_forces / lbvp_read_* / lbvp_synchronize wait.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbvp.h"
+#include "lbvp_internal.h"
+
+using namespace lbvp;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr size_t STAGE_MIN_BYTES = size_t(16) << 20;
+constexpr int64_t DEFAULT_CAPACITY = 16384;
+constexpr int32_t DEFAULT_MAX_BODIES = 8;
+constexpr int32_t MAX_BODIES = 255;
+constexpr uint32_t KNOWN_PARAM_FLAGS = 0u;  // the AA layout is not built yet
+constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS;
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+size_t storage_bytes(int32_t st) { return st == LBVP_F64 ? 8 : st == LBVP_F32 ? 4 : 2; }
+size_t arith_bytes(int32_t st) { return st == LBVP_F64 ? 8 : 4; }
+
+struct Layout {
+    int64_t pitch = 0, plane = 0, plane_f = 0;
+    int32_t tiles_x = 0, n_tiles = 0, tiles_per_xcd = 0;
+    int64_t slot_cap = 0, capacity = 0;
+    int32_t max_bodies = 0;
+    int64_t stage_rows = 0;
+    size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, tile_mass = 0, slot_force = 0,
+           tile_slot_ptr = 0, slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0,
+           ring_mass = 0, rec_count = 0, stage = 0, total = 0;
+};
+
+// Returns an empty string if the parameters are valid.
+std::string validate(const lbvp_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->nx < 3 || p->ny < 3) return "nx and ny must be >= 3";
+    if ((int64_t)p->nx * p->ny > (int64_t(1) << 34)) return "grid too large";
+    if (!std::isfinite(p->tau_plus) || !(p->tau_plus > 0.5)) return "tau_plus must be finite and > 1/2";
+    if (!std::isfinite(p->magic_lambda) || !(p->magic_lambda > 0.0)) return "magic_lambda must be finite and > 0";
+    if (!std::isfinite(p->eta) || !(p->eta > 0.0)) return "eta must be finite and > 0";
+    if (!std::isfinite(p->rho0) || !(p->rho0 > 0.0)) return "rho0 must be finite and > 0";
+    const double vals[] = {p->rho_in, p->u_in[0], p->u_in[1], p->body_force[0], p->body_force[1]};
+    for (double v : vals)
+        if (!std::isfinite(v)) return "non-finite inflow state or body force";
+    auto side_ok = [](int32_t s) { return s == LBVP_BC_PERIODIC || s == LBVP_BC_INFLOW_EQ || s == LBVP_BC_OUTFLOW_ZERO_GRAD; };
+    if (!side_ok(p->bc_west) || !side_ok(p->bc_east)) return "unknown x side";
+    if ((p->bc_west == LBVP_BC_PERIODIC) != (p->bc_east == LBVP_BC_PERIODIC))
+        return "x sides must be both periodic or both non-periodic";
+    if (p->bc_south != LBVP_BC_PERIODIC || p->bc_north != LBVP_BC_PERIODIC) return "y sides must be periodic";
+    if (p->storage < LBVP_F64 || p->storage > LBVP_BF16_DEV) return "unknown storage type";
+    if (p->force_every < 0) return "force_every must be >= 0";
+    if (p->force_capacity < 0 || p->force_capacity > (int64_t(1) << 26)) return "force_capacity out of range";
+    if (p->max_bodies < 0 || p->max_bodies > MAX_BODIES) return "max_bodies must be in 0..255";
+    if (p->flags & ~KNOWN_PARAM_FLAGS) return "unknown or unsupported params flag";
+    return "";
+}
+
+Layout make_layout(const lbvp_params* p)
+{
+    Layout L;
+    const size_t es = storage_bytes(p->storage), rs = arith_bytes(p->storage);
+    L.pitch = (int64_t)align_up((size_t)p->nx, 64);
+    L.plane = (int64_t)align_up((size_t)(p->ny * L.pitch), 2048);
+    L.plane_f = (int64_t)p->ny * L.pitch;
+    L.tiles_x = (p->nx + TILE_X - 1) / TILE_X;
+    L.n_tiles = L.tiles_x * p->ny;
+    L.tiles_per_xcd = (L.n_tiles + N_XCD - 1) / N_XCD;
+    L.slot_cap = 2 * (int64_t)L.n_tiles + 1024;
+    L.capacity = p->force_capacity > 0 ? p->force_capacity : DEFAULT_CAPACITY;
+    L.max_bodies = p->max_bodies > 0 ? p->max_bodies : DEFAULT_MAX_BODIES;
+    const size_t row_bytes = (size_t)p->nx * 9 * sizeof(double);
+    const size_t stage_bytes = std::max(STAGE_MIN_BYTES, row_bytes);
+    L.stage_rows = std::max<int64_t>(1, (int64_t)(stage_bytes / row_bytes));
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, ALIGN); return at; };
+    const size_t lat_bytes = 9 * (size_t)L.plane * es;
+    L.lat[0] = take(lat_bytes);
+    L.lat[1] = take(lat_bytes);
+    L.mask = take((size_t)p->ny * L.pitch);
+    L.bodies = take((size_t)(L.max_bodies + 1) * 5 * rs);
+    L.fields = take(5 * (size_t)L.plane_f * rs);
+    L.tile_mass = take((size_t)L.n_tiles * sizeof(double));
+    L.slot_force = take((size_t)L.slot_cap * 2 * sizeof(double));
+    L.tile_slot_ptr = take((size_t)(L.n_tiles + 1) * sizeof(int32_t));
+    L.slot_body = take((size_t)L.slot_cap * sizeof(int32_t));
+    L.body_slot_ptr = take((size_t)(MAX_BODIES + 2) * sizeof(int32_t));
+    L.body_slots = take((size_t)L.slot_cap * sizeof(int32_t));
+    L.ring_force = take((size_t)L.capacity * L.max_bodies * 2 * sizeof(double));
+    L.ring_mass = take((size_t)L.capacity * sizeof(double));
+    L.rec_count = take(sizeof(int64_t));
+    L.stage = take(stage_bytes);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct lbvp_ctx {
+    lbvp_params p{};
+    Layout L;
+    hipStream_t stream = nullptr;
+    char* mem = nullptr;
+    bool owns = false;
+    int cur = 0;                // lattice holding the current post-collision state
+    int64_t step = 0;
+    int64_t rec_head = 0, rec_tail = 0;
+    bool fields_valid = false;
+    int32_t n_bodies = 0;
+    double tau_minus = 0.0;
+    StepArgs<double> a64{};
+    StepArgs<float> a32{};
+    FinalizeArgs fin{};
+    std::string err;
+
+    template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(mem + off); }
+    int32_t storage() const { return p.storage; }
+    bool is_f64() const { return p.storage == LBVP_F64; }
+    size_t esize() const { return storage_bytes(p.storage); }
+    size_t rsize() const { return arith_bytes(p.storage); }
+
+    lbvp_status fail(lbvp_status s, const std::string& m) { err = m; return s; }
+    lbvp_status hip_fail(hipError_t e, const char* what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBVP_E_DEVICE;
+    }
+};
+
+namespace {
+
+#define LBVP_HIP(ctx, call)                                               \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call);          \
+    } while (0)
+
+// The inflow ghost populations f^eq(rho_in, u_in) - w rho0 (eq. feq), in FP64.
+void inflow_ghost(const lbvp_params& p, double out[9])
+{
+    static const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+    static const double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
+    const double r = p.rho_in, ux = p.u_in[0], uy = p.u_in[1], uu = ux * ux + uy * uy;
+    for (int q = 0; q < 9; ++q) {
+        const double eu = ex[q] * ux + ey[q] * uy;
+        out[q] = w[q] * ((r - p.rho0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    }
+}
+
+template <typename R>
+void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
+{
+    const lbvp_params& p = c->p;
+    const Layout& L = c->L;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.tiles_x = L.tiles_x;
+    a.n_tiles = L.n_tiles;
+    a.tiles_per_xcd = L.tiles_per_xcd;
+    a.west = p.bc_west;
+    a.east = p.bc_east;
+    a.pitch = L.pitch;
+    a.plane = L.plane;
+    a.plane_f = L.plane_f;
+    a.rho0 = (R)p.rho0;
+    a.om_p = (R)(1.0 / p.tau_plus);
+    a.om_m = (R)(1.0 / c->tau_minus);
+    a.k_p = (R)(1.0 - 0.5 / p.tau_plus);
+    a.k_m = (R)(1.0 - 0.5 / c->tau_minus);
+    a.vp_c = (R)(1.0 / (2.0 * p.eta + 1.0));
+    a.fbx = (R)p.body_force[0];
+    a.fby = (R)p.body_force[1];
+    double fin[9];
+    inflow_ghost(p, fin);
+    for (int q = 0; q < 9; ++q) a.feq_in[q] = (R)fin[q];
+    a.mask = c->at<uint8_t>(L.mask);
+    a.bodies = c->at<R>(L.bodies);
+    a.tile_slot_ptr = c->at<int32_t>(L.tile_slot_ptr);
+    a.slot_body = c->at<int32_t>(L.slot_body);
+    a.slot_force = c->at<double>(L.slot_force);
+    a.tile_mass = c->at<double>(L.tile_mass);
+    a.fields = c->at<R>(L.fields);
+}
+
+template <typename R>
+std::vector<char> body_table_bytes(const lbvp_body* bodies, int32_t n, int32_t max_bodies)
+{
+    std::vector<R> t((size_t)(max_bodies + 1) * 5, R(0));
+    for (int32_t k = 0; k < n; ++k) {
+        const double v[5] = {bodies[k].cx, bodies[k].cy, bodies[k].vx, bodies[k].vy, bodies[k].omega};
+        for (int q = 0; q < 5; ++q) t[(size_t)(k + 1) * 5 + q] = (R)v[q];
+    }
+    std::vector<char> out(t.size() * sizeof(R));
+    std::memcpy(out.data(), t.data(), out.size());
+    return out;
+}
+
+ConvArgs conv_args(lbvp_ctx* c, int32_t row0, int32_t rows)
+{
+    ConvArgs a{};
+    a.nx = c->p.nx;
+    a.rows = rows;
+    a.row0 = row0;
+    a.pitch = c->L.pitch;
+    a.plane = c->L.plane;
+    a.plane_f = c->L.plane_f;
+    a.rho0 = c->p.rho0;
+    a.pops = c->at<double>(c->L.stage);
+    return a;
+}
+
+lbvp_status check_ctx(const lbvp_ctx* c) { return c ? LBVP_OK : LBVP_E_ARG; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbvp_footprint_bytes(const lbvp_params* p)
+{
+    if (!validate(p).empty()) return 0;
+    return make_layout(p).total;
+}
+
+lbvp_status lbvp_create(const lbvp_params* p, void* hip_stream, void* dev_mem, size_t dev_bytes,
+                        lbvp_ctx** out)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return LBVP_E_ARG;
+    }
+    *out = nullptr;
+    const std::string why = validate(p);
+    if (!why.empty()) {
+        g_create_error = why;
+        return LBVP_E_ARG;
+    }
+    lbvp_ctx* c = new (std::nothrow) lbvp_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return LBVP_E_NOMEM;
+    }
+    c->p = *p;
+    c->L = make_layout(p);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->tau_minus = 0.5 + p->magic_lambda / (p->tau_plus - 0.5);
+    if (dev_mem) {
+        if (dev_bytes < c->L.total) {
+            g_create_error = "dev_mem smaller than lbvp_footprint_bytes";
+            delete c;
+            return LBVP_E_NOMEM;
+        }
+        if (reinterpret_cast<uintptr_t>(dev_mem) % ALIGN) {
+            g_create_error = "dev_mem must be 256-byte aligned";
+            delete c;
+            return LBVP_E_ARG;
+        }
+        c->mem = static_cast<char*>(dev_mem);
+    } else {
+        void* m = nullptr;
+        hipError_t e = hipMalloc(&m, c->L.total);
+        if (e != hipSuccess) {
+            g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+            delete c;
+            return LBVP_E_NOMEM;
+        }
+        c->mem = static_cast<char*>(m);
+        c->owns = true;
+    }
+    fill_step_args(c, c->a64);
+    fill_step_args(c, c->a32);
+    c->fin.max_bodies = c->L.max_bodies;
+    c->fin.n_tiles = c->L.n_tiles;
+    c->fin.capacity = c->L.capacity;
+    c->fin.mass_offset = p->rho0 * (double)p->nx * (double)p->ny;
+    c->fin.body_slot_ptr = c->at<int32_t>(c->L.body_slot_ptr);
+    c->fin.body_slots = c->at<int32_t>(c->L.body_slots);
+    c->fin.slot_force = c->at<double>(c->L.slot_force);
+    c->fin.tile_mass = c->at<double>(c->L.tile_mass);
+    c->fin.ring_force = c->at<double>(c->L.ring_force);
+    c->fin.ring_mass = c->at<double>(c->L.ring_mass);
+    c->fin.rec_count = c->at<int64_t>(c->L.rec_count);
+    // empty mask, fluid at rest
+    std::vector<uint8_t> zero((size_t)p->nx * p->ny, 0);
+    lbvp_status s = lbvp_set_mask(c, zero.data(), 0, nullptr);
+    if (s == LBVP_OK) s = lbvp_init_equilibrium(c, nullptr, nullptr, nullptr);
+    if (s != LBVP_OK) {
+        g_create_error = c->err;
+        lbvp_destroy(c);
+        return s;
+    }
+    *out = c;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies, const lbvp_body* bodies)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    const lbvp_params& p = c->p;
+    const Layout& L = c->L;
+    if (!body_id) return c->fail(LBVP_E_ARG, "body_id is NULL");
+    if (n_bodies < 0 || n_bodies > L.max_bodies) return c->fail(LBVP_E_ARG, "n_bodies out of range (see max_bodies)");
+    if (n_bodies > 0 && !bodies) return c->fail(LBVP_E_ARG, "bodies is NULL");
+    for (int32_t k = 0; k < n_bodies; ++k) {
+        const double v[5] = {bodies[k].cx, bodies[k].cy, bodies[k].vx, bodies[k].vy, bodies[k].omega};
+        for (double x : v)
+            if (!std::isfinite(x)) return c->fail(LBVP_E_ARG, "non-finite body value");
+    }
+    const int64_t n = (int64_t)p.nx * p.ny;
+    for (int64_t k = 0; k < n; ++k)
+        if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
+
+    // (tile, body) pairs: a slot per body present in each tile, in tile order
+    std::vector<int32_t> tile_ptr((size_t)L.n_tiles + 1, 0), slot_body;
+    std::vector<std::vector<int32_t>> per_body((size_t)n_bodies);
+    std::vector<uint8_t> seen((size_t)n_bodies + 1, 0);
+    for (int32_t t = 0; t < L.n_tiles; ++t) {
+        tile_ptr[t] = (int32_t)slot_body.size();
+        if (n_bodies == 0) continue;
+        const int32_t j = t / L.tiles_x, i0 = (t % L.tiles_x) * TILE_X, i1 = std::min(p.nx, i0 + TILE_X);
+        const uint8_t* row = body_id + (int64_t)j * p.nx;
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int32_t i = i0; i < i1; ++i) seen[row[i]] = 1;
+        for (int32_t b = 1; b <= n_bodies; ++b) {
+            if (!seen[b]) continue;
+            if ((int64_t)slot_body.size() >= L.slot_cap)
+                return c->fail(LBVP_E_NOMEM, "mask has more (tile, body) pairs than the reduction tables hold");
+            per_body[b - 1].push_back((int32_t)slot_body.size());
+            slot_body.push_back(b);
+        }
+    }
+    tile_ptr[L.n_tiles] = (int32_t)slot_body.size();
+    std::vector<int32_t> body_ptr((size_t)n_bodies + 1, 0), body_slots;
+    for (int32_t b = 0; b < n_bodies; ++b) {
+        body_ptr[b] = (int32_t)body_slots.size();
+        body_slots.insert(body_slots.end(), per_body[b].begin(), per_body[b].end());
+    }
+    body_ptr[n_bodies] = (int32_t)body_slots.size();
+    std::vector<char> table = c->is_f64() ? body_table_bytes<double>(bodies, n_bodies, L.max_bodies)
+                                          : body_table_bytes<float>(bodies, n_bodies, L.max_bodies);
+
+    hipStream_t s = c->stream;
+    LBVP_HIP(c, hipMemcpy2DAsync(c->at<uint8_t>(L.mask), (size_t)L.pitch, body_id, (size_t)p.nx,
+                                 (size_t)p.nx, (size_t)p.ny, hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.tile_slot_ptr), tile_ptr.data(), tile_ptr.size() * 4,
+                               hipMemcpyHostToDevice, s));
+    if (!slot_body.empty()) {
+        LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.slot_body), slot_body.data(), slot_body.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+        LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slots), body_slots.data(), body_slots.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+    }
+    LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slot_ptr), body_ptr.data(), body_ptr.size() * 4,
+                               hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipMemcpyAsync(c->at<char>(L.bodies), table.data(), table.size(), hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipStreamSynchronize(s));  // the host tables above go out of scope
+    c->n_bodies = n_bodies;
+    c->fin.n_bodies = n_bodies;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* ux, const double* uy)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    const lbvp_params& p = c->p;
+    const Layout& L = c->L;
+    hipStream_t s = c->stream;
+    const int64_t stage_nodes = L.stage_rows * 9 * p.nx / 3;  // three staged planes
+    const int32_t rows_per = (int32_t)std::max<int64_t>(1, std::min<int64_t>(p.ny, stage_nodes / p.nx));
+    for (int32_t r0 = 0; r0 < p.ny; r0 += rows_per) {
+        const int32_t rows = std::min(rows_per, p.ny - r0);
+        ConvArgs a = conv_args(c, r0, rows);
+        const size_t nn = (size_t)rows * p.nx;
+        double* st = c->at<double>(L.stage);
+        const double* src[3] = {rho, ux, uy};
+        const double* dst[3] = {nullptr, nullptr, nullptr};
+        for (int q = 0; q < 3; ++q) {
+            if (!src[q]) continue;
+            LBVP_HIP(c, hipMemcpyAsync(st + q * nn, src[q] + (size_t)r0 * p.nx, nn * sizeof(double),
+                                       hipMemcpyHostToDevice, s));
+            dst[q] = st + q * nn;
+        }
+        a.rho = dst[0];
+        a.ux = dst[1];
+        a.uy = dst[2];
+        LBVP_HIP(c, launch_init(p.storage, c->at<char>(L.lat[0]), c->at<char>(L.fields), a, s));
+    }
+    LBVP_HIP(c, launch_set_i64(c->fin.rec_count, 0, s));
+    LBVP_HIP(c, hipStreamSynchronize(s));
+    c->cur = 0;
+    c->step = 0;
+    c->rec_head = c->rec_tail = 0;
+    c->fields_valid = true;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (n_steps < 0) return c->fail(LBVP_E_ARG, "n_steps < 0");
+    if (flags & ~KNOWN_STEP_FLAGS) return c->fail(LBVP_E_ARG, "unknown step flag");
+    const int64_t fe = c->p.force_every;
+    if (fe > 0) {
+        const int64_t new_recs = (c->step + n_steps) / fe - c->step / fe;
+        if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
+            return c->fail(LBVP_E_STATE, "force records would overflow the device ring; call lbvp_forces first");
+    }
+    const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t next = c->step + 1;
+        const bool record = fe > 0 && next % fe == 0;
+        const bool keep = (flags & LBVP_KEEP_FIELDS) && k == n_steps - 1;
+        hipError_t e = launch_step(c->p.storage, record, keep, c->at<char>(c->L.lat[c->cur]),
+                                   c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
+        if (record) {
+            e = launch_finalize(c->fin, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+            c->rec_head += 1;
+        }
+        if (keep) c->fields_valid = true;
+        c->cur ^= 1;
+        c->step = next;
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_forces(lbvp_ctx* c, double* out, double* mass, int64_t cap, int64_t* n_out, int64_t* first_step)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (cap < 0) return c->fail(LBVP_E_ARG, "cap < 0");
+    LBVP_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t avail = c->rec_head - c->rec_tail;
+    const int64_t n = std::min(avail, cap);
+    const int64_t C = c->L.capacity, mb = c->L.max_bodies, nb = c->n_bodies;
+    std::vector<double> rf((size_t)std::max<int64_t>(n, 1) * mb * 2), rm((size_t)std::max<int64_t>(n, 1));
+    int64_t done = 0;
+    while (done < n) {
+        const int64_t r = (c->rec_tail + done) % C;
+        const int64_t len = std::min(n - done, C - r);
+        LBVP_HIP(c, hipMemcpy(rf.data() + done * mb * 2, c->at<double>(c->L.ring_force) + r * mb * 2,
+                              (size_t)(len * mb * 2) * sizeof(double), hipMemcpyDeviceToHost));
+        LBVP_HIP(c, hipMemcpy(rm.data() + done, c->at<double>(c->L.ring_mass) + r,
+                              (size_t)len * sizeof(double), hipMemcpyDeviceToHost));
+        done += len;
+    }
+    bool finite = true;
+    for (int64_t k = 0; k < n; ++k) {
+        if (out)
+            for (int64_t b = 0; b < nb; ++b) {
+                out[(k * nb + b) * 2] = rf[(k * mb + b) * 2];
+                out[(k * nb + b) * 2 + 1] = rf[(k * mb + b) * 2 + 1];
+            }
+        if (mass) mass[k] = rm[k];
+        if (!std::isfinite(rm[k])) finite = false;
+    }
+    if (n_out) *n_out = n;
+    if (first_step) *first_step = n > 0 ? (c->rec_tail + 1) * c->p.force_every : 0;
+    c->rec_tail += n;
+    if (!finite) return c->fail(LBVP_E_UNSTABLE, "non-finite global mass: the run went unstable");
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_read_fields(lbvp_ctx* c, double* rho, double* ux, double* uy, double* fx, double* fy)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (!c->fields_valid) return c->fail(LBVP_E_STATE, "no fields kept since the last init");
+    LBVP_HIP(c, hipStreamSynchronize(c->stream));
+    const lbvp_params& p = c->p;
+    double* dst[5] = {rho, ux, uy, fx, fy};
+    const size_t rs = c->rsize();
+    std::vector<char> tmp((size_t)p.nx * p.ny * rs);
+    for (int q = 0; q < 5; ++q) {
+        if (!dst[q]) continue;
+        const char* srcp = c->at<char>(c->L.fields) + (size_t)q * c->L.plane_f * rs;
+        LBVP_HIP(c, hipMemcpy2D(tmp.data(), (size_t)p.nx * rs, srcp, (size_t)c->L.pitch * rs, (size_t)p.nx * rs,
+                                (size_t)p.ny, hipMemcpyDeviceToHost));
+        const size_t n = (size_t)p.nx * p.ny;
+        if (c->is_f64()) std::memcpy(dst[q], tmp.data(), n * sizeof(double));
+        else {
+            const float* f = reinterpret_cast<const float*>(tmp.data());
+            for (size_t k = 0; k < n; ++k) dst[q][k] = (double)f[k];
+        }
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_read_populations(lbvp_ctx* c, double* g)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    const lbvp_params& p = c->p;
+    hipStream_t s = c->stream;
+    const int32_t rows_per = (int32_t)std::min<int64_t>(p.ny, c->L.stage_rows);
+    const size_t N = (size_t)p.nx * p.ny;
+    for (int32_t r0 = 0; r0 < p.ny; r0 += rows_per) {
+        const int32_t rows = std::min(rows_per, p.ny - r0);
+        ConvArgs a = conv_args(c, r0, rows);
+        LBVP_HIP(c, launch_decode(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
+        const size_t nn = (size_t)rows * p.nx;
+        for (int q = 0; q < 9; ++q)
+            LBVP_HIP(c, hipMemcpyAsync(g + q * N + (size_t)r0 * p.nx, a.pops + q * nn, nn * sizeof(double),
+                                       hipMemcpyDeviceToHost, s));
+        LBVP_HIP(c, hipStreamSynchronize(s));
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    const lbvp_params& p = c->p;
+    hipStream_t s = c->stream;
+    const int32_t rows_per = (int32_t)std::min<int64_t>(p.ny, c->L.stage_rows);
+    const size_t N = (size_t)p.nx * p.ny;
+    for (int32_t r0 = 0; r0 < p.ny; r0 += rows_per) {
+        const int32_t rows = std::min(rows_per, p.ny - r0);
+        ConvArgs a = conv_args(c, r0, rows);
+        const size_t nn = (size_t)rows * p.nx;
+        for (int q = 0; q < 9; ++q)
+            LBVP_HIP(c, hipMemcpyAsync(a.pops + q * nn, g + q * N + (size_t)r0 * p.nx, nn * sizeof(double),
+                                       hipMemcpyHostToDevice, s));
+        LBVP_HIP(c, launch_encode(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
+    }
+    LBVP_HIP(c, hipStreamSynchronize(s));
+    return LBVP_OK;
+}
+
+int64_t lbvp_step_count(const lbvp_ctx* c) { return c ? c->step : -1; }
+
+lbvp_status lbvp_synchronize(lbvp_ctx* c)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    LBVP_HIP(c, hipStreamSynchronize(c->stream));
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_destroy(lbvp_ctx* c)
+{
+    if (!c) return LBVP_OK;
+    lbvp_status st = LBVP_OK;
+    if (c->mem) {
+        if (hipStreamSynchronize(c->stream) != hipSuccess) st = LBVP_E_DEVICE;
+        if (c->owns && hipFree(c->mem) != hipSuccess) st = LBVP_E_DEVICE;
+    }
+    delete c;
+    return st;
+}
+
+const char* lbvp_last_error(const lbvp_ctx* c)
+{
+    return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+}  // extern "C"

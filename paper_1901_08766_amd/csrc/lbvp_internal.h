@@ -1,0 +1,78 @@
+// lbvp_internal.h -- kernel argument blocks and launchers shared by the host
+// side of liblbvp (lbvp_api.hip) and its kernels (lbvp_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbvp {
+
+// One workgroup updates one tile of TILE_X consecutive nodes of a row, one node
+// per thread. Workgroups are dealt to the 8 XCDs round-robin by block id; the
+// launch remaps block b to tile (b % 8) * tiles_per_xcd + b / 8 so that each XCD
+// sweeps a contiguous band of rows and neighbouring tiles share one L2.
+constexpr int TILE_X = 256;
+constexpr int N_XCD = 8;
+constexpr int FIN_THREADS = 1024;
+
+enum Side : int32_t { SIDE_PERIODIC = 0, SIDE_INFLOW_EQ = 1, SIDE_OUTFLOW = 2 };
+
+// Storage codes (match lbvp_storage).
+enum Storage : int32_t { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
+
+template <typename R>
+struct StepArgs {
+    int32_t nx, ny;
+    int32_t tiles_x, n_tiles, tiles_per_xcd;
+    int32_t west, east;
+    int64_t pitch;      // elements per row (lattice, mask and fields)
+    int64_t plane;      // elements between population planes
+    int64_t plane_f;    // elements between field planes
+    R rho0;
+    R om_p, om_m;       // 1/tau_plus, 1/tau_minus
+    R k_p, k_m;         // 1 - 1/(2 tau_plus), 1 - 1/(2 tau_minus)
+    R vp_c;             // 1 / (2 eta + 1): the chi = 1 value of chi / (2 eta + chi)
+    R fbx, fby;         // body force
+    R feq_in[9];        // f^eq(rho_in, u_in) - w rho0 of an INFLOW_EQ side
+    const uint8_t* mask;
+    const R* bodies;    // [(n_bodies + 1)][5]; row 0 is all zero (fluid)
+    const int32_t* tile_slot_ptr;   // [n_tiles + 1]
+    const int32_t* slot_body;       // [n_slots]
+    double* slot_force;             // [n_slots][2]
+    double* tile_mass;              // [n_tiles]
+    R* fields;                      // [5][plane_f]
+};
+
+struct FinalizeArgs {
+    int32_t n_bodies, max_bodies, n_tiles;
+    int64_t capacity;
+    double mass_offset;             // rho0 * nx * ny
+    const int32_t* body_slot_ptr;   // [n_bodies + 1]
+    const int32_t* body_slots;      // slots of each body in tile order
+    const double* slot_force;
+    const double* tile_mass;
+    double* ring_force;             // [capacity][max_bodies][2]
+    double* ring_mass;              // [capacity]
+    int64_t* rec_count;             // records written so far
+};
+
+struct ConvArgs {
+    int32_t nx, rows, row0;
+    int64_t pitch, plane, plane_f;
+    double rho0;
+    const double* rho;  // staged [rows][nx] or null
+    const double* ux;
+    const double* uy;
+    double* pops;       // staged [9][rows][nx]
+};
+
+// launchers (lbvp_kernels.hip); all return the launch status
+hipError_t launch_step(int32_t storage, bool record, bool fields, const void* src, void* dst,
+                       const void* step_args, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs& a, hipStream_t s);
+hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);
+hipError_t launch_encode(int32_t storage, void* lat, const ConvArgs& a, hipStream_t s);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+
+}  // namespace lbvp

@@ -1,0 +1,279 @@
+"""Python binding of liblbvp.so: the C ABI of include/lbvp.h, one function per
+entry point with the same name, marshalling only. Every step of the solver runs
+in the library's HIP kernels; there is no CPU fallback. If the library is not
+built, importing this module raises.
+
+``Solver`` wraps a context for a ``Problem`` (see ``inputs``): device memory is
+a torch uint8 tensor (borrowed by the library) and the stream is a torch stream,
+so the caller can time and order the work with torch events.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+# torch must load its HIP runtime before liblbvp.so binds to libamdhip64.so.7,
+# so that one runtime serves both (streams and pointers are shared).
+import torch  # noqa: F401
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblbvp.so")
+
+OK, E_ARG, E_NOMEM, E_BUSY, E_DEVICE, E_STATE, E_UNSTABLE = range(7)
+STATUS_NAMES = ["OK", "E_ARG", "E_NOMEM", "E_BUSY", "E_DEVICE", "E_STATE", "E_UNSTABLE"]
+BC = {"periodic": 0, "inflow_eq": 1, "outflow_zero_grad": 2}
+STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+LAYOUT_AA = 0x1
+KEEP_FIELDS = 0x1
+
+SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_equilibrium",
+           "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations",
+           "lbvp_write_populations", "lbvp_step_count", "lbvp_synchronize", "lbvp_destroy",
+           "lbvp_last_error"]
+
+
+class LbvpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < 7 else status}: {msg}")
+        self.status = status
+
+
+class lbvp_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32),
+                ("tau_plus", C.c_double), ("magic_lambda", C.c_double), ("eta", C.c_double),
+                ("rho0", C.c_double),
+                ("bc_west", C.c_int32), ("bc_east", C.c_int32), ("bc_south", C.c_int32),
+                ("bc_north", C.c_int32),
+                ("rho_in", C.c_double), ("u_in", C.c_double * 2), ("body_force", C.c_double * 2),
+                ("storage", C.c_int32), ("force_every", C.c_int32), ("force_capacity", C.c_int64),
+                ("max_bodies", C.c_int32), ("flags", C.c_uint32)]
+
+
+class lbvp_body(C.Structure):
+    _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
+                ("omega", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "(or python -m paper_1901_08766_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+    P = C.POINTER(lbvp_params)
+    L.lbvp_footprint_bytes.restype = C.c_size_t
+    L.lbvp_footprint_bytes.argtypes = [P]
+    L.lbvp_create.argtypes = [P, vp, vp, C.c_size_t, C.POINTER(vp)]
+    L.lbvp_set_mask.argtypes = [vp, vp, i32, vp]
+    L.lbvp_init_equilibrium.argtypes = [vp, vp, vp, vp]
+    L.lbvp_step.argtypes = [vp, i64, u32]
+    L.lbvp_forces.argtypes = [vp, vp, vp, i64, C.POINTER(i64), C.POINTER(i64)]
+    L.lbvp_read_fields.argtypes = [vp] * 6
+    L.lbvp_read_populations.argtypes = [vp, vp]
+    L.lbvp_write_populations.argtypes = [vp, vp]
+    L.lbvp_step_count.restype = i64
+    L.lbvp_step_count.argtypes = [vp]
+    L.lbvp_synchronize.argtypes = [vp]
+    L.lbvp_destroy.argtypes = [vp]
+    L.lbvp_last_error.restype = C.c_char_p
+    L.lbvp_last_error.argtypes = [vp]
+    for name in SYMBOLS:
+        if name not in ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error"):
+            getattr(L, name).restype = C.c_int
+    return L
+
+
+_L = _load()
+
+
+def lib():
+    return _L
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    return a.ctypes.data
+
+
+def _check(ctx, status: int):
+    if status != OK:
+        raise LbvpError(status, lbvp_last_error(ctx))
+
+
+# ------------------------------------------------------------ the C ABI --
+
+def lbvp_last_error(ctx) -> str:
+    msg = _L.lbvp_last_error(ctx)
+    return msg.decode() if msg else ""
+
+
+def lbvp_footprint_bytes(params: lbvp_params) -> int:
+    return int(_L.lbvp_footprint_bytes(C.byref(params)))
+
+
+def lbvp_create(params: lbvp_params, stream: Optional[int] = None, dev_mem: Optional[int] = None,
+                dev_bytes: int = 0):
+    out = C.c_void_p()
+    _check(None, _L.lbvp_create(C.byref(params), stream, dev_mem, dev_bytes, C.byref(out)))
+    return out.value
+
+
+def lbvp_set_mask(ctx, body_id: np.ndarray, bodies: np.ndarray):
+    body_id = np.ascontiguousarray(body_id, dtype=np.uint8)
+    bodies = np.ascontiguousarray(bodies, dtype=np.float64).reshape(-1, 5)
+    n = bodies.shape[0]
+    _check(ctx, _L.lbvp_set_mask(ctx, _ptr(body_id), n, _ptr(bodies) if n else None))
+
+
+def lbvp_init_equilibrium(ctx, rho=None, ux=None, uy=None):
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy)]
+    _check(ctx, _L.lbvp_init_equilibrium(ctx, *[_ptr(a) for a in arrs]))
+
+
+def lbvp_step(ctx, n_steps: int, flags: int = 0):
+    _check(ctx, _L.lbvp_step(ctx, int(n_steps), int(flags)))
+
+
+def lbvp_forces(ctx, n_bodies: int, cap: int):
+    """Returns (forces [n][n_bodies][2], mass [n], first_step); raises on E_UNSTABLE
+    after filling the arrays (they are attached to the exception as .data)."""
+    out = np.zeros((max(cap, 1), max(n_bodies, 1), 2))
+    mass = np.zeros(max(cap, 1))
+    n = C.c_int64()
+    first = C.c_int64()
+    st = _L.lbvp_forces(ctx, _ptr(out), _ptr(mass), int(cap), C.byref(n), C.byref(first))
+    res = (out[: n.value, :n_bodies].copy(), mass[: n.value].copy(), first.value)
+    if st != OK:
+        err = LbvpError(st, lbvp_last_error(ctx))
+        err.data = res
+        raise err
+    return res
+
+
+def lbvp_read_fields(ctx, nx: int, ny: int) -> Dict[str, np.ndarray]:
+    out = [np.zeros((ny, nx)) for _ in range(5)]
+    _check(ctx, _L.lbvp_read_fields(ctx, *[_ptr(a) for a in out]))
+    return dict(zip(("rho", "ux", "uy", "fx", "fy"), out))
+
+
+def lbvp_read_populations(ctx, nx: int, ny: int) -> np.ndarray:
+    g = np.zeros((9, ny, nx))
+    _check(ctx, _L.lbvp_read_populations(ctx, _ptr(g)))
+    return g
+
+
+def lbvp_write_populations(ctx, g: np.ndarray):
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    _check(ctx, _L.lbvp_write_populations(ctx, _ptr(g)))
+
+
+def lbvp_step_count(ctx) -> int:
+    return int(_L.lbvp_step_count(ctx))
+
+
+def lbvp_synchronize(ctx):
+    _check(ctx, _L.lbvp_synchronize(ctx))
+
+
+def lbvp_destroy(ctx):
+    if ctx:
+        _check(None, _L.lbvp_destroy(ctx))
+
+
+# ------------------------------------------------------------ convenience --
+
+def params_for(prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
+               max_bodies: int = 0, flags: int = 0) -> lbvp_params:
+    p = lbvp_params()
+    p.nx, p.ny = prob.nx, prob.ny
+    p.tau_plus, p.magic_lambda, p.eta, p.rho0 = prob.tau_plus, prob.magic_lambda, prob.eta, prob.rho0
+    p.bc_west, p.bc_east, p.bc_south, p.bc_north = (BC[s] for s in prob.bc)
+    p.rho_in = prob.rho_in
+    p.u_in[0], p.u_in[1] = prob.u_in
+    p.body_force[0], p.body_force[1] = prob.body_force
+    p.storage = STORAGE[storage]
+    p.force_every = force_every
+    p.force_capacity = force_capacity
+    p.max_bodies = max_bodies if max_bodies else max(8, prob.n_bodies)
+    p.flags = flags
+    return p
+
+
+class Solver:
+    """A context for one ``Problem``; device memory from torch, stream from torch."""
+
+    def __init__(self, prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
+                 flags: int = 0, stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda"):
+        self.prob = prob
+        self.nx, self.ny = prob.nx, prob.ny
+        self.n_bodies = prob.n_bodies
+        self.params = params_for(prob, storage, force_every, force_capacity, flags=flags)
+        nbytes = lbvp_footprint_bytes(self.params)
+        if nbytes == 0:
+            raise LbvpError(E_ARG, "invalid parameters")
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.mem.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        self.ctx = lbvp_create(self.params, self.stream.cuda_stream, aligned, nbytes)
+        lbvp_set_mask(self.ctx, prob.mask_or_empty(), prob.bodies_or_empty())
+        lbvp_init_equilibrium(self.ctx, prob.rho_init, prob.ux_init, prob.uy_init)
+
+    @property
+    def footprint(self) -> int:
+        return lbvp_footprint_bytes(self.params)
+
+    def step(self, n: int, keep_fields: bool = False):
+        lbvp_step(self.ctx, n, KEEP_FIELDS if keep_fields else 0)
+
+    def forces(self, cap: Optional[int] = None):
+        cap = cap or (self.params.force_capacity or 16384)
+        return lbvp_forces(self.ctx, self.n_bodies, cap)
+
+    def run(self, n: int, chunk: Optional[int] = None, keep_fields: bool = False):
+        """Advance n steps, draining force records as needed; returns
+        (forces [records][n_bodies][2], mass [records])."""
+        fe = max(self.params.force_every, 1)
+        cap = self.params.force_capacity or 16384
+        chunk = chunk or max(1, cap * fe)
+        fs, ms = [], []
+        done = 0
+        while done < n:
+            k = min(chunk, n - done)
+            self.step(k, keep_fields=keep_fields and done + k == n)
+            f, m, _ = self.forces()
+            fs.append(f)
+            ms.append(m)
+            done += k
+        return np.concatenate(fs) if fs else np.zeros((0, self.n_bodies, 2)), np.concatenate(ms) if ms else np.zeros(0)
+
+    def fields(self) -> Dict[str, np.ndarray]:
+        return lbvp_read_fields(self.ctx, self.nx, self.ny)
+
+    def populations(self) -> np.ndarray:
+        return lbvp_read_populations(self.ctx, self.nx, self.ny)
+
+    def set_populations(self, g: np.ndarray):
+        lbvp_write_populations(self.ctx, g)
+
+    @property
+    def step_count(self) -> int:
+        return lbvp_step_count(self.ctx)
+
+    def synchronize(self):
+        lbvp_synchronize(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            lbvp_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -18,3 +18,11 @@ def oracle():
     from oracle import ref
     ref.lib()
     return ref
+
+
+@pytest.fixture(scope="session")
+def lbvp():
+    """The HIP library's Python binding (imported lazily so that collecting the
+    CPU tests does not need the built library)."""
+    from paper_1901_08766_amd import lbvp as mod
+    return mod

@@ -1,0 +1,192 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Bars: FP64 storage matches to 1e-12 (populations, fields, forces, mass); FP32
+storage matches to velocity relative L2 <= 1e-5 after 1000 laminar steps. Sizes
+span several 256-node tiles with ragged tails; edge cases include the smallest
+grid, reversed inflow/outflow sides and fully periodic domains. The full-size
+8192 x 4096 domain is checked node by node at sampled nodes: the oracle advances
+the GPU's own state by one step at those nodes.
+"""
+import numpy as np
+import pytest
+
+from paper_1901_08766_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel_l2_velocity(a, b):
+    num = np.sum((a["ux"] - b["ux"]) ** 2 + (a["uy"] - b["uy"]) ** 2)
+    den = np.sum(b["ux"] ** 2 + b["uy"] ** 2)
+    return float(np.sqrt(num / den))
+
+
+def _force_scale(prob, fields):
+    """Per-body sum of |F_VP| over the body's nodes (the size of the terms the
+    recorded force sums, for a tolerance on a sum with cancellation)."""
+    out = []
+    for b in range(1, prob.n_bodies + 1):
+        sel = prob.mask_or_empty() == b
+        out.append(np.abs(fields["fx"][sel]).sum() + np.abs(fields["fy"][sel]).sum() + 1e-300)
+    return np.array(out)
+
+
+def _run_both(lbvp, oracle, prob, steps, storage):
+    print(f"case {prob.name} {prob.nx}x{prob.ny} storage={storage} steps={steps}", flush=True)
+    gpu = lbvp.Solver(prob, storage=storage, force_every=1, force_capacity=max(steps, 16))
+    gpu.step(steps, keep_fields=True)
+    gf, gm, first = gpu.forces()
+    ref = oracle.RefSolver(prob)
+    rf, rm = ref.step(steps, record=True)
+    return gpu, ref, (gf, gm, first), (rf, rm)
+
+
+SMALL_CASES = [
+    # (nx, ny, sides, seed)
+    (67, 45, ("inflow_eq", "outflow_zero_grad", "periodic", "periodic"), 1),
+    (300, 19, ("inflow_eq", "outflow_zero_grad", "periodic", "periodic"), 2),
+    (61, 37, ("periodic",) * 4, 3),
+    (3, 3, ("periodic",) * 4, 4),
+    (5, 7, ("outflow_zero_grad", "inflow_eq", "periodic", "periodic"), 5),
+    (513, 6, ("outflow_zero_grad", "outflow_zero_grad", "periodic", "periodic"), 6),
+]
+
+
+@pytest.mark.parametrize("nx,ny,sides,seed", SMALL_CASES)
+def test_fp64_matches_oracle(lbvp, oracle, nx, ny, sides, seed):
+    prob = inputs.random_state_problem(nx, ny, seed=seed, n_disks=3 if min(nx, ny) > 5 else 1,
+                                       bc=sides, body_force=(1e-5, -2e-6))
+    steps = 40
+    gpu, ref, (gf, gm, first), (rf, rm) = _run_both(lbvp, oracle, prob, steps, "f64")
+    g_gpu, g_ref = gpu.populations(), ref.populations()
+    assert np.abs(g_gpu - g_ref).max() <= 1e-12 * np.abs(g_ref).max()
+    fg, fr = gpu.fields(), ref.fields()
+    assert _rel_l2_velocity(fg, fr) <= 1e-12
+    for k in ("rho", "fx", "fy"):
+        assert np.abs(fg[k] - fr[k]).max() <= 1e-12 * max(np.abs(fr[k]).max(), 1e-30), k
+    assert first == 1 and gf.shape == rf.shape
+    scale = _force_scale(prob, fr)
+    if prob.n_bodies:
+        assert np.all(np.abs(gf - rf).max(axis=(0, 2)) <= 1e-11 * scale)
+    assert np.abs(gm - rm).max() <= 1e-13 * rm.max()
+    assert gpu.step_count == steps
+
+
+def test_fp64_couette_2000_steps(lbvp, oracle):
+    """Cylindrical Couette, 64 x 64, 2000 steps, FP64 storage: velocity rel-L2
+    against the oracle <= 1e-12."""
+    prob = inputs.couette()
+    gpu, ref, (gf, gm, _), (rf, rm) = _run_both(lbvp, oracle, prob, 2000, "f64")
+    assert _rel_l2_velocity(gpu.fields(), ref.fields()) <= 1e-12
+    # torque-free: both cylinders feel ~no net force; compare the records anyway
+    assert np.abs(gf - rf).max() <= 1e-11 * _force_scale(prob, ref.fields()).max()
+
+
+LAMINAR_FP32 = [
+    ("couette64", lambda: inputs.couette()),
+    ("cylinder1024x512_noise_free", lambda: inputs.cylinder(noise=False)),
+    ("taylor_green128", lambda: inputs.taylor_green(128)),
+]
+
+
+@pytest.mark.parametrize("name,make", LAMINAR_FP32, ids=[c[0] for c in LAMINAR_FP32])
+def test_fp32_laminar_1000_steps(lbvp, oracle, name, make):
+    """FP32 storage and arithmetic, 1000 steps: velocity rel-L2 <= 1e-5 against
+    the FP64 oracle; drag on each body within 1e-4 of its size."""
+    prob = make()
+    gpu, ref, (gf, gm, _), (rf, rm) = _run_both(lbvp, oracle, prob, 1000, "f32")
+    err = _rel_l2_velocity(gpu.fields(), ref.fields())
+    print(f"{name}: velocity rel-L2 {err:.3e}", flush=True)
+    assert err <= 1e-5
+    if prob.n_bodies:
+        scale = np.maximum(np.abs(rf[-1]).max(axis=1), 1e-12)
+        print(f"{name}: last-step force rel err {np.abs(gf[-1] - rf[-1]).max(axis=1) / scale}", flush=True)
+        assert np.all(np.abs(gf[-1] - rf[-1]).max(axis=1) <= 1e-4 * scale + 1e-7 * _force_scale(prob, ref.fields()))
+    assert np.abs(gm - rm).max() <= 1e-6 * rm.max()
+
+
+def test_fp32_full_size_sampled(lbvp, oracle):
+    """The 8192 x 4096 domain with five bodies (two counter-rotating cylinders, a
+    tandem pair, a NACA-0012) in the launch configuration the benchmark times:
+    after 20 GPU steps the oracle advances the GPU's state by one step at sampled
+    nodes (boundary columns and rows, every solid node of every body, random
+    fluid nodes), and that must equal the GPU's next state to FP32 rounding.
+    The recorded per-body forces of that step must equal the oracle's sums."""
+    prob = inputs.large_domain()
+    gpu = lbvp.Solver(prob, storage="f32", force_every=1, force_capacity=64)
+    gpu.step(20)
+    gpu.forces()
+    g20 = gpu.populations()
+    gpu.step(1, keep_fields=True)
+    gf, _, first = gpu.forces()
+    assert first == 21
+    g21 = gpu.populations()
+    fl = gpu.fields()
+    rng = np.random.Generator(np.random.PCG64(99))
+    nx, ny = prob.nx, prob.ny
+    ys_s, xs_s = np.nonzero(prob.mask)
+    xs = np.concatenate([np.zeros(64, int), np.full(64, nx - 1), rng.integers(0, nx, 64), rng.integers(0, nx, 64),
+                         rng.integers(0, nx, 4096), xs_s])
+    ys = np.concatenate([rng.integers(0, ny, 64), rng.integers(0, ny, 64), np.zeros(64, int), np.full(64, ny - 1),
+                         rng.integers(0, ny, 4096), ys_s])
+    ref = oracle.RefSolver(prob)
+    gout, rfl = ref.step_nodes(g20, xs, ys)
+    got = g21[:, ys, xs].T
+    assert np.abs(got - gout).max() <= 1e-6
+    for q, k in enumerate(("rho", "ux", "uy", "fx", "fy")):
+        assert np.abs(fl[k][ys, xs] - rfl[:, q]).max() <= 2e-6, k
+    # per-body force of step 21 from the oracle's node values, summed in FP64
+    solid = slice(len(xs) - len(xs_s), len(xs))
+    bid = prob.mask[ys_s, xs_s]
+    for b in range(1, prob.n_bodies + 1):
+        sel = bid == b
+        fx = -rfl[solid][sel, 3].sum()
+        fy = -rfl[solid][sel, 4].sum()
+        mag = np.abs(rfl[solid][sel, 3:5]).sum()
+        assert abs(gf[0, b - 1, 0] - fx) <= 1e-5 * mag and abs(gf[0, b - 1, 1] - fy) <= 1e-5 * mag
+
+
+def test_deterministic_rerun(lbvp):
+    """Two runs of the same problem are bitwise identical (fixed-order reductions)."""
+    prob = inputs.random_state_problem(300, 77, seed=21, n_disks=4)
+    outs = []
+    for _ in range(2):
+        s = lbvp.Solver(prob, storage="f32", force_every=1, force_capacity=64)
+        s.step(50)
+        f, m, _ = s.forces()
+        outs.append((s.populations(), f, m))
+        s.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+    assert np.array_equal(outs[0][2], outs[1][2])
+
+
+def test_edge_cases(lbvp):
+    prob = inputs.random_state_problem(17, 9, seed=5, n_disks=1)
+    s = lbvp.Solver(prob, storage="f32", force_every=2, force_capacity=4)
+    g0 = s.populations()
+    s.step(0)
+    assert np.array_equal(s.populations(), g0) and s.step_count == 0
+    s.step(8)                      # 4 records: the ring is full
+    with pytest.raises(lbvp.LbvpError) as e:
+        s.step(2)
+    assert e.value.status == lbvp.E_STATE
+    f, m, first = s.forces()
+    assert f.shape == (4, 1, 2) and first == 2
+    s.step(2)
+    f, m, first = s.forces()
+    assert f.shape == (1, 1, 2) and first == 10
+    with pytest.raises(lbvp.LbvpError) as e:
+        s.step(-1)
+    assert e.value.status == lbvp.E_ARG
+    bad = prob.mask_or_empty().copy()
+    bad[0, 0] = 7
+    with pytest.raises(lbvp.LbvpError) as e:
+        lbvp.lbvp_set_mask(s.ctx, bad, prob.bodies_or_empty())
+    assert e.value.status == lbvp.E_ARG
+    # write/read round trip of an arbitrary state
+    rng = np.random.Generator(np.random.PCG64(3))
+    g = g0 + 1e-3 * rng.uniform(-1, 1, g0.shape)
+    s.set_populations(g)
+    assert np.abs(s.populations() - g).max() <= 1e-7
