@@ -59,8 +59,9 @@ typedef enum lbvp_bc {
 } lbvp_bc;
 
 /* Storage type of the nine populations in device memory. All types store the
- * deviation f_a - w_a rho0. F64 computes in double; F32, F16_DEV and BF16_DEV
- * compute in float (F16/BF16 encode with round-to-nearest-even). */
+ * weight-normalized deviation (f_a - w_a rho0) / w_a. F64 computes in double;
+ * F32, F16_DEV and BF16_DEV compute in float (F16/BF16 encode with
+ * round-to-nearest-even). */
 typedef enum lbvp_storage {
     LBVP_F64 = 0,
     LBVP_F32 = 1,
@@ -172,6 +173,15 @@ lbvp_status lbvp_read_populations(lbvp_ctx* ctx, double* g);
 /* Overwrite the populations with host [9][ny][nx] FP64 values g_a (rounded to
  * the storage type). Keeps the step counter. */
 lbvp_status lbvp_write_populations(lbvp_ctx* ctx, const double* g);
+
+/* Launch configuration of the step kernel: vec nodes per thread (1, or the
+ * storage type's 16-byte width: 2 for F64, 4 for F32, 8 for F16/BF16) and block
+ * threads per workgroup (64, 128 or 256). Results do not depend on it except
+ * through the order of the force and mass sums. A default is chosen from the
+ * grid size at lbvp_create; a tuner may set another. Errors: E_ARG (other
+ * values), E_STATE (undrained force records). Synchronizes the stream. */
+lbvp_status lbvp_set_launch(lbvp_ctx* ctx, int32_t vec, int32_t block);
+lbvp_status lbvp_get_launch(const lbvp_ctx* ctx, int32_t* vec, int32_t* block);
 
 /* Number of steps taken since the last lbvp_init_equilibrium. */
 int64_t lbvp_step_count(const lbvp_ctx* ctx);

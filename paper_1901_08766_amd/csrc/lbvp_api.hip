@@ -36,9 +36,11 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 size_t storage_bytes(int32_t st) { return st == LBVP_F64 ? 8 : st == LBVP_F32 ? 4 : 2; }
 size_t arith_bytes(int32_t st) { return st == LBVP_F64 ? 8 : 4; }
 
+// Device arena layout. Tile tables are sized for the finest tiling any launch
+// configuration uses (one node per thread, 64-thread blocks).
 struct Layout {
     int64_t pitch = 0, plane = 0, plane_f = 0;
-    int32_t tiles_x = 0, n_tiles = 0, tiles_per_xcd = 0;
+    int32_t max_tiles = 0;
     int64_t slot_cap = 0, capacity = 0;
     int32_t max_bodies = 0;
     int64_t stage_rows = 0;
@@ -46,6 +48,37 @@ struct Layout {
            tile_slot_ptr = 0, slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0,
            ring_mass = 0, rec_count = 0, stage = 0, total = 0;
 };
+
+// Launch configuration of the step kernel and the tiling it implies.
+struct Launch {
+    int32_t vec = 1, block = MAX_BLOCK, tile_w = MAX_BLOCK;
+    int32_t tiles_x = 0, n_tiles = 0, tiles_per_xcd = 0;
+};
+
+Launch make_launch(int32_t nx, int32_t ny, int32_t vec, int32_t block)
+{
+    Launch l;
+    l.vec = vec;
+    l.block = block;
+    l.tile_w = vec * block;
+    l.tiles_x = (nx + l.tile_w - 1) / l.tile_w;
+    l.n_tiles = l.tiles_x * ny;
+    l.tiles_per_xcd = (l.n_tiles + N_XCD - 1) / N_XCD;
+    return l;
+}
+
+// Default launch: the 16-byte vector form when it still gives at least 8
+// wavefronts per SIMD (1024 SIMDs: 256 CUs x 4), else one node per thread;
+// small grids use 64-thread blocks to spread over more CUs.
+Launch default_launch(int32_t nx, int32_t ny, int32_t storage)
+{
+    const int64_t n = (int64_t)nx * ny;
+    const int vw = vector_width(storage);
+    const int vec = (n / (64 * vw) >= 8 * 1024) ? vw : 1;
+    const int64_t waves = n / (64 * vec);
+    const int block = waves >= 4096 ? MAX_BLOCK : MIN_BLOCK;
+    return make_launch(nx, ny, vec, block);
+}
 
 // Returns an empty string if the parameters are valid.
 std::string validate(const lbvp_params* p)
@@ -80,10 +113,9 @@ Layout make_layout(const lbvp_params* p)
     L.pitch = (int64_t)align_up((size_t)p->nx, 64);
     L.plane = (int64_t)align_up((size_t)(p->ny * L.pitch), 2048);
     L.plane_f = (int64_t)p->ny * L.pitch;
-    L.tiles_x = (p->nx + TILE_X - 1) / TILE_X;
-    L.n_tiles = L.tiles_x * p->ny;
-    L.tiles_per_xcd = (L.n_tiles + N_XCD - 1) / N_XCD;
-    L.slot_cap = 2 * (int64_t)L.n_tiles + 1024;
+    const Launch finest = make_launch(p->nx, p->ny, 1, MIN_BLOCK);
+    L.max_tiles = finest.n_tiles;
+    L.slot_cap = 2 * (int64_t)L.max_tiles + 1024;
     L.capacity = p->force_capacity > 0 ? p->force_capacity : DEFAULT_CAPACITY;
     L.max_bodies = p->max_bodies > 0 ? p->max_bodies : DEFAULT_MAX_BODIES;
     const size_t row_bytes = (size_t)p->nx * 9 * sizeof(double);
@@ -97,9 +129,9 @@ Layout make_layout(const lbvp_params* p)
     L.mask = take((size_t)p->ny * L.pitch);
     L.bodies = take((size_t)(L.max_bodies + 1) * 5 * rs);
     L.fields = take(5 * (size_t)L.plane_f * rs);
-    L.tile_mass = take((size_t)L.n_tiles * sizeof(double));
-    L.slot_force = take((size_t)L.slot_cap * 2 * sizeof(double));
-    L.tile_slot_ptr = take((size_t)(L.n_tiles + 1) * sizeof(int32_t));
+    L.tile_mass = take(2 * (size_t)L.max_tiles * sizeof(double));          // double-buffered
+    L.slot_force = take(2 * (size_t)L.slot_cap * 2 * sizeof(double));
+    L.tile_slot_ptr = take((size_t)(L.max_tiles + 1) * sizeof(int32_t));
     L.slot_body = take((size_t)L.slot_cap * sizeof(int32_t));
     L.body_slot_ptr = take((size_t)(MAX_BODIES + 2) * sizeof(int32_t));
     L.body_slots = take((size_t)L.slot_cap * sizeof(int32_t));
@@ -122,9 +154,13 @@ struct lbvp_ctx {
     int cur = 0;                // lattice holding the current post-collision state
     int64_t step = 0;
     int64_t rec_head = 0, rec_tail = 0;
+    bool pending = false;       // a recorded step whose sums are not yet in the ring
+    int32_t pending_buf = 0;
     bool fields_valid = false;
     int32_t n_bodies = 0;
     double tau_minus = 0.0;
+    Launch launch;
+    std::vector<uint8_t> mask_host;         // [ny][nx], kept to rebuild the tile tables
     StepArgs<double> a64{};
     StepArgs<float> a32{};
     FinalizeArgs fin{};
@@ -152,17 +188,15 @@ namespace {
         if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call);          \
     } while (0)
 
-// The inflow ghost populations f^eq(rho_in, u_in) - w rho0 (eq. feq), in FP64.
+// The inflow ghost populations (f^eq(rho_in, u_in) - w rho0) / w (eq. feq), in FP64.
 void inflow_ghost(const lbvp_params& p, double out[9])
 {
     static const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     static const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-    static const double w[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
-                                1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
     const double r = p.rho_in, ux = p.u_in[0], uy = p.u_in[1], uu = ux * ux + uy * uy;
     for (int q = 0; q < 9; ++q) {
         const double eu = ex[q] * ux + ey[q] * uy;
-        out[q] = w[q] * ((r - p.rho0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        out[q] = (r - p.rho0) + r * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
     }
 }
 
@@ -171,11 +205,15 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
 {
     const lbvp_params& p = c->p;
     const Layout& L = c->L;
+    const Launch& l = c->launch;
     a.nx = p.nx;
     a.ny = p.ny;
-    a.tiles_x = L.tiles_x;
-    a.n_tiles = L.n_tiles;
-    a.tiles_per_xcd = L.tiles_per_xcd;
+    a.vec = l.vec;
+    a.block = l.block;
+    a.tile_w = l.tile_w;
+    a.tiles_x = l.tiles_x;
+    a.n_tiles = l.n_tiles;
+    a.tiles_per_xcd = l.tiles_per_xcd;
     a.west = p.bc_west;
     a.east = p.bc_east;
     a.pitch = L.pitch;
@@ -189,6 +227,8 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.vp_c = (R)(1.0 / (2.0 * p.eta + 1.0));
     a.fbx = (R)p.body_force[0];
     a.fby = (R)p.body_force[1];
+    a.fbx18 = (R)(18.0 * p.body_force[0]);
+    a.fby18 = (R)(18.0 * p.body_force[1]);
     double fin[9];
     inflow_ghost(p, fin);
     for (int q = 0; q < 9; ++q) a.feq_in[q] = (R)fin[q];
@@ -199,6 +239,9 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.slot_force = c->at<double>(L.slot_force);
     a.tile_mass = c->at<double>(L.tile_mass);
     a.fields = c->at<R>(L.fields);
+    a.part_buf = 0;
+    a.fin_buf = -1;
+    a.fin = c->fin;
 }
 
 template <typename R>
@@ -212,6 +255,67 @@ std::vector<char> body_table_bytes(const lbvp_body* bodies, int32_t n, int32_t m
     std::vector<char> out(t.size() * sizeof(R));
     std::memcpy(out.data(), t.data(), out.size());
     return out;
+}
+
+// The (tile, body) reduction tables for the current tiling and mask: a slot per
+// body present in each tile, numbered in tile order, and each body's slots.
+lbvp_status build_tile_tables(lbvp_ctx* c)
+{
+    const lbvp_params& p = c->p;
+    const Layout& L = c->L;
+    const Launch& l = c->launch;
+    const int32_t nb = c->n_bodies;
+    const uint8_t* body_id = c->mask_host.data();
+    std::vector<int32_t> tile_ptr((size_t)l.n_tiles + 1, 0), slot_body;
+    std::vector<std::vector<int32_t>> per_body((size_t)nb);
+    std::vector<uint8_t> seen((size_t)nb + 1, 0);
+    for (int32_t t = 0; t < l.n_tiles; ++t) {
+        tile_ptr[t] = (int32_t)slot_body.size();
+        if (nb == 0) continue;
+        const int32_t j = t / l.tiles_x, i0 = (t % l.tiles_x) * l.tile_w, i1 = std::min(p.nx, i0 + l.tile_w);
+        const uint8_t* row = body_id + (int64_t)j * p.nx;
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int32_t i = i0; i < i1; ++i) seen[row[i]] = 1;
+        for (int32_t b = 1; b <= nb; ++b) {
+            if (!seen[b]) continue;
+            if ((int64_t)slot_body.size() >= L.slot_cap) {
+                (void)hipStreamSynchronize(c->stream);  // copies from the caller's host buffers
+                return c->fail(LBVP_E_NOMEM, "mask has more (tile, body) pairs than the reduction tables hold");
+            }
+            per_body[b - 1].push_back((int32_t)slot_body.size());
+            slot_body.push_back(b);
+        }
+    }
+    tile_ptr[l.n_tiles] = (int32_t)slot_body.size();
+    std::vector<int32_t> body_ptr((size_t)nb + 1, 0), body_slots;
+    for (int32_t b = 0; b < nb; ++b) {
+        body_ptr[b] = (int32_t)body_slots.size();
+        body_slots.insert(body_slots.end(), per_body[b].begin(), per_body[b].end());
+    }
+    body_ptr[nb] = (int32_t)body_slots.size();
+    hipStream_t s = c->stream;
+    LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.tile_slot_ptr), tile_ptr.data(), tile_ptr.size() * 4,
+                               hipMemcpyHostToDevice, s));
+    if (!slot_body.empty()) {
+        LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.slot_body), slot_body.data(), slot_body.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+        LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slots), body_slots.data(), body_slots.size() * 4,
+                                   hipMemcpyHostToDevice, s));
+    }
+    LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slot_ptr), body_ptr.data(), body_ptr.size() * 4,
+                               hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipStreamSynchronize(s));  // the host tables above go out of scope
+    return LBVP_OK;
+}
+
+// Adopt a launch configuration: kernel arguments, finalize arguments, tile tables.
+lbvp_status apply_launch(lbvp_ctx* c, const Launch& l)
+{
+    c->launch = l;
+    c->fin.n_tiles = l.n_tiles;
+    fill_step_args(c, c->a64);
+    fill_step_args(c, c->a32);
+    return build_tile_tables(c);
 }
 
 ConvArgs conv_args(lbvp_ctx* c, int32_t row0, int32_t rows)
@@ -285,19 +389,22 @@ lbvp_status lbvp_create(const lbvp_params* p, void* hip_stream, void* dev_mem, s
         c->mem = static_cast<char*>(m);
         c->owns = true;
     }
-    fill_step_args(c, c->a64);
-    fill_step_args(c, c->a32);
+    c->launch = default_launch(p->nx, p->ny, p->storage);
     c->fin.max_bodies = c->L.max_bodies;
-    c->fin.n_tiles = c->L.n_tiles;
+    c->fin.n_tiles = c->launch.n_tiles;
     c->fin.capacity = c->L.capacity;
     c->fin.mass_offset = p->rho0 * (double)p->nx * (double)p->ny;
     c->fin.body_slot_ptr = c->at<int32_t>(c->L.body_slot_ptr);
     c->fin.body_slots = c->at<int32_t>(c->L.body_slots);
     c->fin.slot_force = c->at<double>(c->L.slot_force);
     c->fin.tile_mass = c->at<double>(c->L.tile_mass);
+    c->fin.slot_stride = c->L.slot_cap * 2;
+    c->fin.tile_stride = c->L.max_tiles;
     c->fin.ring_force = c->at<double>(c->L.ring_force);
     c->fin.ring_mass = c->at<double>(c->L.ring_mass);
     c->fin.rec_count = c->at<int64_t>(c->L.rec_count);
+    fill_step_args(c, c->a64);
+    fill_step_args(c, c->a32);
     // empty mask, fluid at rest
     std::vector<uint8_t> zero((size_t)p->nx * p->ny, 0);
     lbvp_status s = lbvp_set_mask(c, zero.data(), 0, nullptr);
@@ -328,53 +435,17 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
     for (int64_t k = 0; k < n; ++k)
         if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
 
-    // (tile, body) pairs: a slot per body present in each tile, in tile order
-    std::vector<int32_t> tile_ptr((size_t)L.n_tiles + 1, 0), slot_body;
-    std::vector<std::vector<int32_t>> per_body((size_t)n_bodies);
-    std::vector<uint8_t> seen((size_t)n_bodies + 1, 0);
-    for (int32_t t = 0; t < L.n_tiles; ++t) {
-        tile_ptr[t] = (int32_t)slot_body.size();
-        if (n_bodies == 0) continue;
-        const int32_t j = t / L.tiles_x, i0 = (t % L.tiles_x) * TILE_X, i1 = std::min(p.nx, i0 + TILE_X);
-        const uint8_t* row = body_id + (int64_t)j * p.nx;
-        std::fill(seen.begin(), seen.end(), 0);
-        for (int32_t i = i0; i < i1; ++i) seen[row[i]] = 1;
-        for (int32_t b = 1; b <= n_bodies; ++b) {
-            if (!seen[b]) continue;
-            if ((int64_t)slot_body.size() >= L.slot_cap)
-                return c->fail(LBVP_E_NOMEM, "mask has more (tile, body) pairs than the reduction tables hold");
-            per_body[b - 1].push_back((int32_t)slot_body.size());
-            slot_body.push_back(b);
-        }
-    }
-    tile_ptr[L.n_tiles] = (int32_t)slot_body.size();
-    std::vector<int32_t> body_ptr((size_t)n_bodies + 1, 0), body_slots;
-    for (int32_t b = 0; b < n_bodies; ++b) {
-        body_ptr[b] = (int32_t)body_slots.size();
-        body_slots.insert(body_slots.end(), per_body[b].begin(), per_body[b].end());
-    }
-    body_ptr[n_bodies] = (int32_t)body_slots.size();
     std::vector<char> table = c->is_f64() ? body_table_bytes<double>(bodies, n_bodies, L.max_bodies)
                                           : body_table_bytes<float>(bodies, n_bodies, L.max_bodies);
+    c->mask_host.assign(body_id, body_id + n);
+    c->n_bodies = n_bodies;
+    c->fin.n_bodies = n_bodies;
 
     hipStream_t s = c->stream;
     LBVP_HIP(c, hipMemcpy2DAsync(c->at<uint8_t>(L.mask), (size_t)L.pitch, body_id, (size_t)p.nx,
                                  (size_t)p.nx, (size_t)p.ny, hipMemcpyHostToDevice, s));
-    LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.tile_slot_ptr), tile_ptr.data(), tile_ptr.size() * 4,
-                               hipMemcpyHostToDevice, s));
-    if (!slot_body.empty()) {
-        LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.slot_body), slot_body.data(), slot_body.size() * 4,
-                                   hipMemcpyHostToDevice, s));
-        LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slots), body_slots.data(), body_slots.size() * 4,
-                                   hipMemcpyHostToDevice, s));
-    }
-    LBVP_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slot_ptr), body_ptr.data(), body_ptr.size() * 4,
-                               hipMemcpyHostToDevice, s));
     LBVP_HIP(c, hipMemcpyAsync(c->at<char>(L.bodies), table.data(), table.size(), hipMemcpyHostToDevice, s));
-    LBVP_HIP(c, hipStreamSynchronize(s));  // the host tables above go out of scope
-    c->n_bodies = n_bodies;
-    c->fin.n_bodies = n_bodies;
-    return LBVP_OK;
+    return build_tile_tables(c);  // synchronizes
 }
 
 lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* ux, const double* uy)
@@ -408,6 +479,7 @@ lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* 
     c->cur = 0;
     c->step = 0;
     c->rec_head = c->rec_tail = 0;
+    c->pending = false;
     c->fields_valid = true;
     return LBVP_OK;
 }
@@ -423,22 +495,33 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
         if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
             return c->fail(LBVP_E_STATE, "force records would overflow the device ring; call lbvp_forces first");
     }
-    const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
+    c->a64.fin = c->fin;
+    c->a32.fin = c->fin;
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t next = c->step + 1;
         const bool record = fe > 0 && next % fe == 0;
         const bool keep = (flags & LBVP_KEEP_FIELDS) && k == n_steps - 1;
+        const int32_t part_buf = (int32_t)(c->rec_head & 1);
+        const int32_t fin_buf = c->pending ? c->pending_buf : -1;
+        c->a64.part_buf = c->a32.part_buf = part_buf;
+        c->a64.fin_buf = c->a32.fin_buf = fin_buf;
+        const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
         hipError_t e = launch_step(c->p.storage, record, keep, c->at<char>(c->L.lat[c->cur]),
                                    c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
+        c->pending = record;
         if (record) {
-            e = launch_finalize(c->fin, c->stream);
-            if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+            c->pending_buf = part_buf;
             c->rec_head += 1;
         }
         if (keep) c->fields_valid = true;
         c->cur ^= 1;
         c->step = next;
+    }
+    if (c->pending) {  // the last record of the call is summed on its own
+        hipError_t e = launch_finalize(c->fin, c->pending_buf, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+        c->pending = false;
     }
     return LBVP_OK;
 }
@@ -542,6 +625,25 @@ lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)
         LBVP_HIP(c, launch_encode(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
     }
     LBVP_HIP(c, hipStreamSynchronize(s));
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_set_launch(lbvp_ctx* c, int32_t vec, int32_t block)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (vec != 1 && vec != vector_width(c->p.storage))
+        return c->fail(LBVP_E_ARG, "vec must be 1 or the storage type's 16-byte vector width");
+    if (block != 64 && block != 128 && block != 256) return c->fail(LBVP_E_ARG, "block must be 64, 128 or 256");
+    if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");
+    LBVP_HIP(c, hipStreamSynchronize(c->stream));
+    return apply_launch(c, make_launch(c->p.nx, c->p.ny, vec, block));
+}
+
+lbvp_status lbvp_get_launch(const lbvp_ctx* c, int32_t* vec, int32_t* block)
+{
+    if (!c || !vec || !block) return LBVP_E_ARG;
+    *vec = c->launch.vec;
+    *block = c->launch.block;
     return LBVP_OK;
 }
 

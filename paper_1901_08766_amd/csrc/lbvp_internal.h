@@ -7,24 +7,47 @@
 
 namespace lbvp {
 
-// One workgroup updates one tile of TILE_X consecutive nodes of a row, one node
-// per thread. Workgroups are dealt to the 8 XCDs round-robin by block id; the
-// launch remaps block b to tile (b % 8) * tiles_per_xcd + b / 8 so that each XCD
-// sweeps a contiguous band of rows and neighbouring tiles share one L2.
-constexpr int TILE_X = 256;
+// One workgroup of `block` threads updates one tile of block * vec consecutive
+// nodes of a row, vec nodes per thread. Workgroups are dealt to the 8 XCDs
+// round-robin by block id; the launch remaps block b to tile
+// (b % 8) * tiles_per_xcd + b / 8 so that each XCD sweeps a contiguous band of
+// rows and neighbouring tiles share one L2.
 constexpr int N_XCD = 8;
-constexpr int FIN_THREADS = 1024;
+constexpr int MAX_BLOCK = 256;
+constexpr int MIN_BLOCK = 64;
+constexpr int FIN_THREADS = 256;
 
 enum Side : int32_t { SIDE_PERIODIC = 0, SIDE_INFLOW_EQ = 1, SIDE_OUTFLOW = 2 };
 
 // Storage codes (match lbvp_storage).
 enum Storage : int32_t { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
 
+// Sums one force record: the tile mass partials and the (tile, body) force
+// partials of partial buffer `buf`, in a fixed order, into ring slot
+// rec_count % capacity. The partials are double-buffered so that the record of
+// step k can be summed while step k + 1 writes its own.
+struct FinalizeArgs {
+    int32_t n_bodies, max_bodies, n_tiles;
+    int64_t capacity;
+    double mass_offset;             // rho0 * nx * ny
+    const int32_t* body_slot_ptr;   // [n_bodies + 1]
+    const int32_t* body_slots;      // slots of each body in tile order
+    const double* slot_force;       // [2][slot_stride / 2][2]
+    const double* tile_mass;        // [2][tile_stride]
+    int64_t slot_stride, tile_stride;
+    double* ring_force;             // [capacity][max_bodies][2]
+    double* ring_mass;              // [capacity]
+    int64_t* rec_count;             // records written so far
+};
+
 template <typename R>
 struct StepArgs {
     int32_t nx, ny;
+    int32_t vec, block, tile_w;     // nodes per thread, threads per block, nodes per tile
     int32_t tiles_x, n_tiles, tiles_per_xcd;
     int32_t west, east;
+    int32_t part_buf;   // partial buffer a recording step writes
+    int32_t fin_buf;    // partial buffer whose record block 0 sums first, or -1
     int64_t pitch;      // elements per row (lattice, mask and fields)
     int64_t plane;      // elements between population planes
     int64_t plane_f;    // elements between field planes
@@ -33,27 +56,16 @@ struct StepArgs {
     R k_p, k_m;         // 1 - 1/(2 tau_plus), 1 - 1/(2 tau_minus)
     R vp_c;             // 1 / (2 eta + 1): the chi = 1 value of chi / (2 eta + chi)
     R fbx, fby;         // body force
-    R feq_in[9];        // f^eq(rho_in, u_in) - w rho0 of an INFLOW_EQ side
+    R fbx18, fby18;     // 18 F_b: the body-force half step in units of 36 j
+    R feq_in[9];        // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side
     const uint8_t* mask;
     const R* bodies;    // [(n_bodies + 1)][5]; row 0 is all zero (fluid)
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
-    double* slot_force;             // [n_slots][2]
-    double* tile_mass;              // [n_tiles]
+    double* slot_force;             // [2][n_slots][2]
+    double* tile_mass;              // [2][n_tiles]
     R* fields;                      // [5][plane_f]
-};
-
-struct FinalizeArgs {
-    int32_t n_bodies, max_bodies, n_tiles;
-    int64_t capacity;
-    double mass_offset;             // rho0 * nx * ny
-    const int32_t* body_slot_ptr;   // [n_bodies + 1]
-    const int32_t* body_slots;      // slots of each body in tile order
-    const double* slot_force;
-    const double* tile_mass;
-    double* ring_force;             // [capacity][max_bodies][2]
-    double* ring_mass;              // [capacity]
-    int64_t* rec_count;             // records written so far
+    FinalizeArgs fin;
 };
 
 struct ConvArgs {
@@ -66,10 +78,13 @@ struct ConvArgs {
     double* pops;       // staged [9][rows][nx]
 };
 
+// nodes per thread of the vector form of the step for a storage type (16 bytes)
+int vector_width(int32_t storage);
+
 // launchers (lbvp_kernels.hip); all return the launch status
 hipError_t launch_step(int32_t storage, bool record, bool fields, const void* src, void* dst,
                        const void* step_args, hipStream_t s);
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s);
+hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s);
 hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs& a, hipStream_t s);
 hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);
 hipError_t launch_encode(int32_t storage, void* lat, const ConvArgs& a, hipStream_t s);

@@ -2,13 +2,19 @@
 //
 // Data layout in HBM (structure of arrays): population a of node (i, j) lives at
 // lattice[a * plane + j * pitch + i]; pitch is a multiple of 64 elements, so
-// every row starts on a 256-byte boundary (FP32). All storage types hold the
-// deviation f_a - w_a rho0, which keeps the stored magnitudes small (|u| ~ 0.1
-// gives |deviation| ~ 0.05) and the FP32/FP16/BF16 rounding error with them.
+// every row starts on a 256-byte boundary. All storage types hold the
+// weight-normalized deviation h_a = (f_a - w_a rho0) / w_a. Its size is set by
+// the flow (|h| ~ 3|u|) and is the same for every direction, and the equilibrium
+// in these units carries no weight at all,
+//   h^eq_a = drho + rho (3 eu + 9/2 eu^2 - 3/2 u.u),
+// while the moments use the exact integers 36 w_a = 16, 4, 1:
+//   36 drho = 16 h_0 + 4 sum_axis h + sum_diag h,  36 j = 4 sum_axis e h + sum_diag e h.
+// In FP32 the inexact weights 1/9 and 1/36 would otherwise bias every collision's
+// momentum by ~1e-8, which a freely decaying flow accumulates step after step.
 //
 // One step (Sec. 2.2, steps (2)-(6)), per node, fused:
 //   pull   f_a(x) = g_a(x - e_a)                      eq. (streaming)
-//   rho = rho0 + sum f~_a,  rho u* = sum e_a f~_a + F_b/2   eqs. (rho), (rho*velocity-star)
+//   rho = rho0 + sum w_a h_a,  rho u* = sum e_a w_a h_a + F_b/2   eqs. (rho), (rho*velocity-star)
 //   chi from the mask, U_O = V + omega z x (x - c) of the node's body
 //   du = chi (U_O - u*) / (2 eta + chi),  F_VP = 2 rho du    eqs. (d-V), (force-density)
 //   u = u* + du,  F = F_b + F_VP                       eq. (velocity-r)
@@ -16,12 +22,18 @@
 //         + (1 - 1/(2 tau+)) F+_a + (1 - 1/(2 tau-)) F-_a        eqs. (TRT-collision), (collision-modified)
 // with f^eq of eq. (feq) and F_a of eq. (external-force-term), both taken at the
 // corrected u and split into parts even (+) and odd (-) under a -> opposite(a).
-// For a pair (a, opposite a) with eu = e_a.u and eF = e_a.F the parts are
-//   f^eq+ - w rho0 = w (drho + rho (9/2 eu^2 - 3/2 u.u)),  f^eq- = 3 w rho eu,
-//   F+ = w (9 eu eF - 3 u.F),                           F- = 3 w eF.
+// For a pair (a, opposite a) with eu = e_a.u and eF = e_a.F the parts are, in
+// units of w_a,
+//   h^eq+ = drho + rho (9/2 eu^2 - 3/2 u.u),  h^eq- = 3 rho eu,
+//   F+/w  = 9 eu eF - 3 u.F,                 F-/w  = 3 eF.
 //
 // The step is bound by HBM traffic: 9 loads, 9 stores and one mask byte per node
-// against ~200 flops, so there is no matrix-core work here.
+// against ~200 flops, so there is no matrix-core work here. What limits it is
+// the bytes in flight: each thread owns V consecutive nodes of a row and moves
+// every population with one aligned V-wide (16-byte) load and store. The pull
+// from x -/+ 1 takes the missing end element from the neighbouring lane of the
+// wavefront (a lane shuffle); the two lanes at a wavefront's ends load it
+// themselves, with the domain sides resolved there.
 #include <hip/hip_runtime.h>
 
 #include "lbvp_internal.h"
@@ -41,192 +53,465 @@ __device__ __forceinline__ S enc(R v) { return (S)v; }  // round to nearest even
 template <typename S> struct Arith { using R = float; };
 template <> struct Arith<double> { using R = double; };
 
+// V consecutive elements moved as one aligned access of V * sizeof(S) bytes.
+template <typename S, int V>
+__device__ __forceinline__ void load_vec(const S* p, S (&out)[V])
+{
+    constexpr int B = V * (int)sizeof(S);
+    if constexpr (B == 16) {
+        const uint4 r = *reinterpret_cast<const uint4*>(p);
+        __builtin_memcpy(out, &r, 16);
+    } else if constexpr (B == 8) {
+        const uint2 r = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(out, &r, 8);
+    } else if constexpr (B == 4) {
+        const uint32_t r = *reinterpret_cast<const uint32_t*>(p);
+        __builtin_memcpy(out, &r, 4);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) out[k] = p[k];
+    }
+}
+
+// Stores are non-temporal: the new lattice is not read again before the whole
+// domain has streamed through the caches, so it should not displace anything.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+template <typename S, int V>
+__device__ __forceinline__ void store_vec(S* p, const S (&in)[V])
+{
+    constexpr int B = V * (int)sizeof(S);
+    if constexpr (B == 16) {
+        u32x4_t r;
+        __builtin_memcpy(&r, in, 16);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x4_t*>(p));
+    } else if constexpr (B == 8) {
+        u32x2_t r;
+        __builtin_memcpy(&r, in, 8);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x2_t*>(p));
+    } else if constexpr (B == 4) {
+        uint32_t r;
+        __builtin_memcpy(&r, in, 4);
+        __builtin_nontemporal_store(r, reinterpret_cast<uint32_t*>(p));
+    } else if constexpr (B == 2) {
+        uint16_t r;
+        __builtin_memcpy(&r, in, 2);
+        __builtin_nontemporal_store(r, reinterpret_cast<uint16_t*>(p));
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) p[k] = in[k];
+    }
+}
+
+// The same V elements starting one element off a 16-byte boundary: a single
+// vector access that needs only the element's own (dword or wider) alignment.
+template <typename S, int V>
+__device__ __forceinline__ void load_vec_shifted(const S* p, S (&out)[V])
+{
+    static_assert(sizeof(S) >= 4, "sub-dword elements take the lane-shuffle path");
+    __builtin_memcpy(out, p, V * sizeof(S));
+}
+
+template <int V>
+__device__ __forceinline__ void load_mask(const uint8_t* p, int (&out)[V])
+{
+    uint8_t b[V];
+    if constexpr (V == 8) {
+        const uint2 r = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(b, &r, 8);
+    } else if constexpr (V == 4) {
+        const uint32_t r = *reinterpret_cast<const uint32_t*>(p);
+        __builtin_memcpy(b, &r, 4);
+    } else if constexpr (V == 2) {
+        const uint16_t r = *reinterpret_cast<const uint16_t*>(p);
+        __builtin_memcpy(b, &r, 2);
+    } else {
+        b[0] = p[0];
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] = b[k];
+}
+
 // ------------------------------------------------------------ reductions --
-// Sum over a 256-thread block in a fixed order (deterministic); result valid in
-// thread 0. lds must hold 4 doubles and is reused across calls.
-__device__ __forceinline__ double block_sum_256(double v, double* lds)
+// Sum over the block in a fixed order (deterministic): wavefront shuffles, then
+// the per-wavefront sums in wavefront order. lds holds one double per wavefront
+// and is reused across calls; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* lds)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
     __syncthreads();
-    return (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    const int nw = (int)(blockDim.x >> 6);
+    double s = lds[0];
+    for (int w = 1; w < nw; ++w) s += lds[w];
+    return s;
 }
 
-// ------------------------------------------------------------ the step --
+// ------------------------------------------------------------ the collision --
+// Quotients that must not carry a fixed relative error (see the header): FP64
+// divides; FP32 multiplies by the rounded reciprocal and corrects with the exact
+// residual (one FMA), which returns the quotient to within a hair of correct
+// rounding with no systematic direction, in 3 instructions instead of ~10.
+__device__ __forceinline__ double div36(double s) { return s / 36.0; }
+__device__ __forceinline__ float div36(float s)
+{
+    const float r = 1.0f / 36.0f;
+    const float q = s * r;
+    return __builtin_fmaf(__builtin_fmaf(-36.0f, q, s), r, q);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);            // ~1 ulp
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);  // one Newton step
+}
+
 template <typename R>
 struct Pair {
     R ga, gb;
 };
 
-// Collision of a population pair (a, opposite a) of weight w.
+// Per-node terms shared by the four pair collisions, in weight-normalized units.
 template <typename R>
-__device__ __forceinline__ Pair<R> collide_pair(R fa, R fb, R w, R eu, R eF, R drho, R rho, R uu,
-                                                R uF, const StepArgs<R>& a)
+struct NodeTerms {
+    R A;        // drho - 3/2 rho u.u : the even equilibrium without its eu^2 part
+    R rho45;    // 9/2 rho
+    R rho3;     // 3 rho
+    R uF3;      // -3 u.F
+};
+
+// Collision of a population pair (a, opposite a) with eu = e_a.u, eF = e_a.F:
+//   even part  s+ + (h^eq+ - s+)/tau+ + (1 - 1/(2 tau+)) F+/w,  h^eq+ = A + 9/2 rho eu^2
+//   odd part   s- + (h^eq- - s-)/tau- + (1 - 1/(2 tau-)) F-/w,  h^eq- = 3 rho eu
+// (F+/w = 9 eu eF - 3 u.F, F-/w = 3 eF). Relaxing as x + (y - x)/tau keeps the
+// fixed point x = y exact in floating point.
+template <typename R>
+__device__ __forceinline__ Pair<R> collide_pair(R ha, R hb, R eu, R eF, const NodeTerms<R>& n,
+                                                const StepArgs<R>& a)
 {
-    const R half = R(0.5);
-    const R sp = half * (fa + fb);
-    const R sm = half * (fa - fb);
-    const R ep = w * (drho + rho * (R(4.5) * eu * eu - R(1.5) * uu));
-    const R em = R(3) * w * rho * eu;
-    const R Fp = w * (R(9) * eu * eF - R(3) * uF);
-    const R Fm = R(3) * w * eF;
-    const R gp = sp - a.om_p * (sp - ep) + a.k_p * Fp;
-    const R gm = sm - a.om_m * (sm - em) + a.k_m * Fm;
+    const R sp = R(0.5) * (ha + hb);
+    const R sm = R(0.5) * (ha - hb);
+    const R ep = n.rho45 * (eu * eu) + n.A;
+    const R em = n.rho3 * eu;
+    const R Fp = (R(9) * eu) * eF + n.uF3;
+    const R Fm = R(3) * eF;
+    const R gp = a.om_p * (ep - sp) + sp + a.k_p * Fp;
+    const R gm = a.om_m * (em - sm) + sm + a.k_m * Fm;
     return {gp + gm, gp - gm};
 }
 
-template <typename S, bool RECORD, bool FIELDS>
-__global__ void __launch_bounds__(TILE_X)
-k_step_pull(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
+template <typename R>
+struct NodeResult {
+    R drho, rho, ux, uy, fvx, fvy;
+};
+
+// Steps (4)-(6) of the algorithm at node (i, j) with streamed populations f;
+// overwrites f with the post-collision populations.
+template <typename R>
+__device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i, int j, const StepArgs<R>& a)
 {
-    using R = typename Arith<S>::R;
-    const int blk = blockIdx.x;
-    const int t = (blk % N_XCD) * a.tiles_per_xcd + blk / N_XCD;
-    if (t >= a.n_tiles) return;  // whole block
-    const int j = t / a.tiles_x;
-    const int i = (t - j * a.tiles_x) * TILE_X + (int)threadIdx.x;
-    const bool on = i < a.nx;
+    // moments with the integers 36 w_a = 16, 4, 1 (sum w_a rho0 = rho0 and
+    // sum e_a w_a = 0 drop out); 1/36 and 1/rho through div36 / recip
+    const R s36 = R(16) * f[0] + (R(4) * ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+    const R drho = div36(s36);
+    const R rho = a.rho0 + drho;
+    const R d57 = f[5] - f[7], d86 = f[8] - f[6];
+    const R inv_36rho = recip(R(36) * rho);
+    // u* = (j + F_b/2) / rho with 36 j = 4 (h1 - h3) + ... (eq. rho*velocity-star)
+    R ux = (R(4) * (f[1] - f[3]) + (d57 + d86) + a.fbx18) * inv_36rho;
+    R uy = (R(4) * (f[2] - f[4]) + (d57 - d86) + a.fby18) * inv_36rho;
 
-    R drho = 0, fvx = 0, fvy = 0;
-    int body = 0;
-    if (on) {
-        // source rows/columns of the pull, with the domain sides resolved
-        const int jm = (j == 0) ? a.ny - 1 : j - 1;        // rows are periodic
-        const int jp = (j == a.ny - 1) ? 0 : j + 1;
-        int im = i - 1, ip = i + 1;
-        bool w_in = false, e_in = false;
-        if (i == 0) {
-            if (a.west == SIDE_PERIODIC) im = a.nx - 1;
-            else { im = 0; w_in = (a.west == SIDE_INFLOW_EQ); }
-        }
-        if (i == a.nx - 1) {
-            if (a.east == SIDE_PERIODIC) ip = 0;
-            else { ip = a.nx - 1; e_in = (a.east == SIDE_INFLOW_EQ); }
-        }
-        const int64_t r0 = (int64_t)j * a.pitch, rm = (int64_t)jm * a.pitch, rp = (int64_t)jp * a.pitch;
-        const int64_t P = a.plane;
-        const R f0 = dec(src[r0 + i]);
-        const R f1 = w_in ? a.feq_in[1] : dec(src[1 * P + r0 + im]);
-        const R f2 = dec(src[2 * P + rm + i]);
-        const R f3 = e_in ? a.feq_in[3] : dec(src[3 * P + r0 + ip]);
-        const R f4 = dec(src[4 * P + rp + i]);
-        const R f5 = w_in ? a.feq_in[5] : dec(src[5 * P + rm + im]);
-        const R f6 = e_in ? a.feq_in[6] : dec(src[6 * P + rm + ip]);
-        const R f7 = e_in ? a.feq_in[7] : dec(src[7 * P + rp + ip]);
-        const R f8 = w_in ? a.feq_in[8] : dec(src[8 * P + rp + im]);
-        body = a.mask[r0 + i];
-
-        // moments (deviation form: sum w_a rho0 = rho0, sum e_a w_a = 0)
-        drho = ((f0 + f1) + (f2 + f3)) + ((f4 + f5) + (f6 + f7)) + f8;
-        const R rho = a.rho0 + drho;
-        const R jx = (f1 - f3) + (f5 - f7) + (f8 - f6);
-        const R jy = (f2 - f4) + (f5 - f7) + (f6 - f8);
-        const R inv_rho = R(1) / rho;
-        R ux = (jx + R(0.5) * a.fbx) * inv_rho;   // u*
-        R uy = (jy + R(0.5) * a.fby) * inv_rho;
-
-        // volume penalization, branch-free: row 0 of the body table is zero
+    // volume penalization (eqs. d-V, force-density) on solid nodes only
+    R fvx = R(0), fvy = R(0);
+    if (body) {
         const R* B = a.bodies + 5 * body;
         const R uox = B[2] - B[4] * ((R)j - B[1]);
         const R uoy = B[3] + B[4] * ((R)i - B[0]);
-        const R c = body ? a.vp_c : R(0);
-        const R dux = c * (uox - ux);
-        const R duy = c * (uoy - uy);
+        const R dux = a.vp_c * (uox - ux);
+        const R duy = a.vp_c * (uoy - uy);
         fvx = R(2) * rho * dux;
         fvy = R(2) * rho * duy;
         ux += dux;
         uy += duy;
-        const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
+    }
+    const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
 
-        const R uu = ux * ux + uy * uy;
-        const R uF = ux * Fx + uy * Fy;
-        const R w0 = R(4.0 / 9.0), w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
-        const R g0 = f0 - a.om_p * (f0 - w0 * (drho - R(1.5) * rho * uu)) + a.k_p * (R(-3) * w0 * uF);
-        const Pair<R> p13 = collide_pair(f1, f3, w1, ux, Fx, drho, rho, uu, uF, a);
-        const Pair<R> p24 = collide_pair(f2, f4, w1, uy, Fy, drho, rho, uu, uF, a);
-        const Pair<R> p57 = collide_pair(f5, f7, w5, ux + uy, Fx + Fy, drho, rho, uu, uF, a);
-        const Pair<R> p68 = collide_pair(f6, f8, w5, uy - ux, Fy - Fx, drho, rho, uu, uF, a);
+    NodeTerms<R> n;
+    const R uu = ux * ux + uy * uy;
+    n.A = drho - (R(1.5) * rho) * uu;
+    n.rho45 = R(4.5) * rho;
+    n.rho3 = R(3) * rho;
+    n.uF3 = R(-3) * (ux * Fx + uy * Fy);
+    const R g0 = a.om_p * (n.A - f[0]) + f[0] + a.k_p * n.uF3;
+    const Pair<R> p13 = collide_pair(f[1], f[3], ux, Fx, n, a);
+    const Pair<R> p24 = collide_pair(f[2], f[4], uy, Fy, n, a);
+    const Pair<R> p57 = collide_pair(f[5], f[7], ux + uy, Fx + Fy, n, a);
+    const Pair<R> p68 = collide_pair(f[6], f[8], uy - ux, Fy - Fx, n, a);
+    f[0] = g0;
+    f[1] = p13.ga;
+    f[3] = p13.gb;
+    f[2] = p24.ga;
+    f[4] = p24.gb;
+    f[5] = p57.ga;
+    f[7] = p57.gb;
+    f[6] = p68.ga;
+    f[8] = p68.gb;
+    return {drho, rho, ux, uy, fvx, fvy};
+}
 
-        S* d = dst + r0 + i;
-        d[0] = enc<S>(g0);
-        d[1 * P] = enc<S>(p13.ga);
-        d[2 * P] = enc<S>(p24.ga);
-        d[3 * P] = enc<S>(p13.gb);
-        d[4 * P] = enc<S>(p24.gb);
-        d[5 * P] = enc<S>(p57.ga);
-        d[6 * P] = enc<S>(p68.ga);
-        d[7 * P] = enc<S>(p57.gb);
-        d[8 * P] = enc<S>(p68.gb);
+// Population q pulled from column c (-1 and nx are outside the domain) of the
+// row starting at row_off: the domain sides are resolved here.
+template <typename S, typename R>
+__device__ __forceinline__ R pull_column(const S* __restrict__ src, int q, int64_t row_off, int c,
+                                         const StepArgs<R>& a)
+{
+    if (c < 0) {
+        if (a.west == SIDE_INFLOW_EQ) return a.feq_in[q];
+        c = (a.west == SIDE_PERIODIC) ? a.nx - 1 : 0;
+    } else if (c >= a.nx) {
+        if (a.east == SIDE_INFLOW_EQ) return a.feq_in[q];
+        c = (a.east == SIDE_PERIODIC) ? 0 : a.nx - 1;
+    }
+    return dec(src[(int64_t)q * a.plane + row_off + c]);
+}
 
+// D2Q9 directions by x component (eq. D2Q9), pulled from column i - ex, with
+// source rows j, j - 1, j + 1 for m = 0, 1, 2.
+constexpr int EXP[3] = {1, 5, 8};   // ex = +1: from column i - 1
+constexpr int EXM[3] = {3, 6, 7};   // ex = -1: from column i + 1
+
+// ------------------------------------------------------------ the record --
+// One block sums one force record (see FinalizeArgs) in a fixed order: each
+// thread walks a fixed stride of the partials with eight independent
+// accumulators (so that loads overlap), then the block sums the threads.
+__device__ __forceinline__ double strided_sum(const double* x, int n, int stride2)
+{
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int nt = (int)blockDim.x;
+    int k = (int)threadIdx.x;
+    for (; k + 7 * nt < n; k += 8 * nt) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += x[(int64_t)(k + u * nt) * stride2];
+    }
+#pragma unroll
+    for (int u = 0; u < 7; ++u) {   // at most 7 left
+        const int kk = k + u * nt;
+        if (kk < n) acc[u] += x[(int64_t)kk * stride2];
+    }
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+__device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, double* lds)
+{
+    const double* tm = f.tile_mass + buf * f.tile_stride;
+    const double* sf = f.slot_force + buf * f.slot_stride;
+    const double m = block_sum(strided_sum(tm, f.n_tiles, 1), lds);
+    const int64_t r = *f.rec_count % f.capacity;
+    for (int b = 0; b < f.n_bodies; ++b) {
+        const int s0 = f.body_slot_ptr[b], s1 = f.body_slot_ptr[b + 1];
+        double x = 0.0, y = 0.0;
+        for (int k = s0 + (int)threadIdx.x; k < s1; k += (int)blockDim.x) {
+            const int s = f.body_slots[k];
+            x += sf[2 * s];
+            y += sf[2 * s + 1];
+        }
+        x = block_sum(x, lds);
+        y = block_sum(y, lds);
+        if (threadIdx.x == 0) {
+            f.ring_force[(r * f.max_bodies + b) * 2] = x;
+            f.ring_force[(r * f.max_bodies + b) * 2 + 1] = y;
+        }
+    }
+    if (threadIdx.x == 0) {
+        f.ring_mass[r] = f.mass_offset + m;
+        *f.rec_count += 1;
+    }
+}
+
+// ------------------------------------------------------------ the step --
+template <typename S, int V, bool RECORD, bool FIELDS>
+__global__ void __launch_bounds__(256)
+k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
+{
+    using R = typename Arith<S>::R;
+    __shared__ double lds[MAX_BLOCK / 64];
+    const int blk = blockIdx.x;
+    // block 0 first sums the previous step's force record (no other block waits on it)
+    if (blk == 0 && a.fin_buf >= 0) finalize_record(a.fin, a.fin_buf, lds);
+    const int t = (blk % N_XCD) * a.tiles_per_xcd + blk / N_XCD;
+    if (t >= a.n_tiles) return;  // whole block
+    const int j = t / a.tiles_x;
+    const int i0 = (t - j * a.tiles_x) * a.tile_w + (int)threadIdx.x * V;
+    const int lane = (int)(threadIdx.x & 63);
+    const bool act = i0 < a.nx;          // owns at least one real node
+    const int n_own = act ? min(V, a.nx - i0) : 0;
+
+    const int jm = (j == 0) ? a.ny - 1 : j - 1;     // rows are periodic
+    const int jp = (j == a.ny - 1) ? 0 : j + 1;
+    const int64_t r0 = (int64_t)j * a.pitch, rm = (int64_t)jm * a.pitch, rp = (int64_t)jp * a.pitch;
+    // source row of each direction: ey = 0 -> j, ey = +1 -> j - 1, ey = -1 -> j + 1
+    const int64_t row_of[9] = {r0, r0, rm, r0, rp, rm, rm, rp, rp};
+    const int64_t P = a.plane;
+
+    // Loads of every direction's source row. Dword-or-wider elements take the
+    // x-shifted directions as single vector loads one element off alignment
+    // (columns i0 - 1 .. or i0 + 1 ..; both stay inside the lattice allocation:
+    // plane 0 is never shifted and a row's padding is followed by the next row
+    // or plane). Narrower elements load aligned and shift through lane shuffles.
+    constexpr bool kShiftedLoads = sizeof(S) >= 4 && V > 1;
+    R v[9][V];
+    int body[V];
+    if (act) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            S raw[V];
+            if constexpr (kShiftedLoads) {
+                if (q == 1 || q == 5 || q == 8) load_vec_shifted<S, V>(src + q * P + row_of[q] + (i0 - 1), raw);
+                else if (q == 3 || q == 6 || q == 7) load_vec_shifted<S, V>(src + q * P + row_of[q] + (i0 + 1), raw);
+                else load_vec<S, V>(src + q * P + row_of[q] + i0, raw);
+            } else {
+                load_vec<S, V>(src + q * P + row_of[q] + i0, raw);
+            }
+#pragma unroll
+            for (int k = 0; k < V; ++k) v[q][k] = dec(raw[k]);
+        }
+        load_mask<V>(a.mask + r0 + i0, body);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+#pragma unroll
+            for (int k = 0; k < V; ++k) v[q][k] = R(0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) body[k] = 0;
+    }
+
+    // the end elements of the x-shifted directions, from the neighbouring lanes
+    R left[3], right[3];
+    if constexpr (!kShiftedLoads) {
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            left[m] = __shfl_up(v[EXP[m]][V - 1], 1, 64);
+            right[m] = __shfl_down(v[EXM[m]][0], 1, 64);
+        }
+        if (act && lane == 0) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) left[m] = pull_column<S, R>(src, EXP[m], row_of[EXP[m]], i0 - 1, a);
+        }
+        if (act && lane == 63) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) right[m] = pull_column<S, R>(src, EXM[m], row_of[EXM[m]], i0 + V, a);
+        }
+    } else {
+        (void)lane;
+        if (act && i0 == 0) {  // the west side: column -1 is outside
+#pragma unroll
+            for (int m = 0; m < 3; ++m) v[EXP[m]][0] = pull_column<S, R>(src, EXP[m], row_of[EXP[m]], -1, a);
+        }
+    }
+
+    R fl_rho[V], fl_ux[V], fl_uy[V], fl_fx[V], fl_fy[V];
+    double tile_drho = 0.0;
+    S out[9][V];
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+        R f[9];
+        f[0] = v[0][k];
+        f[2] = v[2][k];
+        f[4] = v[4][k];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+            if constexpr (kShiftedLoads) {
+                f[EXP[m]] = v[EXP[m]][k];
+                f[EXM[m]] = v[EXM[m]][k];
+            } else {
+                f[EXP[m]] = (k == 0) ? left[m] : v[EXP[m]][k > 0 ? k - 1 : 0];
+                f[EXM[m]] = (k == V - 1) ? right[m] : v[EXM[m]][k < V - 1 ? k + 1 : 0];
+            }
+        }
+        const int i = i0 + k;
+        if (i == a.nx - 1) {  // the east side: the neighbour column is outside
+#pragma unroll
+            for (int m = 0; m < 3; ++m) f[EXM[m]] = pull_column<S, R>(src, EXM[m], row_of[EXM[m]], a.nx, a);
+        }
+        const NodeResult<R> n = collide_node<R>(f, body[k], i, j, a);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) out[q][k] = enc<S>(f[q]);
+        fl_rho[k] = n.rho;
+        fl_ux[k] = n.ux;
+        fl_uy[k] = n.uy;
+        fl_fx[k] = n.fvx;
+        fl_fy[k] = n.fvy;
+        if (k < n_own) tile_drho += (double)n.drho;
+    }
+
+    if (n_own == V) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) store_vec<S, V>(dst + q * P + r0 + i0, out[q]);
         if constexpr (FIELDS) {
-            R* fl = a.fields + r0 + i;
+            R* fb = a.fields + r0 + i0;
             const int64_t F = a.plane_f;
-            fl[0] = rho;
-            fl[F] = ux;
-            fl[2 * F] = uy;
-            fl[3 * F] = fvx;
-            fl[4 * F] = fvy;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                fb[k] = fl_rho[k];
+                fb[F + k] = fl_ux[k];
+                fb[2 * F + k] = fl_uy[k];
+                fb[3 * F + k] = fl_fx[k];
+                fb[4 * F + k] = fl_fy[k];
+            }
+        }
+    } else if (n_own > 0) {  // ragged end of a row
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (k < n_own) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) dst[q * P + r0 + i0 + k] = out[q][k];
+                if constexpr (FIELDS) {
+                    R* fb = a.fields + r0 + i0;
+                    const int64_t F = a.plane_f;
+                    fb[k] = fl_rho[k];
+                    fb[F + k] = fl_ux[k];
+                    fb[2 * F + k] = fl_uy[k];
+                    fb[3 * F + k] = fl_fx[k];
+                    fb[4 * F + k] = fl_fy[k];
+                }
+            }
         }
     }
 
     if constexpr (RECORD) {
-        __shared__ double lds[4];
-        const double m = block_sum_256((double)drho, lds);
-        if (threadIdx.x == 0) a.tile_mass[t] = m;
+        double* tile_mass = a.tile_mass + a.part_buf * a.fin.tile_stride;
+        double* slot_force = a.slot_force + a.part_buf * a.fin.slot_stride;
+        const double m = block_sum(tile_drho, lds);
+        if (threadIdx.x == 0) tile_mass[t] = m;
         const int s0 = a.tile_slot_ptr[t], s1 = a.tile_slot_ptr[t + 1];
         for (int s = s0; s < s1; ++s) {   // uniform across the block
             const int b = a.slot_body[s];
-            const bool mine = on && body == b;
-            const double sx = block_sum_256(mine ? -(double)fvx : 0.0, lds);
-            const double sy = block_sum_256(mine ? -(double)fvy : 0.0, lds);
+            double px = 0.0, py = 0.0;
+#pragma unroll
+            for (int k = 0; k < V; ++k) {
+                if (k < n_own && body[k] == b) {
+                    px -= (double)fl_fx[k];
+                    py -= (double)fl_fy[k];
+                }
+            }
+            const double sx = block_sum(px, lds);
+            const double sy = block_sum(py, lds);
             if (threadIdx.x == 0) {
-                a.slot_force[2 * s] = sx;
-                a.slot_force[2 * s + 1] = sy;
+                slot_force[2 * s] = sx;
+                slot_force[2 * s + 1] = sy;
             }
         }
     }
 }
 
-// Sum the per-tile partials of one record into the ring, in a fixed order.
-__global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinalizeArgs a)
+// The last record of an lbvp_step call, summed on its own.
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinalizeArgs a, int32_t buf)
 {
-    __shared__ double sx[FIN_THREADS], sy[FIN_THREADS];
-    const int tid = threadIdx.x;
-    const int64_t r = *a.rec_count % a.capacity;
-    for (int b = 0; b <= a.n_bodies; ++b) {
-        double x = 0.0, y = 0.0;
-        if (b < a.n_bodies) {
-            for (int k = a.body_slot_ptr[b] + tid; k < a.body_slot_ptr[b + 1]; k += FIN_THREADS) {
-                const int s = a.body_slots[k];
-                x += a.slot_force[2 * s];
-                y += a.slot_force[2 * s + 1];
-            }
-        } else {
-            for (int k = tid; k < a.n_tiles; k += FIN_THREADS) x += a.tile_mass[k];
-        }
-        sx[tid] = x;
-        sy[tid] = y;
-        __syncthreads();
-        for (int w = FIN_THREADS / 2; w > 0; w >>= 1) {
-            if (tid < w) {
-                sx[tid] += sx[tid + w];
-                sy[tid] += sy[tid + w];
-            }
-            __syncthreads();
-        }
-        if (tid == 0) {
-            if (b < a.n_bodies) {
-                a.ring_force[(r * a.max_bodies + b) * 2] = sx[0];
-                a.ring_force[(r * a.max_bodies + b) * 2 + 1] = sy[0];
-            } else {
-                a.ring_mass[r] = a.mass_offset + sx[0];
-            }
-        }
-        __syncthreads();
-    }
-    if (tid == 0) *a.rec_count += 1;
+    __shared__ double lds[FIN_THREADS / 64];
+    finalize_record(a, buf, lds);
 }
 
 // ------------------------------------------------------------ conversions --
@@ -236,7 +521,7 @@ __constant__ int EX_ALL[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __constant__ int EY_ALL[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 
 // Algorithm step (1): populations at equilibrium (eq. feq) for staged rows, in
-// FP64, stored as deviations; the fields of step 0 are (rho, u, 0, 0).
+// FP64, stored as normalized deviations; the fields of step 0 are (rho, u, 0, 0).
 template <typename S>
 __global__ void __launch_bounds__(256) k_init(S* lat, typename Arith<S>::R* fields, ConvArgs a)
 {
@@ -251,8 +536,8 @@ __global__ void __launch_bounds__(256) k_init(S* lat, typename Arith<S>::R* fiel
     const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
     for (int q = 0; q < 9; ++q) {
         const double eu = EX_ALL[q] * ux + EY_ALL[q] * uy;
-        const double dev = W_ALL[q] * ((rho - a.rho0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
-        lat[q * a.plane + o] = enc<S>((R)dev);
+        const double h = (rho - a.rho0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        lat[q * a.plane + o] = enc<S>((R)h);
     }
     if (fields) {
         fields[o] = (R)rho;
@@ -271,7 +556,7 @@ __global__ void __launch_bounds__(256) k_decode(const S* lat, ConvArgs a)
     if (k >= n) return;
     const int jl = (int)(k / a.nx), i = (int)(k - (int64_t)jl * a.nx);
     const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
-    for (int q = 0; q < 9; ++q) a.pops[q * n + k] = (double)dec(lat[q * a.plane + o]) + W_ALL[q] * a.rho0;
+    for (int q = 0; q < 9; ++q) a.pops[q * n + k] = W_ALL[q] * ((double)dec(lat[q * a.plane + o]) + a.rho0);
 }
 
 template <typename S>
@@ -283,33 +568,51 @@ __global__ void __launch_bounds__(256) k_encode(S* lat, ConvArgs a)
     if (k >= n) return;
     const int jl = (int)(k / a.nx), i = (int)(k - (int64_t)jl * a.nx);
     const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
-    for (int q = 0; q < 9; ++q) lat[q * a.plane + o] = enc<S>((R)(a.pops[q * n + k] - W_ALL[q] * a.rho0));
+    for (int q = 0; q < 9; ++q) lat[q * a.plane + o] = enc<S>((R)(a.pops[q * n + k] / W_ALL[q] - a.rho0));
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 
+template <typename S, int V>
+hipError_t step_v(bool record, bool fields, const S* in, S* out, const StepArgs<typename Arith<S>::R>& a,
+                  hipStream_t s)
+{
+    const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD)), block((unsigned)a.block);
+    if (record) {
+        if (fields) hipLaunchKernelGGL((k_step<S, V, true, true>), grid, block, 0, s, in, out, a);
+        else hipLaunchKernelGGL((k_step<S, V, true, false>), grid, block, 0, s, in, out, a);
+    } else {
+        if (fields) hipLaunchKernelGGL((k_step<S, V, false, true>), grid, block, 0, s, in, out, a);
+        else hipLaunchKernelGGL((k_step<S, V, false, false>), grid, block, 0, s, in, out, a);
+    }
+    return hipGetLastError();
+}
+
 template <typename S>
-hipError_t step_typed(bool record, bool fields, const void* src, void* dst, const void* args_v,
-                      hipStream_t s)
+hipError_t step_typed(bool record, bool fields, const void* src, void* dst, const void* args_v, hipStream_t s)
 {
     using R = typename Arith<S>::R;
     const StepArgs<R>& a = *static_cast<const StepArgs<R>*>(args_v);
-    const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD)), block(TILE_X);
     const S* in = static_cast<const S*>(src);
     S* out = static_cast<S*>(dst);
-    if (record) {
-        if (fields) hipLaunchKernelGGL((k_step_pull<S, true, true>), grid, block, 0, s, in, out, a);
-        else hipLaunchKernelGGL((k_step_pull<S, true, false>), grid, block, 0, s, in, out, a);
-    } else {
-        if (fields) hipLaunchKernelGGL((k_step_pull<S, false, true>), grid, block, 0, s, in, out, a);
-        else hipLaunchKernelGGL((k_step_pull<S, false, false>), grid, block, 0, s, in, out, a);
-    }
-    return hipGetLastError();
+    constexpr int VW = 16 / (int)sizeof(S);
+    if (a.vec == VW) return step_v<S, VW>(record, fields, in, out, a, s);
+    if (a.vec == 1) return step_v<S, 1>(record, fields, in, out, a, s);
+    return hipErrorInvalidValue;
 }
 
 unsigned conv_blocks(const ConvArgs& a) { return (unsigned)(((int64_t)a.rows * a.nx + 255) / 256); }
 
 }  // namespace
+
+int vector_width(int32_t storage)
+{
+    switch (storage) {
+    case ST_F64: return 2;
+    case ST_F32: return 4;
+    default: return 8;
+    }
+}
 
 hipError_t launch_step(int32_t storage, bool record, bool fields, const void* src, void* dst,
                        const void* step_args, hipStream_t s)
@@ -323,9 +626,9 @@ hipError_t launch_step(int32_t storage, bool record, bool fields, const void* sr
     }
 }
 
-hipError_t launch_finalize(const FinalizeArgs& a, hipStream_t s)
+hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FIN_THREADS), 0, s, a, buf);
     return hipGetLastError();
 }
 

@@ -31,8 +31,8 @@ KEEP_FIELDS = 0x1
 
 SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_equilibrium",
            "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations",
-           "lbvp_write_populations", "lbvp_step_count", "lbvp_synchronize", "lbvp_destroy",
-           "lbvp_last_error"]
+           "lbvp_write_populations", "lbvp_set_launch", "lbvp_get_launch", "lbvp_step_count",
+           "lbvp_synchronize", "lbvp_destroy", "lbvp_last_error"]
 
 
 class LbvpError(RuntimeError):
@@ -74,6 +74,8 @@ def _load():
     L.lbvp_read_fields.argtypes = [vp] * 6
     L.lbvp_read_populations.argtypes = [vp, vp]
     L.lbvp_write_populations.argtypes = [vp, vp]
+    L.lbvp_set_launch.argtypes = [vp, i32, i32]
+    L.lbvp_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.lbvp_step_count.restype = i64
     L.lbvp_step_count.argtypes = [vp]
     L.lbvp_synchronize.argtypes = [vp]
@@ -171,6 +173,16 @@ def lbvp_write_populations(ctx, g: np.ndarray):
     _check(ctx, _L.lbvp_write_populations(ctx, _ptr(g)))
 
 
+def lbvp_set_launch(ctx, vec: int, block: int):
+    _check(ctx, _L.lbvp_set_launch(ctx, int(vec), int(block)))
+
+
+def lbvp_get_launch(ctx) -> Tuple[int, int]:
+    v, b = C.c_int32(), C.c_int32()
+    _check(ctx, _L.lbvp_get_launch(ctx, C.byref(v), C.byref(b)))
+    return v.value, b.value
+
+
 def lbvp_step_count(ctx) -> int:
     return int(_L.lbvp_step_count(ctx))
 
@@ -263,6 +275,13 @@ class Solver:
     @property
     def step_count(self) -> int:
         return lbvp_step_count(self.ctx)
+
+    @property
+    def launch(self) -> Tuple[int, int]:
+        return lbvp_get_launch(self.ctx)
+
+    def set_launch(self, vec: int, block: int):
+        lbvp_set_launch(self.ctx, vec, block)
 
     def synchronize(self):
         lbvp_synchronize(self.ctx)

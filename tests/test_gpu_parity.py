@@ -32,9 +32,11 @@ def _force_scale(prob, fields):
     return np.array(out)
 
 
-def _run_both(lbvp, oracle, prob, steps, storage):
-    print(f"case {prob.name} {prob.nx}x{prob.ny} storage={storage} steps={steps}", flush=True)
+def _run_both(lbvp, oracle, prob, steps, storage, launch=None):
     gpu = lbvp.Solver(prob, storage=storage, force_every=1, force_capacity=max(steps, 16))
+    if launch is not None:
+        gpu.set_launch(*launch)
+    print(f"case {prob.name} {prob.nx}x{prob.ny} storage={storage} steps={steps} launch={gpu.launch}", flush=True)
     gpu.step(steps, keep_fields=True)
     gf, gm, first = gpu.forces()
     ref = oracle.RefSolver(prob)
@@ -53,12 +55,17 @@ SMALL_CASES = [
 ]
 
 
+# (nodes per thread, threads per block); 2 is the FP64 16-byte vector width
+LAUNCHES_F64 = [(1, 64), (2, 256), (2, 64), (1, 256)]
+
+
+@pytest.mark.parametrize("launch", LAUNCHES_F64, ids=[f"v{v}b{b}" for v, b in LAUNCHES_F64])
 @pytest.mark.parametrize("nx,ny,sides,seed", SMALL_CASES)
-def test_fp64_matches_oracle(lbvp, oracle, nx, ny, sides, seed):
+def test_fp64_matches_oracle(lbvp, oracle, nx, ny, sides, seed, launch):
     prob = inputs.random_state_problem(nx, ny, seed=seed, n_disks=3 if min(nx, ny) > 5 else 1,
                                        bc=sides, body_force=(1e-5, -2e-6))
     steps = 40
-    gpu, ref, (gf, gm, first), (rf, rm) = _run_both(lbvp, oracle, prob, steps, "f64")
+    gpu, ref, (gf, gm, first), (rf, rm) = _run_both(lbvp, oracle, prob, steps, "f64", launch)
     g_gpu, g_ref = gpu.populations(), ref.populations()
     assert np.abs(g_gpu - g_ref).max() <= 1e-12 * np.abs(g_ref).max()
     fg, fr = gpu.fields(), ref.fields()
@@ -71,6 +78,14 @@ def test_fp64_matches_oracle(lbvp, oracle, nx, ny, sides, seed):
         assert np.all(np.abs(gf - rf).max(axis=(0, 2)) <= 1e-11 * scale)
     assert np.abs(gm - rm).max() <= 1e-13 * rm.max()
     assert gpu.step_count == steps
+
+
+def test_fp64_taylor_green_low_mach(lbvp, oracle):
+    """Taylor-Green vortex, 128 x 128, U0 = 1e-3, 1000 steps, FP64 storage:
+    velocity rel-L2 against the oracle <= 1e-12."""
+    prob = inputs.taylor_green(128)
+    gpu, ref, _, _ = _run_both(lbvp, oracle, prob, 1000, "f64")
+    assert _rel_l2_velocity(gpu.fields(), ref.fields()) <= 1e-12
 
 
 def test_fp64_couette_2000_steps(lbvp, oracle):
@@ -87,13 +102,16 @@ LAMINAR_FP32 = [
     ("couette64", lambda: inputs.couette()),
     ("cylinder1024x512_noise_free", lambda: inputs.cylinder(noise=False)),
     ("taylor_green128", lambda: inputs.taylor_green(128)),
+    ("taylor_green128_u0.02", lambda: inputs.taylor_green(128, u0=0.02)),
 ]
 
 
 @pytest.mark.parametrize("name,make", LAMINAR_FP32, ids=[c[0] for c in LAMINAR_FP32])
 def test_fp32_laminar_1000_steps(lbvp, oracle, name, make):
     """FP32 storage and arithmetic, 1000 steps: velocity rel-L2 <= 1e-5 against
-    the FP64 oracle; drag on each body within 1e-4 of its size."""
+    the FP64 oracle. Each body's force agrees to 1e-4 of its value plus 1e-5 of
+    the summed magnitude of its nodes' F_VP (the same 1e-5 relative bar as the
+    velocity, on a sum that can cancel to ~0, as for the Couette cylinders)."""
     prob = make()
     gpu, ref, (gf, gm, _), (rf, rm) = _run_both(lbvp, oracle, prob, 1000, "f32")
     err = _rel_l2_velocity(gpu.fields(), ref.fields())
@@ -102,7 +120,7 @@ def test_fp32_laminar_1000_steps(lbvp, oracle, name, make):
     if prob.n_bodies:
         scale = np.maximum(np.abs(rf[-1]).max(axis=1), 1e-12)
         print(f"{name}: last-step force rel err {np.abs(gf[-1] - rf[-1]).max(axis=1) / scale}", flush=True)
-        assert np.all(np.abs(gf[-1] - rf[-1]).max(axis=1) <= 1e-4 * scale + 1e-7 * _force_scale(prob, ref.fields()))
+        assert np.all(np.abs(gf[-1] - rf[-1]).max(axis=1) <= 1e-4 * scale + 1e-5 * _force_scale(prob, ref.fields()))
     assert np.abs(gm - rm).max() <= 1e-6 * rm.max()
 
 
@@ -190,3 +208,48 @@ def test_edge_cases(lbvp):
     g = g0 + 1e-3 * rng.uniform(-1, 1, g0.shape)
     s.set_populations(g)
     assert np.abs(s.populations() - g).max() <= 1e-7
+
+
+@pytest.mark.parametrize("storage,vec", [("f32", 4), ("f16", 8), ("bf16", 8)])
+def test_launch_shapes_bitwise_equal(lbvp, storage, vec):
+    """The per-node arithmetic does not depend on the launch shape: one node per
+    thread and the 16-byte vector form give bitwise identical populations."""
+    prob = inputs.random_state_problem(300, 41, seed=31, n_disks=4)
+    outs = []
+    for launch in ((1, 64), (vec, 256), (vec, 64)):
+        s = lbvp.Solver(prob, storage=storage, force_every=0)
+        s.set_launch(*launch)
+        s.step(30)
+        outs.append(s.populations())
+        s.close()
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("launch", [(1, 64), (4, 256)], ids=["v1b64", "v4b256"])
+@pytest.mark.parametrize("nx,ny,sides,seed", SMALL_CASES[:3] + SMALL_CASES[4:])
+def test_fp32_small_cases(lbvp, oracle, nx, ny, sides, seed, launch):
+    """FP32 on the ragged small cases, both launch shapes: velocity rel-L2 after 40
+    steps within 1e-6 of the oracle."""
+    prob = inputs.random_state_problem(nx, ny, seed=seed, n_disks=3 if min(nx, ny) > 5 else 1,
+                                       bc=sides, body_force=(1e-5, -2e-6))
+    gpu, ref, _, _ = _run_both(lbvp, oracle, prob, 40, "f32", launch)
+    assert _rel_l2_velocity(gpu.fields(), ref.fields()) <= 1e-6
+
+
+REDUCED = [("f16", 2e-3), ("bf16", 2e-2)]
+
+
+@pytest.mark.parametrize("storage,bar", REDUCED, ids=[r[0] for r in REDUCED])
+@pytest.mark.parametrize("name,make", LAMINAR_FP32[:2], ids=[c[0] for c in LAMINAR_FP32[:2]])
+def test_reduced_storage_error(lbvp, oracle, storage, bar, name, make):
+    """FP16 / BF16 storage of the normalized deviations with FP32 arithmetic:
+    the velocity error against the FP64 oracle after 1000 steps is reported and
+    must stay below a bar set by the format's precision (11 and 8 significand
+    bits)."""
+    prob = make()
+    gpu, ref, (gf, _, _), (rf, _) = _run_both(lbvp, oracle, prob, 1000, storage)
+    err = _rel_l2_velocity(gpu.fields(), ref.fields())
+    fscale = np.maximum(np.abs(rf[-1]).max(axis=1), 1e-12)
+    ferr = (np.abs(gf[-1] - rf[-1]).max(axis=1) / fscale).max() if prob.n_bodies else 0.0
+    print(f"PRECISION {storage} {name}: velocity rel-L2 {err:.3e}, force rel err {ferr:.3e}", flush=True)
+    assert err <= bar
