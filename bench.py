@@ -100,6 +100,100 @@ def cpu_baseline(prob, budget_s: float = 15.0):
             "sample": f"{steps} FP64 steps of the full {prob.nx}x{prob.ny} domain ({total:.1f} s)"}
 
 
+def calibrate_copy(nbytes: int, reps: int = 5):
+    """A plain device copy of known size (torch's copy kernel): what the HBM
+    traffic counters read for it calibrates them, and its rate is the copy
+    bandwidth this device reaches."""
+    import torch
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"calibration": "device copy", "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": reps + 1, "ms_per_copy": round(ms, 4),
+                      "GBps": round(2 * nbytes / ms / 1e6, 1)}), flush=True)
+
+
+def _db_rows(db: str, table: str):
+    import sqlite3
+
+    con = sqlite3.connect(db)
+    cols = [d[1] for d in con.execute(f"pragma table_info({table})")]
+    return [dict(zip(cols, r)) for r in con.execute(f"select * from {table}")]
+
+
+def summarize_trace(db: str, out: str, command: str):
+    """Write the per-kernel statistics of a rocprofv3 --kernel-trace --stats run."""
+    rows = _db_rows(db, "top_kernels")
+    lines = ["# rocprofv3 kernel-trace summary", "", "Command:", "", "```", command, "```", "",
+             "| kernel | calls | average (us) | total (us) | share |", "|---|---|---|---|---|"]
+    for r in rows[:12]:
+        lines.append(f"| `{r['name'][:100]}` | {r['total_calls']} | {r['average']:.2f} | "
+                     f"{r['total_duration']:.1f} | {r['percentage']:.1f}% |")
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def _counter_mean(db: str, counter: str, name_part: str) -> float:
+    vals = [r["value"] for r in _db_rows(db, "counters_collection")
+            if r["counter_name"] == counter and name_part in (r["kernel_name"] or "")]
+    if not vals:
+        raise SystemExit(f"no {counter} values for kernels matching {name_part!r} in {db}")
+    return sum(vals) / len(vals)
+
+
+def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_write: str, copy_bytes: int,
+                       storage: str, kernel_part: str, out_json: str, out_md: str, command: str):
+    """HBM bytes per step-kernel launch from FETCH_SIZE / WRITE_SIZE (KiB per
+    dispatch), each scaled by what the counter reads for a plain device copy of
+    copy_bytes read and copy_bytes written."""
+    from paper_1901_08766_amd import inputs
+
+    nodes = inputs.large_domain().nx * inputs.large_domain().ny
+    copy_kib = copy_bytes / 1024.0
+    f_cal = copy_kib / _counter_mean(copy_fetch, "FETCH_SIZE", "copyBuffer")
+    w_cal = copy_kib / _counter_mean(copy_write, "WRITE_SIZE", "copyBuffer")
+    fk = _counter_mean(step_fetch, "FETCH_SIZE", kernel_part)
+    wk = _counter_mean(step_write, "WRITE_SIZE", kernel_part)
+    fetch_b = fk * f_cal * 1024.0
+    write_b = wk * w_cal * 1024.0
+    alg_read = (BYTES_PER_NODE[storage] - 1) // 2 * nodes + nodes   # 9 loads + 1 mask byte
+    alg_write = (BYTES_PER_NODE[storage] - 1) // 2 * nodes
+    entry = {"nodes": nodes, "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
+             "fetch_calibration": round(f_cal, 5), "write_calibration": round(w_cal, 5),
+             "hbm_fetch_bytes": int(fetch_b), "hbm_write_bytes": int(write_b),
+             "hbm_bytes_per_launch": int(fetch_b + write_b),
+             "algorithmic_read_bytes": alg_read, "algorithmic_write_bytes": alg_write,
+             "fetch_over_algorithmic": round(fetch_b / alg_read, 4),
+             "write_over_algorithmic": round(write_b / alg_write, 4)}
+    data = {"kernel_source_hash": kernel_source_hash(), "kernel": kernel_part, "per_storage": {storage: entry},
+            "command": command}
+    with open(out_json, "w") as f:
+        json.dump(data, f, indent=1)
+    md = ["# HBM traffic of the step kernel (rocprofv3 PMC)", "", "Command:", "", "```", command, "```", "",
+          f"Kernel `{kernel_part}`, {nodes} nodes, storage {storage}, kernel source hash "
+          f"`{data['kernel_source_hash']}`.", "",
+          "| quantity | value |", "|---|---|"]
+    for k, v in entry.items():
+        md.append(f"| {k} | {v} |")
+    md += ["", f"Calibration: a device copy of {copy_bytes} bytes read and written reads "
+               f"FETCH_SIZE x {f_cal:.4f} and WRITE_SIZE x {w_cal:.4f} of its true bytes; the step "
+               f"kernel's counters are scaled by these factors."]
+    with open(out_md, "w") as f:
+        f.write("\n".join(md) + "\n")
+    print("\n".join(md))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,7 +204,25 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variants", default="f16,bf16",
                     help="other storage types to time as extra fields ('' for none)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES (counter calibration)")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT_MD", "COMMAND"),
+                    help="write the kernel statistics of a rocprofv3 kernel-trace database")
+    ap.add_argument("--summarize-counters", nargs=8,
+                    metavar=("STEP_FETCH_DB", "STEP_WRITE_DB", "COPY_FETCH_DB", "COPY_WRITE_DB", "COPY_BYTES",
+                             "KERNEL", "OUT_MD", "COMMAND"),
+                    help="write the calibrated HBM traffic of the step kernel from four rocprofv3 PMC runs")
     a = ap.parse_args()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
+    if a.summarize_trace:
+        summarize_trace(*a.summarize_trace)
+        return
+    if a.summarize_counters:
+        sf, sw, cf, cw, cb, kern, md, cmd = a.summarize_counters
+        summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, COUNTERS_FILE, md, cmd)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the single-domain step has "
                                    "no multi-GPU path in this build (--gpus must be 1)"}))

@@ -40,11 +40,11 @@ size_t arith_bytes(int32_t st) { return st == LBVP_F64 ? 8 : 4; }
 // configuration uses (one node per thread, 64-thread blocks).
 struct Layout {
     int64_t pitch = 0, plane = 0, plane_f = 0;
-    int32_t max_tiles = 0;
+    int32_t max_tiles = 0, max_waves = 0;
     int64_t slot_cap = 0, capacity = 0;
     int32_t max_bodies = 0;
     int64_t stage_rows = 0;
-    size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, tile_mass = 0, slot_force = 0,
+    size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, mass_part = 0, slot_force = 0,
            tile_slot_ptr = 0, slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0,
            ring_mass = 0, rec_count = 0, stage = 0, total = 0;
 };
@@ -115,6 +115,11 @@ Layout make_layout(const lbvp_params* p)
     L.plane_f = (int64_t)p->ny * L.pitch;
     const Launch finest = make_launch(p->nx, p->ny, 1, MIN_BLOCK);
     L.max_tiles = finest.n_tiles;
+    for (int vec : {1, vector_width(p->storage)})
+        for (int block : {64, 128, 256}) {
+            const Launch l = make_launch(p->nx, p->ny, vec, block);
+            L.max_waves = std::max(L.max_waves, l.n_tiles * (block / 64));
+        }
     L.slot_cap = 2 * (int64_t)L.max_tiles + 1024;
     L.capacity = p->force_capacity > 0 ? p->force_capacity : DEFAULT_CAPACITY;
     L.max_bodies = p->max_bodies > 0 ? p->max_bodies : DEFAULT_MAX_BODIES;
@@ -129,7 +134,7 @@ Layout make_layout(const lbvp_params* p)
     L.mask = take((size_t)p->ny * L.pitch);
     L.bodies = take((size_t)(L.max_bodies + 1) * 5 * rs);
     L.fields = take(5 * (size_t)L.plane_f * rs);
-    L.tile_mass = take(2 * (size_t)L.max_tiles * sizeof(double));          // double-buffered
+    L.mass_part = take(2 * (size_t)L.max_waves * sizeof(double));          // double-buffered
     L.slot_force = take(2 * (size_t)L.slot_cap * 2 * sizeof(double));
     L.tile_slot_ptr = take((size_t)(L.max_tiles + 1) * sizeof(int32_t));
     L.slot_body = take((size_t)L.slot_cap * sizeof(int32_t));
@@ -237,7 +242,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.tile_slot_ptr = c->at<int32_t>(L.tile_slot_ptr);
     a.slot_body = c->at<int32_t>(L.slot_body);
     a.slot_force = c->at<double>(L.slot_force);
-    a.tile_mass = c->at<double>(L.tile_mass);
+    a.mass_part = c->at<double>(L.mass_part);
     a.fields = c->at<R>(L.fields);
     a.part_buf = 0;
     a.fin_buf = -1;
@@ -312,7 +317,7 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
 lbvp_status apply_launch(lbvp_ctx* c, const Launch& l)
 {
     c->launch = l;
-    c->fin.n_tiles = l.n_tiles;
+    c->fin.n_mass = l.n_tiles * (l.block / 64);
     fill_step_args(c, c->a64);
     fill_step_args(c, c->a32);
     return build_tile_tables(c);
@@ -391,15 +396,15 @@ lbvp_status lbvp_create(const lbvp_params* p, void* hip_stream, void* dev_mem, s
     }
     c->launch = default_launch(p->nx, p->ny, p->storage);
     c->fin.max_bodies = c->L.max_bodies;
-    c->fin.n_tiles = c->launch.n_tiles;
+    c->fin.n_mass = c->launch.n_tiles * (c->launch.block / 64);
     c->fin.capacity = c->L.capacity;
     c->fin.mass_offset = p->rho0 * (double)p->nx * (double)p->ny;
     c->fin.body_slot_ptr = c->at<int32_t>(c->L.body_slot_ptr);
     c->fin.body_slots = c->at<int32_t>(c->L.body_slots);
     c->fin.slot_force = c->at<double>(c->L.slot_force);
-    c->fin.tile_mass = c->at<double>(c->L.tile_mass);
+    c->fin.mass_part = c->at<double>(c->L.mass_part);
     c->fin.slot_stride = c->L.slot_cap * 2;
-    c->fin.tile_stride = c->L.max_tiles;
+    c->fin.mass_stride = c->L.max_waves;
     c->fin.ring_force = c->at<double>(c->L.ring_force);
     c->fin.ring_mass = c->at<double>(c->L.ring_mass);
     c->fin.rec_count = c->at<int64_t>(c->L.rec_count);

@@ -22,19 +22,19 @@ enum Side : int32_t { SIDE_PERIODIC = 0, SIDE_INFLOW_EQ = 1, SIDE_OUTFLOW = 2 };
 // Storage codes (match lbvp_storage).
 enum Storage : int32_t { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
 
-// Sums one force record: the tile mass partials and the (tile, body) force
-// partials of partial buffer `buf`, in a fixed order, into ring slot
+// Sums one force record: the per-wavefront mass partials and the (tile, body)
+// force partials of partial buffer `buf`, in a fixed order, into ring slot
 // rec_count % capacity. The partials are double-buffered so that the record of
 // step k can be summed while step k + 1 writes its own.
 struct FinalizeArgs {
-    int32_t n_bodies, max_bodies, n_tiles;
+    int32_t n_bodies, max_bodies, n_mass;   // n_mass: wavefronts of a launch
     int64_t capacity;
     double mass_offset;             // rho0 * nx * ny
     const int32_t* body_slot_ptr;   // [n_bodies + 1]
     const int32_t* body_slots;      // slots of each body in tile order
     const double* slot_force;       // [2][slot_stride / 2][2]
-    const double* tile_mass;        // [2][tile_stride]
-    int64_t slot_stride, tile_stride;
+    const double* mass_part;        // [2][mass_stride]
+    int64_t slot_stride, mass_stride;
     double* ring_force;             // [capacity][max_bodies][2]
     double* ring_mass;              // [capacity]
     int64_t* rec_count;             // records written so far
@@ -63,7 +63,7 @@ struct StepArgs {
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
     double* slot_force;             // [2][n_slots][2]
-    double* tile_mass;              // [2][n_tiles]
+    double* mass_part;              // [2][n_tiles * block / 64]
     R* fields;                      // [5][plane_f]
     FinalizeArgs fin;
 };

@@ -306,9 +306,9 @@ __device__ __forceinline__ double strided_sum(const double* x, int n, int stride
 
 __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, double* lds)
 {
-    const double* tm = f.tile_mass + buf * f.tile_stride;
+    const double* pm = f.mass_part + buf * f.mass_stride;
     const double* sf = f.slot_force + buf * f.slot_stride;
-    const double m = block_sum(strided_sum(tm, f.n_tiles, 1), lds);
+    const double m = block_sum(strided_sum(pm, f.n_mass, 1), lds);
     const int64_t r = *f.rec_count % f.capacity;
     for (int b = 0; b < f.n_bodies; ++b) {
         const int s0 = f.body_slot_ptr[b], s1 = f.body_slot_ptr[b + 1];
@@ -343,6 +343,11 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     if (blk == 0 && a.fin_buf >= 0) finalize_record(a.fin, a.fin_buf, lds);
     const int t = (blk % N_XCD) * a.tiles_per_xcd + blk / N_XCD;
     if (t >= a.n_tiles) return;  // whole block
+    int s0 = 0, s1 = 0;          // this tile's (tile, body) force slots
+    if constexpr (RECORD) {
+        s0 = a.tile_slot_ptr[t];
+        s1 = a.tile_slot_ptr[t + 1];
+    }
     const int j = t / a.tiles_x;
     const int i0 = (t - j * a.tiles_x) * a.tile_w + (int)threadIdx.x * V;
     const int lane = (int)(threadIdx.x & 63);
@@ -482,12 +487,15 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     }
 
     if constexpr (RECORD) {
-        double* tile_mass = a.tile_mass + a.part_buf * a.fin.tile_stride;
+        // mass: one partial per wavefront (lane shuffles only, no block barrier)
+        double* mass_part = a.mass_part + a.part_buf * a.fin.mass_stride;
         double* slot_force = a.slot_force + a.part_buf * a.fin.slot_stride;
-        const double m = block_sum(tile_drho, lds);
-        if (threadIdx.x == 0) tile_mass[t] = m;
-        const int s0 = a.tile_slot_ptr[t], s1 = a.tile_slot_ptr[t + 1];
-        for (int s = s0; s < s1; ++s) {   // uniform across the block
+        double wm = tile_drho;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) wm += __shfl_down(wm, off, 64);
+        if (lane == 0) mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
+        // forces: only tiles that hold solid nodes (uniform across the block)
+        for (int s = s0; s < s1; ++s) {
             const int b = a.slot_body[s];
             double px = 0.0, py = 0.0;
 #pragma unroll

@@ -1,0 +1,92 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point that
+include/lbvp.h declares, its struct layouts agree with the Python binding, and
+host-side validation rejects bad parameters before any GPU work. No compute call
+is made here (there may be no GPU)."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbvp.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbvp_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_named_calls():
+    names = declared_functions()
+    for must in ("lbvp_create", "lbvp_set_mask", "lbvp_step", "lbvp_forces", "lbvp_read_fields"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lbvp):
+    out = subprocess.run(["nm", "-D", "--defined-only", lbvp.LIB_PATH], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (lbvp_\w+)", out))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, missing
+    assert set(lbvp.SYMBOLS) <= exported
+    for name in declared_functions():
+        getattr(lbvp.lib(), name)
+
+
+def test_struct_layouts_match_header(lbvp):
+    """Compile a C probe of the header with gcc and compare sizeof/offsetof with
+    the ctypes mirrors used by the binding."""
+    fields = [f[0] for f in lbvp.lbvp_params._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbvp.h"', "int main(void) {",
+           'printf("%zu\\n", sizeof(lbvp_params));', 'printf("%zu\\n", sizeof(lbvp_body));']
+    src += [f'printf("%zu\\n", offsetof(lbvp_params, {f}));' for f in fields]
+    src += ["return 0; }"]
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "probe.c")
+        exe = os.path.join(d, "probe")
+        open(c, "w").write("\n".join(src))
+        subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", exe, c], check=True)
+        vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals[0] == C.sizeof(lbvp.lbvp_params)
+    assert vals[1] == C.sizeof(lbvp.lbvp_body)
+    for f, off in zip(fields, vals[2:]):
+        assert getattr(lbvp.lbvp_params, f).offset == off, f
+
+
+def _params(lbvp, **kw):
+    from paper_1901_08766_amd import inputs
+    p = lbvp.params_for(inputs.cylinder(nx=64, ny=32, d=8, cx=16, cy=16, noise=False))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+@pytest.mark.parametrize("field,value", [("nx", 2), ("ny", 0), ("tau_plus", 0.5), ("magic_lambda", 0.0),
+                                         ("eta", -1.0), ("storage", 7), ("bc_north", 1), ("bc_west", 0),
+                                         ("force_every", -1), ("max_bodies", 256), ("flags", 0x80),
+                                         ("rho0", float("nan"))])
+def test_create_rejects_invalid_parameters(lbvp, field, value):
+    p = _params(lbvp, **{field: value})
+    assert lbvp.lbvp_footprint_bytes(p) == 0
+    with pytest.raises(lbvp.LbvpError) as e:
+        lbvp.lbvp_create(p)
+    assert e.value.status == lbvp.E_ARG
+    assert lbvp.lbvp_last_error(None)
+
+
+def test_footprint_scales_with_storage(lbvp):
+    sizes = {st: lbvp.lbvp_footprint_bytes(_params(lbvp, storage=code)) for st, code in lbvp.STORAGE.items()}
+    assert all(v > 0 for v in sizes.values())
+    assert sizes["f64"] > sizes["f32"] > sizes["f16"] == sizes["bf16"]
+
+
+def test_create_rejects_small_borrowed_memory(lbvp):
+    p = _params(lbvp)
+    need = lbvp.lbvp_footprint_bytes(p)
+    with pytest.raises(lbvp.LbvpError) as e:
+        lbvp.lbvp_create(p, None, 256, need - 1)   # never dereferenced: the size check fails first
+    assert e.value.status == lbvp.E_NOMEM
