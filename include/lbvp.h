@@ -69,8 +69,14 @@ typedef enum lbvp_storage {
     LBVP_BF16_DEV = 3
 } lbvp_storage;
 
-/* lbvp_params.flags */
-#define LBVP_LAYOUT_AA 0x1u        /* one in-place lattice streamed with the AA pattern */
+/* lbvp_params.flags
+ * LBVP_LAYOUT_AA: one lattice updated in place with the AA pattern (alternate
+ * steps pull from and push to the neighbours' opposite slots, or read and write
+ * a node's own slots), half the lattice memory of the default two-lattice pull
+ * at the same traffic and the same per-node arithmetic (results are bitwise
+ * equal). lbvp_read_populations / lbvp_write_populations need an even step
+ * count; F16_DEV and BF16_DEV run with one node per thread. */
+#define LBVP_LAYOUT_AA 0x1u
 
 /* lbvp_step flags */
 #define LBVP_KEEP_FIELDS 0x1u      /* store rho, u, F_VP of the last step of the call */
@@ -167,11 +173,13 @@ lbvp_status lbvp_read_fields(lbvp_ctx* ctx, double* rho, double* ux, double* uy,
 
 /* Current post-collision populations g_a (eq. collision-modified) as host
  * [9][ny][nx] FP64 (full values, w_a rho0 added back), in the D2Q9 order of
- * eq. (D2Q9). Synchronizes the stream. */
+ * eq. (D2Q9). Synchronizes the stream. E_STATE in the AA layout after an odd
+ * step count (the lattice then holds streamed, not post-collision, values). */
 lbvp_status lbvp_read_populations(lbvp_ctx* ctx, double* g);
 
 /* Overwrite the populations with host [9][ny][nx] FP64 values g_a (rounded to
- * the storage type). Keeps the step counter. */
+ * the storage type). Keeps the step counter. E_STATE in the AA layout after an
+ * odd step count. */
 lbvp_status lbvp_write_populations(lbvp_ctx* ctx, const double* g);
 
 /* Launch configuration of the step kernel: vec nodes per thread (1, or the

@@ -26,7 +26,7 @@ constexpr size_t STAGE_MIN_BYTES = size_t(16) << 20;
 constexpr int64_t DEFAULT_CAPACITY = 16384;
 constexpr int32_t DEFAULT_MAX_BODIES = 8;
 constexpr int32_t MAX_BODIES = 255;
-constexpr uint32_t KNOWN_PARAM_FLAGS = 0u;  // the AA layout is not built yet
+constexpr uint32_t KNOWN_PARAM_FLAGS = LBVP_LAYOUT_AA;
 constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS;
 
 thread_local std::string g_create_error;
@@ -46,7 +46,7 @@ struct Layout {
     int64_t stage_rows = 0;
     size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, mass_part = 0, slot_force = 0,
            tile_slot_ptr = 0, slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0,
-           ring_mass = 0, rec_count = 0, stage = 0, total = 0;
+           ring_mass = 0, rec_count = 0, stage = 0, ghost_w = 0, ghost_e = 0, total = 0;
 };
 
 // Launch configuration of the step kernel and the tiling it implies.
@@ -67,13 +67,22 @@ Launch make_launch(int32_t nx, int32_t ny, int32_t vec, int32_t block)
     return l;
 }
 
+// Vector widths a launch may use: 1 always; the 16-byte width except for the
+// AA layout with 2-byte storage (its push step moves single elements).
+bool vec_allowed(int32_t storage, uint32_t flags, int32_t vec)
+{
+    if (vec == 1) return true;
+    if (vec != vector_width(storage)) return false;
+    return !((flags & LBVP_LAYOUT_AA) && (storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV));
+}
+
 // Default launch: the 16-byte vector form when it still gives at least 8
 // wavefronts per SIMD (1024 SIMDs: 256 CUs x 4), else one node per thread;
 // small grids use 64-thread blocks to spread over more CUs.
-Launch default_launch(int32_t nx, int32_t ny, int32_t storage)
+Launch default_launch(int32_t nx, int32_t ny, int32_t storage, uint32_t flags)
 {
     const int64_t n = (int64_t)nx * ny;
-    const int vw = vector_width(storage);
+    const int vw = vec_allowed(storage, flags, vector_width(storage)) ? vector_width(storage) : 1;
     const int vec = (n / (64 * vw) >= 8 * 1024) ? vw : 1;
     const int64_t waves = n / (64 * vec);
     const int block = waves >= 4096 ? MAX_BLOCK : MIN_BLOCK;
@@ -129,8 +138,9 @@ Layout make_layout(const lbvp_params* p)
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, ALIGN); return at; };
     const size_t lat_bytes = 9 * (size_t)L.plane * es;
+    const bool aa = (p->flags & LBVP_LAYOUT_AA) != 0;
     L.lat[0] = take(lat_bytes);
-    L.lat[1] = take(lat_bytes);
+    L.lat[1] = aa ? L.lat[0] : take(lat_bytes);   // the AA pattern streams in place
     L.mask = take((size_t)p->ny * L.pitch);
     L.bodies = take((size_t)(L.max_bodies + 1) * 5 * rs);
     L.fields = take(5 * (size_t)L.plane_f * rs);
@@ -143,6 +153,8 @@ Layout make_layout(const lbvp_params* p)
     L.ring_force = take((size_t)L.capacity * L.max_bodies * 2 * sizeof(double));
     L.ring_mass = take((size_t)L.capacity * sizeof(double));
     L.rec_count = take(sizeof(int64_t));
+    L.ghost_w = take(3 * (size_t)p->ny * es);
+    L.ghost_e = take(3 * (size_t)p->ny * es);
     L.stage = take(stage_bytes);
     L.total = o;
     return L;
@@ -172,6 +184,7 @@ struct lbvp_ctx {
     std::string err;
 
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(mem + off); }
+    bool aa() const { return (p.flags & LBVP_LAYOUT_AA) != 0; }
     int32_t storage() const { return p.storage; }
     bool is_f64() const { return p.storage == LBVP_F64; }
     size_t esize() const { return storage_bytes(p.storage); }
@@ -246,6 +259,8 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.fields = c->at<R>(L.fields);
     a.part_buf = 0;
     a.fin_buf = -1;
+    a.ghost_w = c->at<char>(L.ghost_w);
+    a.ghost_e = c->at<char>(L.ghost_e);
     a.fin = c->fin;
 }
 
@@ -333,11 +348,29 @@ ConvArgs conv_args(lbvp_ctx* c, int32_t row0, int32_t rows)
     a.plane = c->L.plane;
     a.plane_f = c->L.plane_f;
     a.rho0 = c->p.rho0;
+    a.swap = c->aa() ? 1 : 0;
     a.pops = c->at<double>(c->L.stage);
     return a;
 }
 
 lbvp_status check_ctx(const lbvp_ctx* c) { return c ? LBVP_OK : LBVP_E_ARG; }
+
+// AA layout after an even step count: refresh the outflow ghost columns.
+hipError_t refresh_aa_ghosts(lbvp_ctx* c)
+{
+    if (!c->aa()) return hipSuccess;
+    GhostArgs g{};
+    g.nx = c->p.nx;
+    g.ny = c->p.ny;
+    g.west_outflow = c->p.bc_west == LBVP_BC_OUTFLOW_ZERO_GRAD;
+    g.east_outflow = c->p.bc_east == LBVP_BC_OUTFLOW_ZERO_GRAD;
+    if (!g.west_outflow && !g.east_outflow) return hipSuccess;
+    g.pitch = c->L.pitch;
+    g.plane = c->L.plane;
+    g.ghost_w = c->at<char>(c->L.ghost_w);
+    g.ghost_e = c->at<char>(c->L.ghost_e);
+    return launch_aa_ghosts(c->p.storage, c->at<char>(c->L.lat[0]), g, c->stream);
+}
 
 }  // namespace
 
@@ -394,7 +427,7 @@ lbvp_status lbvp_create(const lbvp_params* p, void* hip_stream, void* dev_mem, s
         c->mem = static_cast<char*>(m);
         c->owns = true;
     }
-    c->launch = default_launch(p->nx, p->ny, p->storage);
+    c->launch = default_launch(p->nx, p->ny, p->storage, p->flags);
     c->fin.max_bodies = c->L.max_bodies;
     c->fin.n_mass = c->launch.n_tiles * (c->launch.block / 64);
     c->fin.capacity = c->L.capacity;
@@ -479,6 +512,7 @@ lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* 
         a.uy = dst[2];
         LBVP_HIP(c, launch_init(p.storage, c->at<char>(L.lat[0]), c->at<char>(L.fields), a, s));
     }
+    LBVP_HIP(c, refresh_aa_ghosts(c));
     LBVP_HIP(c, launch_set_i64(c->fin.rec_count, 0, s));
     LBVP_HIP(c, hipStreamSynchronize(s));
     c->cur = 0;
@@ -511,7 +545,8 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
         c->a64.part_buf = c->a32.part_buf = part_buf;
         c->a64.fin_buf = c->a32.fin_buf = fin_buf;
         const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
-        hipError_t e = launch_step(c->p.storage, record, keep, c->at<char>(c->L.lat[c->cur]),
+        const int32_t mode = !c->aa() ? MODE_PULL : (c->step % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
+        hipError_t e = launch_step(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
                                    c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
         c->pending = record;
@@ -520,7 +555,7 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
             c->rec_head += 1;
         }
         if (keep) c->fields_valid = true;
-        c->cur ^= 1;
+        if (!c->aa()) c->cur ^= 1;
         c->step = next;
     }
     if (c->pending) {  // the last record of the call is summed on its own
@@ -595,6 +630,8 @@ lbvp_status lbvp_read_populations(lbvp_ctx* c, double* g)
 {
     if (check_ctx(c)) return LBVP_E_ARG;
     if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    if (c->aa() && c->step % 2)
+        return c->fail(LBVP_E_STATE, "the AA layout holds the post-collision populations after an even step count");
     const lbvp_params& p = c->p;
     hipStream_t s = c->stream;
     const int32_t rows_per = (int32_t)std::min<int64_t>(p.ny, c->L.stage_rows);
@@ -616,6 +653,8 @@ lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)
 {
     if (check_ctx(c)) return LBVP_E_ARG;
     if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    if (c->aa() && c->step % 2)
+        return c->fail(LBVP_E_STATE, "the AA layout takes populations after an even step count");
     const lbvp_params& p = c->p;
     hipStream_t s = c->stream;
     const int32_t rows_per = (int32_t)std::min<int64_t>(p.ny, c->L.stage_rows);
@@ -629,6 +668,7 @@ lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)
                                        hipMemcpyHostToDevice, s));
         LBVP_HIP(c, launch_encode(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
     }
+    LBVP_HIP(c, refresh_aa_ghosts(c));
     LBVP_HIP(c, hipStreamSynchronize(s));
     return LBVP_OK;
 }
@@ -636,8 +676,9 @@ lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)
 lbvp_status lbvp_set_launch(lbvp_ctx* c, int32_t vec, int32_t block)
 {
     if (check_ctx(c)) return LBVP_E_ARG;
-    if (vec != 1 && vec != vector_width(c->p.storage))
-        return c->fail(LBVP_E_ARG, "vec must be 1 or the storage type's 16-byte vector width");
+    if (!vec_allowed(c->p.storage, c->p.flags, vec))
+        return c->fail(LBVP_E_ARG, "vec must be 1 or the storage type's 16-byte vector width "
+                                   "(1 only for 2-byte storage in the AA layout)");
     if (block != 64 && block != 128 && block != 256) return c->fail(LBVP_E_ARG, "block must be 64, 128 or 256");
     if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");
     LBVP_HIP(c, hipStreamSynchronize(c->stream));

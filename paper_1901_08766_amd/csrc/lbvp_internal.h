@@ -65,13 +65,28 @@ struct StepArgs {
     double* slot_force;             // [2][n_slots][2]
     double* mass_part;              // [2][n_tiles * block / 64]
     R* fields;                      // [5][plane_f]
+    void* ghost_w;                  // AA layout: [3][ny] zero-gradient ghost columns (storage type)
+    void* ghost_e;
     FinalizeArgs fin;
 };
+
+struct GhostArgs {
+    int32_t nx, ny;
+    int32_t west_outflow, east_outflow;
+    int64_t pitch, plane;
+    void* ghost_w;
+    void* ghost_e;
+};
+
+// Step kinds (see lbvp_kernels.hip): two-lattice pull, AA push (even step
+// count), AA local (odd step count).
+enum StepMode : int32_t { MODE_PULL = 0, MODE_AA_PUSH = 1, MODE_AA_LOCAL = 2 };
 
 struct ConvArgs {
     int32_t nx, rows, row0;
     int64_t pitch, plane, plane_f;
     double rho0;
+    int32_t swap;       // AA layout: population q lives in slot opp(q)
     const double* rho;  // staged [rows][nx] or null
     const double* ux;
     const double* uy;
@@ -82,8 +97,9 @@ struct ConvArgs {
 int vector_width(int32_t storage);
 
 // launchers (lbvp_kernels.hip); all return the launch status
-hipError_t launch_step(int32_t storage, bool record, bool fields, const void* src, void* dst,
+hipError_t launch_step(int32_t storage, int32_t mode, bool record, bool fields, const void* src, void* dst,
                        const void* step_args, hipStream_t s);
+hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s);
 hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs& a, hipStream_t s);
 hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);

@@ -109,7 +109,7 @@ __device__ __forceinline__ void store_vec(S* p, const S (&in)[V])
 template <typename S, int V>
 __device__ __forceinline__ void load_vec_shifted(const S* p, S (&out)[V])
 {
-    static_assert(sizeof(S) >= 4, "sub-dword elements take the lane-shuffle path");
+    static_assert(sizeof(S) >= 4 || V == 1, "sub-dword vectors take the lane-shuffle path");
     __builtin_memcpy(out, p, V * sizeof(S));
 }
 
@@ -262,26 +262,75 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     return {drho, rho, ux, uy, fvx, fvy};
 }
 
-// Population q pulled from column c (-1 and nx are outside the domain) of the
-// row starting at row_off: the domain sides are resolved here.
-template <typename S, typename R>
-__device__ __forceinline__ R pull_column(const S* __restrict__ src, int q, int64_t row_off, int c,
+// D2Q9 directions (eq. D2Q9) and the opposite map (Sec. 2.1: f_{-1} = f_3).
+constexpr int OPP[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+constexpr int EXQ[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+// Directions by x component, with rows ey = 0, +1, -1 for m = 0, 1, 2.
+constexpr int EXP[3] = {1, 5, 8};   // ex = +1: pulled from column i - 1
+constexpr int EXM[3] = {3, 6, 7};   // ex = -1: pulled from column i + 1
+
+// Step kinds. PULL: two lattices, g(n) -> g(n + 1), every node pulls its nine
+// populations from its neighbours' slots of the source lattice. The AA pattern
+// runs on one lattice in two alternating kinds:
+//   AA_PUSH  (n even) reads g_q(x - e_q) from slot opp(q) of the neighbour and
+//            writes g_q(x) into slot q of the neighbour x + e_q, so that the
+//            lattice then holds the streamed populations in place;
+//   AA_LOCAL (n odd) reads its own slots q and writes its own slots opp(q).
+// Each slot is read and written by one node only, so one buffer suffices. The
+// domain sides: in AA_PUSH populations leaving through a non-periodic side are
+// dropped and the ones entering are written into the boundary node's slots
+// (inflow: the equilibrium; zero-gradient outflow: the boundary column's own
+// outgoing value); the outflow values that AA_PUSH pulls come from a ghost
+// column that AA_LOCAL writes, because the lattice slot holding them is
+// overwritten by a neighbour in the same kernel.
+enum Mode { PULL = 0, AA_PUSH = 1, AA_LOCAL = 2 };
+
+// Population q pulled from column c (-1 and nx are outside the domain) of plane
+// `plane_q` in the row starting at row_off (row index `row`): the domain sides
+// are resolved here. Ghost populations are values of the storage type, like
+// every other population (the AA push step stores the inflow ones in the
+// lattice), so the inflow equilibrium is rounded to it.
+template <int MODE, typename S, typename R>
+__device__ __forceinline__ R pull_column(const S* src, int q, int plane_q, int64_t row_off, int row, int c,
                                          const StepArgs<R>& a)
 {
     if (c < 0) {
-        if (a.west == SIDE_INFLOW_EQ) return a.feq_in[q];
+        if (a.west == SIDE_INFLOW_EQ) return dec(enc<S>(a.feq_in[q]));
+        if (MODE == AA_PUSH && a.west == SIDE_OUTFLOW)
+            return dec(static_cast<const S*>(a.ghost_w)[(q == 1 ? 0 : q == 5 ? 1 : 2) * (int64_t)a.ny + row]);
         c = (a.west == SIDE_PERIODIC) ? a.nx - 1 : 0;
     } else if (c >= a.nx) {
-        if (a.east == SIDE_INFLOW_EQ) return a.feq_in[q];
+        if (a.east == SIDE_INFLOW_EQ) return dec(enc<S>(a.feq_in[q]));
+        if (MODE == AA_PUSH && a.east == SIDE_OUTFLOW)
+            return dec(static_cast<const S*>(a.ghost_e)[(q == 3 ? 0 : q == 6 ? 1 : 2) * (int64_t)a.ny + row]);
         c = (a.east == SIDE_PERIODIC) ? 0 : a.nx - 1;
     }
-    return dec(src[(int64_t)q * a.plane + row_off + c]);
+    return dec(src[(int64_t)plane_q * a.plane + row_off + c]);
 }
 
-// D2Q9 directions by x component (eq. D2Q9), pulled from column i - ex, with
-// source rows j, j - 1, j + 1 for m = 0, 1, 2.
-constexpr int EXP[3] = {1, 5, 8};   // ex = +1: from column i - 1
-constexpr int EXM[3] = {3, 6, 7};   // ex = -1: from column i + 1
+// V elements one element off a 16-byte boundary, stored as one vector access
+// that needs only dword alignment.
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <typename S, int V>
+__device__ __forceinline__ void store_vec_shifted(S* p, const S (&in)[V])
+{
+    static_assert(sizeof(S) >= 4 || V == 1, "sub-dword vectors are stored one by one");
+    constexpr int B = V * (int)sizeof(S);
+    if constexpr (B == 16) {
+        u32x4_a4 r;
+        __builtin_memcpy(&r, in, 16);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x4_a4*>(p));
+    } else if constexpr (B == 8) {
+        u32x2_a4 r;
+        __builtin_memcpy(&r, in, 8);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x2_a4*>(p));
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) p[k] = in[k];
+    }
+}
 
 // ------------------------------------------------------------ the record --
 // One block sums one force record (see FinalizeArgs) in a fixed order: each
@@ -332,9 +381,8 @@ __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, 
 }
 
 // ------------------------------------------------------------ the step --
-template <typename S, int V, bool RECORD, bool FIELDS>
-__global__ void __launch_bounds__(256)
-k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
+__device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a)
 {
     using R = typename Arith<S>::R;
     __shared__ double lds[MAX_BLOCK / 64];
@@ -357,28 +405,39 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     const int jm = (j == 0) ? a.ny - 1 : j - 1;     // rows are periodic
     const int jp = (j == a.ny - 1) ? 0 : j + 1;
     const int64_t r0 = (int64_t)j * a.pitch, rm = (int64_t)jm * a.pitch, rp = (int64_t)jp * a.pitch;
-    // source row of each direction: ey = 0 -> j, ey = +1 -> j - 1, ey = -1 -> j + 1
+    // pull source row of each direction (ey = 0 -> j, +1 -> j - 1, -1 -> j + 1)
+    // and push target row (the opposite)
     const int64_t row_of[9] = {r0, r0, rm, r0, rp, rm, rm, rp, rp};
+    const int row_idx[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
+    const int64_t row_to[9] = {r0, r0, rp, r0, rm, rp, rp, rm, rm};
     const int64_t P = a.plane;
 
-    // Loads of every direction's source row. Dword-or-wider elements take the
-    // x-shifted directions as single vector loads one element off alignment
-    // (columns i0 - 1 .. or i0 + 1 ..; both stay inside the lattice allocation:
-    // plane 0 is never shifted and a row's padding is followed by the next row
-    // or plane). Narrower elements load aligned and shift through lane shuffles.
-    constexpr bool kShiftedLoads = sizeof(S) >= 4 && V > 1;
+    // Source plane of direction q: the pull and the AA local step read plane q,
+    // the AA push step the neighbour's opposite slot. Dword-or-wider elements
+    // (and single nodes) take the x-shifted directions as single accesses one
+    // element off alignment (columns i0 - 1 .. or i0 + 1 ..; both stay inside
+    // the allocation: plane 0 is never shifted and a row's padding is followed
+    // by the next row or plane). FP16/BF16 vectors load aligned and shift
+    // through lane shuffles (pull only).
+    constexpr bool kShifted = sizeof(S) >= 4 || V == 1;
+    static_assert(MODE == PULL || kShifted, "the AA pattern needs dword-or-wider elements or one node per thread");
     R v[9][V];
     int body[V];
     if (act) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             S raw[V];
-            if constexpr (kShiftedLoads) {
-                if (q == 1 || q == 5 || q == 8) load_vec_shifted<S, V>(src + q * P + row_of[q] + (i0 - 1), raw);
-                else if (q == 3 || q == 6 || q == 7) load_vec_shifted<S, V>(src + q * P + row_of[q] + (i0 + 1), raw);
-                else load_vec<S, V>(src + q * P + row_of[q] + i0, raw);
+            if constexpr (MODE == AA_LOCAL) {
+                load_vec<S, V>(src + q * P + r0 + i0, raw);
             } else {
-                load_vec<S, V>(src + q * P + row_of[q] + i0, raw);
+                const int pq = (MODE == AA_PUSH) ? OPP[q] : q;
+                if constexpr (kShifted) {
+                    if (EXQ[q] == 1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (i0 - 1), raw);
+                    else if (EXQ[q] == -1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (i0 + 1), raw);
+                    else load_vec<S, V>(src + pq * P + row_of[q] + i0, raw);
+                } else {
+                    load_vec<S, V>(src + pq * P + row_of[q] + i0, raw);
+                }
             }
 #pragma unroll
             for (int k = 0; k < V; ++k) v[q][k] = dec(raw[k]);
@@ -393,9 +452,9 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
         for (int k = 0; k < V; ++k) body[k] = 0;
     }
 
-    // the end elements of the x-shifted directions, from the neighbouring lanes
+    // the end elements of the x-shifted directions (lane-shuffle form only)
     R left[3], right[3];
-    if constexpr (!kShiftedLoads) {
+    if constexpr (!kShifted) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
             left[m] = __shfl_up(v[EXP[m]][V - 1], 1, 64);
@@ -403,17 +462,21 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
         }
         if (act && lane == 0) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) left[m] = pull_column<S, R>(src, EXP[m], row_of[EXP[m]], i0 - 1, a);
+            for (int m = 0; m < 3; ++m)
+                left[m] = pull_column<MODE, S, R>(src, EXP[m], EXP[m], row_of[EXP[m]], row_idx[EXP[m]], i0 - 1, a);
         }
         if (act && lane == 63) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m) right[m] = pull_column<S, R>(src, EXM[m], row_of[EXM[m]], i0 + V, a);
+            for (int m = 0; m < 3; ++m)
+                right[m] = pull_column<MODE, S, R>(src, EXM[m], EXM[m], row_of[EXM[m]], row_idx[EXM[m]], i0 + V, a);
         }
     } else {
-        (void)lane;
-        if (act && i0 == 0) {  // the west side: column -1 is outside
+        if (MODE != AA_LOCAL && act && i0 == 0) {  // the west side: column -1 is outside
 #pragma unroll
-            for (int m = 0; m < 3; ++m) v[EXP[m]][0] = pull_column<S, R>(src, EXP[m], row_of[EXP[m]], -1, a);
+            for (int m = 0; m < 3; ++m) {
+                const int q = EXP[m];
+                v[q][0] = pull_column<MODE, S, R>(src, q, MODE == AA_PUSH ? OPP[q] : q, row_of[q], row_idx[q], -1, a);
+            }
         }
     }
 
@@ -423,23 +486,22 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         R f[9];
-        f[0] = v[0][k];
-        f[2] = v[2][k];
-        f[4] = v[4][k];
 #pragma unroll
-        for (int m = 0; m < 3; ++m) {
-            if constexpr (kShiftedLoads) {
-                f[EXP[m]] = v[EXP[m]][k];
-                f[EXM[m]] = v[EXM[m]][k];
-            } else {
+        for (int q = 0; q < 9; ++q) f[q] = v[q][k];
+        if constexpr (!kShifted) {
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
                 f[EXP[m]] = (k == 0) ? left[m] : v[EXP[m]][k > 0 ? k - 1 : 0];
                 f[EXM[m]] = (k == V - 1) ? right[m] : v[EXM[m]][k < V - 1 ? k + 1 : 0];
             }
         }
         const int i = i0 + k;
-        if (i == a.nx - 1) {  // the east side: the neighbour column is outside
+        if (MODE != AA_LOCAL && i == a.nx - 1) {  // the east side: the neighbour column is outside
 #pragma unroll
-            for (int m = 0; m < 3; ++m) f[EXM[m]] = pull_column<S, R>(src, EXM[m], row_of[EXM[m]], a.nx, a);
+            for (int m = 0; m < 3; ++m) {
+                const int q = EXM[m];
+                f[q] = pull_column<MODE, S, R>(src, q, MODE == AA_PUSH ? OPP[q] : q, row_of[q], row_idx[q], a.nx, a);
+            }
         }
         const NodeResult<R> n = collide_node<R>(f, body[k], i, j, a);
 #pragma unroll
@@ -452,36 +514,99 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
         if (k < n_own) tile_drho += (double)n.drho;
     }
 
-    if (n_own == V) {
+    // ---- stores
+    if constexpr (MODE == PULL || MODE == AA_LOCAL) {
+        // own node: plane q (pull) or plane opp(q) (AA local)
+        if (n_own == V) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) store_vec<S, V>(dst + q * P + r0 + i0, out[q]);
-        if constexpr (FIELDS) {
-            R* fb = a.fields + r0 + i0;
-            const int64_t F = a.plane_f;
+            for (int q = 0; q < 9; ++q) store_vec<S, V>(dst + (MODE == PULL ? q : OPP[q]) * P + r0 + i0, out[q]);
+        } else if (n_own > 0) {  // ragged end of a row
+#pragma unroll
+            for (int k = 0; k < V; ++k)
+                if (k < n_own)
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) dst[(MODE == PULL ? q : OPP[q]) * P + r0 + i0 + k] = out[q][k];
+        }
+        if constexpr (MODE == AA_LOCAL) {
+            // the zero-gradient ghost columns that the next push step pulls from
+            if (a.west == SIDE_OUTFLOW && act && i0 == 0)
+#pragma unroll
+                for (int m = 0; m < 3; ++m) static_cast<S*>(a.ghost_w)[m * (int64_t)a.ny + j] = out[EXP[m]][0];
+            if (a.east == SIDE_OUTFLOW && act && i0 + n_own == a.nx)
+#pragma unroll
+                for (int k = 0; k < V; ++k)
+                    if (k == n_own - 1)
+#pragma unroll
+                        for (int m = 0; m < 3; ++m)
+                            static_cast<S*>(a.ghost_e)[m * (int64_t)a.ny + j] = out[EXM[m]][k];
+        }
+    } else {  // AA push: g_q(x) -> slot q of x + e_q
+        const bool edge = (i0 == 0) || (i0 + V >= a.nx);
+        if (act && !edge) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                if (EXQ[q] == 0) {
+                    store_vec<S, V>(dst + q * P + row_to[q] + i0, out[q]);
+                } else if constexpr (sizeof(S) >= 4) {
+                    if (EXQ[q] == 1) store_vec_shifted<S, V>(dst + q * P + row_to[q] + (i0 + 1), out[q]);
+                    else store_vec_shifted<S, V>(dst + q * P + row_to[q] + (i0 - 1), out[q]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < V; ++k) dst[q * P + row_to[q] + i0 + k + EXQ[q]] = out[q][k];
+                }
+            }
+        } else if (act) {
+            // node by node, with the domain sides resolved
 #pragma unroll
             for (int k = 0; k < V; ++k) {
+                if (k < n_own) {
+                    const int i = i0 + k;
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) {
+                        int c = i + EXQ[q];
+                        bool keep = true;
+                        if (c < 0) {
+                            keep = (a.west == SIDE_PERIODIC);   // else it leaves the domain
+                            c = a.nx - 1;
+                        } else if (c >= a.nx) {
+                            keep = (a.east == SIDE_PERIODIC);
+                            c = 0;
+                        }
+                        if (keep) dst[q * P + row_to[q] + c] = out[q][k];
+                    }
+                    // populations entering through a non-periodic side, for the next step
+                    if (i == 0 && a.west != SIDE_PERIODIC) {
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) {
+                            const int q = EXP[m];
+                            if (a.west == SIDE_INFLOW_EQ) dst[q * P + r0] = enc<S>(a.feq_in[q]);
+                            else dst[q * P + row_to[q]] = out[q][k];
+                        }
+                    }
+                    if (i == a.nx - 1 && a.east != SIDE_PERIODIC) {
+#pragma unroll
+                        for (int m = 0; m < 3; ++m) {
+                            const int q = EXM[m];
+                            if (a.east == SIDE_INFLOW_EQ) dst[q * P + r0 + i] = enc<S>(a.feq_in[q]);
+                            else dst[q * P + row_to[q] + i] = out[q][k];
+                        }
+                    }
+                }
+            }
+        }
+    }
+
+    if constexpr (FIELDS) {
+        R* fb = a.fields + r0 + i0;
+        const int64_t F = a.plane_f;
+#pragma unroll
+        for (int k = 0; k < V; ++k) {
+            if (k < n_own) {
                 fb[k] = fl_rho[k];
                 fb[F + k] = fl_ux[k];
                 fb[2 * F + k] = fl_uy[k];
                 fb[3 * F + k] = fl_fx[k];
                 fb[4 * F + k] = fl_fy[k];
-            }
-        }
-    } else if (n_own > 0) {  // ragged end of a row
-#pragma unroll
-        for (int k = 0; k < V; ++k) {
-            if (k < n_own) {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) dst[q * P + r0 + i0 + k] = out[q][k];
-                if constexpr (FIELDS) {
-                    R* fb = a.fields + r0 + i0;
-                    const int64_t F = a.plane_f;
-                    fb[k] = fl_rho[k];
-                    fb[F + k] = fl_ux[k];
-                    fb[2 * F + k] = fl_uy[k];
-                    fb[3 * F + k] = fl_fx[k];
-                    fb[4 * F + k] = fl_fy[k];
-                }
             }
         }
     }
@@ -515,6 +640,21 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     }
 }
 
+// Two lattices: source and destination never alias.
+template <typename S, int V, bool RECORD, bool FIELDS>
+__global__ void __launch_bounds__(256)
+k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
+{
+    step_body<S, V, PULL, RECORD, FIELDS>(src, dst, a);
+}
+
+// One lattice, read and written in place (no restrict).
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
+__global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith<S>::R> a)
+{
+    step_body<S, V, MODE, RECORD, FIELDS>(lat, lat, a);
+}
+
 // The last record of an lbvp_step call, summed on its own.
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinalizeArgs a, int32_t buf)
 {
@@ -527,9 +667,12 @@ __constant__ double W_ALL[9] = {4.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 
                                 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 __constant__ int EX_ALL[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
 __constant__ int EY_ALL[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int OPP_ALL[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
 
 // Algorithm step (1): populations at equilibrium (eq. feq) for staged rows, in
 // FP64, stored as normalized deviations; the fields of step 0 are (rho, u, 0, 0).
+// In the AA layout the post-collision population q of a node lives in its slot
+// opp(q) after an even number of steps (a.swap).
 template <typename S>
 __global__ void __launch_bounds__(256) k_init(S* lat, typename Arith<S>::R* fields, ConvArgs a)
 {
@@ -545,7 +688,7 @@ __global__ void __launch_bounds__(256) k_init(S* lat, typename Arith<S>::R* fiel
     for (int q = 0; q < 9; ++q) {
         const double eu = EX_ALL[q] * ux + EY_ALL[q] * uy;
         const double h = (rho - a.rho0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        lat[q * a.plane + o] = enc<S>((R)h);
+        lat[(a.swap ? OPP_ALL[q] : q) * a.plane + o] = enc<S>((R)h);
     }
     if (fields) {
         fields[o] = (R)rho;
@@ -564,7 +707,8 @@ __global__ void __launch_bounds__(256) k_decode(const S* lat, ConvArgs a)
     if (k >= n) return;
     const int jl = (int)(k / a.nx), i = (int)(k - (int64_t)jl * a.nx);
     const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
-    for (int q = 0; q < 9; ++q) a.pops[q * n + k] = W_ALL[q] * ((double)dec(lat[q * a.plane + o]) + a.rho0);
+    for (int q = 0; q < 9; ++q)
+        a.pops[q * n + k] = W_ALL[q] * ((double)dec(lat[(a.swap ? OPP_ALL[q] : q) * a.plane + o]) + a.rho0);
 }
 
 template <typename S>
@@ -576,36 +720,79 @@ __global__ void __launch_bounds__(256) k_encode(S* lat, ConvArgs a)
     if (k >= n) return;
     const int jl = (int)(k / a.nx), i = (int)(k - (int64_t)jl * a.nx);
     const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
-    for (int q = 0; q < 9; ++q) lat[q * a.plane + o] = enc<S>((R)(a.pops[q * n + k] / W_ALL[q] - a.rho0));
+    for (int q = 0; q < 9; ++q)
+        lat[(a.swap ? OPP_ALL[q] : q) * a.plane + o] = enc<S>((R)(a.pops[q * n + k] / W_ALL[q] - a.rho0));
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 
+// AA layout after an even number of steps: copy the outflow sides' outgoing
+// post-collision populations into the ghost columns the next push step reads.
+template <typename S>
+__global__ void __launch_bounds__(256) k_aa_ghosts(const S* lat, GhostArgs a)
+{
+    const int y = blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= a.ny) return;
+    const int64_t row = (int64_t)y * a.pitch;
+    const int exp_q[3] = {1, 5, 8}, exm_q[3] = {3, 6, 7};
+    for (int m = 0; m < 3; ++m) {
+        if (a.west_outflow)
+            static_cast<S*>(a.ghost_w)[m * (int64_t)a.ny + y] = lat[OPP_ALL[exp_q[m]] * a.plane + row];
+        if (a.east_outflow)
+            static_cast<S*>(a.ghost_e)[m * (int64_t)a.ny + y] = lat[OPP_ALL[exm_q[m]] * a.plane + row + a.nx - 1];
+    }
+}
+
 template <typename S, int V>
-hipError_t step_v(bool record, bool fields, const S* in, S* out, const StepArgs<typename Arith<S>::R>& a,
+hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const StepArgs<typename Arith<S>::R>& a,
                   hipStream_t s)
 {
     const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD)), block((unsigned)a.block);
-    if (record) {
-        if (fields) hipLaunchKernelGGL((k_step<S, V, true, true>), grid, block, 0, s, in, out, a);
-        else hipLaunchKernelGGL((k_step<S, V, true, false>), grid, block, 0, s, in, out, a);
-    } else {
-        if (fields) hipLaunchKernelGGL((k_step<S, V, false, true>), grid, block, 0, s, in, out, a);
-        else hipLaunchKernelGGL((k_step<S, V, false, false>), grid, block, 0, s, in, out, a);
+    if (mode == PULL) {
+        if (record) {
+            if (fields) hipLaunchKernelGGL((k_step<S, V, true, true>), grid, block, 0, s, in, out, a);
+            else hipLaunchKernelGGL((k_step<S, V, true, false>), grid, block, 0, s, in, out, a);
+        } else {
+            if (fields) hipLaunchKernelGGL((k_step<S, V, false, true>), grid, block, 0, s, in, out, a);
+            else hipLaunchKernelGGL((k_step<S, V, false, false>), grid, block, 0, s, in, out, a);
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    if constexpr (sizeof(S) >= 4 || V == 1) {
+        if (mode == AA_PUSH) {
+            if (record) {
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, true>), grid, block, 0, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, false>), grid, block, 0, s, out, a);
+            } else {
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, true>), grid, block, 0, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, false>), grid, block, 0, s, out, a);
+            }
+        } else {
+            if (record) {
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, true>), grid, block, 0, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, false>), grid, block, 0, s, out, a);
+            } else {
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, true>), grid, block, 0, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, false>), grid, block, 0, s, out, a);
+            }
+        }
+        return hipGetLastError();
+    } else {
+        return hipErrorInvalidValue;  // AA with sub-dword vectors: not built (one node per thread is)
+    }
 }
 
 template <typename S>
-hipError_t step_typed(bool record, bool fields, const void* src, void* dst, const void* args_v, hipStream_t s)
+hipError_t step_typed(int mode, bool record, bool fields, const void* src, void* dst, const void* args_v,
+                      hipStream_t s)
 {
     using R = typename Arith<S>::R;
     const StepArgs<R>& a = *static_cast<const StepArgs<R>*>(args_v);
     const S* in = static_cast<const S*>(src);
     S* out = static_cast<S*>(dst);
     constexpr int VW = 16 / (int)sizeof(S);
-    if (a.vec == VW) return step_v<S, VW>(record, fields, in, out, a, s);
-    if (a.vec == 1) return step_v<S, 1>(record, fields, in, out, a, s);
+    if (a.vec == VW) return step_v<S, VW>(mode, record, fields, in, out, a, s);
+    if (a.vec == 1) return step_v<S, 1>(mode, record, fields, in, out, a, s);
     return hipErrorInvalidValue;
 }
 
@@ -622,16 +809,29 @@ int vector_width(int32_t storage)
     }
 }
 
-hipError_t launch_step(int32_t storage, bool record, bool fields, const void* src, void* dst,
+hipError_t launch_step(int32_t storage, int32_t mode, bool record, bool fields, const void* src, void* dst,
                        const void* step_args, hipStream_t s)
 {
     switch (storage) {
-    case ST_F64: return step_typed<double>(record, fields, src, dst, step_args, s);
-    case ST_F32: return step_typed<float>(record, fields, src, dst, step_args, s);
-    case ST_F16: return step_typed<_Float16>(record, fields, src, dst, step_args, s);
-    case ST_BF16: return step_typed<__bf16>(record, fields, src, dst, step_args, s);
+    case ST_F64: return step_typed<double>(mode, record, fields, src, dst, step_args, s);
+    case ST_F32: return step_typed<float>(mode, record, fields, src, dst, step_args, s);
+    case ST_F16: return step_typed<_Float16>(mode, record, fields, src, dst, step_args, s);
+    case ST_BF16: return step_typed<__bf16>(mode, record, fields, src, dst, step_args, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a, hipStream_t s)
+{
+    const dim3 g((unsigned)((a.ny + 255) / 256)), b(256);
+    switch (storage) {
+    case ST_F64: hipLaunchKernelGGL(k_aa_ghosts<double>, g, b, 0, s, (const double*)lat, a); break;
+    case ST_F32: hipLaunchKernelGGL(k_aa_ghosts<float>, g, b, 0, s, (const float*)lat, a); break;
+    case ST_F16: hipLaunchKernelGGL(k_aa_ghosts<_Float16>, g, b, 0, s, (const _Float16*)lat, a); break;
+    case ST_BF16: hipLaunchKernelGGL(k_aa_ghosts<__bf16>, g, b, 0, s, (const __bf16*)lat, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s)
