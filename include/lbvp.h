@@ -191,6 +191,27 @@ lbvp_status lbvp_write_populations(lbvp_ctx* ctx, const double* g);
 lbvp_status lbvp_set_launch(lbvp_ctx* ctx, int32_t vec, int32_t block);
 lbvp_status lbvp_get_launch(const lbvp_ctx* ctx, int32_t* vec, int32_t* block);
 
+/* ---- Batches: many contexts advanced by one launch per step -------------------
+ * A batch holds contexts of one storage type and layout on one stream. Each step
+ * of lbvp_batch_step is a single launch over the tiles of every member (block ->
+ * (domain, tile) through a tile map), so domains of any size, parameters and mask
+ * share the device. Every member must be at the same force-record phase (and, in
+ * the AA layout, step parity); the members stay ordinary contexts and keep their
+ * own force rings, fields and populations, read with the usual calls. Results
+ * are bitwise those of stepping each member alone with the same launch shape.
+ *
+ * lbvp_batch_create: members[n] (borrowed; they must outlive the batch), vec /
+ * block as in lbvp_set_launch (0: the storage type's vector width, 256), applied
+ * to every member. E_ARG (mixed storage, layout, stream, force cadence or phase),
+ * E_STATE (a member has undrained force records), E_NOMEM, E_DEVICE.
+ * lbvp_batch_step: every member advances n_steps (flags as lbvp_step);
+ * asynchronous; E_STATE if members went out of phase or a ring would overflow. */
+typedef struct lbvp_batch lbvp_batch;
+lbvp_status lbvp_batch_create(lbvp_ctx* const* members, int32_t n, int32_t vec, int32_t block, lbvp_batch** out);
+lbvp_status lbvp_batch_step(lbvp_batch* batch, int64_t n_steps, uint32_t flags);
+lbvp_status lbvp_batch_destroy(lbvp_batch* batch);
+const char* lbvp_batch_last_error(const lbvp_batch* batch);
+
 /* Number of steps taken since the last lbvp_init_equilibrium. */
 int64_t lbvp_step_count(const lbvp_ctx* ctx);
 

@@ -51,18 +51,28 @@ struct Layout {
 
 // Launch configuration of the step kernel and the tiling it implies.
 struct Launch {
-    int32_t vec = 1, block = MAX_BLOCK, tile_w = MAX_BLOCK;
+    int32_t vec = 1, block = MAX_BLOCK, tile_w = MAX_BLOCK, tile_rows = 1;
     int32_t tiles_x = 0, n_tiles = 0, tiles_per_xcd = 0;
 };
 
+int32_t pow2_ceil(int32_t v)
+{
+    int32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// A tile is tile_rows rows of tile_w nodes, vec * block nodes in all: full rows
+// of vec * block nodes on wide grids, several shorter rows on narrow ones.
 Launch make_launch(int32_t nx, int32_t ny, int32_t vec, int32_t block)
 {
     Launch l;
     l.vec = vec;
     l.block = block;
-    l.tile_w = vec * block;
+    l.tile_w = std::min(vec * block, std::max(vec, pow2_ceil(nx)));
+    l.tile_rows = vec * block / l.tile_w;
     l.tiles_x = (nx + l.tile_w - 1) / l.tile_w;
-    l.n_tiles = l.tiles_x * ny;
+    l.n_tiles = l.tiles_x * ((ny + l.tile_rows - 1) / l.tile_rows);
     l.tiles_per_xcd = (l.n_tiles + N_XCD - 1) / N_XCD;
     return l;
 }
@@ -122,11 +132,10 @@ Layout make_layout(const lbvp_params* p)
     L.pitch = (int64_t)align_up((size_t)p->nx, 64);
     L.plane = (int64_t)align_up((size_t)(p->ny * L.pitch), 2048);
     L.plane_f = (int64_t)p->ny * L.pitch;
-    const Launch finest = make_launch(p->nx, p->ny, 1, MIN_BLOCK);
-    L.max_tiles = finest.n_tiles;
     for (int vec : {1, vector_width(p->storage)})
         for (int block : {64, 128, 256}) {
             const Launch l = make_launch(p->nx, p->ny, vec, block);
+            L.max_tiles = std::max(L.max_tiles, l.n_tiles);
             L.max_waves = std::max(L.max_waves, l.n_tiles * (block / 64));
         }
     L.slot_cap = 2 * (int64_t)L.max_tiles + 1024;
@@ -229,6 +238,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.vec = l.vec;
     a.block = l.block;
     a.tile_w = l.tile_w;
+    a.tile_rows = l.tile_rows;
     a.tiles_x = l.tiles_x;
     a.n_tiles = l.n_tiles;
     a.tiles_per_xcd = l.tiles_per_xcd;
@@ -292,10 +302,13 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
     for (int32_t t = 0; t < l.n_tiles; ++t) {
         tile_ptr[t] = (int32_t)slot_body.size();
         if (nb == 0) continue;
-        const int32_t j = t / l.tiles_x, i0 = (t % l.tiles_x) * l.tile_w, i1 = std::min(p.nx, i0 + l.tile_w);
-        const uint8_t* row = body_id + (int64_t)j * p.nx;
+        const int32_t ty = t / l.tiles_x, i0 = (t % l.tiles_x) * l.tile_w, i1 = std::min(p.nx, i0 + l.tile_w);
+        const int32_t j0 = ty * l.tile_rows, j1 = std::min(p.ny, j0 + l.tile_rows);
         std::fill(seen.begin(), seen.end(), 0);
-        for (int32_t i = i0; i < i1; ++i) seen[row[i]] = 1;
+        for (int32_t j = j0; j < j1; ++j) {
+            const uint8_t* row = body_id + (int64_t)j * p.nx;
+            for (int32_t i = i0; i < i1; ++i) seen[row[i]] = 1;
+        }
         for (int32_t b = 1; b <= nb; ++b) {
             if (!seen[b]) continue;
             if ((int64_t)slot_body.size() >= L.slot_cap) {
@@ -370,6 +383,56 @@ hipError_t refresh_aa_ghosts(lbvp_ctx* c)
     g.ghost_w = c->at<char>(c->L.ghost_w);
     g.ghost_e = c->at<char>(c->L.ghost_e);
     return launch_aa_ghosts(c->p.storage, c->at<char>(c->L.lat[0]), g, c->stream);
+}
+
+}  // namespace
+
+
+// A set of contexts advanced together, one launch per step over all their
+// tiles. The contexts stay ordinary contexts: their forces, fields and
+// populations are read through the usual calls.
+struct lbvp_batch {
+    std::vector<lbvp_ctx*> members;
+    hipStream_t stream = nullptr;
+    int32_t storage = 0, vec = 1, block = MAX_BLOCK;
+    bool aa = false;
+    int32_t force_every = 0;
+    char* dev = nullptr;                 // owned: args, tile map, finalize args
+    size_t off_args = 0, off_tile_domain = 0, off_tile_start = 0, off_fins = 0;
+    size_t args_bytes = 0;
+    int32_t total_tiles = 0, tiles_per_xcd = 0;
+    std::vector<char> host_args;         // staging of the per-member arguments
+    std::vector<FinalizeArgs> host_fins;
+    std::string err;
+
+    lbvp_status fail(lbvp_status st, const std::string& m) { err = m; return st; }
+    lbvp_status hip_fail(hipError_t e, const char* what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBVP_E_DEVICE;
+    }
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+// The batch requires one step kind, one record cadence and one stream for all
+// its members at every call.
+std::string batch_consistency(const std::vector<lbvp_ctx*>& m)
+{
+    const lbvp_ctx* c0 = m[0];
+    for (const lbvp_ctx* c : m) {
+        if (c->p.storage != c0->p.storage) return "members differ in storage type";
+        if (c->aa() != c0->aa()) return "members differ in layout";
+        if (c->stream != c0->stream) return "members use different streams";
+        if (c->p.force_every != c0->p.force_every) return "members differ in force_every";
+        if (c->aa() && (c->step % 2) != (c0->step % 2)) return "AA members must be at the same step parity";
+        const int64_t fe = c->p.force_every;
+        if (fe > 1 && (c->step % fe) != (c0->step % fe)) return "members must be at the same force-record phase";
+        if (c->pending) return "a member has an unsummed record";
+    }
+    return "";
 }
 
 }  // namespace
@@ -717,6 +780,186 @@ lbvp_status lbvp_destroy(lbvp_ctx* c)
 const char* lbvp_last_error(const lbvp_ctx* c)
 {
     return c ? c->err.c_str() : g_create_error.c_str();
+}
+
+lbvp_status lbvp_batch_create(lbvp_ctx* const* members, int32_t n, int32_t vec, int32_t block, lbvp_batch** out)
+{
+    if (!out || !members || n < 1) {
+        g_batch_error = "members, n >= 1 and out are required";
+        return LBVP_E_ARG;
+    }
+    *out = nullptr;
+    std::vector<lbvp_ctx*> m(members, members + n);
+    for (lbvp_ctx* c : m)
+        if (!c) {
+            g_batch_error = "a member is NULL";
+            return LBVP_E_ARG;
+        }
+    std::string why = batch_consistency(m);
+    if (!why.empty()) {
+        g_batch_error = why;
+        return LBVP_E_ARG;
+    }
+    const lbvp_ctx* c0 = m[0];
+    if (vec == 0) vec = vec_allowed(c0->p.storage, c0->p.flags, vector_width(c0->p.storage)) ? vector_width(c0->p.storage) : 1;
+    if (block == 0) block = MAX_BLOCK;
+    for (lbvp_ctx* c : m) {
+        const lbvp_status st = lbvp_set_launch(c, vec, block);
+        if (st != LBVP_OK) {
+            g_batch_error = std::string("setting a member's launch shape: ") + c->err;
+            return st;
+        }
+    }
+    lbvp_batch* b = new (std::nothrow) lbvp_batch();
+    if (!b) {
+        g_batch_error = "host allocation failed";
+        return LBVP_E_NOMEM;
+    }
+    b->members = m;
+    b->stream = c0->stream;
+    b->storage = c0->p.storage;
+    b->vec = vec;
+    b->block = block;
+    b->aa = c0->aa();
+    b->force_every = c0->p.force_every;
+    std::vector<int32_t> tile_start((size_t)n), tile_domain;
+    for (int32_t d = 0; d < n; ++d) {
+        tile_start[d] = (int32_t)tile_domain.size();
+        tile_domain.insert(tile_domain.end(), (size_t)m[d]->launch.n_tiles, d);
+    }
+    b->total_tiles = (int32_t)tile_domain.size();
+    b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
+    const size_t arg_size = c0->is_f64() ? sizeof(StepArgs<double>) : sizeof(StepArgs<float>);
+    b->args_bytes = arg_size * (size_t)n;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, ALIGN); return at; };
+    b->off_args = take(b->args_bytes);
+    b->off_tile_domain = take(tile_domain.size() * sizeof(int32_t));
+    b->off_tile_start = take(tile_start.size() * sizeof(int32_t));
+    b->off_fins = take((size_t)n * sizeof(FinalizeArgs));
+    void* dev = nullptr;
+    hipError_t e = hipMalloc(&dev, o);
+    if (e != hipSuccess) {
+        g_batch_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+        delete b;
+        return LBVP_E_NOMEM;
+    }
+    b->dev = static_cast<char*>(dev);
+    e = hipMemcpyAsync(b->dev + b->off_tile_domain, tile_domain.data(), tile_domain.size() * 4,
+                       hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dev + b->off_tile_start, tile_start.data(), tile_start.size() * 4,
+                           hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        g_batch_error = std::string("uploading the tile map: ") + hipGetErrorString(e);
+        lbvp_batch_destroy(b);
+        return LBVP_E_DEVICE;
+    }
+    b->host_args.resize(b->args_bytes);
+    b->host_fins.resize((size_t)n);
+    *out = b;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
+{
+    if (!b) return LBVP_E_ARG;
+    if (n_steps < 0) return b->fail(LBVP_E_ARG, "n_steps < 0");
+    if (flags & ~KNOWN_STEP_FLAGS) return b->fail(LBVP_E_ARG, "unknown step flag");
+    if (n_steps == 0) return LBVP_OK;
+    std::string why = batch_consistency(b->members);
+    if (!why.empty()) return b->fail(LBVP_E_STATE, why);
+    const int64_t fe = b->force_every;
+    const int64_t step0 = b->members[0]->step;
+    const int64_t new_recs = fe > 0 ? (step0 + n_steps) / fe - step0 / fe : 0;
+    for (lbvp_ctx* c : b->members) {
+        if (c->launch.vec != b->vec || c->launch.block != b->block)
+            return b->fail(LBVP_E_STATE, "a member's launch shape was changed after the batch was made");
+        if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
+            return b->fail(LBVP_E_STATE, "a member's force ring would overflow; drain it with lbvp_forces first");
+    }
+    // the members' arguments as of this call (lattice parity, record tables, sums)
+    const size_t arg_size = b->args_bytes / b->members.size();
+    LBVP_HIP(b, hipStreamSynchronize(b->stream));   // the staging buffers are reused
+    for (size_t d = 0; d < b->members.size(); ++d) {
+        lbvp_ctx* c = b->members[d];
+        c->fin.n_bodies = c->n_bodies;
+        if (c->is_f64()) {
+            StepArgs<double> a = c->a64;
+            a.fin = c->fin;
+            a.lat0 = c->at<char>(c->L.lat[0]);
+            a.lat1 = c->at<char>(c->L.lat[1]);
+            a.cur = c->cur;
+            std::memcpy(b->host_args.data() + d * arg_size, &a, sizeof(a));
+        } else {
+            StepArgs<float> a = c->a32;
+            a.fin = c->fin;
+            a.lat0 = c->at<char>(c->L.lat[0]);
+            a.lat1 = c->at<char>(c->L.lat[1]);
+            a.cur = c->cur;
+            std::memcpy(b->host_args.data() + d * arg_size, &a, sizeof(a));
+        }
+        b->host_fins[d] = c->fin;
+    }
+    LBVP_HIP(b, hipMemcpyAsync(b->dev + b->off_args, b->host_args.data(), b->args_bytes, hipMemcpyHostToDevice,
+                               b->stream));
+    LBVP_HIP(b, hipMemcpyAsync(b->dev + b->off_fins, b->host_fins.data(), b->host_fins.size() * sizeof(FinalizeArgs),
+                               hipMemcpyHostToDevice, b->stream));
+    BatchLaunch L{};
+    L.total_tiles = b->total_tiles;
+    L.tiles_per_xcd = b->tiles_per_xcd;
+    L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_domain);
+    L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_start);
+    L.args = b->dev + b->off_args;
+    bool pending = false;
+    int32_t pending_buf = 0;
+    int64_t recs = 0;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t next = step0 + k + 1;
+        const bool record = fe > 0 && next % fe == 0;
+        const bool keep = (flags & LBVP_KEEP_FIELDS) && k == n_steps - 1;
+        const int32_t mode = !b->aa ? MODE_PULL : ((step0 + k) % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
+        L.flip = b->aa ? 0 : (int32_t)(k & 1);
+        L.part_buf = (int32_t)(recs & 1);
+        L.fin_buf = pending ? pending_buf : -1;
+        hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, L, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "batched step launch");
+        pending = record;
+        if (record) {
+            pending_buf = L.part_buf;
+            recs += 1;
+        }
+    }
+    if (pending) {
+        hipError_t e = launch_finalize_batch(reinterpret_cast<const FinalizeArgs*>(b->dev + b->off_fins),
+                                             (int32_t)b->members.size(), pending_buf, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "batched finalize launch");
+    }
+    for (lbvp_ctx* c : b->members) {
+        c->step += n_steps;
+        if (!c->aa() && (n_steps & 1)) c->cur ^= 1;
+        c->rec_head += recs;
+        if (flags & LBVP_KEEP_FIELDS) c->fields_valid = true;
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_batch_destroy(lbvp_batch* b)
+{
+    if (!b) return LBVP_OK;
+    lbvp_status st = LBVP_OK;
+    if (b->dev) {
+        if (hipStreamSynchronize(b->stream) != hipSuccess) st = LBVP_E_DEVICE;
+        if (hipFree(b->dev) != hipSuccess) st = LBVP_E_DEVICE;
+    }
+    delete b;
+    return st;
+}
+
+const char* lbvp_batch_last_error(const lbvp_batch* b)
+{
+    return b ? b->err.c_str() : g_batch_error.c_str();
 }
 
 }  // extern "C"

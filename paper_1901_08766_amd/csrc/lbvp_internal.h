@@ -43,7 +43,8 @@ struct FinalizeArgs {
 template <typename R>
 struct StepArgs {
     int32_t nx, ny;
-    int32_t vec, block, tile_w;     // nodes per thread, threads per block, nodes per tile
+    int32_t vec, block;             // nodes per thread, threads per block
+    int32_t tile_w, tile_rows;      // a tile: tile_rows rows of tile_w nodes (tile_w * tile_rows = vec * block)
     int32_t tiles_x, n_tiles, tiles_per_xcd;
     int32_t west, east;
     int32_t part_buf;   // partial buffer a recording step writes
@@ -67,7 +68,20 @@ struct StepArgs {
     R* fields;                      // [5][plane_f]
     void* ghost_w;                  // AA layout: [3][ny] zero-gradient ghost columns (storage type)
     void* ghost_e;
+    void* lat0;                     // batched launches: the domain's lattices and which one is
+    void* lat1;                     // current (two-lattice pull; the AA layout uses lat0 only)
+    int32_t cur;
     FinalizeArgs fin;
+};
+
+// A launch over many domains (k_step_batch).
+struct BatchLaunch {
+    int32_t total_tiles, tiles_per_xcd;
+    int32_t flip;                   // lattice parity of this step relative to StepArgs::cur
+    int32_t part_buf, fin_buf;      // as in StepArgs, for every domain of the batch
+    const int32_t* tile_domain;     // [total_tiles] domain of each tile
+    const int32_t* tile_start;      // [n_domains] first tile of each domain
+    const void* args;               // StepArgs<R>[n_domains]
 };
 
 struct GhostArgs {
@@ -100,6 +114,9 @@ int vector_width(int32_t storage);
 hipError_t launch_step(int32_t storage, int32_t mode, bool record, bool fields, const void* src, void* dst,
                        const void* step_args, hipStream_t s);
 hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a, hipStream_t s);
+hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_t mode, bool record, bool fields,
+                             const BatchLaunch& b, hipStream_t s);
+hipError_t launch_finalize_batch(const FinalizeArgs* fin_dev, int32_t n, int32_t buf, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s);
 hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs& a, hipStream_t s);
 hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);

@@ -381,25 +381,36 @@ __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, 
 }
 
 // ------------------------------------------------------------ the step --
+// Workgroups are dealt to the 8 XCDs round-robin by block id: block b takes
+// tile (b % 8) * per_xcd + b / 8, so each XCD sweeps a contiguous run of tiles.
+__device__ __forceinline__ int xcd_tile(int per_xcd)
+{
+    return (int)(blockIdx.x % N_XCD) * per_xcd + (int)(blockIdx.x / N_XCD);
+}
+
+// One block updates tile t of a domain: tile_rows rows of tile_w nodes, V
+// consecutive nodes per thread. part_buf / fin_buf: the partial buffer this
+// step's record writes, and the one whose record tile 0 first sums (or -1).
 template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
-__device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a)
+__device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a, int t,
+                                          int part_buf, int fin_buf)
 {
     using R = typename Arith<S>::R;
     __shared__ double lds[MAX_BLOCK / 64];
-    const int blk = blockIdx.x;
-    // block 0 first sums the previous step's force record (no other block waits on it)
-    if (blk == 0 && a.fin_buf >= 0) finalize_record(a.fin, a.fin_buf, lds);
-    const int t = (blk % N_XCD) * a.tiles_per_xcd + blk / N_XCD;
-    if (t >= a.n_tiles) return;  // whole block
+    // tile 0 first sums the previous step's force record (no other block waits on it)
+    if (t == 0 && fin_buf >= 0) finalize_record(a.fin, fin_buf, lds);
     int s0 = 0, s1 = 0;          // this tile's (tile, body) force slots
     if constexpr (RECORD) {
         s0 = a.tile_slot_ptr[t];
         s1 = a.tile_slot_ptr[t + 1];
     }
-    const int j = t / a.tiles_x;
-    const int i0 = (t - j * a.tiles_x) * a.tile_w + (int)threadIdx.x * V;
+    const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
+    const int tpr = a.tile_w / V;                       // threads per tile row
+    const int lr = (int)threadIdx.x / tpr, lc = (int)threadIdx.x - lr * tpr;
+    const int j = min(ty * a.tile_rows + lr, a.ny - 1); // rows past ny idle (clamped for addressing)
+    const int i0 = tx * a.tile_w + lc * V;
     const int lane = (int)(threadIdx.x & 63);
-    const bool act = i0 < a.nx;          // owns at least one real node
+    const bool act = i0 < a.nx && ty * a.tile_rows + lr < a.ny;   // owns at least one real node
     const int n_own = act ? min(V, a.nx - i0) : 0;
 
     const int jm = (j == 0) ? a.ny - 1 : j - 1;     // rows are periodic
@@ -460,12 +471,13 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
             left[m] = __shfl_up(v[EXP[m]][V - 1], 1, 64);
             right[m] = __shfl_down(v[EXM[m]][0], 1, 64);
         }
-        if (act && lane == 0) {
+        // lanes that start a wavefront or a tile row load the end element themselves
+        if (act && (lane == 0 || lc == 0)) {
 #pragma unroll
             for (int m = 0; m < 3; ++m)
                 left[m] = pull_column<MODE, S, R>(src, EXP[m], EXP[m], row_of[EXP[m]], row_idx[EXP[m]], i0 - 1, a);
         }
-        if (act && lane == 63) {
+        if (act && (lane == 63 || lc == tpr - 1)) {
 #pragma unroll
             for (int m = 0; m < 3; ++m)
                 right[m] = pull_column<MODE, S, R>(src, EXM[m], EXM[m], row_of[EXM[m]], row_idx[EXM[m]], i0 + V, a);
@@ -613,8 +625,8 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 
     if constexpr (RECORD) {
         // mass: one partial per wavefront (lane shuffles only, no block barrier)
-        double* mass_part = a.mass_part + a.part_buf * a.fin.mass_stride;
-        double* slot_force = a.slot_force + a.part_buf * a.fin.slot_stride;
+        double* mass_part = a.mass_part + part_buf * a.fin.mass_stride;
+        double* slot_force = a.slot_force + part_buf * a.fin.slot_stride;
         double wm = tile_drho;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) wm += __shfl_down(wm, off, 64);
@@ -645,14 +657,36 @@ template <typename S, int V, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256)
 k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
 {
-    step_body<S, V, PULL, RECORD, FIELDS>(src, dst, a);
+    const int t = xcd_tile(a.tiles_per_xcd);
+    if (t >= a.n_tiles) return;  // whole block
+    step_body<S, V, PULL, RECORD, FIELDS>(src, dst, a, t, a.part_buf, a.fin_buf);
 }
 
 // One lattice, read and written in place (no restrict).
 template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith<S>::R> a)
 {
-    step_body<S, V, MODE, RECORD, FIELDS>(lat, lat, a);
+    const int t = xcd_tile(a.tiles_per_xcd);
+    if (t >= a.n_tiles) return;  // whole block
+    step_body<S, V, MODE, RECORD, FIELDS>(lat, lat, a, t, a.part_buf, a.fin_buf);
+}
+
+// Many domains in one launch: block -> (domain, tile) through the tile map;
+// every domain's arguments (geometry, parameters, lattices) live in device
+// memory. All domains take the same step kind, record flag and partial buffers.
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
+__global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
+{
+    using R = typename Arith<S>::R;
+    const int g = xcd_tile(b.tiles_per_xcd);
+    if (g >= b.total_tiles) return;  // whole block
+    const int d = b.tile_domain[g];
+    const StepArgs<R>& a = static_cast<const StepArgs<R>*>(b.args)[d];
+    const int t = g - b.tile_start[d];
+    const int cur = a.cur ^ b.flip;
+    S* lat_cur = static_cast<S*>(cur ? a.lat1 : a.lat0);
+    S* lat_next = static_cast<S*>(cur ? a.lat0 : a.lat1);
+    step_body<S, V, MODE, RECORD, FIELDS>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, b.fin_buf);
 }
 
 // The last record of an lbvp_step call, summed on its own.
@@ -660,6 +694,13 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinalizeArgs a, int32_
 {
     __shared__ double lds[FIN_THREADS / 64];
     finalize_record(a, buf, lds);
+}
+
+// The same for every domain of a batch, one block each.
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize_batch(const FinalizeArgs* fins, int32_t buf)
+{
+    __shared__ double lds[FIN_THREADS / 64];
+    finalize_record(fins[blockIdx.x], buf, lds);
 }
 
 // ------------------------------------------------------------ conversions --
@@ -796,6 +837,42 @@ hipError_t step_typed(int mode, bool record, bool fields, const void* src, void*
     return hipErrorInvalidValue;
 }
 
+template <typename S, int V, int MODE>
+hipError_t batch_mode(bool record, bool fields, const BatchLaunch& b, int32_t block, hipStream_t s)
+{
+    const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD)), blk((unsigned)block);
+    if (record) {
+        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true>), grid, blk, 0, s, b);
+        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false>), grid, blk, 0, s, b);
+    } else {
+        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, true>), grid, blk, 0, s, b);
+        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, false>), grid, blk, 0, s, b);
+    }
+    return hipGetLastError();
+}
+
+template <typename S, int V>
+hipError_t batch_v(int32_t mode, bool record, bool fields, const BatchLaunch& b, int32_t block, hipStream_t s)
+{
+    if (mode == PULL) return batch_mode<S, V, PULL>(record, fields, b, block, s);
+    if constexpr (sizeof(S) >= 4 || V == 1) {
+        if (mode == AA_PUSH) return batch_mode<S, V, AA_PUSH>(record, fields, b, block, s);
+        return batch_mode<S, V, AA_LOCAL>(record, fields, b, block, s);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <typename S>
+hipError_t batch_typed(int32_t vec, int32_t mode, bool record, bool fields, const BatchLaunch& b, int32_t block,
+                       hipStream_t s)
+{
+    constexpr int VW = 16 / (int)sizeof(S);
+    if (vec == VW) return batch_v<S, VW>(mode, record, fields, b, block, s);
+    if (vec == 1) return batch_v<S, 1>(mode, record, fields, b, block, s);
+    return hipErrorInvalidValue;
+}
+
 unsigned conv_blocks(const ConvArgs& a) { return (unsigned)(((int64_t)a.rows * a.nx + 255) / 256); }
 
 }  // namespace
@@ -819,6 +896,24 @@ hipError_t launch_step(int32_t storage, int32_t mode, bool record, bool fields, 
     case ST_BF16: return step_typed<__bf16>(mode, record, fields, src, dst, step_args, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_t mode, bool record, bool fields,
+                             const BatchLaunch& b, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return batch_typed<double>(vec, mode, record, fields, b, block, s);
+    case ST_F32: return batch_typed<float>(vec, mode, record, fields, b, block, s);
+    case ST_F16: return batch_typed<_Float16>(vec, mode, record, fields, b, block, s);
+    case ST_BF16: return batch_typed<__bf16>(vec, mode, record, fields, b, block, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_finalize_batch(const FinalizeArgs* fin_dev, int32_t n, int32_t buf, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_batch, dim3((unsigned)n), dim3(FIN_THREADS), 0, s, fin_dev, buf);
+    return hipGetLastError();
 }
 
 hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a, hipStream_t s)

@@ -32,7 +32,8 @@ KEEP_FIELDS = 0x1
 SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_equilibrium",
            "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations",
            "lbvp_write_populations", "lbvp_set_launch", "lbvp_get_launch", "lbvp_step_count",
-           "lbvp_synchronize", "lbvp_destroy", "lbvp_last_error"]
+           "lbvp_synchronize", "lbvp_destroy", "lbvp_last_error", "lbvp_batch_create", "lbvp_batch_step",
+           "lbvp_batch_destroy", "lbvp_batch_last_error"]
 
 
 class LbvpError(RuntimeError):
@@ -82,8 +83,13 @@ def _load():
     L.lbvp_destroy.argtypes = [vp]
     L.lbvp_last_error.restype = C.c_char_p
     L.lbvp_last_error.argtypes = [vp]
+    L.lbvp_batch_create.argtypes = [C.POINTER(vp), i32, i32, i32, C.POINTER(vp)]
+    L.lbvp_batch_step.argtypes = [vp, i64, u32]
+    L.lbvp_batch_destroy.argtypes = [vp]
+    L.lbvp_batch_last_error.restype = C.c_char_p
+    L.lbvp_batch_last_error.argtypes = [vp]
     for name in SYMBOLS:
-        if name not in ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error"):
+        if name not in ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error"):
             getattr(L, name).restype = C.c_int
     return L
 
@@ -196,6 +202,32 @@ def lbvp_destroy(ctx):
         _check(None, _L.lbvp_destroy(ctx))
 
 
+def lbvp_batch_last_error(batch) -> str:
+    msg = _L.lbvp_batch_last_error(batch)
+    return msg.decode() if msg else ""
+
+
+def _check_batch(batch, status: int):
+    if status != OK:
+        raise LbvpError(status, lbvp_batch_last_error(batch))
+
+
+def lbvp_batch_create(ctxs, vec: int = 0, block: int = 0):
+    arr = (C.c_void_p * len(ctxs))(*ctxs)
+    out = C.c_void_p()
+    _check_batch(None, _L.lbvp_batch_create(arr, len(ctxs), int(vec), int(block), C.byref(out)))
+    return out.value
+
+
+def lbvp_batch_step(batch, n_steps: int, flags: int = 0):
+    _check_batch(batch, _L.lbvp_batch_step(batch, int(n_steps), int(flags)))
+
+
+def lbvp_batch_destroy(batch):
+    if batch:
+        _check_batch(None, _L.lbvp_batch_destroy(batch))
+
+
 # ------------------------------------------------------------ convenience --
 
 def params_for(prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
@@ -290,6 +322,29 @@ class Solver:
         if getattr(self, "ctx", None):
             lbvp_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Solvers advanced together (one launch per step over all their tiles).
+    The solvers must share one stream (pass the same torch stream)."""
+
+    def __init__(self, solvers, vec: int = 0, block: int = 0):
+        self.solvers = list(solvers)
+        self.handle = lbvp_batch_create([s.ctx for s in self.solvers], vec, block)
+
+    def step(self, n: int, keep_fields: bool = False):
+        lbvp_batch_step(self.handle, n, KEEP_FIELDS if keep_fields else 0)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbvp_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -1,0 +1,142 @@
+"""Batches: many domains advanced by one launch per step. Each member's fields,
+force records and populations must be bitwise those of the same domain stepped
+alone with the same launch shape (the per-node arithmetic and the fixed-order
+sums do not depend on what else shares the launch)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1901_08766_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+SIDES_IO = ("inflow_eq", "outflow_zero_grad", "periodic", "periodic")
+SIDES_P = ("periodic",) * 4
+
+
+def _members():
+    """Uneven sizes (narrow, ragged, wide), sides, relaxation and bodies."""
+    probs = [
+        inputs.random_state_problem(128, 128, seed=41, n_disks=2, bc=SIDES_IO, tau_plus=0.55),
+        inputs.random_state_problem(67, 45, seed=42, n_disks=3, bc=SIDES_IO, tau_plus=0.9),
+        inputs.random_state_problem(256, 19, seed=43, n_disks=1, bc=SIDES_P, tau_plus=0.7,
+                                    body_force=(1e-5, 0.0)),
+        inputs.random_state_problem(300, 64, seed=44, n_disks=4,
+                                    bc=("outflow_zero_grad", "inflow_eq", "periodic", "periodic")),
+        inputs.random_state_problem(5, 7, seed=45, n_disks=1, bc=SIDES_P),
+        inputs.random_state_problem(1024, 33, seed=46, n_disks=2, bc=SIDES_IO, magic_lambda=3 / 16),
+    ]
+    probs[2].magic_lambda = 0.1
+    return probs
+
+
+VW = {"f64": 2, "f32": 4, "f16": 8, "bf16": 8}
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["pull", "aa"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_batched_equals_alone(lbvp, storage, aa):
+    flags = lbvp.LAYOUT_AA if aa else 0
+    vec = 1 if (aa and storage in ("f16", "bf16")) else VW[storage]
+    steps = 13
+    probs = _members()
+    stream = torch.cuda.Stream()
+    members = [lbvp.Solver(p, storage=storage, force_every=1, force_capacity=64, flags=flags, stream=stream)
+               for p in probs]
+    batch = lbvp.Batch(members, vec=vec, block=256)
+    print(f"batch {storage} aa={aa} vec={vec}: {len(members)} members", flush=True)
+    batch.step(steps - 3)
+    batch.step(3, keep_fields=True)
+    for p, m in zip(probs, members):
+        alone = lbvp.Solver(p, storage=storage, force_every=1, force_capacity=64, flags=flags)
+        alone.set_launch(vec, 256)
+        alone.step(steps, keep_fields=True)
+        fb, ff = m.fields(), alone.fields()
+        for k in fb:
+            assert np.array_equal(fb[k], ff[k]), (p.name, k)
+        (gb, mb, sb), (ga, ma, sa) = m.forces(), alone.forces()
+        assert sb == sa == 1 and np.array_equal(gb, ga) and np.array_equal(mb, ma), p.name
+        assert m.step_count == alone.step_count == steps
+        if not aa:
+            assert np.array_equal(m.populations(), alone.populations()), p.name
+        alone.close()
+    # an even step count more, then populations in the AA layout too
+    batch.step(1)
+    for p, m in zip(probs, members):
+        alone = lbvp.Solver(p, storage=storage, force_every=1, force_capacity=64, flags=flags)
+        alone.set_launch(vec, 256)
+        alone.step(steps + 1)
+        assert np.array_equal(m.populations(), alone.populations()), p.name
+        alone.close()
+    batch.close()
+
+
+def test_batched_fp64_matches_oracle(lbvp, oracle):
+    probs = _members()[:4]
+    stream = torch.cuda.Stream()
+    members = [lbvp.Solver(p, storage="f64", force_every=1, force_capacity=64, stream=stream) for p in probs]
+    batch = lbvp.Batch(members)
+    batch.step(30, keep_fields=True)
+    for p, m in zip(probs, members):
+        r = oracle.RefSolver(p)
+        r.step(30)
+        a, b = m.fields(), r.fields()
+        for k in ("rho", "ux", "uy"):
+            assert np.abs(a[k] - b[k]).max() <= 1e-12 * np.abs(b[k]).max(), (p.name, k)
+    batch.close()
+
+
+def test_batch_rejects_mixed_members(lbvp):
+    p = _members()[1]
+    stream = torch.cuda.Stream()
+    a = lbvp.Solver(p, storage="f32", stream=stream)
+    b = lbvp.Solver(p, storage="f16", stream=stream)
+    with pytest.raises(lbvp.LbvpError) as e:
+        lbvp.Batch([a, b])
+    assert e.value.status == lbvp.E_ARG
+    c = lbvp.Solver(p, storage="f32", stream=stream, flags=lbvp.LAYOUT_AA)
+    d = lbvp.Solver(p, storage="f32", stream=stream, flags=lbvp.LAYOUT_AA)
+    c.step(1)
+    c.forces()
+    with pytest.raises(lbvp.LbvpError) as e:
+        lbvp.Batch([c, d])        # AA members at different step parity
+    assert e.value.status == lbvp.E_ARG
+    bt = lbvp.Batch([a, lbvp.Solver(p, storage="f32", stream=stream)])
+    a.step(1)                     # a member stepped alone: out of record phase? (force_every=1: still fine)
+    a.forces()
+    bt.step(2)
+    bt.close()
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_narrow_tiles_shuffle_rows(lbvp, storage):
+    """FP16/BF16 vectors on a narrow domain: several tile rows share a wavefront,
+    so the x-shift falls back to loads at tile-row starts and ends; one node per
+    thread (no shuffles) must give bitwise the same populations."""
+    prob = inputs.random_state_problem(67, 45, seed=51, n_disks=3)
+    out = []
+    for launch in ((1, 64), (8, 256), (8, 64)):
+        s = lbvp.Solver(prob, storage=storage, force_every=0)
+        s.set_launch(*launch)
+        s.step(20)
+        out.append(s.populations())
+        s.close()
+    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+
+
+def test_ensemble_batch_runs(lbvp):
+    """A slice of the random ensemble (uneven sizes, 1-4 cylinders, Re 40-200)
+    in one batch, FP32 and FP16: finite, mass-conserving to the inflow/outflow
+    budget's scale, and every member's step counter advanced."""
+    probs = inputs.ensemble(n=16, steps=200)
+    for storage in ("f32", "f16"):
+        stream = torch.cuda.Stream()
+        members = [lbvp.Solver(p, storage=storage, force_every=1, force_capacity=256, stream=stream) for p in probs]
+        batch = lbvp.Batch(members)
+        batch.step(200)
+        for p, m in zip(probs, members):
+            f, mass, _ = m.forces()
+            assert m.step_count == 200 and len(mass) == 200
+            assert np.all(np.isfinite(f)) and np.all(np.isfinite(mass))
+            assert abs(mass[-1] / (p.nx * p.ny) - 1) < 0.05
+        batch.close()
