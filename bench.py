@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -98,6 +100,128 @@ def cpu_baseline(prob, budget_s: float = 15.0):
     mlups = prob.nx * prob.ny * steps / total / 1e6
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": ref.num_threads(), "kind": "oracle",
             "sample": f"{steps} FP64 steps of the full {prob.nx}x{prob.ny} domain ({total:.1f} s)"}
+
+
+def _timed(stream, fn):
+    import torch
+
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 256, graph_chunk: int = 20):
+    """The batched ensemble (uneven domains, one launch per step over all of them,
+    launch shape and layout from the tuner) against the plain kernel launched per
+    domain per step, domains round-robin on one stream, at the same storage
+    type; both also through HIP graphs."""
+    import torch
+    from paper_1901_08766_amd import inputs, lbvp
+
+    probs = inputs.ensemble(n=n_dom)
+    nodes = sum(p.nx * p.ny for p in probs)
+    stream = torch.cuda.Stream()
+    cap = max(steps, per_domain_steps) + 64
+
+    def make(flags):
+        return [lbvp.Solver(p, storage=storage, force_every=1, force_capacity=cap, flags=flags, stream=stream)
+                for p in probs]
+
+    def drain(ms):
+        for m in ms:
+            m.forces()
+
+    members = make(0)
+    defaults = [m.launch for m in members]
+    rows, best = lbvp.tune(members, steps=40, layouts=True)
+    out = {"domains": n_dom, "nodes": nodes, "storage": storage,
+           "tuned": {"layout": "aa" if best["layout_flags"] else "pull", "vec": best["vec"], "block": best["block"]},
+           "tuner_rows": len(rows)}
+    # per-domain plain launches (pull layout, each domain's default launch shape)
+    for m in members:
+        m.step(2)
+    stream.synchronize()
+    drain(members)
+
+    def per_domain():
+        for _ in range(per_domain_steps):
+            for m in members:
+                m.step(1)
+
+    ms = _timed(stream, per_domain)
+    out["per_domain_MLUPS"] = round(nodes * per_domain_steps / ms / 1e3, 1)
+    drain(members)
+    for m in members:
+        m.step(graph_chunk, graph=True)       # capture outside the timed region
+    stream.synchronize()
+    drain(members)
+
+    def per_domain_graph():
+        for _ in range(per_domain_steps // graph_chunk):
+            for m in members:
+                m.step(graph_chunk, graph=True)
+
+    ms = _timed(stream, per_domain_graph)
+    out["per_domain_graph_MLUPS"] = round(nodes * (per_domain_steps // graph_chunk) * graph_chunk / ms / 1e3, 1)
+    drain(members)
+    assert all(m.launch == d for m, d in zip(members, defaults))
+    if best["layout_flags"]:
+        for m in members:
+            m.close()
+        members = make(lbvp.LAYOUT_AA)
+    batch = lbvp.Batch(members, vec=best["vec"], block=best["block"])
+    batch.step(10)
+    batch.step(steps, graph=True)             # capture outside the timed region
+    stream.synchronize()
+    drain(members)
+    ms = _timed(stream, lambda: batch.step(steps))
+    out["batched_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
+    out["batched_ms_per_step"] = round(ms / steps, 4)
+    drain(members)
+    ms = _timed(stream, lambda: batch.step(steps, graph=True))
+    out["batched_graph_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
+    _, mass, _ = members[0].forces()
+    out["finite"] = bool(np.isfinite(mass).all())
+    drain(members)
+    out["steps"] = {"batched": steps, "per_domain": per_domain_steps}
+    out["batched_vs_per_domain"] = round(out["batched_MLUPS"] / out["per_domain_MLUPS"], 2)
+    out["hbm_frac_batched"] = round(out["batched_MLUPS"] * 1e6 * BYTES_PER_NODE[storage] / (HBM_PEAK_GBPS * 1e9), 4)
+    batch.close()
+    for m in members:
+        m.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_serving(storage: str, rate: float, n_req: int, seed: int = 5, max_slots: int = 256,
+                max_epoch_steps: int = 256, tune_sample: int = 32):
+    """Poisson arrivals of cylinder and airfoil solves through the native pool;
+    p50/p99 latency and aggregate MLUPS over the whole run (first arrival to
+    last result on the host)."""
+    import torch
+    from paper_1901_08766_amd import inputs, lbvp, serve
+
+    reqs = inputs.request_stream(rate=rate, n=n_req, seed=seed)
+    best = serve.sample_pool_shape([r.problem for r in reqs[:tune_sample]], storage)
+    pool = lbvp.Pool(storage=storage, layout_aa=bool(best["layout_flags"]), cap_bytes=200 * 10**9,
+                     max_slots=max_slots, vec=best["vec"], block=best["block"])
+    finite = []
+    rep = serve.serve(reqs, pool, max_epoch_steps=max_epoch_steps,
+                      on_result=lambda r, f, m, _: finite.append(bool(np.isfinite(m).all())))
+    st = pool.stats()
+    pool.close()
+    torch.cuda.empty_cache()
+    out = {"storage": storage, "rate_req_per_s": rate, **rep.summary(),
+           "pool": {"layout": "aa" if best["layout_flags"] else "pull", "vec": best["vec"], "block": best["block"],
+                    "max_slots": max_slots, "cap_bytes": 200 * 10**9, "max_epoch_steps": max_epoch_steps,
+                    "reserved_bytes": st["reserved_bytes"]},
+           "mean_steps": round(float(np.mean([r.problem.steps for r in reqs])), 1),
+           "all_finite": all(finite)}
+    return out
 
 
 def calibrate_copy(nbytes: int, reps: int = 5):
@@ -204,6 +328,15 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variants", default="f16,bf16",
                     help="other storage types to time as extra fields ('' for none)")
+    ap.add_argument("--ensemble-steps", type=int, default=300,
+                    help="batched steps of the 256-domain ensemble comparison (0: skip it)")
+    ap.add_argument("--ensemble-storages", default="f32,f16")
+    ap.add_argument("--serve-requests", type=int, default=100,
+                    help="requests of the serving sample (0: skip it)")
+    ap.add_argument("--serve-rate", type=float, default=100.0)
+    ap.add_argument("--serve-storage", default="f16")
+    ap.add_argument("--serve-sweep", default="",
+                    help="only run the serving stream at these comma-separated rates (req/s)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT_MD", "COMMAND"),
@@ -222,6 +355,10 @@ def main():
     if a.summarize_counters:
         sf, sw, cf, cw, cb, kern, md, cmd = a.summarize_counters
         summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, COUNTERS_FILE, md, cmd)
+        return
+    if a.serve_sweep:
+        for rate in [float(x) for x in a.serve_sweep.split(",")]:
+            print(json.dumps(run_serving(a.serve_storage, rate, a.serve_requests)), flush=True)
         return
     if a.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only: the single-domain step has "
@@ -270,6 +407,14 @@ def main():
                      "traffic": traffic},
         "variants": extra,
     }
+    if a.ensemble_steps > 0:
+        out["ensemble"] = {}
+        for st in [x for x in a.ensemble_storages.split(",") if x]:
+            out["ensemble"][st] = time_ensemble(st, a.ensemble_steps, max(20, a.ensemble_steps // 5))
+            print(f"# ensemble {st}: {out['ensemble'][st]}", file=sys.stderr, flush=True)
+    if a.serve_requests > 0:
+        out["serving"] = run_serving(a.serve_storage, a.serve_rate, a.serve_requests)
+        print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, a.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -78,8 +78,14 @@ typedef enum lbvp_storage {
  * count; F16_DEV and BF16_DEV run with one node per thread. */
 #define LBVP_LAYOUT_AA 0x1u
 
-/* lbvp_step flags */
-#define LBVP_KEEP_FIELDS 0x1u      /* store rho, u, F_VP of the last step of the call */
+/* lbvp_step / lbvp_batch_step flags
+ * LBVP_KEEP_FIELDS: store rho, u, F_VP of the last step of the call.
+ * LBVP_GRAPH: enqueue the call through HIP graphs: each run of up to 512 steps is
+ * captured once per distinct launch sequence (at most 8 kept per context or
+ * batch) and replayed, which removes the per-launch host cost. Results are
+ * bitwise those of the plain call. Needs a stream other than the null stream. */
+#define LBVP_KEEP_FIELDS 0x1u
+#define LBVP_GRAPH 0x2u
 
 /* The problem statement (paper Sec. 2): grid, relaxation, penalization and sides.
  *   tau_plus      symmetric relaxation time tau_s (> 1/2); the viscosity is
@@ -184,10 +190,13 @@ lbvp_status lbvp_write_populations(lbvp_ctx* ctx, const double* g);
 
 /* Launch configuration of the step kernel: vec nodes per thread (1, or the
  * storage type's 16-byte width: 2 for F64, 4 for F32, 8 for F16/BF16) and block
- * threads per workgroup (64, 128 or 256). Results do not depend on it except
- * through the order of the force and mass sums. A default is chosen from the
- * grid size at lbvp_create; a tuner may set another. Errors: E_ARG (other
- * values), E_STATE (undrained force records). Synchronizes the stream. */
+ * threads per workgroup (64, 128 or 256). Populations and fields do not depend
+ * on it; the force and mass records do only through the per-tile partial sums
+ * (each record is then summed in an order fixed by the data, independent of the
+ * block size and of how steps are split over calls). A default is chosen from
+ * the grid size at lbvp_create; lbvp_tune measures the others. Errors: E_ARG
+ * (other values), E_STATE (undrained force records when the shape changes).
+ * Synchronizes the stream when the shape changes. */
 lbvp_status lbvp_set_launch(lbvp_ctx* ctx, int32_t vec, int32_t block);
 lbvp_status lbvp_get_launch(const lbvp_ctx* ctx, int32_t* vec, int32_t* block);
 
@@ -203,14 +212,113 @@ lbvp_status lbvp_get_launch(const lbvp_ctx* ctx, int32_t* vec, int32_t* block);
  * lbvp_batch_create: members[n] (borrowed; they must outlive the batch), vec /
  * block as in lbvp_set_launch (0: the storage type's vector width, 256), applied
  * to every member. E_ARG (mixed storage, layout, stream, force cadence or phase),
- * E_STATE (a member has undrained force records), E_NOMEM, E_DEVICE.
+ * E_STATE (a member whose launch shape changes has undrained force records),
+ * E_NOMEM, E_DEVICE.
  * lbvp_batch_step: every member advances n_steps (flags as lbvp_step);
- * asynchronous; E_STATE if members went out of phase or a ring would overflow. */
+ * asynchronous (the members' arguments go through pinned host buffers, so the
+ * call does not wait for earlier work); E_STATE if members went out of phase or
+ * a ring would overflow. */
 typedef struct lbvp_batch lbvp_batch;
 lbvp_status lbvp_batch_create(lbvp_ctx* const* members, int32_t n, int32_t vec, int32_t block, lbvp_batch** out);
 lbvp_status lbvp_batch_step(lbvp_batch* batch, int64_t n_steps, uint32_t flags);
 lbvp_status lbvp_batch_destroy(lbvp_batch* batch);
 const char* lbvp_batch_last_error(const lbvp_batch* batch);
+
+/* ---- Tuner ----------------------------------------------------------------------
+ * Times the step kernel for every launch shape (vec x block) and, with
+ * LBVP_TUNE_LAYOUTS, in both layouts, on scratch contexts made from the members'
+ * parameters and masks (the members themselves are not stepped; the scratch
+ * contexts need as much device memory again). n > 1 members run as one batch, as
+ * they would in lbvp_batch_step. Each candidate: steps/4 warm-up steps, then the
+ * best of three timed runs of `steps` steps (HIP events on the members' stream).
+ * rows[cap] receives one row per candidate and *best the index of the fastest;
+ * when layouts are compared, the fastest AA row wins if within 3% of the
+ * fastest row, for its halved lattice memory. Results are cached per process,
+ * keyed by storage, layout, record cadence, steps and the members' grid sizes,
+ * unless LBVP_TUNE_FRESH. Errors (message from lbvp_tune_last_error): E_ARG,
+ * E_NOMEM, E_DEVICE. */
+#define LBVP_TUNE_LAYOUTS 0x1u
+#define LBVP_TUNE_FRESH 0x2u
+typedef struct lbvp_tune_row {
+    uint32_t layout_flags;   /* 0 or LBVP_LAYOUT_AA */
+    int32_t vec, block;
+    double ms_per_step;
+    double mlups;            /* million node updates per second over all members */
+} lbvp_tune_row;
+lbvp_status lbvp_tune(lbvp_ctx* const* members, int32_t n, int32_t steps, uint32_t flags, lbvp_tune_row* rows,
+                      int32_t cap, int32_t* n_rows, int32_t* best);
+const char* lbvp_tune_last_error(void);
+
+/* ---- Serving pool: continuous batching of independent solves ---------------------
+ * A pool keeps many solves (a domain, its mask and bodies, its parameters and a
+ * step count) resident on one stream and advances all running ones together, an
+ * epoch at a time, one batched launch per step. lbvp_pool_admit takes a solve
+ * when a slot is free and its footprint fits under cap_bytes; it is set up on a
+ * private stream while earlier epochs run and joins at the next epoch. An epoch
+ * runs up to max_steps steps, fewer if a solve would otherwise overshoot its
+ * count (AA layout: an even number, a solve's odd last step running on its
+ * own), so each solve stops exactly at its count with its final fields kept.
+ * Every solve's populations, fields and force records are bitwise those of the
+ * same problem stepped alone (lbvp_step) with the pool's launch shape.
+ * Device memory comes from chunks of chunk_bytes reserved as needed (never
+ * returned before lbvp_pool_destroy), split first-fit among solves.
+ *
+ * Solve parameters: storage and layout are the pool's; force_every must be 0 or
+ * 1; force_capacity is set by the pool to hold every record of the solve.
+ * Thread use: one host thread per pool. */
+typedef struct lbvp_pool lbvp_pool;
+typedef struct lbvp_pool_config {
+    size_t cap_bytes;        /* admission limit on the summed footprints (and on reserved memory) */
+    size_t chunk_bytes;      /* device memory reserved at a time (0: 1 GiB) */
+    int32_t max_slots;       /* most solves admitted at once (1 .. 65536) */
+    int32_t storage;         /* lbvp_storage of every solve */
+    uint32_t layout_flags;   /* 0 or LBVP_LAYOUT_AA */
+    int32_t vec, block;      /* launch shape as in lbvp_set_launch (0, 0: the storage width, 256) */
+    int32_t max_in_flight;   /* epochs enqueued ahead of the host (0: 2) */
+} lbvp_pool_config;
+
+typedef struct lbvp_pool_stats {
+    int32_t waiting;         /* admitted, not yet stepped */
+    int32_t running;         /* in the batch */
+    int32_t finished;        /* all steps enqueued, not yet complete on the device */
+    int32_t done;            /* complete; results readable until released */
+    int32_t free_slots;
+    size_t used_bytes;       /* summed footprints of admitted solves */
+    size_t reserved_bytes;   /* device memory held by the pool */
+    int64_t epochs;
+    int64_t node_updates;    /* nx * ny * steps summed over every step enqueued */
+} lbvp_pool_stats;
+
+/* hip_stream: borrowed, the stream every epoch runs on (not the null stream).
+ * E_ARG (bad config), E_DEVICE. */
+lbvp_status lbvp_pool_create(const lbvp_pool_config* cfg, void* hip_stream, lbvp_pool** out);
+/* Admit one solve. p, body_id, n_bodies, bodies as lbvp_create / lbvp_set_mask;
+ * rho, ux, uy as lbvp_init_equilibrium (nullable); n_steps >= 1. *slot gets the
+ * handle. E_BUSY (no free slot), E_NOMEM (the footprint does not fit now; retry
+ * after a release), E_ARG. The host arrays are copied before return. */
+lbvp_status lbvp_pool_admit(lbvp_pool* pool, const lbvp_params* p, const uint8_t* body_id, int32_t n_bodies,
+                            const lbvp_body* bodies, const double* rho, const double* ux, const double* uy,
+                            int64_t n_steps, int32_t* slot);
+/* Enqueue one epoch of at most max_steps steps (>= 1) over the admitted solves
+ * and return; waits only while more than max_in_flight epochs are enqueued.
+ * *steps_run: the epoch length (0 if nothing is running). */
+lbvp_status lbvp_pool_run_epoch(lbvp_pool* pool, int64_t max_steps, int64_t* steps_run);
+/* Slots whose solve completed on the device since the last poll (cap at most).
+ * wait != 0: block until at least one completes if any is still finishing. */
+lbvp_status lbvp_pool_poll(lbvp_pool* pool, int32_t wait, int32_t* slots, int32_t cap, int32_t* n_done);
+/* Results of a completed solve, as lbvp_forces / lbvp_read_fields of a context
+ * (fields of its last step). E_STATE if the solve is not complete. These wait
+ * on the pool's private stream only, never on running epochs. */
+lbvp_status lbvp_pool_forces(lbvp_pool* pool, int32_t slot, double* out, double* mass, int64_t cap,
+                             int64_t* n_out, int64_t* first_step);
+lbvp_status lbvp_pool_read_fields(lbvp_pool* pool, int32_t slot, double* rho, double* ux, double* uy,
+                                  double* fx, double* fy);
+/* Free a completed (or not yet started) solve's slot and memory. E_STATE otherwise. */
+lbvp_status lbvp_pool_release(lbvp_pool* pool, int32_t slot);
+lbvp_status lbvp_pool_get_stats(const lbvp_pool* pool, lbvp_pool_stats* out);
+/* Waits for the pool's work, frees everything. NULL is accepted. */
+lbvp_status lbvp_pool_destroy(lbvp_pool* pool);
+const char* lbvp_pool_last_error(const lbvp_pool* pool);
 
 /* Number of steps taken since the last lbvp_init_equilibrium. */
 int64_t lbvp_step_count(const lbvp_ctx* ctx);

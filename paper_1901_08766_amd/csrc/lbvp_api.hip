@@ -10,8 +10,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <sstream>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "lbvp.h"
@@ -27,7 +31,8 @@ constexpr int64_t DEFAULT_CAPACITY = 16384;
 constexpr int32_t DEFAULT_MAX_BODIES = 8;
 constexpr int32_t MAX_BODIES = 255;
 constexpr uint32_t KNOWN_PARAM_FLAGS = LBVP_LAYOUT_AA;
-constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS;
+constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS | LBVP_GRAPH;
+constexpr int64_t GRAPH_CHUNK = 512;   // steps per captured graph; longer calls replay it
 
 thread_local std::string g_create_error;
 
@@ -169,6 +174,121 @@ Layout make_layout(const lbvp_params* p)
     return L;
 }
 
+// The launches of one chunk of steps, identified by everything that is baked
+// into them: chunk length, whether the last step keeps the fields, the lattice
+// parity, the AA step parity, the record phase and buffer, and the argument
+// generation (bumped whenever kernel arguments or tables change).
+struct GraphKey {
+    int64_t n = 0, phase = 0;
+    int32_t keep = 0, cur = 0, par = 0, rec = 0;
+    uint64_t gen = 0;
+    bool same(const GraphKey& o) const
+    {
+        return n == o.n && phase == o.phase && keep == o.keep && cur == o.cur && par == o.par && rec == o.rec &&
+               gen == o.gen;
+    }
+};
+
+// A few instantiated graphs, most recently used last.
+class GraphCache {
+  public:
+    GraphCache() = default;
+    GraphCache(const GraphCache&) = delete;
+    GraphCache& operator=(const GraphCache&) = delete;
+    ~GraphCache() { drop(); }
+    hipGraphExec_t find(const GraphKey& k)
+    {
+        for (size_t i = 0; i < e_.size(); ++i)
+            if (e_[i].first.same(k)) {
+                auto hit = e_[i];
+                e_.erase(e_.begin() + (long)i);
+                e_.push_back(hit);
+                return hit.second;
+            }
+        return nullptr;
+    }
+    // An evicted graph may still run: the stream is drained before it is freed.
+    void put(const GraphKey& k, hipGraphExec_t x, hipStream_t s)
+    {
+        if (e_.size() == CAP) {
+            (void)hipStreamSynchronize(s);
+            (void)hipGraphExecDestroy(e_.front().second);
+            e_.erase(e_.begin());
+        }
+        e_.emplace_back(k, x);
+    }
+    void clear(hipStream_t s)
+    {
+        if (e_.empty()) return;
+        (void)hipStreamSynchronize(s);
+        drop();
+    }
+    bool empty() const { return e_.empty(); }
+
+  private:
+    void drop()
+    {
+        for (auto& x : e_) (void)hipGraphExecDestroy(x.second);
+        e_.clear();
+    }
+    static constexpr size_t CAP = 8;
+    std::vector<std::pair<GraphKey, hipGraphExec_t>> e_;
+};
+
+// Pinned host buffers for uploads that must not wait for the stream: a
+// pageable source would make hipMemcpyAsync wait for the copy. A buffer is
+// reused once the event recorded after its copy has fired.
+class PinnedRing {
+  public:
+    PinnedRing() = default;
+    PinnedRing(const PinnedRing&) = delete;
+    PinnedRing& operator=(const PinnedRing&) = delete;
+    ~PinnedRing()
+    {
+        for (Slot& x : s_) {
+            if (x.ev) {
+                (void)hipEventSynchronize(x.ev);
+                (void)hipEventDestroy(x.ev);
+            }
+            if (x.p) (void)hipHostFree(x.p);
+        }
+    }
+    hipError_t upload(void* dst, const void* src, size_t n, hipStream_t st)
+    {
+        Slot& x = s_[next_];
+        next_ = (next_ + 1) % SLOTS;
+        hipError_t e = hipSuccess;
+        if (!x.ev) e = hipEventCreateWithFlags(&x.ev, hipEventDisableTiming);
+        else e = hipEventSynchronize(x.ev);
+        if (e != hipSuccess) return e;
+        if (x.cap < n) {
+            if (x.p) (void)hipHostFree(x.p);
+            x.p = nullptr;
+            x.cap = 0;
+            const size_t want = std::max(n, size_t(64) << 10);
+            void* m = nullptr;
+            e = hipHostMalloc(&m, want, hipHostMallocDefault);
+            if (e != hipSuccess) return e;
+            x.p = static_cast<char*>(m);
+            x.cap = want;
+        }
+        std::memcpy(x.p, src, n);
+        e = hipMemcpyAsync(dst, x.p, n, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipEventRecord(x.ev, st);
+        return e;
+    }
+
+  private:
+    static constexpr int SLOTS = 4;
+    struct Slot {
+        char* p = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+    };
+    Slot s_[SLOTS];
+    int next_ = 0;
+};
+
 }  // namespace
 
 struct lbvp_ctx {
@@ -187,6 +307,9 @@ struct lbvp_ctx {
     double tau_minus = 0.0;
     Launch launch;
     std::vector<uint8_t> mask_host;         // [ny][nx], kept to rebuild the tile tables
+    std::vector<lbvp_body> bodies_host;
+    uint64_t gen = 0;                       // kernel-argument generation (graph keys)
+    GraphCache graphs;
     StepArgs<double> a64{};
     StepArgs<float> a32{};
     FinalizeArgs fin{};
@@ -345,6 +468,7 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
 lbvp_status apply_launch(lbvp_ctx* c, const Launch& l)
 {
     c->launch = l;
+    c->gen += 1;
     c->fin.n_mass = l.n_tiles * (l.block / 64);
     fill_step_args(c, c->a64);
     fill_step_args(c, c->a32);
@@ -385,6 +509,71 @@ hipError_t refresh_aa_ghosts(lbvp_ctx* c)
     return launch_aa_ghosts(c->p.storage, c->at<char>(c->L.lat[0]), g, c->stream);
 }
 
+// The host bookkeeping that a run of steps advances.
+struct CtxClock {
+    int cur;
+    int64_t step, rec_head;
+    bool pending, fields_valid;
+    int32_t pending_buf;
+};
+
+CtxClock save_clock(const lbvp_ctx* c)
+{
+    return CtxClock{c->cur, c->step, c->rec_head, c->pending, c->fields_valid, c->pending_buf};
+}
+
+void restore_clock(lbvp_ctx* c, const CtxClock& k)
+{
+    c->cur = k.cur;
+    c->step = k.step;
+    c->rec_head = k.rec_head;
+    c->pending = k.pending;
+    c->fields_valid = k.fields_valid;
+    c->pending_buf = k.pending_buf;
+}
+
+// n steps from the current state, one launch each, then the standalone sum of
+// the last record. With launch == false only the bookkeeping advances (the
+// same launches were replayed from a graph).
+lbvp_status enqueue_steps(lbvp_ctx* c, int64_t n_steps, bool keep_last, bool launch)
+{
+    const int64_t fe = c->p.force_every;
+    c->a64.fin = c->fin;
+    c->a32.fin = c->fin;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t next = c->step + 1;
+        const bool record = fe > 0 && next % fe == 0;
+        const bool keep = keep_last && k == n_steps - 1;
+        const int32_t part_buf = (int32_t)(c->rec_head & 1);
+        if (launch) {
+            const int32_t fin_buf = c->pending ? c->pending_buf : -1;
+            c->a64.part_buf = c->a32.part_buf = part_buf;
+            c->a64.fin_buf = c->a32.fin_buf = fin_buf;
+            const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
+            const int32_t mode = !c->aa() ? MODE_PULL : (c->step % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
+            hipError_t e = launch_step(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
+                                       c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
+        }
+        c->pending = record;
+        if (record) {
+            c->pending_buf = part_buf;
+            c->rec_head += 1;
+        }
+        if (keep) c->fields_valid = true;
+        if (!c->aa()) c->cur ^= 1;
+        c->step = next;
+    }
+    if (c->pending) {  // the last record of the run is summed on its own
+        if (launch) {
+            hipError_t e = launch_finalize(c->fin, c->pending_buf, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+        }
+        c->pending = false;
+    }
+    return LBVP_OK;
+}
+
 }  // namespace
 
 
@@ -397,12 +586,15 @@ struct lbvp_batch {
     int32_t storage = 0, vec = 1, block = MAX_BLOCK;
     bool aa = false;
     int32_t force_every = 0;
-    char* dev = nullptr;                 // owned: args, tile map, finalize args
-    size_t off_args = 0, off_tile_domain = 0, off_tile_start = 0, off_fins = 0;
-    size_t args_bytes = 0;
+    char* dev = nullptr;                 // owned: [step args | finalize args | tile map]
+    size_t dev_cap = 0;
+    size_t arg_size = 0, off_fins = 0, off_tile_domain = 0, off_tile_start = 0, bytes = 0;
     int32_t total_tiles = 0, tiles_per_xcd = 0;
-    std::vector<char> host_args;         // staging of the per-member arguments
-    std::vector<FinalizeArgs> host_fins;
+    std::vector<char> image;             // host image of the device block
+    std::vector<char> uploaded;          // the image as last enqueued for upload
+    PinnedRing ring;
+    GraphCache graphs;
+    uint64_t gen = 0;                    // bumped whenever the members or the block change
     std::string err;
 
     lbvp_status fail(lbvp_status st, const std::string& m) { err = m; return st; }
@@ -410,6 +602,14 @@ struct lbvp_batch {
     {
         err = std::string(what) + ": " + hipGetErrorString(e);
         return LBVP_E_DEVICE;
+    }
+    ~lbvp_batch()
+    {
+        graphs.clear(stream);
+        if (dev) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(dev);
+        }
     }
 };
 
@@ -419,20 +619,269 @@ thread_local std::string g_batch_error;
 
 // The batch requires one step kind, one record cadence and one stream for all
 // its members at every call.
-std::string batch_consistency(const std::vector<lbvp_ctx*>& m)
+std::string batch_consistency(const lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
 {
+    if (m.empty()) return "";
     const lbvp_ctx* c0 = m[0];
     for (const lbvp_ctx* c : m) {
-        if (c->p.storage != c0->p.storage) return "members differ in storage type";
-        if (c->aa() != c0->aa()) return "members differ in layout";
-        if (c->stream != c0->stream) return "members use different streams";
-        if (c->p.force_every != c0->p.force_every) return "members differ in force_every";
+        if (!c) return "a member is NULL";
+        if (c->p.storage != b->storage) return "members differ in storage type";
+        if (c->aa() != b->aa) return "members differ in layout";
+        if (c->stream != b->stream) return "members use different streams";
+        if (c->p.force_every != b->force_every) return "members differ in force_every";
         if (c->aa() && (c->step % 2) != (c0->step % 2)) return "AA members must be at the same step parity";
         const int64_t fe = c->p.force_every;
         if (fe > 1 && (c->step % fe) != (c0->step % fe)) return "members must be at the same force-record phase";
         if (c->pending) return "a member has an unsummed record";
     }
     return "";
+}
+
+// Adopt a member list: launch shapes, the tile map in the host image and a
+// device block large enough for it.
+lbvp_status batch_assign(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
+{
+    const std::string why = batch_consistency(b, m);
+    if (!why.empty()) return b->fail(LBVP_E_ARG, why);
+    for (lbvp_ctx* c : m) {
+        const lbvp_status st = lbvp_set_launch(c, b->vec, b->block);
+        if (st != LBVP_OK) return b->fail(st, std::string("setting a member's launch shape: ") + c->err);
+    }
+    const size_t n = m.size();
+    std::vector<int32_t> tile_start(n), tile_domain;
+    for (size_t d = 0; d < n; ++d) {
+        tile_start[d] = (int32_t)tile_domain.size();
+        tile_domain.insert(tile_domain.end(), (size_t)m[d]->launch.n_tiles, (int32_t)d);
+    }
+    b->arg_size = b->storage == LBVP_F64 ? sizeof(StepArgs<double>) : sizeof(StepArgs<float>);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, ALIGN); return at; };
+    take(b->arg_size * std::max<size_t>(n, 1));
+    b->off_fins = take(sizeof(FinalizeArgs) * std::max<size_t>(n, 1));
+    b->off_tile_domain = take(std::max<size_t>(tile_domain.size(), 1) * sizeof(int32_t));
+    b->off_tile_start = take(std::max<size_t>(n, 1) * sizeof(int32_t));
+    b->bytes = o;
+    if (b->bytes > b->dev_cap) {   // rare: grow, after the stream has finished with the old block
+        b->graphs.clear(b->stream);
+        if (b->dev) {
+            LBVP_HIP(b, hipStreamSynchronize(b->stream));
+            LBVP_HIP(b, hipFree(b->dev));
+            b->dev = nullptr;
+            b->dev_cap = 0;
+        }
+        const size_t want = std::max(b->bytes, b->dev_cap * 2);
+        void* d = nullptr;
+        hipError_t e = hipMalloc(&d, want);
+        if (e != hipSuccess) return b->fail(LBVP_E_NOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+        b->dev = static_cast<char*>(d);
+        b->dev_cap = want;
+    }
+    b->image.assign(b->bytes, 0);
+    b->uploaded.clear();
+    std::memcpy(b->image.data() + b->off_tile_domain, tile_domain.data(), tile_domain.size() * sizeof(int32_t));
+    std::memcpy(b->image.data() + b->off_tile_start, tile_start.data(), n * sizeof(int32_t));
+    b->members = m;
+    b->total_tiles = (int32_t)tile_domain.size();
+    b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
+    b->graphs.clear(b->stream);
+    b->gen += 1;
+    return LBVP_OK;
+}
+
+// The members' step and finalize arguments as of now (lattice parity, record
+// tables), uploaded if they differ from what the device block holds.
+lbvp_status batch_refresh_args(lbvp_batch* b)
+{
+    for (size_t d = 0; d < b->members.size(); ++d) {
+        lbvp_ctx* c = b->members[d];
+        c->fin.n_bodies = c->n_bodies;
+        char* dst = b->image.data() + d * b->arg_size;
+        if (c->is_f64()) {
+            StepArgs<double> a = c->a64;
+            a.fin = c->fin;
+            a.lat0 = c->at<char>(c->L.lat[0]);
+            a.lat1 = c->at<char>(c->L.lat[1]);
+            a.cur = c->cur;
+            a.part_buf = 0;
+            a.fin_buf = -1;
+            std::memcpy(dst, &a, sizeof(a));
+        } else {
+            StepArgs<float> a = c->a32;
+            a.fin = c->fin;
+            a.lat0 = c->at<char>(c->L.lat[0]);
+            a.lat1 = c->at<char>(c->L.lat[1]);
+            a.cur = c->cur;
+            a.part_buf = 0;
+            a.fin_buf = -1;
+            std::memcpy(dst, &a, sizeof(a));
+        }
+        std::memcpy(b->image.data() + b->off_fins + d * sizeof(FinalizeArgs), &c->fin, sizeof(FinalizeArgs));
+    }
+    if (b->image == b->uploaded) return LBVP_OK;
+    LBVP_HIP(b, b->ring.upload(b->dev, b->image.data(), b->bytes, b->stream));
+    b->uploaded = b->image;
+    return LBVP_OK;
+}
+
+// Steps k0 .. k0 + n - 1 of a call that started at step step0, one launch
+// each, then the standalone sum of the run's last record. *recs counts the
+// records of the call so far (its parity picks the partial buffer).
+lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool keep_last, int64_t* recs)
+{
+    const int64_t fe = b->force_every;
+    BatchLaunch L{};
+    L.total_tiles = b->total_tiles;
+    L.tiles_per_xcd = b->tiles_per_xcd;
+    L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_domain);
+    L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_start);
+    L.args = b->dev;
+    bool pending = false;
+    int32_t pending_buf = 0;
+    for (int64_t k = k0; k < k0 + n; ++k) {
+        const int64_t next = step0 + k + 1;
+        const bool record = fe > 0 && next % fe == 0;
+        const bool keep = keep_last && k == k0 + n - 1;
+        const int32_t mode = !b->aa ? MODE_PULL : ((step0 + k) % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
+        L.flip = b->aa ? 0 : (int32_t)(k & 1);
+        L.part_buf = (int32_t)(*recs & 1);
+        L.fin_buf = pending ? pending_buf : -1;
+        hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, L, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "batched step launch");
+        pending = record;
+        if (record) {
+            pending_buf = L.part_buf;
+            *recs += 1;
+        }
+    }
+    if (pending) {
+        hipError_t e = launch_finalize_batch(reinterpret_cast<const FinalizeArgs*>(b->dev + b->off_fins),
+                                             (int32_t)b->members.size(), pending_buf, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "batched finalize launch");
+    }
+    return LBVP_OK;
+}
+
+}  // namespace
+
+namespace lbvp {
+
+lbvp_status batch_new(hipStream_t stream, int32_t storage, uint32_t layout_flags, int32_t force_every, int32_t vec,
+                      int32_t block, lbvp_batch** out)
+{
+    lbvp_batch* b = new (std::nothrow) lbvp_batch();
+    if (!b) return LBVP_E_NOMEM;
+    b->stream = stream;
+    b->storage = storage;
+    b->aa = (layout_flags & LBVP_LAYOUT_AA) != 0;
+    b->force_every = force_every;
+    b->vec = vec;
+    b->block = block;
+    *out = b;
+    return LBVP_OK;
+}
+
+lbvp_status batch_set_members(lbvp_batch* b, lbvp_ctx* const* members, int32_t n)
+{
+    return batch_assign(b, std::vector<lbvp_ctx*>(members, members + n));
+}
+
+void ctx_rebind_stream(lbvp_ctx* c, hipStream_t s)
+{
+    c->graphs.clear(c->stream);
+    c->stream = s;
+}
+
+}  // namespace lbvp
+
+namespace {
+
+thread_local std::string g_tune_error;
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<std::vector<lbvp_tune_row>, int32_t>> g_tune_cache;
+
+std::string tune_signature(const std::vector<lbvp_ctx*>& m, int32_t steps, uint32_t flags)
+{
+    std::vector<std::pair<int32_t, int32_t>> shapes;
+    for (const lbvp_ctx* c : m) shapes.emplace_back(c->p.nx, c->p.ny);
+    std::sort(shapes.begin(), shapes.end());
+    std::ostringstream o;
+    const lbvp_ctx* c0 = m[0];
+    o << c0->p.storage << '/' << (c0->p.flags & LBVP_LAYOUT_AA) << '/' << c0->p.force_every << '/' << steps << '/'
+      << (flags & LBVP_TUNE_LAYOUTS);
+    for (auto& x : shapes) o << ';' << x.first << 'x' << x.second;
+    return o.str();
+}
+
+// Time every launch shape in one layout on scratch copies of the members'
+// problems (parameters, mask, bodies; fluid at rest).
+lbvp_status tune_layout(const std::vector<lbvp_ctx*>& m, uint32_t layout, int32_t steps,
+                        std::vector<lbvp_tune_row>& rows)
+{
+    std::vector<lbvp_ctx*> s;
+    lbvp_batch* b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto finish = [&](lbvp_status st, const std::string& why) {
+        if (b) lbvp_batch_destroy(b);
+        for (lbvp_ctx* x : s) lbvp_destroy(x);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st != LBVP_OK) g_tune_error = why;
+        return st;
+    };
+    const hipStream_t stream = m[0]->stream;
+    double nodes = 0.0;
+    for (const lbvp_ctx* c : m) {
+        lbvp_params p = c->p;
+        p.flags = (p.flags & ~LBVP_LAYOUT_AA) | layout;
+        p.force_capacity = std::max<int64_t>(p.force_capacity, 2 * (int64_t)steps + 16);
+        lbvp_ctx* x = nullptr;
+        lbvp_status st = lbvp_create(&p, stream, nullptr, 0, &x);
+        if (st != LBVP_OK) return finish(st, "scratch context: " + g_create_error);
+        s.push_back(x);
+        st = lbvp_set_mask(x, c->mask_host.data(), c->n_bodies, c->bodies_host.data());
+        if (st != LBVP_OK) return finish(st, "scratch mask: " + x->err);
+        nodes += (double)c->p.nx * c->p.ny;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return finish(LBVP_E_DEVICE, "hipEventCreate failed");
+    const int32_t storage = m[0]->p.storage;
+    std::vector<int32_t> vecs{1};
+    if (vec_allowed(storage, layout, vector_width(storage)) && vector_width(storage) != 1)
+        vecs.push_back(vector_width(storage));
+    for (int32_t vec : vecs)
+        for (int32_t block : {64, 128, 256}) {
+            lbvp_status st = LBVP_OK;
+            if (s.size() == 1) st = lbvp_set_launch(s[0], vec, block);
+            else st = lbvp_batch_create(s.data(), (int32_t)s.size(), vec, block, &b);
+            if (st != LBVP_OK) return finish(st, "launch shape: " + (s.size() == 1 ? s[0]->err : g_batch_error));
+            auto run = [&](int64_t k) { return b ? lbvp_batch_step(b, k, 0) : lbvp_step(s[0], k, 0); };
+            double best = 1e300;
+            st = run(std::max(2, steps / 4));
+            for (lbvp_ctx* x : s) x->rec_tail = x->rec_head;   // records are not needed
+            for (int rep = 0; rep < 3 && st == LBVP_OK; ++rep) {
+                if (hipEventRecord(e0, stream) != hipSuccess) return finish(LBVP_E_DEVICE, "hipEventRecord");
+                st = run(steps);
+                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                    return finish(LBVP_E_DEVICE, "timing events failed");
+                float ms = 0.0f;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return finish(LBVP_E_DEVICE, "hipEventElapsedTime");
+                best = std::min(best, (double)ms);
+                for (lbvp_ctx* x : s) x->rec_tail = x->rec_head;   // records are not needed
+            }
+            if (st != LBVP_OK) return finish(st, "timed steps failed");
+            if (b) {
+                lbvp_batch_destroy(b);
+                b = nullptr;
+            }
+            lbvp_tune_row r{};
+            r.layout_flags = layout;
+            r.vec = vec;
+            r.block = block;
+            r.ms_per_step = best / steps;
+            r.mlups = nodes * steps / (best * 1e3);
+            rows.push_back(r);
+        }
+    return finish(LBVP_OK, "");
 }
 
 }  // namespace
@@ -538,9 +987,12 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
 
     std::vector<char> table = c->is_f64() ? body_table_bytes<double>(bodies, n_bodies, L.max_bodies)
                                           : body_table_bytes<float>(bodies, n_bodies, L.max_bodies);
+    c->graphs.clear(c->stream);
     c->mask_host.assign(body_id, body_id + n);
+    c->bodies_host.assign(bodies, bodies + n_bodies);
     c->n_bodies = n_bodies;
     c->fin.n_bodies = n_bodies;
+    c->gen += 1;
 
     hipStream_t s = c->stream;
     LBVP_HIP(c, hipMemcpy2DAsync(c->at<uint8_t>(L.mask), (size_t)L.pitch, body_id, (size_t)p.nx,
@@ -597,34 +1049,49 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
         if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
             return c->fail(LBVP_E_STATE, "force records would overflow the device ring; call lbvp_forces first");
     }
-    c->a64.fin = c->fin;
-    c->a32.fin = c->fin;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const int64_t next = c->step + 1;
-        const bool record = fe > 0 && next % fe == 0;
-        const bool keep = (flags & LBVP_KEEP_FIELDS) && k == n_steps - 1;
-        const int32_t part_buf = (int32_t)(c->rec_head & 1);
-        const int32_t fin_buf = c->pending ? c->pending_buf : -1;
-        c->a64.part_buf = c->a32.part_buf = part_buf;
-        c->a64.fin_buf = c->a32.fin_buf = fin_buf;
-        const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
-        const int32_t mode = !c->aa() ? MODE_PULL : (c->step % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
-        hipError_t e = launch_step(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
-                                   c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
-        if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
-        c->pending = record;
-        if (record) {
-            c->pending_buf = part_buf;
-            c->rec_head += 1;
+    const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
+    if (!(flags & LBVP_GRAPH)) return enqueue_steps(c, n_steps, keep, true);
+    if (!c->stream) return c->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
+    for (int64_t done = 0; done < n_steps;) {
+        const int64_t n = std::min(GRAPH_CHUNK, n_steps - done);
+        const bool keep_here = keep && done + n == n_steps;
+        GraphKey key;
+        key.n = n;
+        key.keep = keep_here;
+        key.cur = c->cur;
+        key.par = c->aa() ? (int32_t)(c->step & 1) : 0;
+        key.phase = fe > 0 ? c->step % fe : 0;
+        key.rec = (int32_t)(c->rec_head & 1);
+        key.gen = c->gen;
+        hipGraphExec_t x = c->graphs.find(key);
+        if (x) {
+            LBVP_HIP(c, hipGraphLaunch(x, c->stream));
+            enqueue_steps(c, n, keep_here, false);
+        } else {
+            const CtxClock saved = save_clock(c);
+            LBVP_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            const lbvp_status st = enqueue_steps(c, n, keep_here, true);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (st != LBVP_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                restore_clock(c, saved);
+                return st != LBVP_OK ? st : c->hip_fail(e, "hipStreamEndCapture");
+            }
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                restore_clock(c, saved);
+                return c->hip_fail(e, "hipGraphInstantiate");
+            }
+            c->graphs.put(key, x, c->stream);
+            e = hipGraphLaunch(x, c->stream);
+            if (e != hipSuccess) {
+                restore_clock(c, saved);
+                return c->hip_fail(e, "hipGraphLaunch");
+            }
         }
-        if (keep) c->fields_valid = true;
-        if (!c->aa()) c->cur ^= 1;
-        c->step = next;
-    }
-    if (c->pending) {  // the last record of the call is summed on its own
-        hipError_t e = launch_finalize(c->fin, c->pending_buf, c->stream);
-        if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
-        c->pending = false;
+        done += n;
     }
     return LBVP_OK;
 }
@@ -642,12 +1109,13 @@ lbvp_status lbvp_forces(lbvp_ctx* c, double* out, double* mass, int64_t cap, int
     while (done < n) {
         const int64_t r = (c->rec_tail + done) % C;
         const int64_t len = std::min(n - done, C - r);
-        LBVP_HIP(c, hipMemcpy(rf.data() + done * mb * 2, c->at<double>(c->L.ring_force) + r * mb * 2,
-                              (size_t)(len * mb * 2) * sizeof(double), hipMemcpyDeviceToHost));
-        LBVP_HIP(c, hipMemcpy(rm.data() + done, c->at<double>(c->L.ring_mass) + r,
-                              (size_t)len * sizeof(double), hipMemcpyDeviceToHost));
+        LBVP_HIP(c, hipMemcpyAsync(rf.data() + done * mb * 2, c->at<double>(c->L.ring_force) + r * mb * 2,
+                                   (size_t)(len * mb * 2) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        LBVP_HIP(c, hipMemcpyAsync(rm.data() + done, c->at<double>(c->L.ring_mass) + r,
+                                   (size_t)len * sizeof(double), hipMemcpyDeviceToHost, c->stream));
         done += len;
     }
+    LBVP_HIP(c, hipStreamSynchronize(c->stream));
     bool finite = true;
     for (int64_t k = 0; k < n; ++k) {
         if (out)
@@ -677,8 +1145,9 @@ lbvp_status lbvp_read_fields(lbvp_ctx* c, double* rho, double* ux, double* uy, d
     for (int q = 0; q < 5; ++q) {
         if (!dst[q]) continue;
         const char* srcp = c->at<char>(c->L.fields) + (size_t)q * c->L.plane_f * rs;
-        LBVP_HIP(c, hipMemcpy2D(tmp.data(), (size_t)p.nx * rs, srcp, (size_t)c->L.pitch * rs, (size_t)p.nx * rs,
-                                (size_t)p.ny, hipMemcpyDeviceToHost));
+        LBVP_HIP(c, hipMemcpy2DAsync(tmp.data(), (size_t)p.nx * rs, srcp, (size_t)c->L.pitch * rs,
+                                     (size_t)p.nx * rs, (size_t)p.ny, hipMemcpyDeviceToHost, c->stream));
+        LBVP_HIP(c, hipStreamSynchronize(c->stream));
         const size_t n = (size_t)p.nx * p.ny;
         if (c->is_f64()) std::memcpy(dst[q], tmp.data(), n * sizeof(double));
         else {
@@ -743,8 +1212,10 @@ lbvp_status lbvp_set_launch(lbvp_ctx* c, int32_t vec, int32_t block)
         return c->fail(LBVP_E_ARG, "vec must be 1 or the storage type's 16-byte vector width "
                                    "(1 only for 2-byte storage in the AA layout)");
     if (block != 64 && block != 128 && block != 256) return c->fail(LBVP_E_ARG, "block must be 64, 128 or 256");
+    if (c->launch.vec == vec && c->launch.block == block) return LBVP_OK;
     if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");
     LBVP_HIP(c, hipStreamSynchronize(c->stream));
+    c->graphs.clear(c->stream);
     return apply_launch(c, make_launch(c->p.nx, c->p.ny, vec, block));
 }
 
@@ -789,75 +1260,25 @@ lbvp_status lbvp_batch_create(lbvp_ctx* const* members, int32_t n, int32_t vec, 
         return LBVP_E_ARG;
     }
     *out = nullptr;
-    std::vector<lbvp_ctx*> m(members, members + n);
-    for (lbvp_ctx* c : m)
-        if (!c) {
+    for (int32_t d = 0; d < n; ++d)
+        if (!members[d]) {
             g_batch_error = "a member is NULL";
             return LBVP_E_ARG;
         }
-    std::string why = batch_consistency(m);
-    if (!why.empty()) {
-        g_batch_error = why;
-        return LBVP_E_ARG;
-    }
-    const lbvp_ctx* c0 = m[0];
+    const lbvp_ctx* c0 = members[0];
     if (vec == 0) vec = vec_allowed(c0->p.storage, c0->p.flags, vector_width(c0->p.storage)) ? vector_width(c0->p.storage) : 1;
     if (block == 0) block = MAX_BLOCK;
-    for (lbvp_ctx* c : m) {
-        const lbvp_status st = lbvp_set_launch(c, vec, block);
-        if (st != LBVP_OK) {
-            g_batch_error = std::string("setting a member's launch shape: ") + c->err;
-            return st;
-        }
-    }
-    lbvp_batch* b = new (std::nothrow) lbvp_batch();
-    if (!b) {
+    lbvp_batch* b = nullptr;
+    if (batch_new(c0->stream, c0->p.storage, c0->p.flags, c0->p.force_every, vec, block, &b) != LBVP_OK) {
         g_batch_error = "host allocation failed";
         return LBVP_E_NOMEM;
     }
-    b->members = m;
-    b->stream = c0->stream;
-    b->storage = c0->p.storage;
-    b->vec = vec;
-    b->block = block;
-    b->aa = c0->aa();
-    b->force_every = c0->p.force_every;
-    std::vector<int32_t> tile_start((size_t)n), tile_domain;
-    for (int32_t d = 0; d < n; ++d) {
-        tile_start[d] = (int32_t)tile_domain.size();
-        tile_domain.insert(tile_domain.end(), (size_t)m[d]->launch.n_tiles, d);
-    }
-    b->total_tiles = (int32_t)tile_domain.size();
-    b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
-    const size_t arg_size = c0->is_f64() ? sizeof(StepArgs<double>) : sizeof(StepArgs<float>);
-    b->args_bytes = arg_size * (size_t)n;
-    size_t o = 0;
-    auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, ALIGN); return at; };
-    b->off_args = take(b->args_bytes);
-    b->off_tile_domain = take(tile_domain.size() * sizeof(int32_t));
-    b->off_tile_start = take(tile_start.size() * sizeof(int32_t));
-    b->off_fins = take((size_t)n * sizeof(FinalizeArgs));
-    void* dev = nullptr;
-    hipError_t e = hipMalloc(&dev, o);
-    if (e != hipSuccess) {
-        g_batch_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+    const lbvp_status st = batch_assign(b, std::vector<lbvp_ctx*>(members, members + n));
+    if (st != LBVP_OK) {
+        g_batch_error = b->err;
         delete b;
-        return LBVP_E_NOMEM;
+        return st;
     }
-    b->dev = static_cast<char*>(dev);
-    e = hipMemcpyAsync(b->dev + b->off_tile_domain, tile_domain.data(), tile_domain.size() * 4,
-                       hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->dev + b->off_tile_start, tile_start.data(), tile_start.size() * 4,
-                           hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        g_batch_error = std::string("uploading the tile map: ") + hipGetErrorString(e);
-        lbvp_batch_destroy(b);
-        return LBVP_E_DEVICE;
-    }
-    b->host_args.resize(b->args_bytes);
-    b->host_fins.resize((size_t)n);
     *out = b;
     return LBVP_OK;
 }
@@ -868,7 +1289,8 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
     if (n_steps < 0) return b->fail(LBVP_E_ARG, "n_steps < 0");
     if (flags & ~KNOWN_STEP_FLAGS) return b->fail(LBVP_E_ARG, "unknown step flag");
     if (n_steps == 0) return LBVP_OK;
-    std::string why = batch_consistency(b->members);
+    if (b->members.empty()) return b->fail(LBVP_E_STATE, "the batch has no members");
+    std::string why = batch_consistency(b, b->members);
     if (!why.empty()) return b->fail(LBVP_E_STATE, why);
     const int64_t fe = b->force_every;
     const int64_t step0 = b->members[0]->step;
@@ -879,68 +1301,53 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
         if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
             return b->fail(LBVP_E_STATE, "a member's force ring would overflow; drain it with lbvp_forces first");
     }
-    // the members' arguments as of this call (lattice parity, record tables, sums)
-    const size_t arg_size = b->args_bytes / b->members.size();
-    LBVP_HIP(b, hipStreamSynchronize(b->stream));   // the staging buffers are reused
-    for (size_t d = 0; d < b->members.size(); ++d) {
-        lbvp_ctx* c = b->members[d];
-        c->fin.n_bodies = c->n_bodies;
-        if (c->is_f64()) {
-            StepArgs<double> a = c->a64;
-            a.fin = c->fin;
-            a.lat0 = c->at<char>(c->L.lat[0]);
-            a.lat1 = c->at<char>(c->L.lat[1]);
-            a.cur = c->cur;
-            std::memcpy(b->host_args.data() + d * arg_size, &a, sizeof(a));
-        } else {
-            StepArgs<float> a = c->a32;
-            a.fin = c->fin;
-            a.lat0 = c->at<char>(c->L.lat[0]);
-            a.lat1 = c->at<char>(c->L.lat[1]);
-            a.cur = c->cur;
-            std::memcpy(b->host_args.data() + d * arg_size, &a, sizeof(a));
-        }
-        b->host_fins[d] = c->fin;
-    }
-    LBVP_HIP(b, hipMemcpyAsync(b->dev + b->off_args, b->host_args.data(), b->args_bytes, hipMemcpyHostToDevice,
-                               b->stream));
-    LBVP_HIP(b, hipMemcpyAsync(b->dev + b->off_fins, b->host_fins.data(), b->host_fins.size() * sizeof(FinalizeArgs),
-                               hipMemcpyHostToDevice, b->stream));
-    BatchLaunch L{};
-    L.total_tiles = b->total_tiles;
-    L.tiles_per_xcd = b->tiles_per_xcd;
-    L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_domain);
-    L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_start);
-    L.args = b->dev + b->off_args;
-    bool pending = false;
-    int32_t pending_buf = 0;
+    const lbvp_status up = batch_refresh_args(b);
+    if (up != LBVP_OK) return up;
+    const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
     int64_t recs = 0;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const int64_t next = step0 + k + 1;
-        const bool record = fe > 0 && next % fe == 0;
-        const bool keep = (flags & LBVP_KEEP_FIELDS) && k == n_steps - 1;
-        const int32_t mode = !b->aa ? MODE_PULL : ((step0 + k) % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
-        L.flip = b->aa ? 0 : (int32_t)(k & 1);
-        L.part_buf = (int32_t)(recs & 1);
-        L.fin_buf = pending ? pending_buf : -1;
-        hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, L, b->stream);
-        if (e != hipSuccess) return b->hip_fail(e, "batched step launch");
-        pending = record;
-        if (record) {
-            pending_buf = L.part_buf;
-            recs += 1;
+    if (!(flags & LBVP_GRAPH)) {
+        const lbvp_status st = batch_run(b, step0, 0, n_steps, keep, &recs);
+        if (st != LBVP_OK) return st;
+    } else {
+        if (!b->stream) return b->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
+        for (int64_t k0 = 0; k0 < n_steps;) {
+            const int64_t n = std::min(GRAPH_CHUNK, n_steps - k0);
+            const bool keep_here = keep && k0 + n == n_steps;
+            GraphKey key;
+            key.n = n;
+            key.keep = keep_here;
+            key.cur = (int32_t)(k0 & 1);
+            key.par = b->aa ? (int32_t)((step0 + k0) & 1) : 0;
+            key.phase = fe > 0 ? (step0 + k0) % fe : 0;
+            key.rec = (int32_t)(recs & 1);
+            key.gen = b->gen;
+            hipGraphExec_t x = b->graphs.find(key);
+            if (x) {
+                LBVP_HIP(b, hipGraphLaunch(x, b->stream));
+                if (fe > 0) recs += (step0 + k0 + n) / fe - (step0 + k0) / fe;
+            } else {
+                LBVP_HIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+                const lbvp_status st = batch_run(b, step0, k0, n, keep_here, &recs);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(b->stream, &g);
+                if (st != LBVP_OK || e != hipSuccess) {
+                    if (g) (void)hipGraphDestroy(g);
+                    return st != LBVP_OK ? st : b->hip_fail(e, "hipStreamEndCapture");
+                }
+                e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                if (e != hipSuccess) return b->hip_fail(e, "hipGraphInstantiate");
+                b->graphs.put(key, x, b->stream);
+                LBVP_HIP(b, hipGraphLaunch(x, b->stream));
+            }
+            k0 += n;
         }
-    }
-    if (pending) {
-        hipError_t e = launch_finalize_batch(reinterpret_cast<const FinalizeArgs*>(b->dev + b->off_fins),
-                                             (int32_t)b->members.size(), pending_buf, b->stream);
-        if (e != hipSuccess) return b->hip_fail(e, "batched finalize launch");
     }
     for (lbvp_ctx* c : b->members) {
         c->step += n_steps;
         if (!c->aa() && (n_steps & 1)) c->cur ^= 1;
         c->rec_head += recs;
-        if (flags & LBVP_KEEP_FIELDS) c->fields_valid = true;
+        if (keep) c->fields_valid = true;
     }
     return LBVP_OK;
 }
@@ -949,10 +1356,7 @@ lbvp_status lbvp_batch_destroy(lbvp_batch* b)
 {
     if (!b) return LBVP_OK;
     lbvp_status st = LBVP_OK;
-    if (b->dev) {
-        if (hipStreamSynchronize(b->stream) != hipSuccess) st = LBVP_E_DEVICE;
-        if (hipFree(b->dev) != hipSuccess) st = LBVP_E_DEVICE;
-    }
+    if (b->dev && hipStreamSynchronize(b->stream) != hipSuccess) st = LBVP_E_DEVICE;
     delete b;
     return st;
 }
@@ -961,5 +1365,68 @@ const char* lbvp_batch_last_error(const lbvp_batch* b)
 {
     return b ? b->err.c_str() : g_batch_error.c_str();
 }
+
+lbvp_status lbvp_tune(lbvp_ctx* const* members, int32_t n, int32_t steps, uint32_t flags, lbvp_tune_row* rows,
+                      int32_t cap, int32_t* n_rows, int32_t* best)
+{
+    if (!members || n < 1 || steps < 1 || cap < 0 || (cap > 0 && !rows) || !n_rows || !best ||
+        (flags & ~(LBVP_TUNE_LAYOUTS | LBVP_TUNE_FRESH))) {
+        g_tune_error = "members, n >= 1, steps >= 1, rows[cap], n_rows, best and known flags are required";
+        return LBVP_E_ARG;
+    }
+    std::vector<lbvp_ctx*> m(members, members + n);
+    for (lbvp_ctx* c : m)
+        if (!c) {
+            g_tune_error = "a member is NULL";
+            return LBVP_E_ARG;
+        }
+    const lbvp_ctx* c0 = m[0];
+    for (const lbvp_ctx* c : m)
+        if (c->p.storage != c0->p.storage || c->aa() != c0->aa() || c->stream != c0->stream ||
+            c->p.force_every != c0->p.force_every) {
+            g_tune_error = "members differ in storage, layout, stream or force_every";
+            return LBVP_E_ARG;
+        }
+    const std::string key = tune_signature(m, steps, flags);
+    std::vector<lbvp_tune_row> table;
+    int32_t pick = 0;
+    bool cached = false;
+    if (!(flags & LBVP_TUNE_FRESH)) {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            table = it->second.first;
+            pick = it->second.second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        const uint32_t own = c0->p.flags & LBVP_LAYOUT_AA;
+        std::vector<uint32_t> layouts{own};
+        if (flags & LBVP_TUNE_LAYOUTS) layouts.push_back(own ^ LBVP_LAYOUT_AA);
+        for (uint32_t layout : layouts) {
+            const lbvp_status st = tune_layout(m, layout, steps, table);
+            if (st != LBVP_OK) return st;
+        }
+        for (int32_t i = 1; i < (int32_t)table.size(); ++i)
+            if (table[i].ms_per_step < table[pick].ms_per_step) pick = i;
+        if (flags & LBVP_TUNE_LAYOUTS) {
+            int32_t aa = -1;
+            for (int32_t i = 0; i < (int32_t)table.size(); ++i)
+                if ((table[i].layout_flags & LBVP_LAYOUT_AA) && (aa < 0 || table[i].ms_per_step < table[aa].ms_per_step))
+                    aa = i;
+            if (aa >= 0 && table[aa].ms_per_step <= 1.03 * table[pick].ms_per_step) pick = aa;
+        }
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tune_cache[key] = {table, pick};
+    }
+    const int32_t k = std::min<int32_t>(cap, (int32_t)table.size());
+    for (int32_t i = 0; i < k; ++i) rows[i] = table[i];
+    *n_rows = (int32_t)table.size();
+    *best = pick;
+    return LBVP_OK;
+}
+
+const char* lbvp_tune_last_error(void) { return g_tune_error.c_str(); }
 
 }  // extern "C"

@@ -1,9 +1,12 @@
 // lbvp_internal.h -- kernel argument blocks and launchers shared by the host
-// side of liblbvp (lbvp_api.hip) and its kernels (lbvp_kernels.hip).
+// side of liblbvp (lbvp_api.hip, lbvp_pool.hip) and its kernels
+// (lbvp_kernels.hip).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include "lbvp.h"
 
 namespace lbvp {
 
@@ -122,5 +125,15 @@ hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs&
 hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);
 hipError_t launch_encode(int32_t storage, void* lat, const ConvArgs& a, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+
+// host-side pieces the serving pool builds on (lbvp_api.hip)
+// An empty batch of the given kind on a stream; members come with batch_set_members.
+lbvp_status batch_new(hipStream_t stream, int32_t storage, uint32_t layout_flags, int32_t force_every, int32_t vec,
+                      int32_t block, lbvp_batch** out);
+// Replace a batch's members (same checks as lbvp_batch_create); no stream wait
+// unless the batch's device block has to grow.
+lbvp_status batch_set_members(lbvp_batch* b, lbvp_ctx* const* members, int32_t n);
+// Move an idle context to another stream (no work of it may be pending).
+void ctx_rebind_stream(lbvp_ctx* c, hipStream_t s);
 
 }  // namespace lbvp

@@ -333,42 +333,67 @@ __device__ __forceinline__ void store_vec_shifted(S* p, const S (&in)[V])
 }
 
 // ------------------------------------------------------------ the record --
-// One block sums one force record (see FinalizeArgs) in a fixed order: each
-// thread walks a fixed stride of the partials with eight independent
-// accumulators (so that loads overlap), then the block sums the threads.
-__device__ __forceinline__ double strided_sum(const double* x, int n, int stride2)
+// One block sums one force record (see FinalizeArgs) in an order fixed by the
+// data alone: the partials are dealt to FIN_LANES virtual lanes (lane v takes
+// v, v + FIN_LANES, ...), each lane adds its share with eight interleaved
+// accumulators (so that loads overlap), and the lanes meet in a fixed binary
+// tree in LDS. Neither the block size of the launch that runs it nor the way
+// steps are split over calls changes a record by one bit.
+constexpr int FIN_LANES = 256;
+
+__device__ __forceinline__ double lane_sum(const double* x, int n, int v)
 {
     double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    const int nt = (int)blockDim.x;
-    int k = (int)threadIdx.x;
-    for (; k + 7 * nt < n; k += 8 * nt) {
+    int k = v;
+    for (; k + 7 * FIN_LANES < n; k += 8 * FIN_LANES) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u] += x[(int64_t)(k + u * nt) * stride2];
+        for (int u = 0; u < 8; ++u) acc[u] += x[k + u * FIN_LANES];
     }
 #pragma unroll
     for (int u = 0; u < 7; ++u) {   // at most 7 left
-        const int kk = k + u * nt;
-        if (kk < n) acc[u] += x[(int64_t)kk * stride2];
+        const int kk = k + u * FIN_LANES;
+        if (kk < n) acc[u] += x[kk];
     }
     return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// Sum of the FIN_LANES values in s (LDS), pairwise with halving spans; every
+// thread of the block must call it and gets the sum.
+__device__ __forceinline__ double tree_sum(double* s)
+{
+    for (int w = FIN_LANES / 2; w > 0; w >>= 1) {
+        __syncthreads();
+        for (int v = (int)threadIdx.x; v < w; v += (int)blockDim.x) s[v] += s[v + w];
+    }
+    __syncthreads();
+    const double r = s[0];
+    __syncthreads();   // s is reused by the next sum
+    return r;
 }
 
 __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, double* lds)
 {
     const double* pm = f.mass_part + buf * f.mass_stride;
     const double* sf = f.slot_force + buf * f.slot_stride;
-    const double m = block_sum(strided_sum(pm, f.n_mass, 1), lds);
+    double* sx = lds;
+    double* sy = lds + FIN_LANES;
+    for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) sx[v] = lane_sum(pm, f.n_mass, v);
+    const double m = tree_sum(sx);
     const int64_t r = *f.rec_count % f.capacity;
     for (int b = 0; b < f.n_bodies; ++b) {
         const int s0 = f.body_slot_ptr[b], s1 = f.body_slot_ptr[b + 1];
-        double x = 0.0, y = 0.0;
-        for (int k = s0 + (int)threadIdx.x; k < s1; k += (int)blockDim.x) {
-            const int s = f.body_slots[k];
-            x += sf[2 * s];
-            y += sf[2 * s + 1];
+        for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
+            double x = 0.0, y = 0.0;
+            for (int k = s0 + v; k < s1; k += FIN_LANES) {
+                const int s = f.body_slots[k];
+                x += sf[2 * s];
+                y += sf[2 * s + 1];
+            }
+            sx[v] = x;
+            sy[v] = y;
         }
-        x = block_sum(x, lds);
-        y = block_sum(y, lds);
+        const double x = tree_sum(sx);
+        const double y = tree_sum(sy);
         if (threadIdx.x == 0) {
             f.ring_force[(r * f.max_bodies + b) * 2] = x;
             f.ring_force[(r * f.max_bodies + b) * 2 + 1] = y;
@@ -396,7 +421,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                                           int part_buf, int fin_buf)
 {
     using R = typename Arith<S>::R;
-    __shared__ double lds[MAX_BLOCK / 64];
+    __shared__ double lds[2 * FIN_LANES];   // the record sums, then the per-wavefront sums
     // tile 0 first sums the previous step's force record (no other block waits on it)
     if (t == 0 && fin_buf >= 0) finalize_record(a.fin, fin_buf, lds);
     int s0 = 0, s1 = 0;          // this tile's (tile, body) force slots
@@ -692,14 +717,14 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
 // The last record of an lbvp_step call, summed on its own.
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinalizeArgs a, int32_t buf)
 {
-    __shared__ double lds[FIN_THREADS / 64];
+    __shared__ double lds[2 * FIN_LANES];
     finalize_record(a, buf, lds);
 }
 
 // The same for every domain of a batch, one block each.
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize_batch(const FinalizeArgs* fins, int32_t buf)
 {
-    __shared__ double lds[FIN_THREADS / 64];
+    __shared__ double lds[2 * FIN_LANES];
     finalize_record(fins[blockIdx.x], buf, lds);
 }
 

@@ -28,12 +28,20 @@ BC = {"periodic": 0, "inflow_eq": 1, "outflow_zero_grad": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 LAYOUT_AA = 0x1
 KEEP_FIELDS = 0x1
+GRAPH = 0x2
+TUNE_LAYOUTS = 0x1
+TUNE_FRESH = 0x2
 
 SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_equilibrium",
            "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations",
            "lbvp_write_populations", "lbvp_set_launch", "lbvp_get_launch", "lbvp_step_count",
            "lbvp_synchronize", "lbvp_destroy", "lbvp_last_error", "lbvp_batch_create", "lbvp_batch_step",
-           "lbvp_batch_destroy", "lbvp_batch_last_error"]
+           "lbvp_batch_destroy", "lbvp_batch_last_error", "lbvp_tune", "lbvp_tune_last_error",
+           "lbvp_pool_create", "lbvp_pool_admit", "lbvp_pool_run_epoch", "lbvp_pool_poll",
+           "lbvp_pool_forces", "lbvp_pool_read_fields", "lbvp_pool_release", "lbvp_pool_get_stats",
+           "lbvp_pool_destroy", "lbvp_pool_last_error"]
+NO_STATUS = ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error",
+             "lbvp_tune_last_error", "lbvp_pool_last_error")
 
 
 class LbvpError(RuntimeError):
@@ -56,6 +64,23 @@ class lbvp_params(C.Structure):
 class lbvp_body(C.Structure):
     _fields_ = [("cx", C.c_double), ("cy", C.c_double), ("vx", C.c_double), ("vy", C.c_double),
                 ("omega", C.c_double)]
+
+
+class lbvp_tune_row(C.Structure):
+    _fields_ = [("layout_flags", C.c_uint32), ("vec", C.c_int32), ("block", C.c_int32),
+                ("ms_per_step", C.c_double), ("mlups", C.c_double)]
+
+
+class lbvp_pool_config(C.Structure):
+    _fields_ = [("cap_bytes", C.c_size_t), ("chunk_bytes", C.c_size_t), ("max_slots", C.c_int32),
+                ("storage", C.c_int32), ("layout_flags", C.c_uint32), ("vec", C.c_int32),
+                ("block", C.c_int32), ("max_in_flight", C.c_int32)]
+
+
+class lbvp_pool_stats(C.Structure):
+    _fields_ = [("waiting", C.c_int32), ("running", C.c_int32), ("finished", C.c_int32),
+                ("done", C.c_int32), ("free_slots", C.c_int32), ("used_bytes", C.c_size_t),
+                ("reserved_bytes", C.c_size_t), ("epochs", C.c_int64), ("node_updates", C.c_int64)]
 
 
 def _load():
@@ -88,8 +113,23 @@ def _load():
     L.lbvp_batch_destroy.argtypes = [vp]
     L.lbvp_batch_last_error.restype = C.c_char_p
     L.lbvp_batch_last_error.argtypes = [vp]
+    L.lbvp_tune.argtypes = [C.POINTER(vp), i32, i32, u32, C.POINTER(lbvp_tune_row), i32, C.POINTER(i32),
+                            C.POINTER(i32)]
+    L.lbvp_tune_last_error.restype = C.c_char_p
+    L.lbvp_tune_last_error.argtypes = []
+    L.lbvp_pool_create.argtypes = [C.POINTER(lbvp_pool_config), vp, C.POINTER(vp)]
+    L.lbvp_pool_admit.argtypes = [vp, P, vp, i32, vp, vp, vp, vp, i64, C.POINTER(i32)]
+    L.lbvp_pool_run_epoch.argtypes = [vp, i64, C.POINTER(i64)]
+    L.lbvp_pool_poll.argtypes = [vp, i32, C.POINTER(i32), i32, C.POINTER(i32)]
+    L.lbvp_pool_forces.argtypes = [vp, i32, vp, vp, i64, C.POINTER(i64), C.POINTER(i64)]
+    L.lbvp_pool_read_fields.argtypes = [vp, i32] + [vp] * 5
+    L.lbvp_pool_release.argtypes = [vp, i32]
+    L.lbvp_pool_get_stats.argtypes = [vp, C.POINTER(lbvp_pool_stats)]
+    L.lbvp_pool_destroy.argtypes = [vp]
+    L.lbvp_pool_last_error.restype = C.c_char_p
+    L.lbvp_pool_last_error.argtypes = [vp]
     for name in SYMBOLS:
-        if name not in ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error"):
+        if name not in NO_STATUS:
             getattr(L, name).restype = C.c_int
     return L
 
@@ -228,6 +268,104 @@ def lbvp_batch_destroy(batch):
         _check_batch(None, _L.lbvp_batch_destroy(batch))
 
 
+def lbvp_tune_last_error() -> str:
+    msg = _L.lbvp_tune_last_error()
+    return msg.decode() if msg else ""
+
+
+def lbvp_tune(ctxs, steps: int, flags: int = 0):
+    """Returns (rows, best): rows = [{layout_flags, vec, block, ms_per_step, mlups}]."""
+    arr = (C.c_void_p * len(ctxs))(*ctxs)
+    cap = 32
+    rows = (lbvp_tune_row * cap)()
+    n, best = C.c_int32(), C.c_int32()
+    st = _L.lbvp_tune(arr, len(ctxs), int(steps), int(flags), rows, cap, C.byref(n), C.byref(best))
+    if st != OK:
+        raise LbvpError(st, lbvp_tune_last_error())
+    out = [{"layout_flags": r.layout_flags, "vec": r.vec, "block": r.block, "ms_per_step": r.ms_per_step,
+            "mlups": r.mlups} for r in rows[: min(n.value, cap)]]
+    return out, best.value
+
+
+def lbvp_pool_last_error(pool) -> str:
+    msg = _L.lbvp_pool_last_error(pool)
+    return msg.decode() if msg else ""
+
+
+def _check_pool(pool, status: int):
+    if status != OK:
+        raise LbvpError(status, lbvp_pool_last_error(pool))
+
+
+def lbvp_pool_create(cfg: lbvp_pool_config, stream: int):
+    out = C.c_void_p()
+    _check_pool(None, _L.lbvp_pool_create(C.byref(cfg), stream, C.byref(out)))
+    return out.value
+
+
+def lbvp_pool_admit(pool, params: lbvp_params, body_id: np.ndarray, bodies: np.ndarray, rho=None, ux=None,
+                    uy=None, n_steps: int = 1) -> Optional[int]:
+    """Slot handle, or None when the pool answers E_BUSY / E_NOMEM (the caller queues)."""
+    body_id = np.ascontiguousarray(body_id, dtype=np.uint8)
+    bodies = np.ascontiguousarray(bodies, dtype=np.float64).reshape(-1, 5)
+    arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy)]
+    slot = C.c_int32()
+    nb = bodies.shape[0]
+    st = _L.lbvp_pool_admit(pool, C.byref(params), _ptr(body_id), nb, _ptr(bodies) if nb else None,
+                            *[_ptr(a) for a in arrs], int(n_steps), C.byref(slot))
+    if st in (E_BUSY, E_NOMEM):
+        return None
+    _check_pool(pool, st)
+    return slot.value
+
+
+def lbvp_pool_run_epoch(pool, max_steps: int) -> int:
+    n = C.c_int64()
+    _check_pool(pool, _L.lbvp_pool_run_epoch(pool, int(max_steps), C.byref(n)))
+    return n.value
+
+
+def lbvp_pool_poll(pool, wait: bool = False, cap: int = 4096):
+    out = (C.c_int32 * cap)()
+    n = C.c_int32()
+    _check_pool(pool, _L.lbvp_pool_poll(pool, 1 if wait else 0, out, cap, C.byref(n)))
+    return list(out[: n.value])
+
+
+def lbvp_pool_forces(pool, slot: int, n_bodies: int, cap: int):
+    out = np.zeros((max(cap, 1), max(n_bodies, 1), 2))
+    mass = np.zeros(max(cap, 1))
+    n, first = C.c_int64(), C.c_int64()
+    st = _L.lbvp_pool_forces(pool, int(slot), _ptr(out), _ptr(mass), int(cap), C.byref(n), C.byref(first))
+    res = (out[: n.value, :n_bodies].copy(), mass[: n.value].copy(), first.value)
+    if st != OK:
+        err = LbvpError(st, lbvp_pool_last_error(pool))
+        err.data = res
+        raise err
+    return res
+
+
+def lbvp_pool_read_fields(pool, slot: int, nx: int, ny: int) -> Dict[str, np.ndarray]:
+    out = [np.zeros((ny, nx)) for _ in range(5)]
+    _check_pool(pool, _L.lbvp_pool_read_fields(pool, int(slot), *[_ptr(a) for a in out]))
+    return dict(zip(("rho", "ux", "uy", "fx", "fy"), out))
+
+
+def lbvp_pool_release(pool, slot: int):
+    _check_pool(pool, _L.lbvp_pool_release(pool, int(slot)))
+
+
+def lbvp_pool_get_stats(pool) -> Dict[str, int]:
+    s = lbvp_pool_stats()
+    _check_pool(pool, _L.lbvp_pool_get_stats(pool, C.byref(s)))
+    return {name: getattr(s, name) for name, _ in lbvp_pool_stats._fields_}
+
+
+def lbvp_pool_destroy(pool):
+    if pool:
+        _check_pool(None, _L.lbvp_pool_destroy(pool))
+
+
 # ------------------------------------------------------------ convenience --
 
 def params_for(prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
@@ -271,8 +409,8 @@ class Solver:
     def footprint(self) -> int:
         return lbvp_footprint_bytes(self.params)
 
-    def step(self, n: int, keep_fields: bool = False):
-        lbvp_step(self.ctx, n, KEEP_FIELDS if keep_fields else 0)
+    def step(self, n: int, keep_fields: bool = False, graph: bool = False):
+        lbvp_step(self.ctx, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0))
 
     def forces(self, cap: Optional[int] = None):
         cap = cap or (self.params.force_capacity or 16384)
@@ -338,12 +476,82 @@ class Batch:
         self.solvers = list(solvers)
         self.handle = lbvp_batch_create([s.ctx for s in self.solvers], vec, block)
 
-    def step(self, n: int, keep_fields: bool = False):
-        lbvp_batch_step(self.handle, n, KEEP_FIELDS if keep_fields else 0)
+    def step(self, n: int, keep_fields: bool = False, graph: bool = False):
+        lbvp_batch_step(self.handle, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0))
 
     def close(self):
         if getattr(self, "handle", None):
             lbvp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tune(solvers, steps: int = 50, layouts: bool = False, fresh: bool = False):
+    """Measure every launch shape (and with ``layouts`` both layouts) for these
+    solvers run together; returns (rows, best row). The solvers are not stepped."""
+    flags = (TUNE_LAYOUTS if layouts else 0) | (TUNE_FRESH if fresh else 0)
+    rows, best = lbvp_tune([s.ctx for s in solvers], steps, flags)
+    return rows, rows[best]
+
+
+class Pool:
+    """A serving pool (continuous batching) on one torch stream. ``admit`` takes a
+    ``Problem`` and a step count and returns a slot, or None if the pool is full
+    now; ``run_epoch`` enqueues one epoch; ``poll`` lists completed slots."""
+
+    def __init__(self, storage: str = "f32", layout_aa: bool = False, cap_bytes: int = 200 * 10**9,
+                 max_slots: int = 256, vec: int = 0, block: int = 0, max_in_flight: int = 2,
+                 chunk_bytes: int = 0, stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda"):
+        self.storage = storage
+        self.flags = LAYOUT_AA if layout_aa else 0
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        cfg = lbvp_pool_config()
+        cfg.cap_bytes, cfg.chunk_bytes, cfg.max_slots = int(cap_bytes), int(chunk_bytes), int(max_slots)
+        cfg.storage, cfg.layout_flags = STORAGE[storage], self.flags
+        cfg.vec, cfg.block, cfg.max_in_flight = int(vec), int(block), int(max_in_flight)
+        self.handle = lbvp_pool_create(cfg, self.stream.cuda_stream)
+        self.probs: Dict[int, object] = {}
+        self.steps: Dict[int, int] = {}
+
+    def admit(self, prob, n_steps: int) -> Optional[int]:
+        params = params_for(prob, self.storage, 1, 0, flags=self.flags)
+        slot = lbvp_pool_admit(self.handle, params, prob.mask_or_empty(), prob.bodies_or_empty(),
+                               prob.rho_init, prob.ux_init, prob.uy_init, n_steps)
+        if slot is not None:
+            self.probs[slot] = prob
+            self.steps[slot] = n_steps
+        return slot
+
+    def run_epoch(self, max_steps: int) -> int:
+        return lbvp_pool_run_epoch(self.handle, max_steps)
+
+    def poll(self, wait: bool = False):
+        return lbvp_pool_poll(self.handle, wait)
+
+    def forces(self, slot: int):
+        prob = self.probs[slot]
+        return lbvp_pool_forces(self.handle, slot, prob.n_bodies, self.steps[slot] + 1)
+
+    def fields(self, slot: int) -> Dict[str, np.ndarray]:
+        prob = self.probs[slot]
+        return lbvp_pool_read_fields(self.handle, slot, prob.nx, prob.ny)
+
+    def release(self, slot: int):
+        lbvp_pool_release(self.handle, slot)
+        self.probs.pop(slot, None)
+        self.steps.pop(slot, None)
+
+    def stats(self) -> Dict[str, int]:
+        return lbvp_pool_get_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbvp_pool_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -37,13 +37,16 @@ def test_library_exports_every_declared_symbol(lbvp):
         getattr(lbvp.lib(), name)
 
 
-def test_struct_layouts_match_header(lbvp):
+@pytest.mark.parametrize("name", ["lbvp_params", "lbvp_body", "lbvp_tune_row", "lbvp_pool_config",
+                                  "lbvp_pool_stats"])
+def test_struct_layouts_match_header(lbvp, name):
     """Compile a C probe of the header with gcc and compare sizeof/offsetof with
     the ctypes mirrors used by the binding."""
-    fields = [f[0] for f in lbvp.lbvp_params._fields_]
+    mirror = getattr(lbvp, name)
+    fields = [f[0] for f in mirror._fields_]
     src = ["#include <stdio.h>", "#include <stddef.h>", '#include "lbvp.h"', "int main(void) {",
-           'printf("%zu\\n", sizeof(lbvp_params));', 'printf("%zu\\n", sizeof(lbvp_body));']
-    src += [f'printf("%zu\\n", offsetof(lbvp_params, {f}));' for f in fields]
+           f'printf("%zu\\n", sizeof({name}));']
+    src += [f'printf("%zu\\n", offsetof({name}, {f}));' for f in fields]
     src += ["return 0; }"]
     with tempfile.TemporaryDirectory() as d:
         c = os.path.join(d, "probe.c")
@@ -51,10 +54,35 @@ def test_struct_layouts_match_header(lbvp):
         open(c, "w").write("\n".join(src))
         subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), "-o", exe, c], check=True)
         vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()]
-    assert vals[0] == C.sizeof(lbvp.lbvp_params)
-    assert vals[1] == C.sizeof(lbvp.lbvp_body)
-    for f, off in zip(fields, vals[2:]):
-        assert getattr(lbvp.lbvp_params, f).offset == off, f
+    assert vals[0] == C.sizeof(mirror)
+    for f, off in zip(fields, vals[1:]):
+        assert getattr(mirror, f).offset == off, f
+    assert len(vals) == len(fields) + 1
+
+
+def test_pool_and_tuner_reject_bad_arguments_on_the_host(lbvp):
+    """Argument checks that return before any device call."""
+    L = lbvp.lib()
+    cfg = lbvp.lbvp_pool_config()
+    cfg.cap_bytes, cfg.max_slots, cfg.storage = 1 << 30, 4, 1
+    out = C.c_void_p()
+    assert L.lbvp_pool_create(C.byref(cfg), None, C.byref(out)) == lbvp.E_ARG      # null stream
+    fake_stream = C.c_void_p(1)                                                     # never used: checks come first
+    for field, value in [("max_slots", 0), ("storage", 9), ("layout_flags", 4), ("block", 32),
+                         ("vec", 3), ("max_in_flight", -1), ("cap_bytes", 0)]:
+        bad = lbvp.lbvp_pool_config.from_buffer_copy(cfg)
+        setattr(bad, field, value)
+        assert L.lbvp_pool_create(C.byref(bad), fake_stream, C.byref(out)) == lbvp.E_ARG, field
+        assert lbvp.lbvp_pool_last_error(None)
+    aa16 = lbvp.lbvp_pool_config.from_buffer_copy(cfg)
+    aa16.storage, aa16.layout_flags, aa16.vec = 2, lbvp.LAYOUT_AA, 8   # 2-byte AA runs one node per thread
+    assert L.lbvp_pool_create(C.byref(aa16), fake_stream, C.byref(out)) == lbvp.E_ARG
+    rows = (lbvp.lbvp_tune_row * 4)()
+    n, best = C.c_int32(), C.c_int32()
+    assert L.lbvp_tune(None, 0, 10, 0, rows, 4, C.byref(n), C.byref(best)) == lbvp.E_ARG
+    assert lbvp.lbvp_tune_last_error()
+    assert L.lbvp_pool_admit(None, None, None, 0, None, None, None, None, 1, None) == lbvp.E_ARG
+    assert L.lbvp_pool_destroy(None) == lbvp.OK
 
 
 def _params(lbvp, **kw):
