@@ -44,7 +44,7 @@ size_t arith_bytes(int32_t st) { return st == LBVP_F64 ? 8 : 4; }
 // Device arena layout. Tile tables are sized for the finest tiling any launch
 // configuration uses (one node per thread, 64-thread blocks).
 struct Layout {
-    int64_t pitch = 0, plane = 0, plane_f = 0;
+    int64_t pitch = 0, plane = 0, lstride = 0, plane_f = 0;
     int32_t max_tiles = 0, max_waves = 0;
     int64_t slot_cap = 0, capacity = 0;
     int32_t max_bodies = 0;
@@ -135,7 +135,8 @@ Layout make_layout(const lbvp_params* p)
     Layout L;
     const size_t es = storage_bytes(p->storage), rs = arith_bytes(p->storage);
     L.pitch = (int64_t)align_up((size_t)p->nx, 64);
-    L.plane = (int64_t)align_up((size_t)(p->ny * L.pitch), 2048);
+    L.plane = L.pitch;          // population rows of a lattice row back to back
+    L.lstride = 9 * L.pitch;
     L.plane_f = (int64_t)p->ny * L.pitch;
     for (int vec : {1, vector_width(p->storage)})
         for (int block : {64, 128, 256}) {
@@ -151,7 +152,7 @@ Layout make_layout(const lbvp_params* p)
     L.stage_rows = std::max<int64_t>(1, (int64_t)(stage_bytes / row_bytes));
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t at = o; o = align_up(o + bytes, ALIGN); return at; };
-    const size_t lat_bytes = 9 * (size_t)L.plane * es;
+    const size_t lat_bytes = (size_t)p->ny * (size_t)L.lstride * es;
     const bool aa = (p->flags & LBVP_LAYOUT_AA) != 0;
     L.lat[0] = take(lat_bytes);
     L.lat[1] = aa ? L.lat[0] : take(lat_bytes);   // the AA pattern streams in place
@@ -369,6 +370,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.east = p.bc_east;
     a.pitch = L.pitch;
     a.plane = L.plane;
+    a.lstride = L.lstride;
     a.plane_f = L.plane_f;
     a.rho0 = (R)p.rho0;
     a.om_p = (R)(1.0 / p.tau_plus);
@@ -483,6 +485,7 @@ ConvArgs conv_args(lbvp_ctx* c, int32_t row0, int32_t rows)
     a.row0 = row0;
     a.pitch = c->L.pitch;
     a.plane = c->L.plane;
+    a.lstride = c->L.lstride;
     a.plane_f = c->L.plane_f;
     a.rho0 = c->p.rho0;
     a.swap = c->aa() ? 1 : 0;
@@ -504,6 +507,7 @@ hipError_t refresh_aa_ghosts(lbvp_ctx* c)
     if (!g.west_outflow && !g.east_outflow) return hipSuccess;
     g.pitch = c->L.pitch;
     g.plane = c->L.plane;
+    g.lstride = c->L.lstride;
     g.ghost_w = c->at<char>(c->L.ghost_w);
     g.ghost_e = c->at<char>(c->L.ghost_e);
     return launch_aa_ghosts(c->p.storage, c->at<char>(c->L.lat[0]), g, c->stream);

@@ -52,8 +52,9 @@ struct StepArgs {
     int32_t west, east;
     int32_t part_buf;   // partial buffer a recording step writes
     int32_t fin_buf;    // partial buffer whose record block 0 sums first, or -1
-    int64_t pitch;      // elements per row (lattice, mask and fields)
-    int64_t plane;      // elements between population planes
+    int64_t pitch;      // elements per row of one population, of the mask and of a field
+    int64_t plane;      // elements between the rows of populations q and q + 1 (= pitch)
+    int64_t lstride;    // elements between lattice rows j and j + 1 (= 9 pitch)
     int64_t plane_f;    // elements between field planes
     R rho0;
     R om_p, om_m;       // 1/tau_plus, 1/tau_minus
@@ -90,7 +91,7 @@ struct BatchLaunch {
 struct GhostArgs {
     int32_t nx, ny;
     int32_t west_outflow, east_outflow;
-    int64_t pitch, plane;
+    int64_t pitch, plane, lstride;
     void* ghost_w;
     void* ghost_e;
 };
@@ -101,7 +102,7 @@ enum StepMode : int32_t { MODE_PULL = 0, MODE_AA_PUSH = 1, MODE_AA_LOCAL = 2 };
 
 struct ConvArgs {
     int32_t nx, rows, row0;
-    int64_t pitch, plane, plane_f;
+    int64_t pitch, plane, lstride, plane_f;
     double rho0;
     int32_t swap;       // AA layout: population q lives in slot opp(q)
     const double* rho;  // staged [rows][nx] or null

@@ -1,8 +1,12 @@
 // lbvp_kernels.hip -- gfx950 kernels of the fused D2Q9 TRT-VP time step.
 //
-// Data layout in HBM (structure of arrays): population a of node (i, j) lives at
-// lattice[a * plane + j * pitch + i]; pitch is a multiple of 64 elements, so
-// every row starts on a 256-byte boundary. All storage types hold the
+// Data layout in HBM (rows of structures of arrays): population a of node (i, j)
+// lives at lattice[j * lstride + a * plane + i] with plane = pitch and
+// lstride = 9 pitch: the nine population rows of a lattice row lie back to back.
+// pitch is a multiple of 64 elements, so every population row starts on a
+// 128-byte (2-byte types) or 256-byte boundary. A tile's loads and stores then
+// stay within a few neighbouring lattice rows of memory instead of touching
+// nine planes a whole domain apart, which HBM serves measurably faster. All storage types hold the
 // weight-normalized deviation h_a = (f_a - w_a rho0) / w_a. Its size is set by
 // the flow (|h| ~ 3|u|) and is the same for every direction, and the equilibrium
 // in these units carries no weight at all,
@@ -440,20 +444,22 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 
     const int jm = (j == 0) ? a.ny - 1 : j - 1;     // rows are periodic
     const int jp = (j == a.ny - 1) ? 0 : j + 1;
-    const int64_t r0 = (int64_t)j * a.pitch, rm = (int64_t)jm * a.pitch, rp = (int64_t)jp * a.pitch;
-    // pull source row of each direction (ey = 0 -> j, +1 -> j - 1, -1 -> j + 1)
-    // and push target row (the opposite)
-    const int64_t row_of[9] = {r0, r0, rm, r0, rp, rm, rm, rp, rp};
+    const int64_t r0 = (int64_t)j * a.pitch;   // mask and fields
+    const int64_t l0 = (int64_t)j * a.lstride, lm = (int64_t)jm * a.lstride, lp = (int64_t)jp * a.lstride;
+    // lattice pull source row of each direction (ey = 0 -> j, +1 -> j - 1,
+    // -1 -> j + 1) and push target row (the opposite)
+    const int64_t row_of[9] = {l0, l0, lm, l0, lp, lm, lm, lp, lp};
     const int row_idx[9] = {j, j, jm, j, jp, jm, jm, jp, jp};
-    const int64_t row_to[9] = {r0, r0, rp, r0, rm, rp, rp, rm, rm};
+    const int64_t row_to[9] = {l0, l0, lp, l0, lm, lp, lp, lm, lm};
     const int64_t P = a.plane;
 
     // Source plane of direction q: the pull and the AA local step read plane q,
     // the AA push step the neighbour's opposite slot. Dword-or-wider elements
     // (and single nodes) take the x-shifted directions as single accesses one
     // element off alignment (columns i0 - 1 .. or i0 + 1 ..; both stay inside
-    // the allocation: plane 0 is never shifted and a row's padding is followed
-    // by the next row or plane). FP16/BF16 vectors load aligned and shift
+    // the allocation: population 0 of row 0 is never shifted left, the last
+    // population row (8 of row ny - 1) is never shifted right, and every other
+    // population row is preceded and followed by another). FP16/BF16 vectors load aligned and shift
     // through lane shuffles (pull only).
     constexpr bool kShifted = sizeof(S) >= 4 || V == 1;
     static_assert(MODE == PULL || kShifted, "the AA pattern needs dword-or-wider elements or one node per thread");
@@ -464,7 +470,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         for (int q = 0; q < 9; ++q) {
             S raw[V];
             if constexpr (MODE == AA_LOCAL) {
-                load_vec<S, V>(src + q * P + r0 + i0, raw);
+                load_vec<S, V>(src + q * P + l0 + i0, raw);
             } else {
                 const int pq = (MODE == AA_PUSH) ? OPP[q] : q;
                 if constexpr (kShifted) {
@@ -556,13 +562,13 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         // own node: plane q (pull) or plane opp(q) (AA local)
         if (n_own == V) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) store_vec<S, V>(dst + (MODE == PULL ? q : OPP[q]) * P + r0 + i0, out[q]);
+            for (int q = 0; q < 9; ++q) store_vec<S, V>(dst + (MODE == PULL ? q : OPP[q]) * P + l0 + i0, out[q]);
         } else if (n_own > 0) {  // ragged end of a row
 #pragma unroll
             for (int k = 0; k < V; ++k)
                 if (k < n_own)
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) dst[(MODE == PULL ? q : OPP[q]) * P + r0 + i0 + k] = out[q][k];
+                    for (int q = 0; q < 9; ++q) dst[(MODE == PULL ? q : OPP[q]) * P + l0 + i0 + k] = out[q][k];
         }
         if constexpr (MODE == AA_LOCAL) {
             // the zero-gradient ghost columns that the next push step pulls from
@@ -616,7 +622,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
                         for (int m = 0; m < 3; ++m) {
                             const int q = EXP[m];
-                            if (a.west == SIDE_INFLOW_EQ) dst[q * P + r0] = enc<S>(a.feq_in[q]);
+                            if (a.west == SIDE_INFLOW_EQ) dst[q * P + l0] = enc<S>(a.feq_in[q]);
                             else dst[q * P + row_to[q]] = out[q][k];
                         }
                     }
@@ -624,7 +630,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
                         for (int m = 0; m < 3; ++m) {
                             const int q = EXM[m];
-                            if (a.east == SIDE_INFLOW_EQ) dst[q * P + r0 + i] = enc<S>(a.feq_in[q]);
+                            if (a.east == SIDE_INFLOW_EQ) dst[q * P + l0 + i] = enc<S>(a.feq_in[q]);
                             else dst[q * P + row_to[q] + i] = out[q][k];
                         }
                     }
@@ -751,10 +757,11 @@ __global__ void __launch_bounds__(256) k_init(S* lat, typename Arith<S>::R* fiel
     const double uy = a.uy ? a.uy[k] : 0.0;
     const double uu = ux * ux + uy * uy;
     const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
+    const int64_t lo = (int64_t)(a.row0 + jl) * a.lstride + i;
     for (int q = 0; q < 9; ++q) {
         const double eu = EX_ALL[q] * ux + EY_ALL[q] * uy;
         const double h = (rho - a.rho0) + rho * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        lat[(a.swap ? OPP_ALL[q] : q) * a.plane + o] = enc<S>((R)h);
+        lat[(a.swap ? OPP_ALL[q] : q) * a.plane + lo] = enc<S>((R)h);
     }
     if (fields) {
         fields[o] = (R)rho;
@@ -772,9 +779,9 @@ __global__ void __launch_bounds__(256) k_decode(const S* lat, ConvArgs a)
     const int64_t n = (int64_t)a.rows * a.nx;
     if (k >= n) return;
     const int jl = (int)(k / a.nx), i = (int)(k - (int64_t)jl * a.nx);
-    const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
+    const int64_t lo = (int64_t)(a.row0 + jl) * a.lstride + i;
     for (int q = 0; q < 9; ++q)
-        a.pops[q * n + k] = W_ALL[q] * ((double)dec(lat[(a.swap ? OPP_ALL[q] : q) * a.plane + o]) + a.rho0);
+        a.pops[q * n + k] = W_ALL[q] * ((double)dec(lat[(a.swap ? OPP_ALL[q] : q) * a.plane + lo]) + a.rho0);
 }
 
 template <typename S>
@@ -785,9 +792,9 @@ __global__ void __launch_bounds__(256) k_encode(S* lat, ConvArgs a)
     const int64_t n = (int64_t)a.rows * a.nx;
     if (k >= n) return;
     const int jl = (int)(k / a.nx), i = (int)(k - (int64_t)jl * a.nx);
-    const int64_t o = (int64_t)(a.row0 + jl) * a.pitch + i;
+    const int64_t lo = (int64_t)(a.row0 + jl) * a.lstride + i;
     for (int q = 0; q < 9; ++q)
-        lat[(a.swap ? OPP_ALL[q] : q) * a.plane + o] = enc<S>((R)(a.pops[q * n + k] / W_ALL[q] - a.rho0));
+        lat[(a.swap ? OPP_ALL[q] : q) * a.plane + lo] = enc<S>((R)(a.pops[q * n + k] / W_ALL[q] - a.rho0));
 }
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
@@ -799,7 +806,7 @@ __global__ void __launch_bounds__(256) k_aa_ghosts(const S* lat, GhostArgs a)
 {
     const int y = blockIdx.x * blockDim.x + threadIdx.x;
     if (y >= a.ny) return;
-    const int64_t row = (int64_t)y * a.pitch;
+    const int64_t row = (int64_t)y * a.lstride;
     const int exp_q[3] = {1, 5, 8}, exm_q[3] = {3, 6, 7};
     for (int m = 0; m < 3; ++m) {
         if (a.west_outflow)
