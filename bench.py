@@ -263,6 +263,15 @@ def summarize_trace(db: str, out: str, command: str):
     for r in rows[:12]:
         lines.append(f"| `{r['name'][:100]}` | {r['total_calls']} | {r['average']:.2f} | "
                      f"{r['total_duration']:.1f} | {r['percentage']:.1f}% |")
+    if rows:   # per-dispatch spread and resources of the dominant kernel
+        top = rows[0]["name"]
+        ks = [k for k in _db_rows(db, "kernels") if k["name"] == top]
+        d = sorted(k["duration"] / 1e3 for k in ks)
+        k0 = ks[0]
+        lines += ["", f"Dominant kernel: {len(d)} dispatches, duration median {d[len(d) // 2]:.2f} us, "
+                      f"min {d[0]:.2f} us, max {d[-1]:.2f} us; {k0['grid_x']} work-items in {k0['workgroup_x']}-thread "
+                      f"workgroups, {k0['vgpr_count']} VGPRs, {k0['accum_vgpr_count']} AGPRs, "
+                      f"{k0['sgpr_count']} SGPRs, {k0['lds_size']} B LDS, {k0['scratch_size']} B scratch."]
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))
