@@ -188,8 +188,9 @@ lbvp_status lbvp_read_populations(lbvp_ctx* ctx, double* g);
  * odd step count. */
 lbvp_status lbvp_write_populations(lbvp_ctx* ctx, const double* g);
 
-/* Launch configuration of the step kernel: vec nodes per thread (1, or the
- * storage type's 16-byte width: 2 for F64, 4 for F32, 8 for F16/BF16) and block
+/* Launch configuration of the step kernel: vec nodes per thread (1, the
+ * storage type's 16-byte width: 2 for F64, 4 for F32, 8 for F16/BF16, or 4 for
+ * F16/BF16; 2-byte types in the AA layout take 1 only) and block
  * threads per workgroup (64, 128 or 256). Populations and fields do not depend
  * on it; the force and mass records do only through the per-tile partial sums
  * (each record is then summed in an order fixed by the data, independent of the

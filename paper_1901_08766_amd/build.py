@@ -19,6 +19,10 @@ HIPCC_FLAGS = [
     "-shared",
     # packed FP32 instructions stay off: plain scalar/float2 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # multiply-adds fuse only within one source expression: the rounding of every
+    # result is then fixed by the source, not by how a kernel variant happens to be
+    # scheduled, so batched, single-domain, recording and graph launches agree bitwise
+    "-ffp-contract=on",
     "-Wall",
 ]
 

@@ -82,13 +82,22 @@ Launch make_launch(int32_t nx, int32_t ny, int32_t vec, int32_t block)
     return l;
 }
 
-// Vector widths a launch may use: 1 always; the 16-byte width except for the
-// AA layout with 2-byte storage (its push step moves single elements).
+// Vector widths a launch may use: 1 always; the 16-byte width, and for 2-byte
+// storage also 4 nodes (8 bytes), except in the AA layout with 2-byte storage
+// (its push step moves single elements).
+std::vector<int32_t> vec_options(int32_t storage, uint32_t flags)
+{
+    const bool two_byte = storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV;
+    if (two_byte && (flags & LBVP_LAYOUT_AA)) return {1};
+    if (two_byte) return {1, 4, vector_width(storage)};
+    return {1, vector_width(storage)};
+}
+
 bool vec_allowed(int32_t storage, uint32_t flags, int32_t vec)
 {
-    if (vec == 1) return true;
-    if (vec != vector_width(storage)) return false;
-    return !((flags & LBVP_LAYOUT_AA) && (storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV));
+    for (int32_t v : vec_options(storage, flags))
+        if (v == vec) return true;
+    return false;
 }
 
 // Default launch: the 16-byte vector form when it still gives at least 8
@@ -138,7 +147,7 @@ Layout make_layout(const lbvp_params* p)
     L.plane = L.pitch;          // population rows of a lattice row back to back
     L.lstride = 9 * L.pitch;
     L.plane_f = (int64_t)p->ny * L.pitch;
-    for (int vec : {1, vector_width(p->storage)})
+    for (int vec : vec_options(p->storage, p->flags))
         for (int block : {64, 128, 256}) {
             const Launch l = make_launch(p->nx, p->ny, vec, block);
             L.max_tiles = std::max(L.max_tiles, l.n_tiles);
@@ -849,10 +858,7 @@ lbvp_status tune_layout(const std::vector<lbvp_ctx*>& m, uint32_t layout, int32_
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return finish(LBVP_E_DEVICE, "hipEventCreate failed");
     const int32_t storage = m[0]->p.storage;
-    std::vector<int32_t> vecs{1};
-    if (vec_allowed(storage, layout, vector_width(storage)) && vector_width(storage) != 1)
-        vecs.push_back(vector_width(storage));
-    for (int32_t vec : vecs)
+    for (int32_t vec : vec_options(storage, layout))
         for (int32_t block : {64, 128, 256}) {
             lbvp_status st = LBVP_OK;
             if (s.size() == 1) st = lbvp_set_launch(s[0], vec, block);
@@ -1213,8 +1219,8 @@ lbvp_status lbvp_set_launch(lbvp_ctx* c, int32_t vec, int32_t block)
 {
     if (check_ctx(c)) return LBVP_E_ARG;
     if (!vec_allowed(c->p.storage, c->p.flags, vec))
-        return c->fail(LBVP_E_ARG, "vec must be 1 or the storage type's 16-byte vector width "
-                                   "(1 only for 2-byte storage in the AA layout)");
+        return c->fail(LBVP_E_ARG, "vec must be 1, the storage type's 16-byte vector width or, for "
+                                   "2-byte storage, 4 (1 only for 2-byte storage in the AA layout)");
     if (block != 64 && block != 128 && block != 256) return c->fail(LBVP_E_ARG, "block must be 64, 128 or 256");
     if (c->launch.vec == vec && c->launch.block == block) return LBVP_OK;
     if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");

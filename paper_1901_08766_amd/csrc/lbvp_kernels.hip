@@ -40,6 +40,8 @@
 // themselves, with the domain sides resolved there.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbvp_internal.h"
 
 namespace lbvp {
@@ -50,6 +52,14 @@ __device__ __forceinline__ double dec(double v) { return v; }
 __device__ __forceinline__ float dec(float v) { return v; }
 __device__ __forceinline__ float dec(_Float16 v) { return (float)v; }
 __device__ __forceinline__ float dec(__bf16 v) { return (float)v; }
+
+// A loaded element kept in the storage type (LV = S) or decoded (LV = R).
+template <typename LV, typename S>
+__device__ __forceinline__ LV as_lv(S x)
+{
+    if constexpr (std::is_same<LV, S>::value) return x;
+    else return dec(x);
+}
 
 template <typename S, typename R>
 __device__ __forceinline__ S enc(R v) { return (S)v; }  // round to nearest even
@@ -138,6 +148,16 @@ __device__ __forceinline__ void load_mask(const uint8_t* p, int (&out)[V])
 }
 
 // ------------------------------------------------------------ reductions --
+// Dynamic LDS of a recording step launch: [2][V][blockDim] values of the
+// arithmetic type (the penalization force of every node of the tile).
+template <typename R>
+__device__ __forceinline__ R* dyn_lds()
+{
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    return reinterpret_cast<R*>(lds_dyn);
+}
+
+
 // Sum over the block in a fixed order (deterministic): wavefront shuffles, then
 // the per-wavefront sums in wavefront order. lds holds one double per wavefront
 // and is reused across calls; every thread gets the result.
@@ -463,7 +483,11 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     // through lane shuffles (pull only).
     constexpr bool kShifted = sizeof(S) >= 4 || V == 1;
     static_assert(MODE == PULL || kShifted, "the AA pattern needs dword-or-wider elements or one node per thread");
-    R v[9][V];
+    // The lane-shuffle form (2-byte types, V > 1) keeps the loaded values in the
+    // storage type and decodes each node's nine just before its collision, so
+    // that the packed loads, not 9 V decoded floats, stay live across the tile.
+    using LV = typename std::conditional<kShifted, R, S>::type;
+    LV v[9][V];
     int body[V];
     if (act) {
 #pragma unroll
@@ -482,14 +506,14 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 }
             }
 #pragma unroll
-            for (int k = 0; k < V; ++k) v[q][k] = dec(raw[k]);
+            for (int k = 0; k < V; ++k) v[q][k] = as_lv<LV>(raw[k]);
         }
         load_mask<V>(a.mask + r0 + i0, body);
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
 #pragma unroll
-            for (int k = 0; k < V; ++k) v[q][k] = R(0);
+            for (int k = 0; k < V; ++k) v[q][k] = LV{};
 #pragma unroll
         for (int k = 0; k < V; ++k) body[k] = 0;
     }
@@ -499,8 +523,8 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     if constexpr (!kShifted) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            left[m] = __shfl_up(v[EXP[m]][V - 1], 1, 64);
-            right[m] = __shfl_down(v[EXM[m]][0], 1, 64);
+            left[m] = __shfl_up(dec(v[EXP[m]][V - 1]), 1, 64);
+            right[m] = __shfl_down(dec(v[EXM[m]][0]), 1, 64);
         }
         // lanes that start a wavefront or a tile row load the end element themselves
         if (act && (lane == 0 || lc == 0)) {
@@ -530,12 +554,12 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     for (int k = 0; k < V; ++k) {
         R f[9];
 #pragma unroll
-        for (int q = 0; q < 9; ++q) f[q] = v[q][k];
+        for (int q = 0; q < 9; ++q) f[q] = dec(v[q][k]);
         if constexpr (!kShifted) {
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                f[EXP[m]] = (k == 0) ? left[m] : v[EXP[m]][k > 0 ? k - 1 : 0];
-                f[EXM[m]] = (k == V - 1) ? right[m] : v[EXM[m]][k < V - 1 ? k + 1 : 0];
+                f[EXP[m]] = (k == 0) ? left[m] : dec(v[EXP[m]][k > 0 ? k - 1 : 0]);
+                f[EXM[m]] = (k == V - 1) ? right[m] : dec(v[EXM[m]][k < V - 1 ? k + 1 : 0]);
             }
         }
         const int i = i0 + k;
@@ -554,6 +578,15 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         fl_uy[k] = n.uy;
         fl_fx[k] = n.fvx;
         fl_fy[k] = n.fvy;
+        if constexpr (RECORD) {
+            // penalization force of every node to LDS (tiles holding solid nodes
+            // only), summed per body after the stores
+            if (s1 > s0) {
+                R* fv = dyn_lds<R>();
+                fv[k * (int)blockDim.x + (int)threadIdx.x] = n.fvx;
+                fv[(V + k) * (int)blockDim.x + (int)threadIdx.x] = n.fvy;
+            }
+        }
         if (k < n_own) tile_drho += (double)n.drho;
     }
 
@@ -662,15 +695,21 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) wm += __shfl_down(wm, off, 64);
         if (lane == 0) mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
-        // forces: only tiles that hold solid nodes (uniform across the block)
+        // forces: only tiles that hold solid nodes (uniform across the block);
+        // the body ids are read again (cache hit) rather than kept live
+        int bid[V];
+#pragma unroll
+        for (int k = 0; k < V; ++k) bid[k] = 0;
+        if (s1 > s0 && act) load_mask<V>(a.mask + r0 + i0, bid);
+        const R* fv = dyn_lds<R>();
         for (int s = s0; s < s1; ++s) {
             const int b = a.slot_body[s];
             double px = 0.0, py = 0.0;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
-                if (k < n_own && body[k] == b) {
-                    px -= (double)fl_fx[k];
-                    py -= (double)fl_fy[k];
+                if (k < n_own && bid[k] == b) {
+                    px -= (double)fv[k * (int)blockDim.x + (int)threadIdx.x];
+                    py -= (double)fv[(V + k) * (int)blockDim.x + (int)threadIdx.x];
                 }
             }
             const double sx = block_sum(px, lds);
@@ -816,15 +855,22 @@ __global__ void __launch_bounds__(256) k_aa_ghosts(const S* lat, GhostArgs a)
     }
 }
 
+template <typename R>
+size_t record_lds_bytes(int v, int block)
+{
+    return 2 * (size_t)v * (size_t)block * sizeof(R);
+}
+
 template <typename S, int V>
 hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const StepArgs<typename Arith<S>::R>& a,
                   hipStream_t s)
 {
     const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD)), block((unsigned)a.block);
+    const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, a.block);
     if (mode == PULL) {
         if (record) {
-            if (fields) hipLaunchKernelGGL((k_step<S, V, true, true>), grid, block, 0, s, in, out, a);
-            else hipLaunchKernelGGL((k_step<S, V, true, false>), grid, block, 0, s, in, out, a);
+            if (fields) hipLaunchKernelGGL((k_step<S, V, true, true>), grid, block, lds, s, in, out, a);
+            else hipLaunchKernelGGL((k_step<S, V, true, false>), grid, block, lds, s, in, out, a);
         } else {
             if (fields) hipLaunchKernelGGL((k_step<S, V, false, true>), grid, block, 0, s, in, out, a);
             else hipLaunchKernelGGL((k_step<S, V, false, false>), grid, block, 0, s, in, out, a);
@@ -834,16 +880,16 @@ hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const
     if constexpr (sizeof(S) >= 4 || V == 1) {
         if (mode == AA_PUSH) {
             if (record) {
-                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, true>), grid, block, 0, s, out, a);
-                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, false>), grid, block, 0, s, out, a);
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, true>), grid, block, lds, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, false>), grid, block, lds, s, out, a);
             } else {
                 if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, true>), grid, block, 0, s, out, a);
                 else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, false>), grid, block, 0, s, out, a);
             }
         } else {
             if (record) {
-                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, true>), grid, block, 0, s, out, a);
-                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, false>), grid, block, 0, s, out, a);
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, true>), grid, block, lds, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, false>), grid, block, lds, s, out, a);
             } else {
                 if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, true>), grid, block, 0, s, out, a);
                 else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, false>), grid, block, 0, s, out, a);
@@ -866,6 +912,9 @@ hipError_t step_typed(int mode, bool record, bool fields, const void* src, void*
     constexpr int VW = 16 / (int)sizeof(S);
     if (a.vec == VW) return step_v<S, VW>(mode, record, fields, in, out, a, s);
     if (a.vec == 1) return step_v<S, 1>(mode, record, fields, in, out, a, s);
+    if constexpr (sizeof(S) == 2) {   // 2-byte types also run 4 nodes (8 bytes) per thread
+        if (a.vec == 4) return step_v<S, 4>(mode, record, fields, in, out, a, s);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -873,9 +922,10 @@ template <typename S, int V, int MODE>
 hipError_t batch_mode(bool record, bool fields, const BatchLaunch& b, int32_t block, hipStream_t s)
 {
     const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD)), blk((unsigned)block);
+    const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, block);
     if (record) {
-        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true>), grid, blk, 0, s, b);
-        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false>), grid, blk, 0, s, b);
+        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true>), grid, blk, lds, s, b);
+        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false>), grid, blk, lds, s, b);
     } else {
         if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, true>), grid, blk, 0, s, b);
         else hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, false>), grid, blk, 0, s, b);
@@ -902,6 +952,9 @@ hipError_t batch_typed(int32_t vec, int32_t mode, bool record, bool fields, cons
     constexpr int VW = 16 / (int)sizeof(S);
     if (vec == VW) return batch_v<S, VW>(mode, record, fields, b, block, s);
     if (vec == 1) return batch_v<S, 1>(mode, record, fields, b, block, s);
+    if constexpr (sizeof(S) == 2) {
+        if (vec == 4) return batch_v<S, 4>(mode, record, fields, b, block, s);
+    }
     return hipErrorInvalidValue;
 }
 

@@ -242,7 +242,9 @@ lbvp_status lbvp_pool_create(const lbvp_pool_config* cfg, void* hip_stream, lbvp
     if (why.empty()) {
         if (c.vec == 0) c.vec = two_byte_aa ? 1 : vw;
         if (c.block == 0) c.block = 256;
-        if (c.vec != 1 && (c.vec != vw || two_byte_aa)) why = "vec must be 1 or the storage type's vector width";
+        const bool two_byte = c.storage == LBVP_F16_DEV || c.storage == LBVP_BF16_DEV;
+        const bool ok = c.vec == 1 || (!two_byte_aa && (c.vec == vw || (two_byte && c.vec == 4)));
+        if (!ok) why = "vec must be 1, the storage type's vector width or, for 2-byte storage, 4";
     }
     if (!why.empty()) {
         g_pool_error = why;

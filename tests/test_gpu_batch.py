@@ -33,11 +33,13 @@ def _members():
 VW = {"f64": 2, "f32": 4, "f16": 8, "bf16": 8}
 
 
-@pytest.mark.parametrize("aa", [False, True], ids=["pull", "aa"])
+@pytest.mark.parametrize("aa,vec4", [(False, False), (True, False), (False, True)], ids=["pull", "aa", "pull-v4"])
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
-def test_batched_equals_alone(lbvp, storage, aa):
+def test_batched_equals_alone(lbvp, storage, aa, vec4):
+    if vec4 and storage not in ("f16", "bf16"):
+        pytest.skip("the 4-node form is for 2-byte storage")
     flags = lbvp.LAYOUT_AA if aa else 0
-    vec = 1 if (aa and storage in ("f16", "bf16")) else VW[storage]
+    vec = 1 if (aa and storage in ("f16", "bf16")) else (4 if vec4 else VW[storage])
     steps = 13
     probs = _members()
     stream = torch.cuda.Stream()
@@ -115,13 +117,14 @@ def test_narrow_tiles_shuffle_rows(lbvp, storage):
     thread (no shuffles) must give bitwise the same populations."""
     prob = inputs.random_state_problem(67, 45, seed=51, n_disks=3)
     out = []
-    for launch in ((1, 64), (8, 256), (8, 64)):
+    for launch in ((1, 64), (8, 256), (8, 64), (4, 256), (4, 64)):
         s = lbvp.Solver(prob, storage=storage, force_every=0)
         s.set_launch(*launch)
         s.step(20)
         out.append(s.populations())
         s.close()
-    assert np.array_equal(out[0], out[1]) and np.array_equal(out[0], out[2])
+    for o in out[1:]:
+        assert np.array_equal(out[0], o)
 
 
 def test_ensemble_batch_runs(lbvp):

@@ -210,19 +210,21 @@ def test_edge_cases(lbvp):
     assert np.abs(s.populations() - g).max() <= 1e-7
 
 
-@pytest.mark.parametrize("storage,vec", [("f32", 4), ("f16", 8), ("bf16", 8)])
-def test_launch_shapes_bitwise_equal(lbvp, storage, vec):
+@pytest.mark.parametrize("storage,vecs", [("f32", (4,)), ("f16", (8, 4)), ("bf16", (8, 4))])
+def test_launch_shapes_bitwise_equal(lbvp, storage, vecs):
     """The per-node arithmetic does not depend on the launch shape: one node per
-    thread and the 16-byte vector form give bitwise identical populations."""
+    thread and the vector forms (16 bytes; 8 bytes for 2-byte types) give bitwise
+    identical populations."""
     prob = inputs.random_state_problem(300, 41, seed=31, n_disks=4)
     outs = []
-    for launch in ((1, 64), (vec, 256), (vec, 64)):
+    for launch in [(1, 64)] + [(v, b) for v in vecs for b in (256, 128, 64)]:
         s = lbvp.Solver(prob, storage=storage, force_every=0)
         s.set_launch(*launch)
         s.step(30)
         outs.append(s.populations())
         s.close()
-    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    for o in outs[1:]:
+        assert np.array_equal(outs[0], o)
 
 
 @pytest.mark.parametrize("launch", [(1, 64), (4, 256)], ids=["v1b64", "v4b256"])
