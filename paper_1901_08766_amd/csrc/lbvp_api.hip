@@ -100,16 +100,19 @@ bool vec_allowed(int32_t storage, uint32_t flags, int32_t vec)
     return false;
 }
 
-// Default launch: the 16-byte vector form when it still gives at least 8
+// Default launch: the vector form (16 bytes; 8 bytes and 128-thread blocks for
+// 2-byte types, which measure fastest there) when it still gives at least 8
 // wavefronts per SIMD (1024 SIMDs: 256 CUs x 4), else one node per thread;
 // small grids use 64-thread blocks to spread over more CUs.
 Launch default_launch(int32_t nx, int32_t ny, int32_t storage, uint32_t flags)
 {
     const int64_t n = (int64_t)nx * ny;
-    const int vw = vec_allowed(storage, flags, vector_width(storage)) ? vector_width(storage) : 1;
+    const bool two_byte = storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV;
+    const int wide = two_byte ? 4 : vector_width(storage);
+    const int vw = vec_allowed(storage, flags, wide) ? wide : 1;
     const int vec = (n / (64 * vw) >= 8 * 1024) ? vw : 1;
     const int64_t waves = n / (64 * vec);
-    const int block = waves >= 4096 ? MAX_BLOCK : MIN_BLOCK;
+    const int block = waves >= 4096 ? (two_byte ? 128 : MAX_BLOCK) : MIN_BLOCK;
     return make_launch(nx, ny, vec, block);
 }
 
