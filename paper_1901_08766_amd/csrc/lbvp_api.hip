@@ -761,6 +761,8 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
         L.flip = b->aa ? 0 : (int32_t)(k & 1);
         L.part_buf = (int32_t)(*recs & 1);
         L.fin_buf = pending ? pending_buf : -1;
+        L.n_domains = (int32_t)b->members.size();
+        L.n_fin = L.fin_buf >= 0 ? (L.n_domains + N_XCD - 1) / N_XCD * N_XCD : 0;
         hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, L, b->stream);
         if (e != hipSuccess) return b->hip_fail(e, "batched step launch");
         pending = record;

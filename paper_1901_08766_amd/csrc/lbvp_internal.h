@@ -51,7 +51,7 @@ struct StepArgs {
     int32_t tiles_x, n_tiles, tiles_per_xcd;
     int32_t west, east;
     int32_t part_buf;   // partial buffer a recording step writes
-    int32_t fin_buf;    // partial buffer whose record block 0 sums first, or -1
+    int32_t fin_buf;    // partial buffer whose record a leading block of the launch sums, or -1
     int64_t pitch;      // elements per row of one population, of the mask and of a field
     int64_t plane;      // elements between the rows of populations q and q + 1 (= pitch)
     int64_t lstride;    // elements between lattice rows j and j + 1 (= 9 pitch)
@@ -83,6 +83,9 @@ struct BatchLaunch {
     int32_t total_tiles, tiles_per_xcd;
     int32_t flip;                   // lattice parity of this step relative to StepArgs::cur
     int32_t part_buf, fin_buf;      // as in StepArgs, for every domain of the batch
+    int32_t n_domains;
+    int32_t n_fin;                  // leading blocks that sum the fin_buf records: n_domains
+                                    // rounded up to a multiple of 8, or 0 if fin_buf < 0
     const int32_t* tile_domain;     // [total_tiles] domain of each tile
     const int32_t* tile_start;      // [n_domains] first tile of each domain
     const void* args;               // StepArgs<R>[n_domains]

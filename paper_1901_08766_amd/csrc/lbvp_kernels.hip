@@ -430,24 +430,24 @@ __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, 
 }
 
 // ------------------------------------------------------------ the step --
-// Workgroups are dealt to the 8 XCDs round-robin by block id: block b takes
-// tile (b % 8) * per_xcd + b / 8, so each XCD sweeps a contiguous run of tiles.
-__device__ __forceinline__ int xcd_tile(int per_xcd)
+// Workgroups are dealt to the 8 XCDs round-robin by block id: block b (counted
+// from first_block) takes tile (b % 8) * per_xcd + b / 8, so each XCD sweeps a
+// contiguous run of tiles.
+__device__ __forceinline__ int xcd_tile(int per_xcd, int first_block)
 {
-    return (int)(blockIdx.x % N_XCD) * per_xcd + (int)(blockIdx.x / N_XCD);
+    const int blk = (int)blockIdx.x - first_block;   // first_block is a multiple of 8
+    return (blk % N_XCD) * per_xcd + blk / N_XCD;
 }
 
 // One block updates tile t of a domain: tile_rows rows of tile_w nodes, V
-// consecutive nodes per thread. part_buf / fin_buf: the partial buffer this
-// step's record writes, and the one whose record tile 0 first sums (or -1).
+// consecutive nodes per thread. part_buf: the partial buffer this step's record
+// writes (the previous record is summed by leading blocks of the same launch).
+// lds: the kernel's 2 FIN_LANES doubles.
 template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
 __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a, int t,
-                                          int part_buf, int fin_buf)
+                                          int part_buf, double* lds)
 {
     using R = typename Arith<S>::R;
-    __shared__ double lds[2 * FIN_LANES];   // the record sums, then the per-wavefront sums
-    // tile 0 first sums the previous step's force record (no other block waits on it)
-    if (t == 0 && fin_buf >= 0) finalize_record(a.fin, fin_buf, lds);
     int s0 = 0, s1 = 0;          // this tile's (tile, body) force slots
     if constexpr (RECORD) {
         s0 = a.tile_slot_ptr[t];
@@ -727,18 +727,31 @@ template <typename S, int V, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256)
 k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
 {
-    const int t = xcd_tile(a.tiles_per_xcd);
+    __shared__ double lds[2 * FIN_LANES];   // the record sums, then the per-wavefront sums
+    // block 0 of the first 8 sums the previous step's record (no block waits on it)
+    const int lead = a.fin_buf >= 0 ? N_XCD : 0;
+    if ((int)blockIdx.x < lead) {
+        if (blockIdx.x == 0) finalize_record(a.fin, a.fin_buf, lds);
+        return;
+    }
+    const int t = xcd_tile(a.tiles_per_xcd, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, PULL, RECORD, FIELDS>(src, dst, a, t, a.part_buf, a.fin_buf);
+    step_body<S, V, PULL, RECORD, FIELDS>(src, dst, a, t, a.part_buf, lds);
 }
 
 // One lattice, read and written in place (no restrict).
 template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith<S>::R> a)
 {
-    const int t = xcd_tile(a.tiles_per_xcd);
+    __shared__ double lds[2 * FIN_LANES];
+    const int lead = a.fin_buf >= 0 ? N_XCD : 0;
+    if ((int)blockIdx.x < lead) {
+        if (blockIdx.x == 0) finalize_record(a.fin, a.fin_buf, lds);
+        return;
+    }
+    const int t = xcd_tile(a.tiles_per_xcd, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, MODE, RECORD, FIELDS>(lat, lat, a, t, a.part_buf, a.fin_buf);
+    step_body<S, V, MODE, RECORD, FIELDS>(lat, lat, a, t, a.part_buf, lds);
 }
 
 // Many domains in one launch: block -> (domain, tile) through the tile map;
@@ -748,15 +761,24 @@ template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
 {
     using R = typename Arith<S>::R;
-    const int g = xcd_tile(b.tiles_per_xcd);
+    __shared__ double lds[2 * FIN_LANES];
+    const StepArgs<R>* args = static_cast<const StepArgs<R>*>(b.args);
+    // the first n_fin blocks sum the previous step's record of one domain each:
+    // dispatched first and spread over the XCDs, they overlap the streaming
+    // tiles instead of trailing them (n_fin is a multiple of 8)
+    if ((int)blockIdx.x < b.n_fin) {
+        if ((int)blockIdx.x < b.n_domains) finalize_record(args[blockIdx.x].fin, b.fin_buf, lds);
+        return;
+    }
+    const int g = xcd_tile(b.tiles_per_xcd, b.n_fin);
     if (g >= b.total_tiles) return;  // whole block
     const int d = b.tile_domain[g];
-    const StepArgs<R>& a = static_cast<const StepArgs<R>*>(b.args)[d];
+    const StepArgs<R>& a = args[d];
     const int t = g - b.tile_start[d];
     const int cur = a.cur ^ b.flip;
     S* lat_cur = static_cast<S*>(cur ? a.lat1 : a.lat0);
     S* lat_next = static_cast<S*>(cur ? a.lat0 : a.lat1);
-    step_body<S, V, MODE, RECORD, FIELDS>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, b.fin_buf);
+    step_body<S, V, MODE, RECORD, FIELDS>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, lds);
 }
 
 // The last record of an lbvp_step call, summed on its own.
@@ -865,7 +887,7 @@ template <typename S, int V>
 hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const StepArgs<typename Arith<S>::R>& a,
                   hipStream_t s)
 {
-    const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD)), block((unsigned)a.block);
+    const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD + (a.fin_buf >= 0 ? N_XCD : 0))), block((unsigned)a.block);
     const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, a.block);
     if (mode == PULL) {
         if (record) {
@@ -921,7 +943,7 @@ hipError_t step_typed(int mode, bool record, bool fields, const void* src, void*
 template <typename S, int V, int MODE>
 hipError_t batch_mode(bool record, bool fields, const BatchLaunch& b, int32_t block, hipStream_t s)
 {
-    const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD)), blk((unsigned)block);
+    const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD + b.n_fin)), blk((unsigned)block);
     const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, block);
     if (record) {
         if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true>), grid, blk, lds, s, b);
