@@ -188,6 +188,21 @@ lbvp_status lbvp_read_populations(lbvp_ctx* ctx, double* g);
  * odd step count. */
 lbvp_status lbvp_write_populations(lbvp_ctx* ctx, const double* g);
 
+/* Checkpoint and resume. lbvp_save_state writes the context's exact state into
+ * a caller-allocated host buffer: the lattice as stored (any step parity, any
+ * layout), the AA outflow ghost columns, the mask and bodies, the fields, the
+ * step and record counters. *size gets the bytes needed; with buf NULL or cap
+ * too small nothing is written and E_NOMEM is returned (call once to size).
+ * E_STATE if force records are undrained (call lbvp_forces first).
+ * Synchronizes the stream.
+ * lbvp_load_state restores such a blob into a context created with the same
+ * grid, storage type and layout (E_ARG otherwise, or for a damaged blob); the
+ * context's own relaxation, penalization and side parameters apply from then
+ * on. Stepping a restored context gives bitwise the results the saved one
+ * would have given. Synchronizes the stream. */
+lbvp_status lbvp_save_state(lbvp_ctx* ctx, void* buf, size_t cap, size_t* size);
+lbvp_status lbvp_load_state(lbvp_ctx* ctx, const void* buf, size_t size);
+
 /* Launch configuration of the step kernel: vec nodes per thread (1, the
  * storage type's 16-byte width: 2 for F64, 4 for F32, 8 for F16/BF16, or 4 for
  * F16/BF16; 2-byte types in the AA layout take 1 only) and block

