@@ -224,6 +224,86 @@ def run_serving(storage: str, rate: float, n_req: int, seed: int = 5, max_slots:
     return out
 
 
+def _rel_l2(a, b):
+    return float(np.sqrt(np.sum((a - b) ** 2) / max(np.sum(b ** 2), 1e-300)))
+
+
+def precision_study(checkpoints=(1000, 5000, 50000), rec_every: int = 10):
+    """Reduced-storage error of the large 8192 x 4096 domain against an FP64 run on
+    the GPU (whose arithmetic matches the oracle to 1e-12): per-field rel-L2 of
+    (rho - 1, u_x, u_y) at the checkpoints, and per-body C_d mean / C_l amplitude
+    over the second half of the run."""
+    from paper_1901_08766_amd import diagnostics, inputs, lbvp
+
+    prob = inputs.large_domain()
+    last = checkpoints[-1]
+    cap = last // rec_every + 16
+    runs = {st: lbvp.Solver(prob, storage=st, force_every=rec_every, force_capacity=cap)
+            for st in ("f64", "f32", "f16", "bf16")}
+    forces = {st: [] for st in runs}
+    out = {"workload": f"{prob.name}, Re 200, U 0.04", "checkpoints": {}}
+    done = 0
+    for cp in checkpoints:
+        fl = {}
+        for st, s in runs.items():
+            s.step(cp - done, keep_fields=True)
+            try:
+                f, _, _ = s.forces()
+            except lbvp.LbvpError as e:
+                f, _, _ = e.data
+            forces[st].append(f)
+            fl[st] = s.fields()
+        done = cp
+        ref = fl["f64"]
+        row = {}
+        for st in ("f32", "f16", "bf16"):
+            row[st] = {"rho": _rel_l2(fl[st]["rho"] - 1.0, ref["rho"] - 1.0), "ux": _rel_l2(fl[st]["ux"], ref["ux"]),
+                       "uy": _rel_l2(fl[st]["uy"], ref["uy"])}
+        out["checkpoints"][str(cp)] = row
+        print(f"# precision at step {cp}: {row}", file=sys.stderr, flush=True)
+        del fl
+    half = last // rec_every // 2
+    stats = {}
+    for st in runs:
+        f = np.concatenate(forces[st])[half:]
+        # a 50k-step run holds about one shedding period at D = 160, so no Strouhal number
+        stats[st] = [{k: v for k, v in diagnostics.shedding(f[:, b], rec_every, prob.u_ref,
+                                                             prob.l_ref if b < 4 else 5 * prob.l_ref).items()
+                      if k != "st"} for b in range(prob.n_bodies)]
+    out["body_stats_second_half"] = stats
+    for s in runs.values():
+        s.close()
+    return out
+
+
+def steady_wake(res=(20.0, 40.0), steps: int = 60000, storages=("f32", "f64")):
+    """The single cylinder (1024 x 512, D = 40, U = 0.05) at low Re run to a steady
+    state: C_d from the force record, recirculation length L_s/D and separation
+    angle theta_s from the final fields."""
+    from paper_1901_08766_amd import diagnostics, inputs, lbvp
+
+    out = []
+    for re in res:
+        for st in storages:
+            prob = inputs.cylinder(re=re, noise=False)
+            s = lbvp.Solver(prob, storage=st, force_every=100, force_capacity=steps // 100 + 8)
+            s.step(steps - 1000)
+            s.forces()
+            s.step(1000, keep_fields=True)
+            f, _, _ = s.forces()
+            fields = s.fields()
+            cd, cl = diagnostics.force_coefficients(f[-1, 0], prob.u_ref, prob.l_ref)
+            drift = float(abs(diagnostics.force_coefficients(f[0, 0], prob.u_ref, prob.l_ref)[0] - cd) / abs(cd))
+            cx, cy = prob.bodies[0, 0], prob.bodies[0, 1]
+            ls, th = diagnostics.steady_wake(fields, cx, cy, prob.l_ref / 2.0)
+            row = {"re": re, "storage": st, "steps": steps, "cd": round(float(cd), 5), "cl": round(float(cl), 6),
+                   "cd_drift_last_1000_steps": drift, "ls_over_d": round(ls, 4), "theta_s_deg": round(th, 2)}
+            print(json.dumps(row), flush=True)
+            out.append(row)
+            s.close()
+    return out
+
+
 def calibrate_copy(nbytes: int, reps: int = 5):
     """A plain device copy of known size (torch's copy kernel): what the HBM
     traffic counters read for it calibrates them, and its rate is the copy
@@ -346,6 +426,10 @@ def main():
     ap.add_argument("--serve-storage", default="f16")
     ap.add_argument("--serve-sweep", default="",
                     help="only run the serving stream at these comma-separated rates (req/s)")
+    ap.add_argument("--precision-study", action="store_true",
+                    help="only run FP32/FP16/BF16 against FP64 on the large domain (1k/5k/50k steps)")
+    ap.add_argument("--steady-wake", action="store_true",
+                    help="only run the low-Re steady cylinder diagnostics (Re 20 and 40)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES (counter calibration)")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("DB", "OUT_MD", "COMMAND"),
@@ -364,6 +448,12 @@ def main():
     if a.summarize_counters:
         sf, sw, cf, cw, cb, kern, md, cmd = a.summarize_counters
         summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, COUNTERS_FILE, md, cmd)
+        return
+    if a.precision_study:
+        print(json.dumps(precision_study()), flush=True)
+        return
+    if a.steady_wake:
+        steady_wake()
         return
     if a.serve_sweep:
         for rate in [float(x) for x in a.serve_sweep.split(",")]:
