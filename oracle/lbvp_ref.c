@@ -392,3 +392,13 @@ int lbvp_ref_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the row loops from now on (timing only; results do not depend on it). */
+void lbvp_ref_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -82,6 +82,7 @@ def lib():
         L.lbvp_ref_collide_node.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                             C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
         L.lbvp_ref_num_threads.restype = C.c_int
+        L.lbvp_ref_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -140,6 +141,10 @@ def collide_node(f, tau_s: float, tau_a: float, eta: float, chi: int, uo=(0.0, 0
 
 def num_threads() -> int:
     return lib().lbvp_ref_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    lib().lbvp_ref_set_num_threads(int(n))
 
 
 # ------------------------------------------------------------------ solver --
