@@ -313,6 +313,23 @@ def steady_wake(res=(20.0, 40.0), steps: int = 60000, storages=("f32", "f64")):
     return out
 
 
+def copy_bandwidth(nbytes: int = 1207959552, reps: int = 20) -> float:
+    """GB/s (bytes read + written) of the library's 16-byte non-temporal device
+    copy over nbytes, the access pattern of the step kernels."""
+    import torch
+    from paper_1901_08766_amd import lbvp
+
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    s = torch.cuda.Stream()
+    lbvp.lbvp_device_copy(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+    ms = _timed(s, lambda: [lbvp.lbvp_device_copy(a.data_ptr(), b.data_ptr(), nbytes, s.cuda_stream)
+                            for _ in range(reps)]) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / ms / 1e6
+
+
 def calibrate_copy(nbytes: int, reps: int = 5):
     """A plain device copy of known size (torch's copy kernel): what the HBM
     traffic counters read for it calibrates them, and its rate is the copy
@@ -493,6 +510,7 @@ def main():
                     "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok}
         print(f"# {v}: {extra[v]}", file=sys.stderr, flush=True)
     traffic = measured_traffic(a.storage, nodes)
+    copy_gbps = copy_bandwidth()
     out = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -514,6 +532,8 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic},
         "variants": extra,
+        "copy": {"GBps": round(copy_gbps, 1), "step_frac_of_copy": round(achieved / copy_gbps, 4),
+                 "kernel": "16-byte non-temporal device copy (lbvp_device_copy), 1.2 GB"},
     }
     if a.ensemble_steps > 0:
         out["ensemble"] = {}

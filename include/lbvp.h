@@ -336,6 +336,13 @@ lbvp_status lbvp_pool_get_stats(const lbvp_pool* pool, lbvp_pool_stats* out);
 lbvp_status lbvp_pool_destroy(lbvp_pool* pool);
 const char* lbvp_pool_last_error(const lbvp_pool* pool);
 
+/* Measurement aid, not part of the method: copy bytes (a multiple of 16) from
+ * src to dst, both device pointers 16-byte aligned, with the 16-byte
+ * non-temporal loads and stores the step kernels use, on hip_stream
+ * (asynchronous). Its rate is the copy bandwidth the step is compared with.
+ * E_ARG on misaligned pointers or sizes, E_DEVICE on a launch failure. */
+lbvp_status lbvp_device_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* Number of steps taken since the last lbvp_init_equilibrium. */
 int64_t lbvp_step_count(const lbvp_ctx* ctx);
 

@@ -1370,6 +1370,15 @@ lbvp_status lbvp_get_launch(const lbvp_ctx* c, int32_t* vec, int32_t* block)
 
 int64_t lbvp_step_count(const lbvp_ctx* c) { return c ? c->step : -1; }
 
+lbvp_status lbvp_device_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
+{
+    if (!src || !dst || bytes % 16 || reinterpret_cast<uintptr_t>(src) % 16 || reinterpret_cast<uintptr_t>(dst) % 16)
+        return LBVP_E_ARG;
+    if (bytes == 0) return LBVP_OK;
+    return launch_copy16(src, dst, (int64_t)(bytes / 16), static_cast<hipStream_t>(hip_stream)) == hipSuccess
+               ? LBVP_OK : LBVP_E_DEVICE;
+}
+
 lbvp_status lbvp_synchronize(lbvp_ctx* c)
 {
     if (check_ctx(c)) return LBVP_E_ARG;

@@ -129,6 +129,7 @@ hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs&
 hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);
 hipError_t launch_encode(int32_t storage, void* lat, const ConvArgs& a, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
 
 // host-side pieces the serving pool builds on (lbvp_api.hip)
 // An empty batch of the given kind on a stream; members come with batch_set_members.

@@ -40,6 +40,7 @@
 // themselves, with the domain sides resolved there.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lbvp_internal.h"
@@ -860,6 +861,16 @@ __global__ void __launch_bounds__(256) k_encode(S* lat, ConvArgs a)
 
 __global__ void k_set_i64(int64_t* p, int64_t v) { *p = v; }
 
+// A plain device copy with the step's access width and cache policy (16-byte
+// non-temporal loads and stores): the bandwidth the memory system gives this
+// access pattern, against which the step is measured.
+__global__ void __launch_bounds__(256) k_copy16(const u32x4_t* __restrict__ src, u32x4_t* __restrict__ dst, int64_t n)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + k), dst + k);
+}
+
 // AA layout after an even number of steps: copy the outflow sides' outgoing
 // post-collision populations into the ghost columns the next push step reads.
 template <typename S>
@@ -1078,6 +1089,14 @@ hipError_t launch_encode(int32_t storage, void* lat, const ConvArgs& a, hipStrea
     case ST_BF16: hipLaunchKernelGGL(k_encode<__bf16>, g, b, 0, s, (__bf16*)lat, a); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)
+{
+    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 256 * 64);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s,
+                       static_cast<const u32x4_t*>(src), static_cast<u32x4_t*>(dst), n16);
     return hipGetLastError();
 }
 

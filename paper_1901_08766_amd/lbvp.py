@@ -39,7 +39,8 @@ SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_eq
            "lbvp_batch_destroy", "lbvp_batch_last_error", "lbvp_tune", "lbvp_tune_last_error",
            "lbvp_pool_create", "lbvp_pool_admit", "lbvp_pool_run_epoch", "lbvp_pool_poll",
            "lbvp_pool_forces", "lbvp_pool_read_fields", "lbvp_pool_release", "lbvp_pool_get_stats",
-           "lbvp_pool_destroy", "lbvp_pool_last_error", "lbvp_save_state", "lbvp_load_state"]
+           "lbvp_pool_destroy", "lbvp_pool_last_error", "lbvp_save_state", "lbvp_load_state",
+           "lbvp_device_copy"]
 NO_STATUS = ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error",
              "lbvp_tune_last_error", "lbvp_pool_last_error")
 
@@ -113,6 +114,7 @@ def _load():
     L.lbvp_batch_destroy.argtypes = [vp]
     L.lbvp_batch_last_error.restype = C.c_char_p
     L.lbvp_batch_last_error.argtypes = [vp]
+    L.lbvp_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
     L.lbvp_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbvp_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbvp_tune.argtypes = [C.POINTER(vp), i32, i32, u32, C.POINTER(lbvp_tune_row), i32, C.POINTER(i32),
@@ -219,6 +221,12 @@ def lbvp_read_populations(ctx, nx: int, ny: int) -> np.ndarray:
 def lbvp_write_populations(ctx, g: np.ndarray):
     g = np.ascontiguousarray(g, dtype=np.float64)
     _check(ctx, _L.lbvp_write_populations(ctx, _ptr(g)))
+
+
+def lbvp_device_copy(src: int, dst: int, nbytes: int, stream: Optional[int] = None):
+    st = _L.lbvp_device_copy(src, dst, int(nbytes), stream)
+    if st != OK:
+        raise LbvpError(st, "lbvp_device_copy: pointers and size must be multiples of 16 bytes")
 
 
 def lbvp_save_state(ctx) -> np.ndarray:

@@ -118,3 +118,11 @@ def test_create_rejects_small_borrowed_memory(lbvp):
     with pytest.raises(lbvp.LbvpError) as e:
         lbvp.lbvp_create(p, None, 256, need - 1)   # never dereferenced: the size check fails first
     assert e.value.status == lbvp.E_NOMEM
+
+
+def test_device_copy_rejects_misaligned_arguments(lbvp):
+    L = lbvp.lib()
+    assert L.lbvp_device_copy(C.c_void_p(16), C.c_void_p(32), 17, None) == lbvp.E_ARG
+    assert L.lbvp_device_copy(C.c_void_p(8), C.c_void_p(32), 16, None) == lbvp.E_ARG
+    assert L.lbvp_device_copy(None, C.c_void_p(32), 16, None) == lbvp.E_ARG
+    assert L.lbvp_device_copy(C.c_void_p(16), C.c_void_p(32), 0, None) == lbvp.OK

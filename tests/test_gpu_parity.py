@@ -294,3 +294,13 @@ def test_eighth_scale_large_domain(lbvp, oracle):
         print(f"  velocity rel-L2 {err:.3e}", flush=True)
         assert err <= tol, (storage, err)
         s.close()
+
+
+def test_device_copy(lbvp):
+    import torch
+    a = torch.arange(1 << 20, dtype=torch.int32, device="cuda")
+    b = torch.zeros_like(a)
+    s = torch.cuda.Stream()
+    lbvp.lbvp_device_copy(a.data_ptr(), b.data_ptr(), a.numel() * 4, s.cuda_stream)
+    s.synchronize()
+    assert torch.equal(a, b)
