@@ -1,0 +1,66 @@
+"""Cylindrical Couette (Sec. 3.1) on the GPU in FP64: the TRT-vs-SRT accuracy
+comparison and its grid convergence at 64^2, 128^2, 256^2 (geometry scaled,
+steps scaled with the diffusion time), against u = A r + B / r (reading R12).
+At 64^2 the GPU's error equals the oracle's (the arithmetic matches to 1e-12)."""
+import numpy as np
+import pytest
+
+from paper_1901_08766_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _error(fl, n, scale):
+    c = (n - 1) / 2
+    x, y = np.meshgrid(np.arange(n, dtype=float), np.arange(n, dtype=float))
+    dx, dy = x - c, y - c
+    r = np.hypot(dx, dy)
+    ut = (-dy * fl["ux"] + dx * fl["uy"]) / np.maximum(r, 1e-30)
+    ri, ro, u0 = 12 * scale, 28 * scale, 0.01
+    sel = (r >= ri + 1.5) & (r <= ro - 1.5)
+    exact = u0 * ri * (ro ** 2 / r - r) / (ro ** 2 - ri ** 2)
+    return float(np.sqrt(np.sum((ut[sel] - exact[sel]) ** 2) / np.sum(exact[sel] ** 2)))
+
+
+def _problem(n, tau, lam):
+    scale = n / 64
+    p = inputs.couette(n=n, r_in=12 * scale, r_out=28 * scale, tau_plus=tau, magic_lambda=lam)
+    steps = int(round(2000 * scale * scale * 0.1 / ((tau - 0.5) / 3)))
+    return p, scale, steps
+
+
+def _gpu_error(lbvp, n, tau, lam):
+    p, scale, steps = _problem(n, tau, lam)
+    s = lbvp.Solver(p, storage="f64", force_every=0)
+    s.step(steps, keep_fields=True)
+    e = _error(s.fields(), n, scale)
+    s.close()
+    return e
+
+
+def test_couette_gpu_equals_oracle_at_64(lbvp, oracle):
+    p, scale, steps = _problem(64, 0.8, 0.25)
+    r = oracle.RefSolver(p)
+    r.step(steps)
+    e_ref = _error(r.fields(), 64, scale)
+    assert abs(_gpu_error(lbvp, 64, 0.8, 0.25) - e_ref) <= 1e-9 * e_ref
+
+
+def test_couette_trt_vs_srt_convergence(lbvp):
+    table = {}
+    for n in (64, 128, 256):
+        for tau in (0.8, 1.5):
+            table[(n, tau, "trt")] = _gpu_error(lbvp, n, tau, 0.25)
+            table[(n, tau, "srt")] = _gpu_error(lbvp, n, tau, (tau - 0.5) ** 2)
+            print(f"couette n={n} tau+={tau}: TRT {table[(n, tau, 'trt')]:.4%}  SRT {table[(n, tau, 'srt')]:.4%}",
+                  flush=True)
+    for n in (64, 128, 256):
+        # TRT with a fixed Lambda: the error barely depends on tau+ (measured ratio 1.008,
+        # 1.019, 1.032 at 64, 128, 256: the penalized walls are not exactly
+        # tau-independent); SRT's grows with tau+ (2.0-2.2x TRT's at tau+ = 1.5)
+        assert abs(table[(n, 1.5, "trt")] / table[(n, 0.8, "trt")] - 1) < 0.05
+        assert table[(n, 1.5, "trt")] < 0.6 * table[(n, 1.5, "srt")]
+    for tau in (0.8, 1.5):
+        # first order under grid doubling (the staircase mask), both ratios >= 1.6
+        assert table[(64, tau, "trt")] / table[(128, tau, "trt")] >= 1.6
+        assert table[(128, tau, "trt")] / table[(256, tau, "trt")] >= 1.6
