@@ -77,6 +77,15 @@ typedef enum lbvp_storage {
  * equal). lbvp_read_populations / lbvp_write_populations need an even step
  * count; F16_DEV and BF16_DEV run with one node per thread. */
 #define LBVP_LAYOUT_AA 0x1u
+/* LBVP_MOVING_BODIES: the mask function chi(x, t) follows each body's rigid
+ * motion (eq. mask function with a time-dependent chi; eq. boundary-condition):
+ * at the step that takes the counter to k, body b has moved to
+ * c_b(t) = c_b + V_b t and turned by omega_b t (t = k), and node x belongs to it
+ * when the mask given to lbvp_set_mask (the bodies at t = 0) holds b at the node
+ * nearest to R(-omega_b t)(x - c_b(t)) + c_b (first such body wins); U_O uses
+ * c_b(t). At most 8 bodies; one node per thread; not with LBVP_GRAPH, batches,
+ * the pool or the tuner, which cannot carry a per-step time. */
+#define LBVP_MOVING_BODIES 0x2u
 
 /* lbvp_step / lbvp_batch_step flags
  * LBVP_KEEP_FIELDS: store rho, u, F_VP of the last step of the call.

@@ -73,6 +73,7 @@ typedef struct ref_params {
     int32_t bc_west, bc_east, bc_south, bc_north;
     double rho_in, u_in_x, u_in_y;
     double fb_x, fb_y;    /* uniform body force F_b */
+    int32_t moving;       /* bodies move rigidly: chi(x, t) follows them */
 } ref_params;
 
 typedef struct ref_ctx {
@@ -243,12 +244,59 @@ int lbvp_ref_set_mask(ref_ctx *c, const uint8_t *body_id, int32_t n_bodies, cons
     return 0;
 }
 
-/* rigid-body velocity of body b (1-based) at node (x, y) */
-static void obstacle_velocity(const ref_ctx *c, int b, double x, double y, double *UOx, double *UOy)
+/* Centre of body b (1-based) at time level t: fixed, or c(t) = c + V t for
+ * moving bodies. */
+static void body_centre(const ref_ctx *c, int b, double t, double *cx, double *cy)
 {
     const double *B = c->bodies + 5 * (b - 1);
-    *UOx = B[2] - B[4] * (y - B[1]);
-    *UOy = B[3] + B[4] * (x - B[0]);
+    if (!c->p.moving) {
+        *cx = B[0];
+        *cy = B[1];
+        return;
+    }
+    *cx = B[0] + B[2] * t;
+    *cy = B[1] + B[3] * t;
+}
+
+/* rigid-body velocity of body b at node (x, y) and time level t (eq.
+ * boundary-condition): U_O = V + omega z x (x - c(t)) */
+static void obstacle_velocity(const ref_ctx *c, int b, double x, double y, double t, double *UOx, double *UOy)
+{
+    const double *B = c->bodies + 5 * (b - 1);
+    double cx, cy;
+    body_centre(c, b, t, &cx, &cy);
+    *UOx = B[2] - B[4] * (y - cy);
+    *UOy = B[3] + B[4] * (x - cx);
+}
+
+/* The mask function chi(x, t) as the body id at node (i, j), time level t. A
+ * fixed mask is the one given. A moving body b, translated to c(t) and turned
+ * by omega t, covers the nodes whose position carried back by that motion,
+ * R(-omega t) (x - c(t)) + c, lands (to the nearest node, halves rounded up)
+ * on a node of the given t = 0 mask holding b; the first such body wins. */
+static int body_at(const ref_ctx *c, int i, int j, double t)
+{
+    if (!c->p.moving) return c->body_id[(int64_t)j * c->p.nx + i];
+    for (int b = 1; b <= c->n_bodies; ++b) {
+        const double *B = c->bodies + 5 * (b - 1);
+        double cx, cy;
+        body_centre(c, b, t, &cx, &cy);
+        const double th = B[4] * t;
+        const double cs = cos(th), sn = sin(th);
+        const double dx = (double)i - cx, dy = (double)j - cy;
+        const double xr = cs * dx + sn * dy + B[0];
+        const double yr = cs * dy - sn * dx + B[1];
+        const double ir = floor(xr + 0.5), jr = floor(yr + 0.5);
+        if (ir < 0.0 || jr < 0.0 || ir >= (double)c->p.nx || jr >= (double)c->p.ny) continue;
+        if (c->body_id[(int64_t)jr * c->p.nx + (int64_t)ir] == b) return b;
+    }
+    return 0;
+}
+
+int lbvp_ref_body_at(const ref_ctx *c, int32_t i, int32_t j, int64_t t_level)
+{
+    if (i < 0 || j < 0 || i >= c->p.nx || j >= c->p.ny) return -1;
+    return body_at(c, i, j, (double)t_level);
 }
 
 /* Step (1): g = f^eq(rho0(x), u0(x)); fields(0) = (rho0, u0, 0). */
@@ -292,15 +340,18 @@ static double pull(const ref_ctx *c, const double *g, int a, int i, int j)
     return g[(int64_t)a * c->n + (int64_t)sj * nx + si];
 }
 
-static void node_update(const ref_ctx *c, const double *g, int i, int j, double gout[Q], double fl[5])
+/* One node of the step that produces time level t (the step count after it);
+ * returns the node's body id. */
+static int node_update(const ref_ctx *c, const double *g, int i, int j, double t, double gout[Q], double fl[5])
 {
     double f[Q];
     for (int a = 0; a < Q; ++a) f[a] = pull(c, g, a, i, j);
-    int b = c->body_id[(int64_t)j * c->p.nx + i];
+    int b = body_at(c, i, j, t);
     double UOx = 0.0, UOy = 0.0;
-    if (b > 0) obstacle_velocity(c, b, (double)i, (double)j, &UOx, &UOy);
+    if (b > 0) obstacle_velocity(c, b, (double)i, (double)j, t, &UOx, &UOy);
     lbvp_ref_collide_node(f, c->p.tau_plus, c->tau_minus, c->p.eta, b > 0, UOx, UOy,
                           c->p.fb_x, c->p.fb_y, gout, fl);
+    return b;
 }
 
 /* Advance n steps. If forces is non-NULL it receives [n][n_bodies][2] (force on
@@ -311,6 +362,7 @@ int lbvp_ref_step(ref_ctx *c, int64_t n_steps, double *forces, double *mass)
     for (int64_t s = 0; s < n_steps; ++s) {
         const double *g = c->g;
         double *gn = c->g_next;
+        const double t = (double)(c->step + 1);
         /* rows in parallel only when the grid is big enough to pay for the fork */
 #pragma omp parallel for schedule(static) if ((int64_t)nx * ny >= 65536)
         for (int j = 0; j < ny; ++j) {
@@ -319,11 +371,10 @@ int lbvp_ref_step(ref_ctx *c, int64_t n_steps, double *forces, double *mass)
             double rm = 0.0;
             for (int i = 0; i < nx; ++i) {
                 double gout[Q], fl[5];
-                node_update(c, g, i, j, gout, fl);
+                int b = node_update(c, g, i, j, t, gout, fl);
                 int64_t k = (int64_t)j * nx + i;
                 for (int a = 0; a < Q; ++a) gn[(int64_t)a * c->n + k] = gout[a];
                 for (int q = 0; q < 5; ++q) c->fields[(int64_t)q * c->n + k] = fl[q];
-                int b = c->body_id[k];
                 if (b > 0) {
                     rf[2 * (b - 1)] -= fl[3];
                     rf[2 * (b - 1) + 1] -= fl[4];
@@ -358,7 +409,7 @@ int lbvp_ref_step_nodes(const ref_ctx *c, const double *g, int64_t n_nodes, cons
     for (int64_t k = 0; k < n_nodes; ++k) {
         if (xs[k] < 0 || xs[k] >= c->p.nx || ys[k] < 0 || ys[k] >= c->p.ny) return 1;
         double fl[5];
-        node_update(c, g, xs[k], ys[k], gout + Q * k, fl);
+        node_update(c, g, xs[k], ys[k], (double)(c->step + 1), gout + Q * k, fl);
         if (fields)
             for (int q = 0; q < 5; ++q) fields[5 * k + q] = fl[q];
     }

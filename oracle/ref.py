@@ -41,7 +41,7 @@ class _Params(C.Structure):
                 ("bc_west", C.c_int32), ("bc_east", C.c_int32), ("bc_south", C.c_int32),
                 ("bc_north", C.c_int32),
                 ("rho_in", C.c_double), ("u_in_x", C.c_double), ("u_in_y", C.c_double),
-                ("fb_x", C.c_double), ("fb_y", C.c_double)]
+                ("fb_x", C.c_double), ("fb_y", C.c_double), ("moving", C.c_int32)]
 
 
 _lib = None
@@ -82,6 +82,8 @@ def lib():
         L.lbvp_ref_collide_node.argtypes = [dp, C.c_double, C.c_double, C.c_double, C.c_int,
                                             C.c_double, C.c_double, C.c_double, C.c_double, dp, dp]
         L.lbvp_ref_num_threads.restype = C.c_int
+        L.lbvp_ref_body_at.restype = C.c_int
+        L.lbvp_ref_body_at.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int64]
         L.lbvp_ref_set_num_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
@@ -158,7 +160,8 @@ class RefSolver:
                     bc_west=_SIDE[prob.bc[0]], bc_east=_SIDE[prob.bc[1]],
                     bc_south=_SIDE[prob.bc[2]], bc_north=_SIDE[prob.bc[3]],
                     rho_in=prob.rho_in, u_in_x=prob.u_in[0], u_in_y=prob.u_in[1],
-                    fb_x=prob.body_force[0], fb_y=prob.body_force[1])
+                    fb_x=prob.body_force[0], fb_y=prob.body_force[1],
+                    moving=1 if getattr(prob, "moving", False) else 0)
         self.nx, self.ny = prob.nx, prob.ny
         self._h = lib().lbvp_ref_create(C.byref(P))
         if not self._h:
@@ -170,6 +173,10 @@ class RefSolver:
             raise ValueError("oracle rejected the mask")
         self._keep = (mask, bodies)
         self.init(prob.rho_init, prob.ux_init, prob.uy_init)
+
+    def body_at(self, i: int, j: int, t_level: int) -> int:
+        """The mask function chi(x, t) as a body id (moving bodies follow their motion)."""
+        return int(lib().lbvp_ref_body_at(self._h, int(i), int(j), int(t_level)))
 
     def init(self, rho=None, ux=None, uy=None):
         arrs = [None if a is None else np.ascontiguousarray(a, np.float64) for a in (rho, ux, uy)]

@@ -30,7 +30,7 @@ constexpr size_t STAGE_MIN_BYTES = size_t(16) << 20;
 constexpr int64_t DEFAULT_CAPACITY = 16384;
 constexpr int32_t DEFAULT_MAX_BODIES = 8;
 constexpr int32_t MAX_BODIES = 255;
-constexpr uint32_t KNOWN_PARAM_FLAGS = LBVP_LAYOUT_AA;
+constexpr uint32_t KNOWN_PARAM_FLAGS = LBVP_LAYOUT_AA | LBVP_MOVING_BODIES;
 constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS | LBVP_GRAPH;
 constexpr int64_t GRAPH_CHUNK = 512;   // steps per captured graph; longer calls replay it
 
@@ -51,7 +51,7 @@ struct Layout {
     int64_t stage_rows = 0;
     size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, mass_part = 0, slot_force = 0,
            tile_slot_ptr = 0, slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0,
-           ring_mass = 0, rec_count = 0, stage = 0, ghost_w = 0, ghost_e = 0, total = 0;
+           ring_mass = 0, rec_count = 0, stage = 0, ghost_w = 0, ghost_e = 0, pose = 0, total = 0;
 };
 
 // Launch configuration of the step kernel and the tiling it implies.
@@ -87,6 +87,7 @@ Launch make_launch(int32_t nx, int32_t ny, int32_t vec, int32_t block)
 // (its push step moves single elements).
 std::vector<int32_t> vec_options(int32_t storage, uint32_t flags)
 {
+    if (flags & LBVP_MOVING_BODIES) return {1};   // moving masks run one node per thread
     const bool two_byte = storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV;
     if (two_byte && (flags & LBVP_LAYOUT_AA)) return {1};
     if (two_byte) return {1, 4, vector_width(storage)};
@@ -139,6 +140,8 @@ std::string validate(const lbvp_params* p)
     if (p->force_capacity < 0 || p->force_capacity > (int64_t(1) << 26)) return "force_capacity out of range";
     if (p->max_bodies < 0 || p->max_bodies > MAX_BODIES) return "max_bodies must be in 0..255";
     if (p->flags & ~KNOWN_PARAM_FLAGS) return "unknown or unsupported params flag";
+    if ((p->flags & LBVP_MOVING_BODIES) && p->max_bodies > MAX_MOVING)
+        return "moving bodies: max_bodies must be at most 8";
     return "";
 }
 
@@ -156,9 +159,11 @@ Layout make_layout(const lbvp_params* p)
             L.max_tiles = std::max(L.max_tiles, l.n_tiles);
             L.max_waves = std::max(L.max_waves, l.n_tiles * (block / 64));
         }
-    L.slot_cap = 2 * (int64_t)L.max_tiles + 1024;
     L.capacity = p->force_capacity > 0 ? p->force_capacity : DEFAULT_CAPACITY;
     L.max_bodies = p->max_bodies > 0 ? p->max_bodies : DEFAULT_MAX_BODIES;
+    L.slot_cap = 2 * (int64_t)L.max_tiles + 1024;
+    if (p->flags & LBVP_MOVING_BODIES)   // a slot for every (tile, body): bodies can reach any tile
+        L.slot_cap = std::max<int64_t>(L.slot_cap, (int64_t)L.max_tiles * L.max_bodies);
     const size_t row_bytes = (size_t)p->nx * 9 * sizeof(double);
     const size_t stage_bytes = std::max(STAGE_MIN_BYTES, row_bytes);
     L.stage_rows = std::max<int64_t>(1, (int64_t)(stage_bytes / row_bytes));
@@ -183,6 +188,7 @@ Layout make_layout(const lbvp_params* p)
     L.ghost_w = take(3 * (size_t)p->ny * es);
     L.ghost_e = take(3 * (size_t)p->ny * es);
     L.stage = take(stage_bytes);
+    L.pose = take((p->flags & LBVP_MOVING_BODIES) ? (size_t)POSE_ROWS * MAX_MOVING * POSE_STRIDE * sizeof(double) : 0);
     L.total = o;
     return L;
 }
@@ -321,6 +327,9 @@ struct lbvp_ctx {
     Launch launch;
     std::vector<uint8_t> mask_host;         // [ny][nx], kept to rebuild the tile tables
     std::vector<lbvp_body> bodies_host;
+    std::vector<double> mov_r2;             // moving bodies: squared reach about the centre
+    std::vector<double> pose_host;          // moving bodies: the uploaded pose table
+    int64_t pose_first = -1;                // its first time level (-1: none)
     uint64_t gen = 0;                       // kernel-argument generation (graph keys)
     GraphCache graphs;
     StepArgs<double> a64{};
@@ -330,6 +339,7 @@ struct lbvp_ctx {
 
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(mem + off); }
     bool aa() const { return (p.flags & LBVP_LAYOUT_AA) != 0; }
+    bool moving() const { return (p.flags & LBVP_MOVING_BODIES) != 0; }
     int32_t storage() const { return p.storage; }
     bool is_f64() const { return p.storage == LBVP_F64; }
     size_t esize() const { return storage_bytes(p.storage); }
@@ -409,6 +419,31 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.ghost_w = c->at<char>(L.ghost_w);
     a.ghost_e = c->at<char>(L.ghost_e);
     a.fin = c->fin;
+    a.n_moving = 0;
+    a.pose_row = 0;
+    a.pose = c->at<double>(L.pose);
+}
+
+// Moving bodies: each body's pose at time level t into a pose row (one
+// rounding per operation, as the kernels and the reference evaluate it).
+void moving_pose(const lbvp_ctx* c, int64_t t_level, double* row)
+{
+    const double t = (double)t_level;
+    for (int32_t b = 0; b < c->n_bodies; ++b) {
+        const lbvp_body& B = c->bodies_host[b];
+        const double th = B.omega * t;
+        const double vxt = B.vx * t;
+        const double vyt = B.vy * t;
+        double* m = row + (size_t)b * POSE_STRIDE;
+        m[0] = std::cos(th);
+        m[1] = std::sin(th);
+        m[2] = B.cx + vxt;
+        m[3] = B.cy + vyt;
+        m[4] = B.cx;
+        m[5] = B.cy;
+        m[6] = c->mov_r2[b];
+        m[7] = 0.0;
+    }
 }
 
 template <typename R>
@@ -439,6 +474,13 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
     for (int32_t t = 0; t < l.n_tiles; ++t) {
         tile_ptr[t] = (int32_t)slot_body.size();
         if (nb == 0) continue;
+        if (c->moving()) {   // dense: a slot for every body in every tile, in body order
+            for (int32_t b = 1; b <= nb; ++b) {
+                per_body[b - 1].push_back((int32_t)slot_body.size());
+                slot_body.push_back(b);
+            }
+            continue;
+        }
         const int32_t ty = t / l.tiles_x, i0 = (t % l.tiles_x) * l.tile_w, i1 = std::min(p.nx, i0 + l.tile_w);
         const int32_t j0 = ty * l.tile_rows, j1 = std::min(p.ny, j0 + l.tile_rows);
         std::fill(seen.begin(), seen.end(), 0);
@@ -567,8 +609,28 @@ lbvp_status enqueue_steps(lbvp_ctx* c, int64_t n_steps, bool keep_last, bool lau
             c->a64.fin_buf = c->a32.fin_buf = fin_buf;
             const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
             const int32_t mode = !c->aa() ? MODE_PULL : (c->step % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
-            hipError_t e = launch_step(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
+            hipError_t e;
+            if (c->moving()) {   // the bodies' poses at the time level this step computes
+                if (c->pose_first < 0 || next < c->pose_first || next >= c->pose_first + POSE_ROWS) {
+                    // a new table of poses from this time level on; the previous
+                    // upload must have been read from its host buffer first
+                    LBVP_HIP(c, hipStreamSynchronize(c->stream));
+                    const size_t row = (size_t)MAX_MOVING * POSE_STRIDE;
+                    c->pose_host.assign(row * POSE_ROWS, 0.0);
+                    for (int32_t r = 0; r < POSE_ROWS; ++r) moving_pose(c, next + r, c->pose_host.data() + r * row);
+                    LBVP_HIP(c, hipMemcpyAsync(c->at<double>(c->L.pose), c->pose_host.data(),
+                                               c->pose_host.size() * sizeof(double), hipMemcpyHostToDevice,
+                                               c->stream));
+                    c->pose_first = next;
+                }
+                c->a64.n_moving = c->a32.n_moving = c->n_bodies;
+                c->a64.pose_row = c->a32.pose_row = (int32_t)(next - c->pose_first);
+                e = launch_step_moving(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
                                        c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
+            } else {
+                e = launch_step(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
+                                c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
+            }
             if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
         }
         c->pending = record;
@@ -649,6 +711,7 @@ std::string batch_consistency(const lbvp_batch* b, const std::vector<lbvp_ctx*>&
         const int64_t fe = c->p.force_every;
         if (fe > 1 && (c->step % fe) != (c0->step % fe)) return "members must be at the same force-record phase";
         if (c->pending) return "a member has an unsummed record";
+        if (c->moving()) return "members with moving bodies run alone";
     }
     return "";
 }
@@ -1002,9 +1065,23 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
 
     std::vector<char> table = c->is_f64() ? body_table_bytes<double>(bodies, n_bodies, L.max_bodies)
                                           : body_table_bytes<float>(bodies, n_bodies, L.max_bodies);
+    if (c->moving() && n_bodies > MAX_MOVING) return c->fail(LBVP_E_ARG, "moving bodies: at most 8");
     c->graphs.clear(c->stream);
     c->mask_host.assign(body_id, body_id + n);
     c->bodies_host.assign(bodies, bodies + n_bodies);
+    c->mov_r2.assign((size_t)n_bodies, 0.0);
+    c->pose_first = -1;   // the poses follow the new bodies
+    if (c->moving()) {   // reach of each body about its centre: farthest node + 1
+        std::vector<double> rmax((size_t)n_bodies, 0.0);
+        for (int32_t j = 0; j < p.ny; ++j)
+            for (int32_t i = 0; i < p.nx; ++i) {
+                const int b = body_id[(int64_t)j * p.nx + i];
+                if (!b) continue;
+                const double dx = i - bodies[b - 1].cx, dy = j - bodies[b - 1].cy;
+                rmax[b - 1] = std::max(rmax[b - 1], std::sqrt(dx * dx + dy * dy));
+            }
+        for (int32_t b = 0; b < n_bodies; ++b) c->mov_r2[b] = (rmax[b] + 1.0) * (rmax[b] + 1.0);
+    }
     c->n_bodies = n_bodies;
     c->fin.n_bodies = n_bodies;
     c->gen += 1;
@@ -1066,6 +1143,7 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
     }
     const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
     if (!(flags & LBVP_GRAPH)) return enqueue_steps(c, n_steps, keep, true);
+    if (c->moving()) return c->fail(LBVP_E_ARG, "LBVP_GRAPH cannot carry the per-step poses of moving bodies");
     if (!c->stream) return c->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
     for (int64_t done = 0; done < n_steps;) {
         const int64_t n = std::min(GRAPH_CHUNK, n_steps - done);
@@ -1531,12 +1609,17 @@ lbvp_status lbvp_tune(lbvp_ctx* const* members, int32_t n, int32_t steps, uint32
             return LBVP_E_ARG;
         }
     const lbvp_ctx* c0 = m[0];
-    for (const lbvp_ctx* c : m)
+    for (const lbvp_ctx* c : m) {
+        if (c->moving()) {
+            g_tune_error = "members with moving bodies run alone, one node per thread: nothing to tune";
+            return LBVP_E_ARG;
+        }
         if (c->p.storage != c0->p.storage || c->aa() != c0->aa() || c->stream != c0->stream ||
             c->p.force_every != c0->p.force_every) {
             g_tune_error = "members differ in storage, layout, stream or force_every";
             return LBVP_E_ARG;
         }
+    }
     const std::string key = tune_signature(m, steps, flags);
     std::vector<lbvp_tune_row> table;
     int32_t pick = 0;

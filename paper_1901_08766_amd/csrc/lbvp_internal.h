@@ -19,6 +19,9 @@ constexpr int N_XCD = 8;
 constexpr int MAX_BLOCK = 256;
 constexpr int MIN_BLOCK = 64;
 constexpr int FIN_THREADS = 256;
+constexpr int MAX_MOVING = 8;       // bodies of a domain with moving masks
+constexpr int POSE_STRIDE = 8;      // doubles per body pose row
+constexpr int POSE_ROWS = 1024;     // time levels per uploaded pose table
 
 enum Side : int32_t { SIDE_PERIODIC = 0, SIDE_INFLOW_EQ = 1, SIDE_OUTFLOW = 2 };
 
@@ -76,6 +79,14 @@ struct StepArgs {
     void* lat1;                     // current (two-lattice pull; the AA layout uses lat0 only)
     int32_t cur;
     FinalizeArgs fin;
+    // moving bodies: pose[(pose_row * MAX_MOVING + b) * POSE_STRIDE + k] holds body
+    // b's pose at this step's time level t, k = 0..6: cos th, sin th, cx(t),
+    // cy(t), cx(0), cy(0) with th = omega t, c(t) = c(0) + V t, and the square
+    // of a radius about c(t) outside which no node can belong to the body;
+    // n_moving = 0 for fixed masks
+    int32_t n_moving;
+    int32_t pose_row;
+    const double* pose;
 };
 
 // A launch over many domains (k_step_batch).
@@ -120,6 +131,9 @@ int vector_width(int32_t storage);
 // launchers (lbvp_kernels.hip); all return the launch status
 hipError_t launch_step(int32_t storage, int32_t mode, bool record, bool fields, const void* src, void* dst,
                        const void* step_args, hipStream_t s);
+// the same with the mask moved to the step's time level (one node per thread)
+hipError_t launch_step_moving(int32_t storage, int32_t mode, bool record, bool fields, const void* src, void* dst,
+                              const void* step_args, hipStream_t s);
 hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a, hipStream_t s);
 hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_t mode, bool record, bool fields,
                              const BatchLaunch& b, hipStream_t s);

@@ -235,7 +235,7 @@ struct NodeResult {
 
 // Steps (4)-(6) of the algorithm at node (i, j) with streamed populations f;
 // overwrites f with the post-collision populations.
-template <typename R>
+template <typename R, bool MOVING = false>
 __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i, int j, const StepArgs<R>& a)
 {
     // moments with the integers 36 w_a = 16, 4, 1 (sum w_a rho0 = rho0 and
@@ -253,8 +253,14 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     R fvx = R(0), fvy = R(0);
     if (body) {
         const R* B = a.bodies + 5 * body;
-        const R uox = B[2] - B[4] * ((R)j - B[1]);
-        const R uoy = B[3] + B[4] * ((R)i - B[0]);
+        R bcx = B[0], bcy = B[1];                 // the body's centre, at time t if it moves
+        if constexpr (MOVING) {
+            const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
+            bcx = (R)m[2];
+            bcy = (R)m[3];
+        }
+        const R uox = B[2] - B[4] * ((R)j - bcy);
+        const R uoy = B[3] + B[4] * ((R)i - bcx);
         const R dux = a.vp_c * (uox - ux);
         const R duy = a.vp_c * (uoy - uy);
         fvx = R(2) * rho * dux;
@@ -285,6 +291,39 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     f[6] = p68.ga;
     f[8] = p68.gb;
     return {drho, rho, ux, uy, fvx, fvy};
+}
+
+// Moving masks: the body occupying node (i, j) at the step's time level. Node
+// x belongs to body b when the reference (t = 0) mask holds b at the node
+// nearest to R(-th) (x - c(t)) + c(0), the node carried back by the body's
+// rigid motion; the first such body in order wins. Evaluated in FP64 one
+// operation per statement (no fused multiply-adds), so that membership does
+// not depend on the storage type. Nodes outside a body's radius skip it.
+template <typename R>
+__device__ __forceinline__ int moving_body(const StepArgs<R>& a, int i, int j)
+{
+    const double* row = a.pose + (int64_t)a.pose_row * MAX_MOVING * POSE_STRIDE;
+    for (int b = 0; b < a.n_moving; ++b) {
+        const double* m = row + b * POSE_STRIDE;
+        const double dx = (double)i - m[2];
+        const double dy = (double)j - m[3];
+        const double dx2 = dx * dx;
+        const double dy2 = dy * dy;
+        if (dx2 + dy2 > m[6]) continue;
+        const double a1 = m[0] * dx;
+        const double a2 = m[1] * dy;
+        const double s1 = a1 + a2;
+        const double xr = s1 + m[4];
+        const double b1 = m[0] * dy;
+        const double b2 = m[1] * dx;
+        const double s2 = b1 - b2;
+        const double yr = s2 + m[5];
+        const double fx = floor(xr + 0.5);
+        const double fy = floor(yr + 0.5);
+        if (fx < 0.0 || fy < 0.0 || fx >= (double)a.nx || fy >= (double)a.ny) continue;
+        if (a.mask[(int64_t)fy * a.pitch + (int64_t)fx] == b + 1) return b + 1;
+    }
+    return 0;
 }
 
 // D2Q9 directions (eq. D2Q9) and the opposite map (Sec. 2.1: f_{-1} = f_3).
@@ -444,7 +483,7 @@ __device__ __forceinline__ int xcd_tile(int per_xcd, int first_block)
 // consecutive nodes per thread. part_buf: the partial buffer this step's record
 // writes (the previous record is summed by leading blocks of the same launch).
 // lds: the kernel's 2 FIN_LANES doubles.
-template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false>
 __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a, int t,
                                           int part_buf, double* lds)
 {
@@ -509,7 +548,12 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
             for (int k = 0; k < V; ++k) v[q][k] = as_lv<LV>(raw[k]);
         }
-        load_mask<V>(a.mask + r0 + i0, body);
+        if constexpr (MOVING) {
+#pragma unroll
+            for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, i0 + k, j) : 0;
+        } else {
+            load_mask<V>(a.mask + r0 + i0, body);
+        }
     } else {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
@@ -571,7 +615,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 f[q] = pull_column<MODE, S, R>(src, q, MODE == AA_PUSH ? OPP[q] : q, row_of[q], row_idx[q], a.nx, a);
             }
         }
-        const NodeResult<R> n = collide_node<R>(f, body[k], i, j, a);
+        const NodeResult<R> n = collide_node<R, MOVING>(f, body[k], i, j, a);
 #pragma unroll
         for (int q = 0; q < 9; ++q) out[q][k] = enc<S>(f[q]);
         fl_rho[k] = n.rho;
@@ -701,10 +745,33 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         int bid[V];
 #pragma unroll
         for (int k = 0; k < V; ++k) bid[k] = 0;
-        if (s1 > s0 && act) load_mask<V>(a.mask + r0 + i0, bid);
+        if (s1 > s0 && act) {
+            if constexpr (MOVING) {
+#pragma unroll
+                for (int k = 0; k < V; ++k) bid[k] = (k < n_own) ? moving_body(a, i0 + k, j) : 0;
+            } else {
+                load_mask<V>(a.mask + r0 + i0, bid);
+            }
+        }
         const R* fv = dyn_lds<R>();
         for (int s = s0; s < s1; ++s) {
             const int b = a.slot_body[s];
+            if constexpr (MOVING) {
+                // slots are dense (every tile, every body): skip bodies whose radius
+                // misses this tile's rectangle (uniform across the block)
+                const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (b - 1)) * POSE_STRIDE;
+                const double x0 = (double)(tx * a.tile_w), x1 = x0 + (double)(a.tile_w - 1);
+                const double y0 = (double)(ty * a.tile_rows), y1 = y0 + (double)(a.tile_rows - 1);
+                const double ex = m[2] < x0 ? x0 - m[2] : (m[2] > x1 ? m[2] - x1 : 0.0);
+                const double ey = m[3] < y0 ? y0 - m[3] : (m[3] > y1 ? m[3] - y1 : 0.0);
+                if (ex * ex + ey * ey > m[6]) {
+                    if (threadIdx.x == 0) {
+                        slot_force[2 * s] = 0.0;
+                        slot_force[2 * s + 1] = 0.0;
+                    }
+                    continue;
+                }
+            }
             double px = 0.0, py = 0.0;
 #pragma unroll
             for (int k = 0; k < V; ++k) {
@@ -724,7 +791,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 }
 
 // Two lattices: source and destination never alias.
-template <typename S, int V, bool RECORD, bool FIELDS>
+template <typename S, int V, bool RECORD, bool FIELDS, bool MOVING = false>
 __global__ void __launch_bounds__(256)
 k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
 {
@@ -737,11 +804,11 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     }
     const int t = xcd_tile(a.tiles_per_xcd, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, PULL, RECORD, FIELDS>(src, dst, a, t, a.part_buf, lds);
+    step_body<S, V, PULL, RECORD, FIELDS, MOVING>(src, dst, a, t, a.part_buf, lds);
 }
 
 // One lattice, read and written in place (no restrict).
-template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false>
 __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith<S>::R> a)
 {
     __shared__ double lds[2 * FIN_LANES];
@@ -752,7 +819,7 @@ __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith
     }
     const int t = xcd_tile(a.tiles_per_xcd, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, MODE, RECORD, FIELDS>(lat, lat, a, t, a.part_buf, lds);
+    step_body<S, V, MODE, RECORD, FIELDS, MOVING>(lat, lat, a, t, a.part_buf, lds);
 }
 
 // Many domains in one launch: block -> (domain, tile) through the tile map;
@@ -902,7 +969,7 @@ size_t record_lds_bytes(int v, int block)
     return 2 * (size_t)v * (size_t)block * sizeof(R);
 }
 
-template <typename S, int V>
+template <typename S, int V, bool MOVING = false>
 hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const StepArgs<typename Arith<S>::R>& a,
                   hipStream_t s)
 {
@@ -910,30 +977,30 @@ hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const
     const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, a.block);
     if (mode == PULL) {
         if (record) {
-            if (fields) hipLaunchKernelGGL((k_step<S, V, true, true>), grid, block, lds, s, in, out, a);
-            else hipLaunchKernelGGL((k_step<S, V, true, false>), grid, block, lds, s, in, out, a);
+            if (fields) hipLaunchKernelGGL((k_step<S, V, true, true, MOVING>), grid, block, lds, s, in, out, a);
+            else hipLaunchKernelGGL((k_step<S, V, true, false, MOVING>), grid, block, lds, s, in, out, a);
         } else {
-            if (fields) hipLaunchKernelGGL((k_step<S, V, false, true>), grid, block, 0, s, in, out, a);
-            else hipLaunchKernelGGL((k_step<S, V, false, false>), grid, block, 0, s, in, out, a);
+            if (fields) hipLaunchKernelGGL((k_step<S, V, false, true, MOVING>), grid, block, 0, s, in, out, a);
+            else hipLaunchKernelGGL((k_step<S, V, false, false, MOVING>), grid, block, 0, s, in, out, a);
         }
         return hipGetLastError();
     }
     if constexpr (sizeof(S) >= 4 || V == 1) {
         if (mode == AA_PUSH) {
             if (record) {
-                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, true>), grid, block, lds, s, out, a);
-                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, false>), grid, block, lds, s, out, a);
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, true, MOVING>), grid, block, lds, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, true, false, MOVING>), grid, block, lds, s, out, a);
             } else {
-                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, true>), grid, block, 0, s, out, a);
-                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, false>), grid, block, 0, s, out, a);
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, true, MOVING>), grid, block, 0, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_PUSH, false, false, MOVING>), grid, block, 0, s, out, a);
             }
         } else {
             if (record) {
-                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, true>), grid, block, lds, s, out, a);
-                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, false>), grid, block, lds, s, out, a);
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, true, MOVING>), grid, block, lds, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, true, false, MOVING>), grid, block, lds, s, out, a);
             } else {
-                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, true>), grid, block, 0, s, out, a);
-                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, false>), grid, block, 0, s, out, a);
+                if (fields) hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, true, MOVING>), grid, block, 0, s, out, a);
+                else hipLaunchKernelGGL((k_step_aa<S, V, AA_LOCAL, false, false, MOVING>), grid, block, 0, s, out, a);
             }
         }
         return hipGetLastError();
@@ -957,6 +1024,16 @@ hipError_t step_typed(int mode, bool record, bool fields, const void* src, void*
         if (a.vec == 4) return step_v<S, 4>(mode, record, fields, in, out, a, s);
     }
     return hipErrorInvalidValue;
+}
+
+template <typename S>
+hipError_t step_typed_moving(int mode, bool record, bool fields, const void* src, void* dst, const void* args_v,
+                             hipStream_t s)
+{
+    using R = typename Arith<S>::R;
+    const StepArgs<R>& a = *static_cast<const StepArgs<R>*>(args_v);
+    if (a.vec != 1) return hipErrorInvalidValue;   // moving masks run one node per thread
+    return step_v<S, 1, true>(mode, record, fields, static_cast<const S*>(src), static_cast<S*>(dst), a, s);
 }
 
 template <typename S, int V, int MODE>
@@ -1020,6 +1097,18 @@ hipError_t launch_step(int32_t storage, int32_t mode, bool record, bool fields, 
     case ST_F32: return step_typed<float>(mode, record, fields, src, dst, step_args, s);
     case ST_F16: return step_typed<_Float16>(mode, record, fields, src, dst, step_args, s);
     case ST_BF16: return step_typed<__bf16>(mode, record, fields, src, dst, step_args, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step_moving(int32_t storage, int32_t mode, bool record, bool fields, const void* src, void* dst,
+                              const void* step_args, hipStream_t s)
+{
+    switch (storage) {
+    case ST_F64: return step_typed_moving<double>(mode, record, fields, src, dst, step_args, s);
+    case ST_F32: return step_typed_moving<float>(mode, record, fields, src, dst, step_args, s);
+    case ST_F16: return step_typed_moving<_Float16>(mode, record, fields, src, dst, step_args, s);
+    case ST_BF16: return step_typed_moving<__bf16>(mode, record, fields, src, dst, step_args, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -287,6 +287,7 @@ lbvp_status lbvp_pool_admit(lbvp_pool* p, const lbvp_params* prm, const uint8_t*
     if (n_steps > (int64_t(1) << 26)) return p->fail(LBVP_E_ARG, "n_steps larger than the force ring allows");
     if (prm->storage != p->cfg.storage || (prm->flags & LBVP_LAYOUT_AA) != p->cfg.layout_flags)
         return p->fail(LBVP_E_ARG, "the solve's storage and layout must be the pool's");
+    if (prm->flags & LBVP_MOVING_BODIES) return p->fail(LBVP_E_ARG, "solves with moving bodies run alone");
     if (n_bodies < 0 || n_bodies > 255) return p->fail(LBVP_E_ARG, "n_bodies must be in 0..255");
     if (p->free_slots.empty()) return p->fail(LBVP_E_BUSY, "no free slot");
     lbvp_params q = *prm;

@@ -54,6 +54,7 @@ class Problem:
     steps: int = 0
     u_ref: float = 0.0                       # U_inf for force coefficients
     l_ref: float = 1.0                       # D (or chord) for force coefficients
+    moving: bool = False                     # bodies move rigidly (the mask follows them)
 
     @property
     def n_bodies(self) -> int:
@@ -347,6 +348,38 @@ def request_stream(rate: float, n: int, seed: int = 5, step_lo: int = 1000,
         p.steps = int(round(math.exp(rng.uniform(math.log(step_lo), math.log(step_hi)))))
         out.append(Request(rid=k, arrival=t, problem=p))
     return out
+
+
+def moving_bodies(nx: int = 160, ny: int = 96, seed: int = 7, bc=(PERIODIC,) * 4, u_in: float = 0.0,
+                  tau_plus: float = 0.7, magic_lambda: float = 0.25, eta: float = 1e-4) -> Problem:
+    """Rigidly moving bodies (time-dependent mask): a disk translating with
+    V = (0.03, 0.012), an elliptic body turning at omega = 0.004 about its centre
+    while drifting, and a NACA-0012 (chord 24) pitching at omega = -0.003 about
+    its quarter chord. Fluid with small random velocities."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    paint_disk(mask, 40.0, 30.0, 7.0, 1)
+    x, y = _grid(nx, ny)
+    ex, ey = 90.0, 62.0
+    ang = math.radians(25.0)
+    xr = (x - ex) * math.cos(ang) + (y - ey) * math.sin(ang)
+    yr = -(x - ex) * math.sin(ang) + (y - ey) * math.cos(ang)
+    mask[((xr / 10.0) ** 2 + (yr / 4.0) ** 2 <= 1.0) & (mask == 0)] = 2
+    chord, le = 24.0, (112.0, 28.0)
+    pivot = (le[0] + chord / 4.0, le[1])
+    foil = np.zeros_like(mask)
+    paint_naca0012(foil, le[0], le[1], chord, 8.0, pivot, 3)
+    mask[(foil == 3) & (mask == 0)] = 3
+    bodies = np.array([[40.0, 30.0, 0.03, 0.012, 0.0],
+                       [ex, ey, -0.01, 0.005, 0.004],
+                       [pivot[0], pivot[1], 0.0, 0.0, -0.003]])
+    u = 0.02
+    rho = 1.0 + 0.002 * rng.uniform(-1, 1, size=(ny, nx))
+    ux = u_in + u * rng.uniform(-1, 1, size=(ny, nx))
+    uy = u * rng.uniform(-1, 1, size=(ny, nx))
+    return Problem(name=f"moving{nx}x{ny}", nx=nx, ny=ny, tau_plus=tau_plus, magic_lambda=magic_lambda, eta=eta,
+                   bc=tuple(bc), rho_in=1.0, u_in=(u_in, 0.0), mask=mask, bodies=bodies, rho_init=rho,
+                   ux_init=ux, uy_init=uy, u_ref=max(u_in, 0.03), l_ref=14.0, moving=True)
 
 
 def taylor_green(n: int = 64, u0: float = 1e-3, tau_plus: float = 0.8, magic_lambda: float = 0.25,

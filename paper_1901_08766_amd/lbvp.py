@@ -27,6 +27,7 @@ STATUS_NAMES = ["OK", "E_ARG", "E_NOMEM", "E_BUSY", "E_DEVICE", "E_STATE", "E_UN
 BC = {"periodic": 0, "inflow_eq": 1, "outflow_zero_grad": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 LAYOUT_AA = 0x1
+MOVING_BODIES = 0x2
 KEEP_FIELDS = 0x1
 GRAPH = 0x2
 TUNE_LAYOUTS = 0x1
@@ -408,7 +409,7 @@ def params_for(prob, storage: str = "f32", force_every: int = 1, force_capacity:
     p.force_every = force_every
     p.force_capacity = force_capacity
     p.max_bodies = max_bodies if max_bodies else max(8, prob.n_bodies)
-    p.flags = flags
+    p.flags = flags | (MOVING_BODIES if getattr(prob, "moving", False) else 0)
     return p
 
 

@@ -126,3 +126,10 @@ def test_device_copy_rejects_misaligned_arguments(lbvp):
     assert L.lbvp_device_copy(C.c_void_p(8), C.c_void_p(32), 16, None) == lbvp.E_ARG
     assert L.lbvp_device_copy(None, C.c_void_p(32), 16, None) == lbvp.E_ARG
     assert L.lbvp_device_copy(C.c_void_p(16), C.c_void_p(32), 0, None) == lbvp.OK
+
+
+def test_moving_bodies_limit(lbvp):
+    p = _params(lbvp, flags=lbvp.MOVING_BODIES, max_bodies=9)
+    out = C.c_void_p()
+    assert lbvp.lib().lbvp_create(C.byref(p), None, None, 0, C.byref(out)) == lbvp.E_ARG
+    assert "moving" in lbvp.lbvp_last_error(None)

@@ -19,7 +19,7 @@ MUTANTS = [
     ("guo factor applied twice", "(1.0 - 1.0 / (2.0 * tau_s)) * Fs",
      "(1.0 - 1.0 / (2.0 * tau_s)) * (1.0 - 1.0 / (2.0 * tau_s)) * Fs"),
     ("antisymmetric forcing factor dropped", "(1.0 - 1.0 / (2.0 * tau_a)) * Fa;", "Fa;"),
-    ("rotation sign", "*UOx = B[2] - B[4] * (y - B[1]);", "*UOx = B[2] + B[4] * (y - B[1]);"),
+    ("rotation sign", "*UOx = B[2] - B[4] * (y - cy);", "*UOx = B[2] + B[4] * (y - cy);"),
     ("opposite map mirrored", "{0, 3, 4, 1, 2, 7, 8, 5, 6}", "{0, 3, 4, 1, 2, 8, 7, 6, 5}"),
     ("body-force half step dropped", "(jx + 0.5 * fbx)", "(jx)"),
     ("equilibrium at u*", "lbvp_ref_feq(rho, ux, uy, feq);", "lbvp_ref_feq(rho, usx, usy, feq);"),
@@ -40,6 +40,12 @@ MUTANTS = [
      "out[0] = c * (UOx - usx) / (eta + c);"),
     ("mass not summed over all rows", "for (int j = 0; j < ny; ++j) m += c->row_mass[j];",
      "for (int j = 1; j < ny; ++j) m += c->row_mass[j];"),
+    ("moving body turned the wrong way", "const double xr = cs * dx + sn * dy + B[0];",
+     "const double xr = cs * dx - sn * dy + B[0];"),
+    ("moving body not translated", "*cx = B[0] + B[2] * t;", "*cx = B[0];"),
+    ("moving mask one step behind", "const double t = (double)(c->step + 1);", "const double t = (double)(c->step);"),
+    ("moving mask rounded down", "const double ir = floor(xr + 0.5), jr = floor(yr + 0.5);",
+     "const double ir = floor(xr), jr = floor(yr);"),
 ]
 
 
@@ -59,7 +65,8 @@ def _run_mutant(case, tmpdir):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         "-m", "not slow",
                         os.path.join(ROOT, "tests", "test_oracle_node.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_grid.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_grid.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_moving.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 
