@@ -1,0 +1,277 @@
+"""Pins of the FP64 D3Q19 oracle against what the mathematics fixes.
+
+Node level:
+- the velocity set is the 19 integer vectors of length^2 <= 2, each with its
+  opposite, and the weights are the unique speed-class weights whose moments are
+  isotropic up to fourth order;
+- the equilibrium reproduces rho, rho u and rho (c_s^2 I + u u);
+- the Guo term has moments 0, F and u F + F u;
+- the TRT collision relaxes symmetric and antisymmetric deviations at 1/tau_s
+  and 1/tau_a, and is BGK when the two coincide;
+- a node update conserves mass and adds exactly F_b + F_VP of momentum, and the
+  penalized velocity satisfies the implicit closed form.
+Grid level:
+- a z-invariant problem reduces to the (separately pinned) D2Q9 oracle: the
+  D3Q19 populations summed over their z components are the D2Q9 populations;
+- relabelling the axes of a periodic problem relabels the solution, and a whole-
+  cell translation moves it bitwise;
+- a periodic box conserves mass and changes its momentum by the applied forces;
+- a shear wave decays at nu k^2 with nu = c_s^2 (tau_+ - 1/2), along every axis;
+- a plate channel reaches the Poiseuille curvature -F/(rho nu).
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from paper_1901_08766_amd import inputs, inputs3
+
+CS2 = 1.0 / 3.0
+
+
+@pytest.fixture(scope="module")
+def ref3():
+    from oracle import ref3 as mod
+    mod.lib()
+    return mod
+
+
+def _E(ref3):
+    ex, ey, ez, w, opp = ref3.lattice()
+    return np.stack([ex, ey, ez], axis=1).astype(np.float64), w, opp
+
+
+# ------------------------------------------------------------------ node --
+
+def test_velocity_set_and_weights(ref3):
+    E, w, opp = _E(ref3)
+    expect = {v for v in itertools.product((-1, 0, 1), repeat=3) if sum(c * c for c in v) <= 2}
+    got = [tuple(int(c) for c in e) for e in E]
+    assert len(got) == 19 and set(got) == expect
+    assert got[0] == (0, 0, 0)
+    for a in range(19):
+        assert np.array_equal(E[opp[a]], -E[a]) and opp[opp[a]] == a
+    by_class = {0: 1.0 / 3.0, 1: 1.0 / 18.0, 2: 1.0 / 36.0}
+    for a in range(19):
+        assert w[a] == by_class[int((E[a] ** 2).sum())]
+    # isotropy up to fourth order
+    d = np.eye(3)
+    assert abs(w.sum() - 1.0) < 1e-15
+    assert np.abs(np.einsum("a,ai->i", w, E)).max() < 1e-16
+    assert np.abs(np.einsum("a,ai,aj->ij", w, E, E) - CS2 * d).max() < 1e-15
+    assert np.abs(np.einsum("a,ai,aj,ak->ijk", w, E, E, E)).max() < 1e-16
+    m4 = np.einsum("a,ai,aj,ak,al->ijkl", w, E, E, E, E)
+    iso = CS2 * CS2 * (np.einsum("ij,kl->ijkl", d, d) + np.einsum("ik,jl->ijkl", d, d)
+                       + np.einsum("il,jk->ijkl", d, d))
+    assert np.abs(m4 - iso).max() < 1e-15
+
+
+def test_equilibrium_moments(ref3):
+    E, _, _ = _E(ref3)
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = rng.uniform(0.8, 1.2)
+        u = rng.uniform(-0.1, 0.1, 3)
+        fe = ref3.feq(rho, u)
+        assert abs(fe.sum() - rho) < 1e-15
+        assert np.abs(E.T @ fe - rho * u).max() < 1e-16
+        pi = np.einsum("a,ai,aj->ij", fe, E, E)
+        assert np.abs(pi - rho * (CS2 * np.eye(3) + np.outer(u, u))).max() < 1e-15
+
+
+def test_guo_moments(ref3):
+    E, _, _ = _E(ref3)
+    rng = np.random.default_rng(2)
+    for _ in range(20):
+        u = rng.uniform(-0.1, 0.1, 3)
+        F = rng.uniform(-1e-3, 1e-3, 3)
+        Fa = ref3.guo(u, F)
+        assert abs(Fa.sum()) < 1e-18
+        assert np.abs(E.T @ Fa - F).max() < 1e-18
+        m2 = np.einsum("a,ai,aj->ij", Fa, E, E)
+        assert np.abs(m2 - (np.outer(u, F) + np.outer(F, u))).max() < 1e-18
+
+
+def test_trt_relaxes_each_parity_at_its_own_rate(ref3):
+    _, _, opp = _E(ref3)
+    rng = np.random.default_rng(3)
+    fe = ref3.feq(1.02, [0.03, -0.02, 0.01])
+    s = rng.uniform(-1e-3, 1e-3, 19)
+    sym, anti = 0.5 * (s + s[opp]), 0.5 * (s - s[opp])
+    ts, ta = 0.83, 1.37
+    zero = np.zeros(19)
+    g = ref3.trt_collide(fe + sym, fe, zero, ts, ta)
+    assert np.abs(g - (fe + sym * (1.0 - 1.0 / ts))).max() < 1e-16
+    g = ref3.trt_collide(fe + anti, fe, zero, ts, ta)
+    assert np.abs(g - (fe + anti * (1.0 - 1.0 / ta))).max() < 1e-16
+    # forcing: each parity of the source weighted by (1 - 1/(2 tau)) of its rate
+    F = rng.uniform(-1e-4, 1e-4, 19)
+    Fs, Fa = 0.5 * (F + F[opp]), 0.5 * (F - F[opp])
+    g = ref3.trt_collide(fe, fe, F, ts, ta)
+    assert np.abs(g - (fe + (1 - 0.5 / ts) * Fs + (1 - 0.5 / ta) * Fa)).max() < 1e-17
+
+
+def test_equal_rates_give_bgk(ref3):
+    rng = np.random.default_rng(4)
+    f = ref3.feq(1.0, [0.02, 0.01, -0.03]) + rng.uniform(-1e-3, 1e-3, 19)
+    fe = ref3.feq(1.01, [0.021, 0.012, -0.028])
+    F = rng.uniform(-1e-4, 1e-4, 19)
+    tau = 0.9
+    g = ref3.trt_collide(f, fe, F, tau, tau)
+    assert np.abs(g - (f - (f - fe) / tau + (1 - 0.5 / tau) * F)).max() < 1e-16
+
+
+@pytest.mark.parametrize("chi", [0, 1])
+def test_node_update_budget_and_penalization(ref3, chi):
+    E, _, _ = _E(ref3)
+    rng = np.random.default_rng(5 + chi)
+    f = ref3.feq(1.03, [0.04, -0.01, 0.02]) + rng.uniform(-2e-3, 2e-3, 19)
+    uo = np.array([0.01, -0.02, 0.005])
+    fb = np.array([1e-5, -2e-5, 3e-5])
+    eta = 1e-3
+    g, fl = ref3.collide_node(f, 0.77, 1.1, eta, chi, uo, fb)
+    rho, u, fvp = fl[0], fl[1:4], fl[4:7]
+    j = E.T @ f
+    assert abs(rho - f.sum()) < 1e-15
+    assert abs(g.sum() - f.sum()) < 1e-14
+    assert np.abs(E.T @ g - (j + fb + fvp)).max() < 1e-15
+    us = (j + 0.5 * fb) / rho
+    assert np.abs(fvp - 2.0 * rho * (u - us)).max() < 1e-16
+    if chi:
+        assert np.abs((u - uo) - (us - uo) * 2 * eta / (2 * eta + 1)).max() < 1e-16
+    else:
+        assert np.abs(fvp).max() == 0.0 and np.abs(u - us).max() < 1e-16
+
+
+# ------------------------------------------------------------------ grid --
+
+def test_z_invariant_problem_is_the_2d_scheme(ref3, oracle):
+    p2 = inputs.random_state_problem(26, 18, seed=4, n_disks=3, body_force=(2e-5, -1e-5))
+    p2.rho_in = 1.01                              # distinct from rho0: the inflow density shows
+    nz = 3
+    p3 = inputs3.extrude(p2, nz)
+    s2, s3 = oracle.RefSolver(p2), ref3.RefSolver3(p3)
+    f2, m2 = s2.step(12, record=True)
+    f3, m3 = s3.step(12, record=True)
+    ex2, ey2, _, _ = oracle.lattice()
+    E3, _, _ = _E(ref3)
+    g2, g3 = s2.populations(), s3.populations()
+    proj = np.zeros_like(g2)
+    for a in range(19):
+        b = [q for q in range(9) if ex2[q] == E3[a, 0] and ey2[q] == E3[a, 1]]
+        assert len(b) == 1
+        proj[b[0]] += g3[a].sum(axis=0) / nz
+    assert np.abs(proj - g2).max() < 1e-14
+    # every plane is the same 2-D state
+    for k in range(1, nz):
+        assert np.abs(g3[:, k] - g3[:, 0]).max() < 1e-15
+    fl2, fl3 = s2.fields(), s3.fields()
+    for name in ("rho", "ux", "uy", "fx", "fy"):
+        assert np.abs(fl3[name] - fl2[name][None]).max() < 1e-14, name
+    assert np.abs(fl3["uz"]).max() < 1e-18 and np.abs(fl3["fz"]).max() < 1e-18
+    assert np.abs(f3[..., :2] - nz * f2).max() < 1e-13 * max(1.0, np.abs(f2).max())
+    assert np.abs(f3[..., 2]).max() < 1e-16
+    assert np.abs(m3 - nz * m2).max() < 1e-10
+
+
+def _periodic_problem(seed=6, shape=(12, 10, 8)):
+    p = inputs3.random_state_problem3(*shape, seed=seed, n_spheres=3, bc=("periodic", "periodic"),
+                                      body_force=(1e-5, -2e-5, 3e-5))
+    return p
+
+
+@pytest.mark.parametrize("order", [(1, 2, 0), (0, 2, 1), (2, 1, 0)])
+def test_axis_relabelling(ref3, order):
+    p = _periodic_problem()
+    q = inputs3.permute_axes(p, order)
+    sp, sq = ref3.RefSolver3(p), ref3.RefSolver3(q)
+    fp, _ = sp.step(6, record=True)
+    fq, _ = sq.step(6, record=True)
+    a, b = sp.fields(), sq.fields()
+    perm = tuple(2 - order[2 - k] for k in range(3))
+    names = (("ux", "fx"), ("uy", "fy"), ("uz", "fz"))
+    assert np.abs(np.transpose(a["rho"], perm) - b["rho"]).max() < 1e-14
+    for d in range(3):
+        for c in range(2):
+            assert np.abs(np.transpose(a[names[order[d]][c]], perm) - b[names[d][c]]).max() < 1e-14
+    assert np.abs(fp[..., list(order)] - fq).max() < 1e-13
+
+
+def test_whole_cell_translation_is_bitwise(ref3):
+    nx, ny, nz = 14, 12, 10
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    inputs3.paint_sphere(mask, 5.5, 5.25, 4.75, 2.6, 1)
+    inputs3.paint_box(mask, (8, 2, 2), (10, 5, 4), 2)
+    bodies = np.array([[5.5, 5.25, 4.75, 0.01, -0.004, 0.002, 0.003, -0.002, 0.005],
+                       [9.0, 3.5, 3.0, 0.0, 0.002, 0.0, 0.004, 0.0, -0.001]])
+    base = _periodic_problem(seed=7, shape=(nx, ny, nz))
+    base.mask, base.bodies = mask, bodies
+    s = (2, 3, 1)                                 # no solid node wraps round
+    moved = inputs3.Problem3(**{**base.__dict__})
+    roll = lambda a: np.roll(a, shift=(s[2], s[1], s[0]), axis=(0, 1, 2))  # noqa: E731
+    moved.mask = roll(mask)
+    moved.bodies = bodies.copy()
+    moved.bodies[:, :3] += np.array(s, np.float64)
+    moved.rho_init, moved.ux_init, moved.uy_init, moved.uz_init = (
+        roll(a) for a in (base.rho_init, base.ux_init, base.uy_init, base.uz_init))
+    sa, sb = ref3.RefSolver3(base), ref3.RefSolver3(moved)
+    sa.step(5)
+    sb.step(5)
+    assert np.array_equal(roll(sa.populations().transpose(1, 2, 3, 0)), sb.populations().transpose(1, 2, 3, 0))
+
+
+def test_periodic_box_budgets(ref3):
+    p = _periodic_problem(seed=8, shape=(10, 9, 8))
+    s = ref3.RefSolver3(p)
+    E, _, _ = _E(ref3)
+    n = p.n_nodes
+    fb = np.array(p.body_force)
+    for _ in range(5):
+        g0 = s.populations()
+        M0 = g0.sum()
+        P0 = np.einsum("aijk,ad->d", g0, E)
+        f, m = s.step(1, record=True)
+        g1 = s.populations()
+        fl = s.fields()
+        P1 = np.einsum("aijk,ad->d", g1, E)
+        F = np.array([fl["fx"].sum(), fl["fy"].sum(), fl["fz"].sum()])
+        assert abs(g1.sum() - M0) < 1e-13 * n
+        assert abs(m[0] - fl["rho"].sum()) < 1e-12
+        assert np.abs(P1 - P0 - n * fb - F).max() < 1e-14 * n
+        assert np.abs(f[0].sum(axis=0) + F).max() < 1e-13
+
+
+@pytest.mark.parametrize("axes", [(0, 2), (2, 0), (1, 0)])
+def test_shear_wave_decays_at_the_lattice_viscosity(ref3, axes):
+    n, steps = 24, 300
+    p = inputs3.shear_wave(n=n, axis_u=axes[0], axis_k=axes[1], tau_plus=0.8)
+    s = ref3.RefSolver3(p)
+    comp = ("ux", "uy", "uz")[axes[0]]
+    a0 = np.abs(s.fields()[comp]).max()
+    s.step(steps)
+    fl = s.fields()
+    a1 = np.abs(fl[comp]).max()
+    nu = CS2 * (p.tau_plus - 0.5)
+    k = 2.0 * math.pi / n
+    rate = -math.log(a1 / a0) / steps
+    assert abs(rate / (nu * k * k) - 1.0) < 0.005
+    # the other velocity components stay at rest
+    for c in ("ux", "uy", "uz"):
+        if c != comp:
+            assert np.abs(fl[c]).max() < 1e-15
+
+
+@pytest.mark.slow
+def test_plate_channel_poiseuille_curvature(ref3):
+    p = inputs3.plate_channel(nz=24, nxy=4, wall=2, fx=1e-6, tau_plus=0.9)
+    s = ref3.RefSolver3(p)
+    s.step(20_000)
+    fl = s.fields()
+    ux = fl["ux"][:, 0, 0]
+    assert np.abs(fl["ux"] - ux[:, None, None]).max() < 1e-15
+    nu = CS2 * (p.tau_plus - 0.5)
+    rho = fl["rho"][6:18, 0, 0]
+    d2 = ux[5:17] + ux[7:19] - 2 * ux[6:18]
+    assert np.abs(d2 / (-p.body_force[0] / (rho * nu)) - 1.0).max() < 1e-4
+    assert np.abs(fl["uy"]).max() < 1e-18 and np.abs(fl["uz"]).max() < 1e-12
