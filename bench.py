@@ -34,7 +34,7 @@ COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("lbvp_kernels.hip", "lbvp_internal.h"):
+    for name in ("lbvp_kernels.hip", "lbvp_device.h", "lbvp_internal.h"):
         with open(os.path.join(ROOT, "paper_1901_08766_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]

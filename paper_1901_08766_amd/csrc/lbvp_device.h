@@ -1,0 +1,270 @@
+// lbvp_device.h -- device building blocks shared by the D2Q9 and D3Q19 step
+// kernels: storage codecs, aligned and one-off vector accesses, deterministic
+// block and record sums, the quotients whose rounding must not drift, the
+// collision of one population pair, and the XCD-aware tile order.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+namespace lbvp {
+namespace {
+
+constexpr int N_XCD_DEV = 8;   // XCDs of an MI355X; workgroups are dealt to them round-robin
+// ------------------------------------------------------------ storage codecs --
+__device__ __forceinline__ double dec(double v) { return v; }
+__device__ __forceinline__ float dec(float v) { return v; }
+__device__ __forceinline__ float dec(_Float16 v) { return (float)v; }
+__device__ __forceinline__ float dec(__bf16 v) { return (float)v; }
+
+// A loaded element kept in the storage type (LV = S) or decoded (LV = R).
+template <typename LV, typename S>
+__device__ __forceinline__ LV as_lv(S x)
+{
+    if constexpr (std::is_same<LV, S>::value) return x;
+    else return dec(x);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ S enc(R v) { return (S)v; }  // round to nearest even
+
+template <typename S> struct Arith { using R = float; };
+template <> struct Arith<double> { using R = double; };
+
+// V consecutive elements moved as one aligned access of V * sizeof(S) bytes.
+template <typename S, int V>
+__device__ __forceinline__ void load_vec(const S* p, S (&out)[V])
+{
+    constexpr int B = V * (int)sizeof(S);
+    if constexpr (B == 16) {
+        const uint4 r = *reinterpret_cast<const uint4*>(p);
+        __builtin_memcpy(out, &r, 16);
+    } else if constexpr (B == 8) {
+        const uint2 r = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(out, &r, 8);
+    } else if constexpr (B == 4) {
+        const uint32_t r = *reinterpret_cast<const uint32_t*>(p);
+        __builtin_memcpy(out, &r, 4);
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) out[k] = p[k];
+    }
+}
+
+// Stores are non-temporal: the new lattice is not read again before the whole
+// domain has streamed through the caches, so it should not displace anything.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2_t __attribute__((ext_vector_type(2)));
+
+template <typename S, int V>
+__device__ __forceinline__ void store_vec(S* p, const S (&in)[V])
+{
+    constexpr int B = V * (int)sizeof(S);
+    if constexpr (B == 16) {
+        u32x4_t r;
+        __builtin_memcpy(&r, in, 16);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x4_t*>(p));
+    } else if constexpr (B == 8) {
+        u32x2_t r;
+        __builtin_memcpy(&r, in, 8);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x2_t*>(p));
+    } else if constexpr (B == 4) {
+        uint32_t r;
+        __builtin_memcpy(&r, in, 4);
+        __builtin_nontemporal_store(r, reinterpret_cast<uint32_t*>(p));
+    } else if constexpr (B == 2) {
+        uint16_t r;
+        __builtin_memcpy(&r, in, 2);
+        __builtin_nontemporal_store(r, reinterpret_cast<uint16_t*>(p));
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) p[k] = in[k];
+    }
+}
+
+// The same V elements starting one element off a 16-byte boundary: a single
+// vector access that needs only the element's own (dword or wider) alignment.
+template <typename S, int V>
+__device__ __forceinline__ void load_vec_shifted(const S* p, S (&out)[V])
+{
+    static_assert(sizeof(S) >= 4 || V == 1, "sub-dword vectors take the lane-shuffle path");
+    __builtin_memcpy(out, p, V * sizeof(S));
+}
+
+template <int V>
+__device__ __forceinline__ void load_mask(const uint8_t* p, int (&out)[V])
+{
+    uint8_t b[V];
+    if constexpr (V == 8) {
+        const uint2 r = *reinterpret_cast<const uint2*>(p);
+        __builtin_memcpy(b, &r, 8);
+    } else if constexpr (V == 4) {
+        const uint32_t r = *reinterpret_cast<const uint32_t*>(p);
+        __builtin_memcpy(b, &r, 4);
+    } else if constexpr (V == 2) {
+        const uint16_t r = *reinterpret_cast<const uint16_t*>(p);
+        __builtin_memcpy(b, &r, 2);
+    } else {
+        b[0] = p[0];
+    }
+#pragma unroll
+    for (int k = 0; k < V; ++k) out[k] = b[k];
+}
+
+// ------------------------------------------------------------ reductions --
+// Dynamic LDS of a recording step launch: [2][V][blockDim] values of the
+// arithmetic type (the penalization force of every node of the tile).
+template <typename R>
+__device__ __forceinline__ R* dyn_lds()
+{
+    extern __shared__ __align__(16) unsigned char lds_dyn[];
+    return reinterpret_cast<R*>(lds_dyn);
+}
+
+
+// Sum over the block in a fixed order (deterministic): wavefront shuffles, then
+// the per-wavefront sums in wavefront order. lds holds one double per wavefront
+// and is reused across calls; every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* lds)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const int nw = (int)(blockDim.x >> 6);
+    double s = lds[0];
+    for (int w = 1; w < nw; ++w) s += lds[w];
+    return s;
+}
+
+// ------------------------------------------------------------ the collision --
+// Quotients that must not carry a fixed relative error (a biased 1/36 or 1/rho
+// would bias every collision's momentum, which a decaying flow accumulates): FP64
+// divides; FP32 multiplies by the rounded reciprocal and corrects with the exact
+// residual (one FMA), which returns the quotient to within a hair of correct
+// rounding with no systematic direction, in 3 instructions instead of ~10.
+__device__ __forceinline__ double div36(double s) { return s / 36.0; }
+__device__ __forceinline__ float div36(float s)
+{
+    const float r = 1.0f / 36.0f;
+    const float q = s * r;
+    return __builtin_fmaf(__builtin_fmaf(-36.0f, q, s), r, q);
+}
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);            // ~1 ulp
+    return __builtin_fmaf(__builtin_fmaf(-x, r, 1.0f), r, r);  // one Newton step
+}
+
+template <typename R>
+struct Pair {
+    R ga, gb;
+};
+
+// Per-node terms shared by the pair collisions of a node, in weight-normalized
+// units (h_a = (f_a - w_a rho0) / w_a).
+template <typename R>
+struct NodeTerms {
+    R A;        // drho - 3/2 rho u.u : the even equilibrium without its eu^2 part
+    R rho45;    // 9/2 rho
+    R rho3;     // 3 rho
+    R uF3;      // -3 u.F
+};
+
+// Collision of a population pair (a, opposite a) with eu = e_a.u, eF = e_a.F:
+//   even part  s+ + (h^eq+ - s+)/tau+ + (1 - 1/(2 tau+)) F+/w,  h^eq+ = A + 9/2 rho eu^2
+//   odd part   s- + (h^eq- - s-)/tau- + (1 - 1/(2 tau-)) F-/w,  h^eq- = 3 rho eu
+// (F+/w = 9 eu eF - 3 u.F, F-/w = 3 eF). Relaxing as x + (y - x)/tau keeps the
+// fixed point x = y exact in floating point.
+template <typename R, typename Args>
+__device__ __forceinline__ Pair<R> collide_pair(R ha, R hb, R eu, R eF, const NodeTerms<R>& n, const Args& a)
+{
+    const R sp = R(0.5) * (ha + hb);
+    const R sm = R(0.5) * (ha - hb);
+    const R ep = n.rho45 * (eu * eu) + n.A;
+    const R em = n.rho3 * eu;
+    const R Fp = (R(9) * eu) * eF + n.uF3;
+    const R Fm = R(3) * eF;
+    const R gp = a.om_p * (ep - sp) + sp + a.k_p * Fp;
+    const R gm = a.om_m * (em - sm) + sm + a.k_m * Fm;
+    return {gp + gm, gp - gm};
+}
+
+// V elements one element off a 16-byte boundary, stored as one vector access
+// that needs only dword alignment.
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <typename S, int V>
+__device__ __forceinline__ void store_vec_shifted(S* p, const S (&in)[V])
+{
+    static_assert(sizeof(S) >= 4 || V == 1, "sub-dword vectors are stored one by one");
+    constexpr int B = V * (int)sizeof(S);
+    if constexpr (B == 16) {
+        u32x4_a4 r;
+        __builtin_memcpy(&r, in, 16);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x4_a4*>(p));
+    } else if constexpr (B == 8) {
+        u32x2_a4 r;
+        __builtin_memcpy(&r, in, 8);
+        __builtin_nontemporal_store(r, reinterpret_cast<u32x2_a4*>(p));
+    } else {
+#pragma unroll
+        for (int k = 0; k < V; ++k) p[k] = in[k];
+    }
+}
+
+// ------------------------------------------------------------ the record --
+// One block sums one force record (see FinalizeArgs) in an order fixed by the
+// data alone: the partials are dealt to FIN_LANES virtual lanes (lane v takes
+// v, v + FIN_LANES, ...), each lane adds its share with eight interleaved
+// accumulators (so that loads overlap), and the lanes meet in a fixed binary
+// tree in LDS. Neither the block size of the launch that runs it nor the way
+// steps are split over calls changes a record by one bit.
+constexpr int FIN_LANES = 256;
+
+__device__ __forceinline__ double lane_sum(const double* x, int n, int v)
+{
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int k = v;
+    for (; k + 7 * FIN_LANES < n; k += 8 * FIN_LANES) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u] += x[k + u * FIN_LANES];
+    }
+#pragma unroll
+    for (int u = 0; u < 7; ++u) {   // at most 7 left
+        const int kk = k + u * FIN_LANES;
+        if (kk < n) acc[u] += x[kk];
+    }
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+// Sum of the FIN_LANES values in s (LDS), pairwise with halving spans; every
+// thread of the block must call it and gets the sum.
+__device__ __forceinline__ double tree_sum(double* s)
+{
+    for (int w = FIN_LANES / 2; w > 0; w >>= 1) {
+        __syncthreads();
+        for (int v = (int)threadIdx.x; v < w; v += (int)blockDim.x) s[v] += s[v + w];
+    }
+    __syncthreads();
+    const double r = s[0];
+    __syncthreads();   // s is reused by the next sum
+    return r;
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin by block id: block b (counted
+// from first_block) takes tile (b % 8) * per_xcd + b / 8, so each XCD sweeps a
+// contiguous run of tiles.
+__device__ __forceinline__ int xcd_tile(int per_xcd, int first_block)
+{
+    const int blk = (int)blockIdx.x - first_block;   // first_block is a multiple of 8
+    return (blk % N_XCD_DEV) * per_xcd + blk / N_XCD_DEV;
+}
+
+}  // namespace
+}  // namespace lbvp
