@@ -81,6 +81,37 @@ def time_gpu(storage: str, steps: int, warmup: int, prob):
     return ms / steps, ok
 
 
+BYTES_PER_NODE_3D = {"f64": 305, "f32": 153, "f16": 77, "bf16": 77}
+
+
+def time_d3q19(storages, steps: int, warmup: int):
+    """The D3Q19 step on the 512 x 256 x 256 sphere domain (default launch, force
+    and mass recorded every step), per storage type."""
+    import torch
+    from paper_1901_08766_amd import inputs3, lbvp3
+
+    prob = inputs3.sphere()
+    n = prob.n_nodes
+    out = {"workload": f"flow past a sphere {prob.nx}x{prob.ny}x{prob.nz}, D={prob.l_ref:g}, Re=300, U=0.05",
+           "nodes": n, "per_storage": {}}
+    for st in storages:
+        s = lbvp3.Solver3(prob, storage=st, force_every=1, force_capacity=steps + warmup + 16)
+        s.step(warmup)
+        s.synchronize()
+        s.forces()
+        ms = _timed(s.stream, lambda: s.step(steps)) / steps
+        _, mass, _ = s.forces()
+        gbps = BYTES_PER_NODE_3D[st] * n / (ms * 1e-3) / 1e9
+        out["per_storage"][st] = {"launch": list(s.launch), "ms_per_step": round(ms, 4),
+                                  "MLUPS": round(n / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbps, 1),
+                                  "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+                                  "finite": bool(np.isfinite(mass).all() and len(mass) == steps)}
+        print(f"# d3q19 {st}: {out['per_storage'][st]}", file=sys.stderr, flush=True)
+        s.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(prob, budget_s: float = 15.0):
     """The FP64 oracle on this host's cores, on the same domain, for as many
     whole steps as fit in about ``budget_s`` seconds (at least one); then one
@@ -446,6 +477,9 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=300,
                     help="batched steps of the 256-domain ensemble comparison (0: skip it)")
     ap.add_argument("--ensemble-storages", default="f32,f16")
+    ap.add_argument("--d3q19-steps", type=int, default=50,
+                    help="timed steps of the D3Q19 sphere domain (0: skip it)")
+    ap.add_argument("--d3q19-storages", default="f32,f16,f64")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests of the serving sample (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=100.0)
@@ -540,6 +574,8 @@ def main():
         for st in [x for x in a.ensemble_storages.split(",") if x]:
             out["ensemble"][st] = time_ensemble(st, a.ensemble_steps, max(20, a.ensemble_steps // 5))
             print(f"# ensemble {st}: {out['ensemble'][st]}", file=sys.stderr, flush=True)
+    if a.d3q19_steps > 0:
+        out["d3q19"] = time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, 5)
     if a.serve_requests > 0:
         out["serving"] = run_serving(a.serve_storage, a.serve_rate, a.serve_requests)
         print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)

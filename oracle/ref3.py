@@ -199,8 +199,14 @@ class RefSolver3:
         assert g.shape == (Q, self.nz, self.ny, self.nx)
         lib().lbvp3_ref_write_populations(self._h, g)
 
-    def __del__(self):
+    def close(self):
         h = getattr(self, "_h", None)
         if h:
-            lib().lbvp3_ref_destroy(h)
             self._h = None
+            lib().lbvp3_ref_destroy(h)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: the module may already be gone
+            pass

@@ -1,0 +1,636 @@
+// lbvp3_api.hip -- host side of the D3Q19 C ABI (include/lbvp3.h): validation,
+// the device memory layout, tiling and record tables, and the step sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbvp3.h"
+#include "lbvp3_internal.h"
+
+using namespace lbvp3;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr size_t STAGE_MIN_BYTES = size_t(64) << 20;
+constexpr int64_t DEFAULT_CAPACITY = 4096;
+constexpr int32_t DEFAULT_MAX_BODIES = 8;
+constexpr int32_t MAX_BODIES = 255;
+constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS;
+constexpr int32_t VECS[3] = {1, 2, 4};
+constexpr int32_t BLOCKS[3] = {64, 128, 256};
+
+thread_local std::string g_create_error;
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+size_t storage_bytes(int32_t st) { return st == LBVP_F64 ? 8 : st == LBVP_F32 ? 4 : 2; }
+size_t arith_bytes(int32_t st) { return st == LBVP_F64 ? 8 : 4; }
+
+struct Launch3 {
+    int32_t vec = 1, block = 256, tile_w = 256, tile_rows = 1;
+    int32_t tiles_x = 0, n_tiles = 0, tiles_per_xcd = 0;
+};
+
+int32_t pow2_ceil(int32_t v)
+{
+    int32_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// A tile is tile_rows lattice rows of tile_w nodes (vec * block nodes): full
+// rows of vec * block nodes on wide grids, several shorter rows on narrow ones.
+Launch3 make_launch(int32_t nx, int64_t rows, int32_t vec, int32_t block)
+{
+    Launch3 l;
+    l.vec = vec;
+    l.block = block;
+    l.tile_w = std::min(vec * block, std::max(vec, pow2_ceil(nx)));
+    l.tile_rows = vec * block / l.tile_w;
+    l.tiles_x = (nx + l.tile_w - 1) / l.tile_w;
+    l.n_tiles = (int32_t)(l.tiles_x * ((rows + l.tile_rows - 1) / l.tile_rows));
+    l.tiles_per_xcd = (l.n_tiles + N_XCD - 1) / N_XCD;
+    return l;
+}
+
+// Default: one node per thread, which measures fastest for every storage type on
+// a 512 x 256 x 256 domain (the 19 loads of a node already keep enough bytes in
+// flight, and the narrow form keeps ~70 VGPRs and 7 waves per SIMD, against ~150
+// VGPRs and 3 waves for four nodes per thread); 256-thread blocks for FP32, 128 for
+// FP64, 64 for the 2-byte types, and 64 on grids too small to fill the chip.
+Launch3 default_launch(const lbvp3_params& p)
+{
+    const int64_t rows = (int64_t)p.ny * p.nz, n = rows * p.nx;
+    const int32_t wide = p.storage == LBVP_F32 ? 256 : p.storage == LBVP_F64 ? 128 : 64;
+    const int32_t block = n / 64 >= 4096 ? wide : 64;
+    return make_launch(p.nx, rows, 1, block);
+}
+
+std::string validate(const lbvp3_params* p)
+{
+    if (!p) return "params is NULL";
+    if (p->nx < 3 || p->ny < 3 || p->nz < 3) return "nx, ny and nz must be >= 3";
+    const int64_t rows = (int64_t)p->ny * p->nz;
+    if (rows > (int64_t(1) << 30) || rows * p->nx > (int64_t(1) << 34)) return "grid too large";
+    if (!std::isfinite(p->tau_plus) || !(p->tau_plus > 0.5)) return "tau_plus must be finite and > 1/2";
+    if (!std::isfinite(p->magic_lambda) || !(p->magic_lambda > 0.0)) return "magic_lambda must be finite and > 0";
+    if (!std::isfinite(p->eta) || !(p->eta > 0.0)) return "eta must be finite and > 0";
+    if (!std::isfinite(p->rho0) || !(p->rho0 > 0.0)) return "rho0 must be finite and > 0";
+    const double vals[] = {p->rho_in, p->u_in[0], p->u_in[1], p->u_in[2], p->body_force[0], p->body_force[1],
+                           p->body_force[2]};
+    for (double v : vals)
+        if (!std::isfinite(v)) return "non-finite inflow state or body force";
+    const int32_t sides[2] = {p->bc_west, p->bc_east};
+    for (int32_t s : sides)
+        if (s != LBVP_BC_PERIODIC && s != LBVP_BC_INFLOW_EQ && s != LBVP_BC_OUTFLOW_ZERO_GRAD) return "unknown side";
+    if ((p->bc_west == LBVP_BC_PERIODIC) != (p->bc_east == LBVP_BC_PERIODIC))
+        return "x sides must be both periodic or both non-periodic";
+    if (p->storage < LBVP_F64 || p->storage > LBVP_BF16_DEV) return "unknown storage";
+    if (p->force_every < 0) return "force_every < 0";
+    if (p->force_capacity < 0) return "force_capacity < 0";
+    if (p->max_bodies < 0 || p->max_bodies > MAX_BODIES) return "max_bodies out of range";
+    if (p->flags != 0) return "unknown flag";
+    return "";
+}
+
+// Device memory of a context: every table sized for the finest tiling any
+// launch configuration uses.
+struct Layout3 {
+    int64_t pitch = 0, lstride = 0, plane_f = 0, rows = 0;
+    int32_t max_tiles = 0, max_waves = 0, max_bodies = 0;
+    int64_t slot_cap = 0, capacity = 0, stage_planes = 0;
+    size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, mass_part = 0, slot_force = 0, tile_slot_ptr = 0,
+           slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0, ring_mass = 0, rec_count = 0,
+           stage = 0, total = 0;
+};
+
+Layout3 make_layout(const lbvp3_params& p)
+{
+    Layout3 L;
+    L.pitch = (int64_t)align_up((size_t)p.nx, 64);
+    L.lstride = (int64_t)Q * L.pitch;
+    L.rows = (int64_t)p.ny * p.nz;
+    L.plane_f = L.rows * L.pitch;
+    for (int32_t v : VECS)
+        for (int32_t b : BLOCKS) {
+            const Launch3 l = make_launch(p.nx, L.rows, v, b);
+            L.max_tiles = std::max(L.max_tiles, l.n_tiles);
+            L.max_waves = std::max(L.max_waves, l.n_tiles * (b / 64));
+        }
+    L.max_bodies = p.max_bodies > 0 ? p.max_bodies : DEFAULT_MAX_BODIES;
+    L.capacity = p.force_capacity > 0 ? p.force_capacity : DEFAULT_CAPACITY;
+    // (tile, body) pairs: one body per tile, two where bodies meet, plus headroom
+    L.slot_cap = 2 * (int64_t)L.max_tiles + 4096;
+    const size_t es = storage_bytes(p.storage), rs = arith_bytes(p.storage);
+    const size_t plane_pops = (size_t)Q * 8 * (size_t)p.nx * (size_t)p.ny;
+    const size_t stage_bytes = std::max(STAGE_MIN_BYTES, plane_pops);
+    L.stage_planes = std::max<int64_t>(1, std::min<int64_t>(p.nz, (int64_t)(stage_bytes / plane_pops)));
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, ALIGN);
+        return o;
+    };
+    const size_t lat_bytes = (size_t)L.rows * L.lstride * es;
+    L.lat[0] = take(lat_bytes);
+    L.lat[1] = take(lat_bytes);
+    L.mask = take((size_t)L.rows * L.pitch);
+    L.bodies = take((size_t)(L.max_bodies + 1) * 9 * rs);
+    L.fields = take((size_t)7 * L.plane_f * rs);
+    L.mass_part = take((size_t)L.max_waves * 8);
+    L.slot_force = take((size_t)L.slot_cap * 3 * 8);
+    L.tile_slot_ptr = take((size_t)(L.max_tiles + 1) * 4);
+    L.slot_body = take((size_t)L.slot_cap * 4);
+    L.body_slot_ptr = take((size_t)(L.max_bodies + 1) * 4);
+    L.body_slots = take((size_t)L.slot_cap * 4);
+    L.ring_force = take((size_t)L.capacity * L.max_bodies * 3 * 8);
+    L.ring_mass = take((size_t)L.capacity * 8);
+    L.rec_count = take(8);
+    L.stage = take((size_t)L.stage_planes * plane_pops);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lbvp3_ctx {
+    lbvp3_params p{};
+    Layout3 L;
+    Launch3 launch;
+    hipStream_t stream = nullptr;
+    char* mem = nullptr;
+    int cur = 0;
+    int64_t step = 0, rec_head = 0, rec_tail = 0;
+    bool fields_valid = false;
+    int32_t n_bodies = 0;
+    double tau_minus = 0.0;
+    std::vector<uint8_t> mask_host;   // [nz][ny][nx], kept to rebuild the tile tables
+    Step3Args<double> a64{};
+    Step3Args<float> a32{};
+    Fin3Args fin{};
+    std::string err;
+
+    template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(mem + off); }
+    bool is_f64() const { return p.storage == LBVP_F64; }
+    size_t rsize() const { return arith_bytes(p.storage); }
+    lbvp_status fail(lbvp_status s, const std::string& m)
+    {
+        err = m;
+        return s;
+    }
+    lbvp_status hip_fail(hipError_t e, const char* what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBVP_E_DEVICE;
+    }
+};
+
+namespace {
+
+#define LBVP3_HIP(ctx, call)                                              \
+    do {                                                                  \
+        hipError_t e_ = (call);                                           \
+        if (e_ != hipSuccess) return (ctx)->hip_fail(e_, #call);          \
+    } while (0)
+
+template <typename R>
+void fill_args(lbvp3_ctx* c, Step3Args<R>& a)
+{
+    const lbvp3_params& p = c->p;
+    const Layout3& L = c->L;
+    const Launch3& l = c->launch;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.nz;
+    a.vec = l.vec;
+    a.block = l.block;
+    a.tile_w = l.tile_w;
+    a.tile_rows = l.tile_rows;
+    a.tiles_x = l.tiles_x;
+    a.n_tiles = l.n_tiles;
+    a.tiles_per_xcd = l.tiles_per_xcd;
+    a.west = p.bc_west;
+    a.east = p.bc_east;
+    a.pitch = L.pitch;
+    a.lstride = L.lstride;
+    a.plane_f = L.plane_f;
+    a.rho0 = (R)p.rho0;
+    a.om_p = (R)(1.0 / p.tau_plus);
+    a.om_m = (R)(1.0 / c->tau_minus);
+    a.k_p = (R)(1.0 - 0.5 / p.tau_plus);
+    a.k_m = (R)(1.0 - 0.5 / c->tau_minus);
+    a.vp_c = (R)(1.0 / (2.0 * p.eta + 1.0));
+    for (int d = 0; d < 3; ++d) {
+        a.fb[d] = (R)p.body_force[d];
+        a.fb18[d] = (R)(18.0 * p.body_force[d]);
+    }
+    // the inflow populations (f^eq(rho_in, u_in) - w rho0) / w (eq. feq), in FP64
+    const double* u = p.u_in;
+    const double uu = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+    for (int q = 0; q < Q; ++q) {
+        const double eu = (CX[q] * u[0] + CY[q] * u[1]) + CZ[q] * u[2];
+        a.feq_in[q] = (R)((p.rho_in - p.rho0) + p.rho_in * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    }
+    a.mask = c->at<uint8_t>(L.mask);
+    a.bodies = c->at<R>(L.bodies);
+    a.tile_slot_ptr = c->at<int32_t>(L.tile_slot_ptr);
+    a.slot_body = c->at<int32_t>(L.slot_body);
+    a.slot_force = c->at<double>(L.slot_force);
+    a.mass_part = c->at<double>(L.mass_part);
+    a.fields = c->at<R>(L.fields);
+}
+
+// The (tile, body) tables for the current tiling and mask: a slot per body
+// present in each tile, numbered in tile order, and the slots of each body.
+lbvp_status build_tile_tables(lbvp3_ctx* c)
+{
+    const lbvp3_params& p = c->p;
+    const Launch3& l = c->launch;
+    const int32_t nb = c->n_bodies;
+    const int64_t rows = c->L.rows;
+    std::vector<int32_t> tile_ptr((size_t)l.n_tiles + 1, 0), slot_body;
+    std::vector<std::vector<int32_t>> per_body((size_t)nb);
+    std::vector<uint8_t> seen((size_t)nb + 1, 0);
+    for (int32_t t = 0; t < l.n_tiles; ++t) {
+        tile_ptr[t] = (int32_t)slot_body.size();
+        if (nb == 0) continue;
+        const int32_t ty = t / l.tiles_x, i0 = (t % l.tiles_x) * l.tile_w, i1 = std::min(p.nx, i0 + l.tile_w);
+        const int64_t r0 = (int64_t)ty * l.tile_rows, r1 = std::min(rows, r0 + l.tile_rows);
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int64_t r = r0; r < r1; ++r) {
+            const uint8_t* row = c->mask_host.data() + r * p.nx;
+            for (int32_t i = i0; i < i1; ++i) seen[row[i]] = 1;
+        }
+        for (int32_t b = 1; b <= nb; ++b) {
+            if (!seen[b]) continue;
+            if ((int64_t)slot_body.size() >= c->L.slot_cap) {
+                (void)hipStreamSynchronize(c->stream);   // copies from the caller's host buffers
+                return c->fail(LBVP_E_NOMEM, "mask has more (tile, body) pairs than the reduction tables hold");
+            }
+            per_body[b - 1].push_back((int32_t)slot_body.size());
+            slot_body.push_back(b);
+        }
+    }
+    tile_ptr[l.n_tiles] = (int32_t)slot_body.size();
+    std::vector<int32_t> body_ptr((size_t)nb + 1, 0), body_slots;
+    for (int32_t b = 0; b < nb; ++b) {
+        body_ptr[b] = (int32_t)body_slots.size();
+        body_slots.insert(body_slots.end(), per_body[b].begin(), per_body[b].end());
+    }
+    body_ptr[nb] = (int32_t)body_slots.size();
+    hipStream_t s = c->stream;
+    const Layout3& L = c->L;
+    LBVP3_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.tile_slot_ptr), tile_ptr.data(), tile_ptr.size() * 4,
+                                hipMemcpyHostToDevice, s));
+    if (!slot_body.empty()) {
+        LBVP3_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.slot_body), slot_body.data(), slot_body.size() * 4,
+                                    hipMemcpyHostToDevice, s));
+        LBVP3_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slots), body_slots.data(), body_slots.size() * 4,
+                                    hipMemcpyHostToDevice, s));
+    }
+    LBVP3_HIP(c, hipMemcpyAsync(c->at<int32_t>(L.body_slot_ptr), body_ptr.data(), body_ptr.size() * 4,
+                                hipMemcpyHostToDevice, s));
+    LBVP3_HIP(c, hipStreamSynchronize(s));   // the host tables above go out of scope
+    c->fin.n_bodies = nb;
+    return LBVP_OK;
+}
+
+lbvp_status apply_launch(lbvp3_ctx* c, const Launch3& l)
+{
+    c->launch = l;
+    c->fin.n_mass = l.n_tiles * (l.block / 64);
+    fill_args(c, c->a64);
+    fill_args(c, c->a32);
+    return build_tile_tables(c);
+}
+
+Conv3Args conv_args(lbvp3_ctx* c, int32_t plane0, int32_t planes)
+{
+    Conv3Args a{};
+    a.nx = c->p.nx;
+    a.ny = c->p.ny;
+    a.plane0 = plane0;
+    a.planes = planes;
+    a.pitch = c->L.pitch;
+    a.lstride = c->L.lstride;
+    a.plane_f = c->L.plane_f;
+    a.rho0 = c->p.rho0;
+    a.pops = c->at<double>(c->L.stage);
+    return a;
+}
+
+bool bad_range(const lbvp3_ctx* c, int32_t z0, int32_t n) { return z0 < 0 || n < 0 || (int64_t)z0 + n > c->p.nz; }
+
+}  // namespace
+
+extern "C" {
+
+size_t lbvp3_footprint_bytes(const lbvp3_params* p)
+{
+    if (!validate(p).empty()) return 0;
+    return make_layout(*p).total;
+}
+
+lbvp_status lbvp3_create(const lbvp3_params* p, void* hip_stream, lbvp3_ctx** out)
+{
+    if (!out) {
+        g_create_error = "out is NULL";
+        return LBVP_E_ARG;
+    }
+    *out = nullptr;
+    const std::string why = validate(p);
+    if (!why.empty()) {
+        g_create_error = why;
+        return LBVP_E_ARG;
+    }
+    lbvp3_ctx* c = new (std::nothrow) lbvp3_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return LBVP_E_NOMEM;
+    }
+    c->p = *p;
+    c->L = make_layout(*p);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    c->tau_minus = 0.5 + p->magic_lambda / (p->tau_plus - 0.5);
+    void* m = nullptr;
+    hipError_t e = hipMalloc(&m, c->L.total);
+    if (e != hipSuccess) {
+        g_create_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+        delete c;
+        return LBVP_E_NOMEM;
+    }
+    c->mem = static_cast<char*>(m);
+    const Layout3& L = c->L;
+    c->fin.max_bodies = L.max_bodies;
+    c->fin.capacity = L.capacity;
+    c->fin.mass_offset = p->rho0 * (double)p->nx * (double)p->ny * (double)p->nz;
+    c->fin.body_slot_ptr = c->at<int32_t>(L.body_slot_ptr);
+    c->fin.body_slots = c->at<int32_t>(L.body_slots);
+    c->fin.slot_force = c->at<double>(L.slot_force);
+    c->fin.mass_part = c->at<double>(L.mass_part);
+    c->fin.ring_force = c->at<double>(L.ring_force);
+    c->fin.ring_mass = c->at<double>(L.ring_mass);
+    c->fin.rec_count = c->at<int64_t>(L.rec_count);
+    c->launch = default_launch(*p);
+    c->mask_host.assign((size_t)L.rows * p->nx, 0);
+    lbvp_status s = lbvp3_set_mask(c, c->mask_host.data(), 0, nullptr);
+    if (s == LBVP_OK) s = lbvp3_init_equilibrium(c, nullptr, nullptr, nullptr, nullptr);
+    if (s != LBVP_OK) {
+        g_create_error = c->err;
+        lbvp3_destroy(c);
+        return s;
+    }
+    *out = c;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_set_mask(lbvp3_ctx* c, const uint8_t* body_id, int32_t n_bodies, const lbvp3_body* bodies)
+{
+    if (!c) return LBVP_E_ARG;
+    const lbvp3_params& p = c->p;
+    const Layout3& L = c->L;
+    if (!body_id) return c->fail(LBVP_E_ARG, "body_id is NULL");
+    if (n_bodies < 0 || n_bodies > L.max_bodies) return c->fail(LBVP_E_ARG, "n_bodies out of range (see max_bodies)");
+    if (n_bodies > 0 && !bodies) return c->fail(LBVP_E_ARG, "bodies is NULL");
+    for (int32_t b = 0; b < n_bodies; ++b)
+        for (int d = 0; d < 3; ++d)
+            if (!std::isfinite(bodies[b].c[d]) || !std::isfinite(bodies[b].v[d]) || !std::isfinite(bodies[b].omega[d]))
+                return c->fail(LBVP_E_ARG, "non-finite body value");
+    const int64_t n = L.rows * p.nx;
+    for (int64_t k = 0; k < n; ++k)
+        if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
+    // body table: row 0 all zero (fluid), row b = c, v, omega of body b, in the arithmetic type
+    const size_t rs = c->rsize();
+    std::vector<char> table((size_t)(L.max_bodies + 1) * 9 * rs, 0);
+    for (int32_t b = 0; b < n_bodies; ++b)
+        for (int d = 0; d < 3; ++d) {
+            const double vals[3] = {bodies[b].c[d], bodies[b].v[d], bodies[b].omega[d]};
+            for (int g = 0; g < 3; ++g) {
+                const size_t idx = (size_t)(b + 1) * 9 + 3 * g + d;
+                if (c->is_f64()) reinterpret_cast<double*>(table.data())[idx] = vals[g];
+                else reinterpret_cast<float*>(table.data())[idx] = (float)vals[g];
+            }
+        }
+    if (body_id != c->mask_host.data()) c->mask_host.assign(body_id, body_id + n);
+    c->n_bodies = n_bodies;
+    hipStream_t s = c->stream;
+    LBVP3_HIP(c, hipMemcpy2DAsync(c->at<uint8_t>(L.mask), (size_t)L.pitch, c->mask_host.data(), (size_t)p.nx,
+                                  (size_t)p.nx, (size_t)L.rows, hipMemcpyHostToDevice, s));
+    LBVP3_HIP(c, hipMemcpyAsync(c->at<char>(L.bodies), table.data(), table.size(), hipMemcpyHostToDevice, s));
+    return apply_launch(c, c->launch);   // synchronizes
+}
+
+lbvp_status lbvp3_init_equilibrium(lbvp3_ctx* c, const double* rho, const double* ux, const double* uy,
+                                   const double* uz)
+{
+    if (!c) return LBVP_E_ARG;
+    const lbvp3_params& p = c->p;
+    const Layout3& L = c->L;
+    hipStream_t s = c->stream;
+    const size_t plane_nodes = (size_t)p.nx * p.ny;
+    // four staged FP64 arrays per node fit the 19 the stage holds
+    const int32_t per = (int32_t)std::max<int64_t>(1, std::min<int64_t>(p.nz, L.stage_planes * Q / 4));
+    for (int32_t z0 = 0; z0 < p.nz; z0 += per) {
+        const int32_t planes = std::min(per, p.nz - z0);
+        Conv3Args a = conv_args(c, z0, planes);
+        const size_t nn = (size_t)planes * plane_nodes;
+        double* st = c->at<double>(L.stage);
+        const double* src[4] = {rho, ux, uy, uz};
+        const double* dst[4] = {nullptr, nullptr, nullptr, nullptr};
+        for (int q = 0; q < 4; ++q) {
+            if (!src[q]) continue;
+            LBVP3_HIP(c, hipMemcpyAsync(st + q * nn, src[q] + (size_t)z0 * plane_nodes, nn * sizeof(double),
+                                        hipMemcpyHostToDevice, s));
+            dst[q] = st + q * nn;
+        }
+        a.rho = dst[0];
+        for (int d = 0; d < 3; ++d) a.u[d] = dst[1 + d];
+        LBVP3_HIP(c, launch_init3(p.storage, c->at<char>(L.lat[0]), c->at<char>(L.fields), a, s));
+        LBVP3_HIP(c, hipStreamSynchronize(s));   // the next chunk reuses the stage
+    }
+    LBVP3_HIP(c, launch_zero_i64(c->fin.rec_count, s));
+    LBVP3_HIP(c, hipStreamSynchronize(s));
+    c->cur = 0;
+    c->step = 0;
+    c->rec_head = c->rec_tail = 0;
+    c->fields_valid = true;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_step(lbvp3_ctx* c, int64_t n_steps, uint32_t flags)
+{
+    if (!c) return LBVP_E_ARG;
+    if (n_steps < 0) return c->fail(LBVP_E_ARG, "n_steps < 0");
+    if (flags & ~KNOWN_STEP_FLAGS) return c->fail(LBVP_E_ARG, "unknown step flag");
+    const int64_t fe = c->p.force_every;
+    if (fe > 0) {
+        const int64_t new_recs = (c->step + n_steps) / fe - c->step / fe;
+        if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
+            return c->fail(LBVP_E_STATE, "force records would overflow the device ring; call lbvp3_forces first");
+    }
+    const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
+    const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t next = c->step + 1;
+        const bool record = fe > 0 && next % fe == 0;
+        const bool keep_here = keep && k == n_steps - 1;
+        hipError_t e = launch_step3(c->p.storage, record, keep_here, c->at<char>(c->L.lat[c->cur]),
+                                    c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
+        if (record) {
+            e = launch_finalize3(c->fin, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+            c->rec_head += 1;
+        }
+        if (keep_here) c->fields_valid = true;
+        c->cur ^= 1;
+        c->step = next;
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_forces(lbvp3_ctx* c, double* out, double* mass, int64_t cap, int64_t* n_out, int64_t* first_step)
+{
+    if (!c) return LBVP_E_ARG;
+    if (cap < 0) return c->fail(LBVP_E_ARG, "cap < 0");
+    LBVP3_HIP(c, hipStreamSynchronize(c->stream));
+    const int64_t n = std::min(c->rec_head - c->rec_tail, cap);
+    const int64_t C = c->L.capacity, mb = c->L.max_bodies, nb = c->n_bodies;
+    std::vector<double> rf((size_t)std::max<int64_t>(n, 1) * mb * 3), rm((size_t)std::max<int64_t>(n, 1));
+    for (int64_t done = 0; done < n;) {
+        const int64_t r = (c->rec_tail + done) % C;
+        const int64_t len = std::min(n - done, C - r);
+        LBVP3_HIP(c, hipMemcpyAsync(rf.data() + done * mb * 3, c->at<double>(c->L.ring_force) + r * mb * 3,
+                                    (size_t)(len * mb * 3) * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        LBVP3_HIP(c, hipMemcpyAsync(rm.data() + done, c->at<double>(c->L.ring_mass) + r, (size_t)len * sizeof(double),
+                                    hipMemcpyDeviceToHost, c->stream));
+        done += len;
+    }
+    LBVP3_HIP(c, hipStreamSynchronize(c->stream));
+    bool finite = true;
+    for (int64_t k = 0; k < n; ++k) {
+        if (out)
+            for (int64_t b = 0; b < nb; ++b)
+                for (int d = 0; d < 3; ++d) out[(k * nb + b) * 3 + d] = rf[(k * mb + b) * 3 + d];
+        if (mass) mass[k] = rm[k];
+        if (!std::isfinite(rm[k])) finite = false;
+    }
+    if (n_out) *n_out = n;
+    if (first_step) *first_step = n > 0 ? (c->rec_tail + 1) * c->p.force_every : 0;
+    c->rec_tail += n;
+    if (!finite) return c->fail(LBVP_E_UNSTABLE, "non-finite global mass: the run went unstable");
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_read_fields(lbvp3_ctx* c, int32_t z0, int32_t n_planes, double* out)
+{
+    if (!c) return LBVP_E_ARG;
+    if (!out) return c->fail(LBVP_E_ARG, "out is NULL");
+    if (bad_range(c, z0, n_planes)) return c->fail(LBVP_E_ARG, "plane range outside the grid");
+    if (!c->fields_valid) return c->fail(LBVP_E_STATE, "no fields kept since the last init");
+    const lbvp3_params& p = c->p;
+    const size_t rs = c->rsize();
+    const size_t rows = (size_t)n_planes * p.ny, n = rows * p.nx;
+    std::vector<char> tmp(std::max<size_t>(n, 1) * rs);
+    for (int f = 0; f < 7; ++f) {
+        const char* srcp = c->at<char>(c->L.fields) + ((size_t)f * c->L.plane_f + (size_t)z0 * p.ny * c->L.pitch) * rs;
+        if (n) {
+            LBVP3_HIP(c, hipMemcpy2DAsync(tmp.data(), (size_t)p.nx * rs, srcp, (size_t)c->L.pitch * rs,
+                                          (size_t)p.nx * rs, rows, hipMemcpyDeviceToHost, c->stream));
+        }
+        LBVP3_HIP(c, hipStreamSynchronize(c->stream));
+        double* dst = out + (size_t)f * n;
+        if (c->is_f64()) std::memcpy(dst, tmp.data(), n * sizeof(double));
+        else {
+            const float* v = reinterpret_cast<const float*>(tmp.data());
+            for (size_t k = 0; k < n; ++k) dst[k] = (double)v[k];
+        }
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_read_populations(lbvp3_ctx* c, int32_t z0, int32_t n_planes, double* g)
+{
+    if (!c) return LBVP_E_ARG;
+    if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    if (bad_range(c, z0, n_planes)) return c->fail(LBVP_E_ARG, "plane range outside the grid");
+    const lbvp3_params& p = c->p;
+    hipStream_t s = c->stream;
+    const size_t plane_nodes = (size_t)p.nx * p.ny, N = (size_t)n_planes * plane_nodes;
+    for (int32_t k0 = 0; k0 < n_planes; k0 += (int32_t)c->L.stage_planes) {
+        const int32_t planes = std::min<int32_t>((int32_t)c->L.stage_planes, n_planes - k0);
+        Conv3Args a = conv_args(c, z0 + k0, planes);
+        LBVP3_HIP(c, launch_decode3(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
+        const size_t nn = (size_t)planes * plane_nodes;
+        for (int q = 0; q < Q; ++q)
+            LBVP3_HIP(c, hipMemcpyAsync(g + q * N + (size_t)k0 * plane_nodes, a.pops + q * nn, nn * sizeof(double),
+                                        hipMemcpyDeviceToHost, s));
+        LBVP3_HIP(c, hipStreamSynchronize(s));
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_write_populations(lbvp3_ctx* c, int32_t z0, int32_t n_planes, const double* g)
+{
+    if (!c) return LBVP_E_ARG;
+    if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    if (bad_range(c, z0, n_planes)) return c->fail(LBVP_E_ARG, "plane range outside the grid");
+    const lbvp3_params& p = c->p;
+    hipStream_t s = c->stream;
+    const size_t plane_nodes = (size_t)p.nx * p.ny, N = (size_t)n_planes * plane_nodes;
+    for (int32_t k0 = 0; k0 < n_planes; k0 += (int32_t)c->L.stage_planes) {
+        const int32_t planes = std::min<int32_t>((int32_t)c->L.stage_planes, n_planes - k0);
+        Conv3Args a = conv_args(c, z0 + k0, planes);
+        const size_t nn = (size_t)planes * plane_nodes;
+        for (int q = 0; q < Q; ++q)
+            LBVP3_HIP(c, hipMemcpyAsync(a.pops + q * nn, g + q * N + (size_t)k0 * plane_nodes, nn * sizeof(double),
+                                        hipMemcpyHostToDevice, s));
+        LBVP3_HIP(c, launch_encode3(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
+        LBVP3_HIP(c, hipStreamSynchronize(s));
+    }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_set_launch(lbvp3_ctx* c, int32_t vec, int32_t block)
+{
+    if (!c) return LBVP_E_ARG;
+    if (!vec_supported(c->p.storage, vec)) return c->fail(LBVP_E_ARG, "vec not built for this storage type");
+    if (block != 64 && block != 128 && block != 256) return c->fail(LBVP_E_ARG, "block must be 64, 128 or 256");
+    LBVP3_HIP(c, hipStreamSynchronize(c->stream));   // running steps still read the old tables
+    return apply_launch(c, make_launch(c->p.nx, c->L.rows, vec, block));
+}
+
+lbvp_status lbvp3_get_launch(const lbvp3_ctx* c, int32_t* vec, int32_t* block)
+{
+    if (!c) return LBVP_E_ARG;
+    if (vec) *vec = c->launch.vec;
+    if (block) *block = c->launch.block;
+    return LBVP_OK;
+}
+
+int64_t lbvp3_step_count(const lbvp3_ctx* c) { return c ? c->step : -1; }
+
+lbvp_status lbvp3_synchronize(lbvp3_ctx* c)
+{
+    if (!c) return LBVP_E_ARG;
+    LBVP3_HIP(c, hipStreamSynchronize(c->stream));
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_destroy(lbvp3_ctx* c)
+{
+    if (!c) return LBVP_E_ARG;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->mem) (void)hipFree(c->mem);
+    delete c;
+    return LBVP_OK;
+}
+
+const char* lbvp3_last_error(const lbvp3_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// lbvp3_internal.h -- argument blocks and launchers of the D3Q19 step, shared by
+// its host side (lbvp3_api.hip) and its kernels (lbvp3_kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "lbvp3.h"
+
+namespace lbvp3 {
+
+constexpr int Q = 19;
+constexpr int N_XCD = 8;
+constexpr int FIN_THREADS = 256;
+
+// Velocity components of the 19 directions in the interface order: rest, the
+// faces +x -x +y -y +z -z, then the edges as (opposite) pairs in the xy, xz and
+// yz planes. Device code indexes them with compile-time indices only.
+constexpr int CX[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+
+// Sums one force record: the per-wavefront mass partials and the (tile, body)
+// force partials, in a fixed order, into ring slot rec_count % capacity.
+struct Fin3Args {
+    int32_t n_bodies, max_bodies, n_mass;   // n_mass: wavefronts of a step launch
+    int64_t capacity;
+    double mass_offset;             // rho0 * nx * ny * nz
+    const int32_t* body_slot_ptr;   // [n_bodies + 1]
+    const int32_t* body_slots;      // slots of each body in tile order
+    const double* slot_force;       // [n_slots][3]
+    const double* mass_part;        // [n_mass]
+    double* ring_force;             // [capacity][max_bodies][3]
+    double* ring_mass;              // [capacity]
+    int64_t* rec_count;             // records written so far
+};
+
+// One workgroup updates one tile: tile_rows consecutive lattice rows of tile_w
+// nodes (vec nodes per thread), a lattice row being the nx nodes of one (y, z);
+// rows are numbered r = z * ny + y.
+template <typename R>
+struct Step3Args {
+    int32_t nx, ny, nz;
+    int32_t vec, block, tile_w, tile_rows;
+    int32_t tiles_x, n_tiles, tiles_per_xcd;
+    int32_t west, east;             // lbvp_bc of the x sides
+    int64_t pitch;                  // elements per population row, mask row and field row
+    int64_t lstride;                // elements between lattice rows r and r + 1 (= 19 pitch)
+    int64_t plane_f;                // elements between field planes (= ny nz pitch)
+    R rho0;
+    R om_p, om_m;                   // 1/tau_plus, 1/tau_minus
+    R k_p, k_m;                     // 1 - 1/(2 tau_plus), 1 - 1/(2 tau_minus)
+    R vp_c;                         // 1 / (2 eta + 1)
+    R fb[3];                        // body force
+    R fb18[3];                      // 18 F_b: the half step in units of 36 j
+    R feq_in[Q];                    // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side
+    const uint8_t* mask;            // [ny nz][pitch]
+    const R* bodies;                // [(max_bodies + 1)][9]: c, v, omega; row 0 all zero
+    const int32_t* tile_slot_ptr;   // [n_tiles + 1]
+    const int32_t* slot_body;       // [n_slots]
+    double* slot_force;             // [n_slots][3]
+    double* mass_part;              // [n_tiles * block / 64]
+    R* fields;                      // [7][plane_f]
+};
+
+struct Conv3Args {
+    int32_t nx, ny, plane0, planes;
+    int64_t pitch, lstride, plane_f;
+    double rho0;
+    const double* rho;   // staged [planes][ny][nx] or null
+    const double* u[3];
+    double* pops;        // staged [19][planes][ny][nx]
+};
+
+// nodes per thread the step kernel is built for, per storage type
+bool vec_supported(int32_t storage, int32_t vec);
+
+hipError_t launch_step3(int32_t storage, bool record, bool fields, const void* src, void* dst, const void* step_args,
+                        hipStream_t s);
+hipError_t launch_finalize3(const Fin3Args& a, hipStream_t s);
+hipError_t launch_init3(int32_t storage, void* lat, void* fields, const Conv3Args& a, hipStream_t s);
+hipError_t launch_decode3(int32_t storage, const void* lat, const Conv3Args& a, hipStream_t s);
+hipError_t launch_encode3(int32_t storage, void* lat, const Conv3Args& a, hipStream_t s);
+hipError_t launch_zero_i64(int64_t* p, hipStream_t s);
+
+}  // namespace lbvp3

@@ -28,7 +28,7 @@
 // corrected u and split into parts even (+) and odd (-) under a -> opposite(a).
 // For a pair (a, opposite a) with eu = e_a.u and eF = e_a.F the parts are, in
 // units of w_a,
-//   h^eq+ = drho + rho (9/2 eu^2 - 3/2 u.u),  h^eq- = 3 rho eu,
+//   h^eq+ = drho + rho (9/2 eu^2 - 3/2 u.u),  h^eq- = 3 rho eu = e.(36 j + 18 F)/12,
 //   F+/w  = 9 eu eF - 3 u.F,                 F-/w  = 3 eF.
 //
 // The step is bound by HBM traffic: 9 loads, 9 stores and one mask byte per node
@@ -68,8 +68,10 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     const R d57 = f[5] - f[7], d86 = f[8] - f[6];
     const R inv_36rho = recip(R(36) * rho);
     // u* = (j + F_b/2) / rho with 36 j = 4 (h1 - h3) + ... (eq. rho*velocity-star)
-    R ux = (R(4) * (f[1] - f[3]) + (d57 + d86) + a.fbx18) * inv_36rho;
-    R uy = (R(4) * (f[2] - f[4]) + (d57 - d86) + a.fby18) * inv_36rho;
+    const R jx36 = R(4) * (f[1] - f[3]) + (d57 + d86) + a.fbx18;
+    const R jy36 = R(4) * (f[2] - f[4]) + (d57 - d86) + a.fby18;
+    R ux = jx36 * inv_36rho;
+    R uy = jy36 * inv_36rho;
 
     // volume penalization (eqs. d-V, force-density) on solid nodes only
     R fvx = R(0), fvy = R(0);
@@ -91,18 +93,18 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
         uy += duy;
     }
     const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
+    const R px = momentum3(jx36, fvx), py = momentum3(jy36, fvy);   // 3 rho u
 
     NodeTerms<R> n;
     const R uu = ux * ux + uy * uy;
     n.A = drho - (R(1.5) * rho) * uu;
     n.rho45 = R(4.5) * rho;
-    n.rho3 = R(3) * rho;
     n.uF3 = R(-3) * (ux * Fx + uy * Fy);
     const R g0 = a.om_p * (n.A - f[0]) + f[0] + a.k_p * n.uF3;
-    const Pair<R> p13 = collide_pair(f[1], f[3], ux, Fx, n, a);
-    const Pair<R> p24 = collide_pair(f[2], f[4], uy, Fy, n, a);
-    const Pair<R> p57 = collide_pair(f[5], f[7], ux + uy, Fx + Fy, n, a);
-    const Pair<R> p68 = collide_pair(f[6], f[8], uy - ux, Fy - Fx, n, a);
+    const Pair<R> p13 = collide_pair(f[1], f[3], ux, px, Fx, n, a);
+    const Pair<R> p24 = collide_pair(f[2], f[4], uy, py, Fy, n, a);
+    const Pair<R> p57 = collide_pair(f[5], f[7], ux + uy, px + py, Fx + Fy, n, a);
+    const Pair<R> p68 = collide_pair(f[6], f[8], uy - ux, py - px, Fy - Fx, n, a);
     f[0] = g0;
     f[1] = p13.ga;
     f[3] = p13.gb;

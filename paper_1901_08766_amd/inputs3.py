@@ -222,3 +222,22 @@ def plate_channel(nz: int = 24, nxy: int = 4, wall: int = 2, fx: float = 1e-6, t
     bodies = np.array([[nxy / 2.0, nxy / 2.0, nz / 2.0, 0, 0, 0, 0, 0, 0]], dtype=np.float64)
     return Problem3(name=f"plates{nz}", nx=nxy, ny=nxy, nz=nz, tau_plus=tau_plus, magic_lambda=magic_lambda,
                     eta=eta, body_force=(fx, 0.0, 0.0), mask=mask, bodies=bodies)
+
+
+def slab(p: Problem3, k0: int, n: int) -> Problem3:
+    """Planes k0 .. k0 + n - 1 (taken modulo nz) of a problem as a problem of their
+    own, periodic along z over the n planes, with the body centres moved by -k0
+    along z. A node update in the middle plane of a 3-plane slab reads that slab
+    only. The initial fields are cut the same way."""
+    ks = [(k0 + s) % p.nz for s in range(n)]
+
+    def cut(a):
+        return None if a is None else np.ascontiguousarray(a[ks])
+
+    b = p.bodies_or_empty().copy()
+    b[:, 2] -= k0
+    return Problem3(name=f"{p.name}_slab{k0}+{n}", nx=p.nx, ny=p.ny, nz=n, tau_plus=p.tau_plus,
+                    magic_lambda=p.magic_lambda, eta=p.eta, rho0=p.rho0, bc=p.bc, rho_in=p.rho_in, u_in=p.u_in,
+                    body_force=p.body_force, mask=cut(p.mask_or_empty()), bodies=b if b.shape[0] else None,
+                    rho_init=cut(p.rho_init), ux_init=cut(p.ux_init), uy_init=cut(p.uy_init),
+                    uz_init=cut(p.uz_init), steps=p.steps, u_ref=p.u_ref, l_ref=p.l_ref)

@@ -21,8 +21,22 @@ def oracle():
 
 
 @pytest.fixture(scope="session")
+def ref3():
+    from oracle import ref3 as mod
+    mod.lib()
+    return mod
+
+
+@pytest.fixture(scope="session")
 def lbvp():
     """The HIP library's Python binding (imported lazily so that collecting the
     CPU tests does not need the built library)."""
     from paper_1901_08766_amd import lbvp as mod
+    return mod
+
+
+@pytest.fixture(scope="session")
+def lbvp3():
+    """The binding of the D3Q19 entry points (imported lazily, as ``lbvp``)."""
+    from paper_1901_08766_amd import lbvp3 as mod
     return mod

@@ -30,13 +30,6 @@ from paper_1901_08766_amd import inputs, inputs3
 CS2 = 1.0 / 3.0
 
 
-@pytest.fixture(scope="module")
-def ref3():
-    from oracle import ref3 as mod
-    mod.lib()
-    return mod
-
-
 def _E(ref3):
     ex, ey, ez, w, opp = ref3.lattice()
     return np.stack([ex, ey, ez], axis=1).astype(np.float64), w, opp
