@@ -30,25 +30,34 @@ HBM_PEAK_GBPS = 8000.0
 METRIC = "MLUPS + % of HBM peak, plain vs batched/FP16; p50/p99 solve latency"
 BYTES_PER_NODE = {"f64": 145, "f32": 73, "f16": 37, "bf16": 37}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
+# per lattice: populations per node, the sources its step kernel is built from,
+# and the committed counter summary of that kernel
+LATTICES = {
+    "d2q9": {"q": 9, "sources": ("lbvp_kernels.hip", "lbvp_device.h", "lbvp_internal.h"),
+             "counters": COUNTERS_FILE},
+    "d3q19": {"q": 19, "sources": ("lbvp3_kernels.hip", "lbvp_device.h", "lbvp3_internal.h"),
+              "counters": os.path.join(ROOT, "profiles", "step3_kernel_counters.json")},
+}
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(lattice: str = "d2q9") -> str:
     h = hashlib.sha256()
-    for name in ("lbvp_kernels.hip", "lbvp_device.h", "lbvp_internal.h"):
+    for name in LATTICES[lattice]["sources"]:
         with open(os.path.join(ROOT, "paper_1901_08766_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, nodes: int):
+def measured_traffic(storage: str, nodes: int, lattice: str = "d2q9"):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(LATTICES[lattice]["counters"]) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("kernel_source_hash") != kernel_source_hash():
+    if c.get("kernel_source_hash") != kernel_source_hash(lattice):
         return None
     entry = c.get("per_storage", {}).get(storage)
     if not entry or entry.get("nodes") != nodes:
@@ -105,6 +114,7 @@ def time_d3q19(storages, steps: int, warmup: int):
         out["per_storage"][st] = {"launch": list(s.launch), "ms_per_step": round(ms, 4),
                                   "MLUPS": round(n / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbps, 1),
                                   "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+                                  "traffic": measured_traffic(st, n, "d3q19"),
                                   "finite": bool(np.isfinite(mass).all() and len(mass) == steps)}
         print(f"# d3q19 {st}: {out['per_storage'][st]}", file=sys.stderr, flush=True)
         s.close()
@@ -423,13 +433,18 @@ def _counter_mean(db: str, counter: str, name_part: str) -> float:
 
 
 def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_write: str, copy_bytes: int,
-                       storage: str, kernel_part: str, out_json: str, out_md: str, command: str):
+                       storage: str, kernel_part: str, out_md: str, command: str, lattice: str = "d2q9"):
     """HBM bytes per step-kernel launch from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by what the counter reads for a plain device copy of
     copy_bytes read and copy_bytes written."""
-    from paper_1901_08766_amd import inputs
-
-    nodes = inputs.large_domain().nx * inputs.large_domain().ny
+    if lattice == "d2q9":
+        from paper_1901_08766_amd import inputs
+        nodes = inputs.large_domain().nx * inputs.large_domain().ny
+    else:
+        from paper_1901_08766_amd import inputs3
+        nodes = int(np.prod(inputs3.SPHERE_SHAPE))
+    out_json = LATTICES[lattice]["counters"]
+    pop_bytes = LATTICES[lattice]["q"] * STORAGE_BYTES[storage]
     copy_kib = copy_bytes / 1024.0
     f_cal = copy_kib / _counter_mean(copy_fetch, "FETCH_SIZE", "copyBuffer")
     w_cal = copy_kib / _counter_mean(copy_write, "WRITE_SIZE", "copyBuffer")
@@ -437,8 +452,8 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
     wk = _counter_mean(step_write, "WRITE_SIZE", kernel_part)
     fetch_b = fk * f_cal * 1024.0
     write_b = wk * w_cal * 1024.0
-    alg_read = (BYTES_PER_NODE[storage] - 1) // 2 * nodes + nodes   # 9 loads + 1 mask byte
-    alg_write = (BYTES_PER_NODE[storage] - 1) // 2 * nodes
+    alg_read = pop_bytes * nodes + nodes   # every population once, one mask byte
+    alg_write = pop_bytes * nodes
     entry = {"nodes": nodes, "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
              "fetch_calibration": round(f_cal, 5), "write_calibration": round(w_cal, 5),
              "hbm_fetch_bytes": int(fetch_b), "hbm_write_bytes": int(write_b),
@@ -446,7 +461,7 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
              "algorithmic_read_bytes": alg_read, "algorithmic_write_bytes": alg_write,
              "fetch_over_algorithmic": round(fetch_b / alg_read, 4),
              "write_over_algorithmic": round(write_b / alg_write, 4)}
-    data = {"kernel_source_hash": kernel_source_hash(), "kernel": kernel_part, "per_storage": {storage: entry},
+    data = {"kernel_source_hash": kernel_source_hash(lattice), "kernel": kernel_part, "per_storage": {storage: entry},
             "command": command}
     with open(out_json, "w") as f:
         json.dump(data, f, indent=1)
@@ -480,6 +495,9 @@ def main():
     ap.add_argument("--d3q19-steps", type=int, default=50,
                     help="timed steps of the D3Q19 sphere domain (0: skip it)")
     ap.add_argument("--d3q19-storages", default="f32,f16,f64")
+    ap.add_argument("--d3q19-only", action="store_true", help="only run the D3Q19 timing leg")
+    ap.add_argument("--lattice", default="d2q9", choices=sorted(LATTICES),
+                    help="the step kernel --summarize-counters describes")
     ap.add_argument("--serve-requests", type=int, default=100,
                     help="requests of the serving sample (0: skip it)")
     ap.add_argument("--serve-rate", type=float, default=100.0)
@@ -507,7 +525,10 @@ def main():
         return
     if a.summarize_counters:
         sf, sw, cf, cw, cb, kern, md, cmd = a.summarize_counters
-        summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, COUNTERS_FILE, md, cmd)
+        summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, md, cmd, a.lattice)
+        return
+    if a.d3q19_only:
+        print(json.dumps(time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, 5)), flush=True)
         return
     if a.precision_study:
         print(json.dumps(precision_study()), flush=True)

@@ -106,7 +106,7 @@ struct Layout3 {
     int64_t slot_cap = 0, capacity = 0, stage_planes = 0;
     size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, mass_part = 0, slot_force = 0, tile_slot_ptr = 0,
            slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0, ring_mass = 0, rec_count = 0,
-           stage = 0, total = 0;
+           arrivals = 0, fin_stage = 0, stage = 0, total = 0;
 };
 
 Layout3 make_layout(const lbvp3_params& p)
@@ -142,8 +142,8 @@ Layout3 make_layout(const lbvp3_params& p)
     L.mask = take((size_t)L.rows * L.pitch);
     L.bodies = take((size_t)(L.max_bodies + 1) * 9 * rs);
     L.fields = take((size_t)7 * L.plane_f * rs);
-    L.mass_part = take((size_t)L.max_waves * 8);
-    L.slot_force = take((size_t)L.slot_cap * 3 * 8);
+    L.mass_part = take((size_t)2 * L.max_waves * 8);       // double-buffered partials
+    L.slot_force = take((size_t)2 * L.slot_cap * 3 * 8);
     L.tile_slot_ptr = take((size_t)(L.max_tiles + 1) * 4);
     L.slot_body = take((size_t)L.slot_cap * 4);
     L.body_slot_ptr = take((size_t)(L.max_bodies + 1) * 4);
@@ -151,6 +151,8 @@ Layout3 make_layout(const lbvp3_params& p)
     L.ring_force = take((size_t)L.capacity * L.max_bodies * 3 * 8);
     L.ring_mass = take((size_t)L.capacity * 8);
     L.rec_count = take(8);
+    L.arrivals = take(8);
+    L.fin_stage = take((size_t)N_LEAD * (1 + 3 * L.max_bodies) * 8);
     L.stage = take((size_t)L.stage_planes * plane_pops);
     L.total = off;
     return L;
@@ -166,6 +168,8 @@ struct lbvp3_ctx {
     char* mem = nullptr;
     int cur = 0;
     int64_t step = 0, rec_head = 0, rec_tail = 0;
+    bool pending = false;       // a recorded step whose sums are not yet in the ring
+    int32_t pending_buf = 0;
     bool fields_valid = false;
     int32_t n_bodies = 0;
     double tau_minus = 0.0;
@@ -243,6 +247,9 @@ void fill_args(lbvp3_ctx* c, Step3Args<R>& a)
     a.slot_force = c->at<double>(L.slot_force);
     a.mass_part = c->at<double>(L.mass_part);
     a.fields = c->at<R>(L.fields);
+    a.part_buf = 0;
+    a.fin_buf = -1;
+    a.fin = c->fin;
 }
 
 // The (tile, body) tables for the current tiling and mask: a slot per body
@@ -373,9 +380,13 @@ lbvp_status lbvp3_create(const lbvp3_params* p, void* hip_stream, lbvp3_ctx** ou
     c->fin.body_slots = c->at<int32_t>(L.body_slots);
     c->fin.slot_force = c->at<double>(L.slot_force);
     c->fin.mass_part = c->at<double>(L.mass_part);
+    c->fin.slot_stride = L.slot_cap * 3;
+    c->fin.mass_stride = L.max_waves;
     c->fin.ring_force = c->at<double>(L.ring_force);
     c->fin.ring_mass = c->at<double>(L.ring_mass);
     c->fin.rec_count = c->at<int64_t>(L.rec_count);
+    c->fin.arrivals = c->at<int64_t>(L.arrivals);
+    c->fin.stage = c->at<double>(L.fin_stage);
     c->launch = default_launch(*p);
     c->mask_host.assign((size_t)L.rows * p->nx, 0);
     lbvp_status s = lbvp3_set_mask(c, c->mask_host.data(), 0, nullptr);
@@ -454,10 +465,12 @@ lbvp_status lbvp3_init_equilibrium(lbvp3_ctx* c, const double* rho, const double
         LBVP3_HIP(c, hipStreamSynchronize(s));   // the next chunk reuses the stage
     }
     LBVP3_HIP(c, launch_zero_i64(c->fin.rec_count, s));
+    LBVP3_HIP(c, launch_zero_i64(c->fin.arrivals, s));
     LBVP3_HIP(c, hipStreamSynchronize(s));
     c->cur = 0;
     c->step = 0;
     c->rec_head = c->rec_tail = 0;
+    c->pending = false;
     c->fields_valid = true;
     return LBVP_OK;
 }
@@ -475,21 +488,31 @@ lbvp_status lbvp3_step(lbvp3_ctx* c, int64_t n_steps, uint32_t flags)
     }
     const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
     const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
+    c->a64.fin = c->fin;
+    c->a32.fin = c->fin;
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t next = c->step + 1;
         const bool record = fe > 0 && next % fe == 0;
         const bool keep_here = keep && k == n_steps - 1;
+        const int32_t part_buf = (int32_t)(c->rec_head & 1);
+        c->a64.part_buf = c->a32.part_buf = part_buf;
+        c->a64.fin_buf = c->a32.fin_buf = c->pending ? c->pending_buf : -1;
         hipError_t e = launch_step3(c->p.storage, record, keep_here, c->at<char>(c->L.lat[c->cur]),
                                     c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
         if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
+        c->pending = record;
         if (record) {
-            e = launch_finalize3(c->fin, c->stream);
-            if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+            c->pending_buf = part_buf;
             c->rec_head += 1;
         }
         if (keep_here) c->fields_valid = true;
         c->cur ^= 1;
         c->step = next;
+    }
+    if (c->pending) {   // the last record of the call is summed on its own
+        hipError_t e = launch_finalize3(c->fin, c->pending_buf, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+        c->pending = false;
     }
     return LBVP_OK;
 }

@@ -12,6 +12,7 @@ namespace lbvp3 {
 constexpr int Q = 19;
 constexpr int N_XCD = 8;
 constexpr int FIN_THREADS = 256;
+constexpr int N_LEAD = 32;   // blocks that sum one record, a multiple of the 8 XCDs
 
 // Velocity components of the 19 directions in the interface order: rest, the
 // faces +x -x +y -y +z -z, then the edges as (opposite) pairs in the xy, xz and
@@ -21,18 +22,26 @@ constexpr int CY[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1,
 constexpr int CZ[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
 
 // Sums one force record: the per-wavefront mass partials and the (tile, body)
-// force partials, in a fixed order, into ring slot rec_count % capacity.
+// force partials of partial buffer `buf`, in a fixed order, into ring slot
+// rec_count % capacity. N_LEAD blocks each sum a fixed slice into a row of
+// `stage`; the last to arrive (counted in `arrivals`) adds the rows in block
+// order. The partials are double-buffered so that the record of one step is
+// summed by leading blocks of the next step's launch while that step writes the
+// other buffer.
 struct Fin3Args {
     int32_t n_bodies, max_bodies, n_mass;   // n_mass: wavefronts of a step launch
     int64_t capacity;
     double mass_offset;             // rho0 * nx * ny * nz
     const int32_t* body_slot_ptr;   // [n_bodies + 1]
     const int32_t* body_slots;      // slots of each body in tile order
-    const double* slot_force;       // [n_slots][3]
-    const double* mass_part;        // [n_mass]
+    const double* slot_force;       // [2][slot_stride]: [n_slots][3] per buffer
+    const double* mass_part;        // [2][mass_stride]
+    int64_t slot_stride, mass_stride;
     double* ring_force;             // [capacity][max_bodies][3]
     double* ring_mass;              // [capacity]
     int64_t* rec_count;             // records written so far
+    double* stage;                  // [N_LEAD][1 + 3 max_bodies] slice sums
+    int64_t* arrivals;              // slices summed of the record in progress (0 between records)
 };
 
 // One workgroup updates one tile: tile_rows consecutive lattice rows of tile_w
@@ -58,9 +67,12 @@ struct Step3Args {
     const R* bodies;                // [(max_bodies + 1)][9]: c, v, omega; row 0 all zero
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
-    double* slot_force;             // [n_slots][3]
-    double* mass_part;              // [n_tiles * block / 64]
+    double* slot_force;             // [2][fin.slot_stride]
+    double* mass_part;              // [2][fin.mass_stride]
     R* fields;                      // [7][plane_f]
+    int32_t part_buf;               // partial buffer a recording step writes
+    int32_t fin_buf;                // partial buffer whose record a leading block sums, or -1
+    Fin3Args fin;
 };
 
 struct Conv3Args {
@@ -77,7 +89,7 @@ bool vec_supported(int32_t storage, int32_t vec);
 
 hipError_t launch_step3(int32_t storage, bool record, bool fields, const void* src, void* dst, const void* step_args,
                         hipStream_t s);
-hipError_t launch_finalize3(const Fin3Args& a, hipStream_t s);
+hipError_t launch_finalize3(const Fin3Args& a, int32_t buf, hipStream_t s);
 hipError_t launch_init3(int32_t storage, void* lat, void* fields, const Conv3Args& a, hipStream_t s);
 hipError_t launch_decode3(int32_t storage, const void* lat, const Conv3Args& a, hipStream_t s);
 hipError_t launch_encode3(int32_t storage, void* lat, const Conv3Args& a, hipStream_t s);

@@ -53,8 +53,10 @@ using lbvp::momentum3;
 using lbvp::NodeTerms;
 using lbvp::Pair;
 using lbvp::recip;
+using lbvp::store_one;
 using lbvp::store_vec;
 using lbvp::tree_sum;
+using lbvp::wave_sum_lane63;
 using lbvp::xcd_tile;
 
 template <typename R>
@@ -64,7 +66,8 @@ struct Node3 {
 
 // Steps (4)-(6) at node (i, j, k) with streamed populations f (weight-normalized);
 // overwrites f with the post-collision populations.
-template <typename R>
+// EXACT_MOM as in the 2-D step: the 2-byte storage types take 3 rho u as (3 rho) u.
+template <typename R, bool EXACT_MOM = true>
 __device__ __forceinline__ Node3<R> collide3(R (&f)[Q], int body, int i, int j, int k, const Step3Args<R>& a)
 {
     const R faces = ((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]);
@@ -102,7 +105,8 @@ __device__ __forceinline__ Node3<R> collide3(R (&f)[Q], int body, int i, int j, 
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
         F[d] = a.fb[d] + fv[d];
-        P[d] = momentum3(j36[d], fv[d]);
+        if constexpr (EXACT_MOM) P[d] = momentum3(j36[d], fv[d]);
+        else P[d] = (R(3) * rho) * u[d];
     }
 
     NodeTerms<R> n;
@@ -204,6 +208,13 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     const int64_t own_row = (int64_t)row * a.lstride;
     const int64_t r0 = (int64_t)row * a.pitch;       // mask and fields
 
+    // this tile's (tile, body) force slots: loaded first, so that waiting for them
+    // never waits for the stores (a vector-memory wait covers every earlier access)
+    int s0 = 0, s1 = 0;
+    if constexpr (RECORD) {
+        s0 = a.tile_slot_ptr[t];
+        s1 = a.tile_slot_ptr[t + 1];
+    }
     R v[Q][V];
     int body[V];
     if (act) {
@@ -232,11 +243,6 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
         for (int e = 0; e < V; ++e) body[e] = 0;
     }
 
-    int s0 = 0, s1 = 0;   // this tile's (tile, body) force slots
-    if constexpr (RECORD) {
-        s0 = a.tile_slot_ptr[t];
-        s1 = a.tile_slot_ptr[t + 1];
-    }
     R fl[7][V];
     double tile_drho = 0.0;
     S out[Q][V];
@@ -251,7 +257,7 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
             for (int q = 0; q < Q; ++q)
                 if (CX[q] == -1) f[q] = pull_col<S, R>(src, q, src_row[q], a.nx, a);
         }
-        const Node3<R> n = collide3<R>(f, body[e], i, j, k, a);
+        const Node3<R> n = collide3<R, (sizeof(S) >= 4)>(f, body[e], i, j, k, a);
 #pragma unroll
         for (int q = 0; q < Q; ++q) out[q][e] = enc<S>(f[q]);
         fl[0][e] = n.rho;
@@ -280,7 +286,7 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
         for (int e = 0; e < V; ++e)
             if (e < n_own)
 #pragma unroll
-                for (int q = 0; q < Q; ++q) dst[own_row + (int64_t)q * a.pitch + i0 + e] = out[q][e];
+                for (int q = 0; q < Q; ++q) store_one<S>(dst + own_row + (int64_t)q * a.pitch + i0 + e, out[q][e]);
     }
 
     if constexpr (FIELDS) {
@@ -293,11 +299,12 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     }
 
     if constexpr (RECORD) {
+        // mass: one partial per wavefront (DPP moves only, no block barrier)
         const int lane = (int)(threadIdx.x & 63);
-        double wm = tile_drho;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) wm += __shfl_down(wm, off, 64);
-        if (lane == 0) a.mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
+        const double wm = wave_sum_lane63(tile_drho);
+        double* mass_part = a.mass_part + a.part_buf * a.fin.mass_stride;
+        double* slot_force = a.slot_force + a.part_buf * a.fin.slot_stride;
+        if (lane == 63) mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
         if (s1 > s0) {   // tiles that hold solid nodes (uniform across the block)
             const R* fv = force_lds<R>();
             const int nt = (int)blockDim.x;
@@ -312,62 +319,88 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const double sum = block_sum(p[c], lds);
-                    if (threadIdx.x == 0) a.slot_force[3 * s + c] = sum;
+                    if (threadIdx.x == 0) slot_force[3 * s + c] = sum;
                 }
             }
         }
     }
 }
 
+// One record: mass and the force on each body, each summed in an order fixed by
+// the partials alone, so that neither the block size of the launch that runs it
+// nor the way steps are split over calls changes a record by one bit. Block
+// `part` of N_LEAD sums its fixed slice of every partial list (FIN_LANES virtual
+// lanes, then a binary tree in lds, which holds FIN_LANES doubles) into its stage
+// row; the last block to arrive adds the N_LEAD rows in block order.
+__device__ __forceinline__ void finalize3(const Fin3Args& f, int buf, int part, double* lds, int* flag)
+{
+    const double* pm = f.mass_part + buf * f.mass_stride;
+    const double* sf = f.slot_force + buf * f.slot_stride;
+    const int row_len = 1 + 3 * f.max_bodies;
+    double* row = f.stage + (int64_t)part * row_len;
+    const int m0 = (int)((int64_t)f.n_mass * part / N_LEAD), m1 = (int)((int64_t)f.n_mass * (part + 1) / N_LEAD);
+    for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) lds[v] = lane_sum(pm + m0, m1 - m0, v);
+    const double m = tree_sum(lds);
+    if (threadIdx.x == 0) row[0] = m;
+    for (int b = 0; b < f.n_bodies; ++b) {
+        const int s0 = f.body_slot_ptr[b], n = f.body_slot_ptr[b + 1] - s0;
+        const int a0 = s0 + (int)((int64_t)n * part / N_LEAD), a1 = s0 + (int)((int64_t)n * (part + 1) / N_LEAD);
+        for (int c = 0; c < 3; ++c) {
+            for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
+                double x = 0.0;
+                for (int kk = a0 + v; kk < a1; kk += FIN_LANES) x += sf[3 * f.body_slots[kk] + c];
+                lds[v] = x;
+            }
+            const double X = tree_sum(lds);
+            if (threadIdx.x == 0) row[1 + 3 * b + c] = X;
+        }
+    }
+    __threadfence();   // publish the row before counting in
+    if (threadIdx.x == 0)
+        *flag = atomicAdd(reinterpret_cast<unsigned long long*>(f.arrivals), 1ull) == (unsigned long long)(N_LEAD - 1);
+    __syncthreads();
+    if (!*flag) return;
+    __threadfence();   // the other blocks' rows are visible from here on
+    if (threadIdx.x == 0) {
+        const int64_t r = *f.rec_count % f.capacity;
+        double mass = 0.0;
+        for (int p = 0; p < N_LEAD; ++p) mass += f.stage[(int64_t)p * row_len];
+        for (int b = 0; b < f.n_bodies; ++b)
+            for (int c = 0; c < 3; ++c) {
+                double x = 0.0;
+                for (int p = 0; p < N_LEAD; ++p) x += f.stage[(int64_t)p * row_len + 1 + 3 * b + c];
+                f.ring_force[(r * f.max_bodies + b) * 3 + c] = x;
+            }
+        f.ring_mass[r] = f.mass_offset + mass;
+        *f.rec_count += 1;
+        *f.arrivals = 0;
+    }
+}
+
+// A step launch: when the previous step recorded (fin_buf >= 0), N_LEAD leading
+// blocks sum that record while the other blocks stream their tiles.
 template <typename S, int V, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256)
 k_step3(const S* __restrict__ src, S* __restrict__ dst, Step3Args<typename Arith<S>::R> a)
 {
-    __shared__ double lds[4];   // per-wavefront sums of block_sum
-    const int t = xcd_tile(a.tiles_per_xcd, 0);
+    __shared__ double lds[FIN_LANES];   // the record sums; per-wavefront sums of block_sum
+    const int lead = a.fin_buf >= 0 ? N_LEAD : 0;
+    if ((int)blockIdx.x < lead) {
+        __shared__ int last;
+        finalize3(a.fin, a.fin_buf, (int)blockIdx.x, lds, &last);
+        return;
+    }
+    const int t = xcd_tile(a.tiles_per_xcd, lead);
     if (t >= a.n_tiles) return;   // whole block
     step3_body<S, V, RECORD, FIELDS>(src, dst, a, t, lds);
 }
 
-// One record: mass and the force on each body, each summed in an order fixed by
-// the partials alone (FIN_LANES virtual lanes, then a binary tree).
-__global__ void __launch_bounds__(FIN_THREADS) k_finalize3(Fin3Args f)
+// The last record of an lbvp3_step call, summed on its own (N_LEAD blocks).
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize3(Fin3Args f, int32_t buf)
 {
-    __shared__ double lds[3 * FIN_LANES];
-    double* sx = lds;
-    double* sy = lds + FIN_LANES;
-    double* sz = lds + 2 * FIN_LANES;
-    for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) sx[v] = lane_sum(f.mass_part, f.n_mass, v);
-    const double m = tree_sum(sx);
-    const int64_t r = *f.rec_count % f.capacity;
-    for (int b = 0; b < f.n_bodies; ++b) {
-        const int s0 = f.body_slot_ptr[b], s1 = f.body_slot_ptr[b + 1];
-        for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
-            double x = 0.0, y = 0.0, z = 0.0;
-            for (int kk = s0 + v; kk < s1; kk += FIN_LANES) {
-                const int s = f.body_slots[kk];
-                x += f.slot_force[3 * s];
-                y += f.slot_force[3 * s + 1];
-                z += f.slot_force[3 * s + 2];
-            }
-            sx[v] = x;
-            sy[v] = y;
-            sz[v] = z;
-        }
-        const double X = tree_sum(sx);
-        const double Y = tree_sum(sy);
-        const double Z = tree_sum(sz);
-        if (threadIdx.x == 0) {
-            double* o = f.ring_force + (r * f.max_bodies + b) * 3;
-            o[0] = X;
-            o[1] = Y;
-            o[2] = Z;
-        }
-    }
-    if (threadIdx.x == 0) {
-        f.ring_mass[r] = f.mass_offset + m;
-        *f.rec_count += 1;
-    }
+    __shared__ double lds[FIN_LANES];
+    __shared__ int last;
+    finalize3(f, buf, (int)blockIdx.x, lds, &last);
 }
 
 // ------------------------------------------------------------ conversions --
@@ -446,7 +479,7 @@ hipError_t step_v(bool record, bool fields, const S* in, S* out, const Step3Args
                   hipStream_t s)
 {
     using R = typename Arith<S>::R;
-    const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD)), block((unsigned)a.block);
+    const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD + (a.fin_buf >= 0 ? N_LEAD : 0))), block((unsigned)a.block);
     const size_t lds = record ? 3 * (size_t)V * (size_t)a.block * sizeof(R) : 0;
     if (record) {
         if (fields) hipLaunchKernelGGL((k_step3<S, V, true, true>), grid, block, lds, s, in, out, a);
@@ -502,9 +535,9 @@ hipError_t launch_step3(int32_t storage, bool record, bool fields, const void* s
     }
 }
 
-hipError_t launch_finalize3(const Fin3Args& a, hipStream_t s)
+hipError_t launch_finalize3(const Fin3Args& a, int32_t buf, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize3, dim3(1), dim3(FIN_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_finalize3, dim3(N_LEAD), dim3(FIN_THREADS), 0, s, a, buf);
     return hipGetLastError();
 }
 

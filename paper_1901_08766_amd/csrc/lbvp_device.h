@@ -84,6 +84,17 @@ __device__ __forceinline__ void store_vec(S* p, const S (&in)[V])
     }
 }
 
+// One element, non-temporal like the vector stores. Every store of the lattice
+// carries the hint: where the compiler merges a vector path and an element path
+// into one store, it keeps only the hints both carry, and a plain element store
+// there once stripped it from all 19 stores of a 3-D step (7% slower).
+template <typename S>
+__device__ __forceinline__ void store_one(S* p, S v)
+{
+    const S tmp[1] = {v};
+    store_vec<S, 1>(p, tmp);
+}
+
 // The same V elements starting one element off a 16-byte boundary: a single
 // vector access that needs only the element's own (dword or wider) alignment.
 template <typename S, int V>
@@ -114,6 +125,33 @@ __device__ __forceinline__ void load_mask(const uint8_t* p, int (&out)[V])
 }
 
 // ------------------------------------------------------------ reductions --
+// One DPP move of a double (both 32-bit halves with the same control); lanes
+// whose source lies outside the pattern, or whose row is masked off, read 0.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROW_MASK, BANK_MASK, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROW_MASK, BANK_MASK, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 64 lanes of a wavefront, returned in lane 63, in an order fixed
+// by the code: running sums over 2, 4, 8, 16 lanes within each row of 16
+// (row_shr 1, 2, 4, 8), then row 0's total into row 1 and row 2's into row 3
+// (row_bcast 15), then rows 0-1 into rows 2-3 (row_bcast 31). DPP moves are
+// ALU operations of a few cycles; a chain of six LDS-permute shuffles at the end
+// of every wavefront of a recording step cost ~7% of a 3-D step.
+__device__ __forceinline__ double wave_sum_lane63(double x)
+{
+    x += dpp_f64<0x111, 0xf, 0xf>(x);   // row_shr:1
+    x += dpp_f64<0x112, 0xf, 0xf>(x);   // row_shr:2
+    x += dpp_f64<0x114, 0xf, 0xf>(x);   // row_shr:4
+    x += dpp_f64<0x118, 0xf, 0xf>(x);   // row_shr:8: lane 16 r + 15 holds row r's sum
+    x += dpp_f64<0x142, 0xa, 0xf>(x);   // row_bcast:15 into rows 1 and 3
+    x += dpp_f64<0x143, 0xc, 0xf>(x);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 // Dynamic LDS of a recording step launch: [2][V][blockDim] values of the
 // arithmetic type (the penalization force of every node of the tile).
 template <typename R>

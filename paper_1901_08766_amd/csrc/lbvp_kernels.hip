@@ -57,7 +57,10 @@ struct NodeResult {
 
 // Steps (4)-(6) of the algorithm at node (i, j) with streamed populations f;
 // overwrites f with the post-collision populations.
-template <typename R, bool MOVING = false>
+// EXACT_MOM: the odd equilibrium from the momentum (momentum3); the 2-byte
+// storage types take 3 rho u as (3 rho) u instead, whose ~1e-8 momentum bias is
+// far below their own rounding, for two fewer quotients per node.
+template <typename R, bool MOVING = false, bool EXACT_MOM = true>
 __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i, int j, const StepArgs<R>& a)
 {
     // moments with the integers 36 w_a = 16, 4, 1 (sum w_a rho0 = rho0 and
@@ -93,7 +96,15 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
         uy += duy;
     }
     const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
-    const R px = momentum3(jx36, fvx), py = momentum3(jy36, fvy);   // 3 rho u
+    R px, py;   // 3 rho u
+    if constexpr (EXACT_MOM) {
+        px = momentum3(jx36, fvx);
+        py = momentum3(jy36, fvy);
+    } else {
+        const R rho3 = R(3) * rho;
+        px = rho3 * ux;
+        py = rho3 * uy;
+    }
 
     NodeTerms<R> n;
     const R uu = ux * ux + uy * uy;
@@ -370,7 +381,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 f[q] = pull_column<MODE, S, R>(src, q, MODE == AA_PUSH ? OPP[q] : q, row_of[q], row_idx[q], a.nx, a);
             }
         }
-        const NodeResult<R> n = collide_node<R, MOVING>(f, body[k], i, j, a);
+        const NodeResult<R> n = collide_node<R, MOVING, (sizeof(S) >= 4)>(f, body[k], i, j, a);
 #pragma unroll
         for (int q = 0; q < 9; ++q) out[q][k] = enc<S>(f[q]);
         fl_rho[k] = n.rho;
@@ -401,7 +412,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
             for (int k = 0; k < V; ++k)
                 if (k < n_own)
 #pragma unroll
-                    for (int q = 0; q < 9; ++q) dst[(MODE == PULL ? q : OPP[q]) * P + l0 + i0 + k] = out[q][k];
+                    for (int q = 0; q < 9; ++q) store_one<S>(dst + (MODE == PULL ? q : OPP[q]) * P + l0 + i0 + k, out[q][k]);
         }
         if constexpr (MODE == AA_LOCAL) {
             // the zero-gradient ghost columns that the next push step pulls from
@@ -428,7 +439,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                     else store_vec_shifted<S, V>(dst + q * P + row_to[q] + (i0 - 1), out[q]);
                 } else {
 #pragma unroll
-                    for (int k = 0; k < V; ++k) dst[q * P + row_to[q] + i0 + k + EXQ[q]] = out[q][k];
+                    for (int k = 0; k < V; ++k) store_one<S>(dst + q * P + row_to[q] + i0 + k + EXQ[q], out[q][k]);
                 }
             }
         } else if (act) {
@@ -448,23 +459,23 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                             keep = (a.east == SIDE_PERIODIC);
                             c = 0;
                         }
-                        if (keep) dst[q * P + row_to[q] + c] = out[q][k];
+                        if (keep) store_one<S>(dst + q * P + row_to[q] + c, out[q][k]);
                     }
                     // populations entering through a non-periodic side, for the next step
                     if (i == 0 && a.west != SIDE_PERIODIC) {
 #pragma unroll
                         for (int m = 0; m < 3; ++m) {
                             const int q = EXP[m];
-                            if (a.west == SIDE_INFLOW_EQ) dst[q * P + l0] = enc<S>(a.feq_in[q]);
-                            else dst[q * P + row_to[q]] = out[q][k];
+                            if (a.west == SIDE_INFLOW_EQ) store_one<S>(dst + q * P + l0, enc<S>(a.feq_in[q]));
+                            else store_one<S>(dst + q * P + row_to[q], out[q][k]);
                         }
                     }
                     if (i == a.nx - 1 && a.east != SIDE_PERIODIC) {
 #pragma unroll
                         for (int m = 0; m < 3; ++m) {
                             const int q = EXM[m];
-                            if (a.east == SIDE_INFLOW_EQ) dst[q * P + l0 + i] = enc<S>(a.feq_in[q]);
-                            else dst[q * P + row_to[q] + i] = out[q][k];
+                            if (a.east == SIDE_INFLOW_EQ) store_one<S>(dst + q * P + l0 + i, enc<S>(a.feq_in[q]));
+                            else store_one<S>(dst + q * P + row_to[q] + i, out[q][k]);
                         }
                     }
                 }
@@ -488,13 +499,11 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     }
 
     if constexpr (RECORD) {
-        // mass: one partial per wavefront (lane shuffles only, no block barrier)
+        // mass: one partial per wavefront (DPP moves only, no block barrier)
         double* mass_part = a.mass_part + part_buf * a.fin.mass_stride;
         double* slot_force = a.slot_force + part_buf * a.fin.slot_stride;
-        double wm = tile_drho;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1) wm += __shfl_down(wm, off, 64);
-        if (lane == 0) mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
+        const double wm = wave_sum_lane63(tile_drho);
+        if (lane == 63) mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
         // forces: only tiles that hold solid nodes (uniform across the block);
         // the body ids are read again (cache hit) rather than kept live
         int bid[V];

@@ -23,6 +23,7 @@ import numpy as np
 from .inputs import INFLOW_EQ, OUTFLOW, PERIODIC, Problem, tau_plus_from_viscosity, viscosity_from_re
 
 BODY_COLS = 9
+SPHERE_SHAPE = (512, 256, 256)   # nx, ny, nz of the sphere workload
 
 
 @dataclasses.dataclass
@@ -170,7 +171,8 @@ def random_state_problem3(nx: int, ny: int, nz: int, seed, n_spheres: int = 3,
                     uz_init=uz, u_ref=u, l_ref=1.0)
 
 
-def sphere(nx: int = 512, ny: int = 256, nz: int = 256, d: float = 32.0, cx: Optional[float] = None,
+def sphere(nx: int = SPHERE_SHAPE[0], ny: int = SPHERE_SHAPE[1], nz: int = SPHERE_SHAPE[2], d: float = 32.0,
+           cx: Optional[float] = None,
            u: float = 0.05, re: float = 300.0, magic_lambda: float = 0.25, eta: float = 1e-4,
            amp: float = 0.01, seed: int = 11, steps: int = 0) -> Problem3:
     """Uniform flow past a fixed sphere (the 3-D counterpart of the cylinder
