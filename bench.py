@@ -15,6 +15,7 @@ sample of the same workload.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16|bf16|f64]
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -119,6 +120,56 @@ def time_d3q19(storages, steps: int, warmup: int):
         print(f"# d3q19 {st}: {out['per_storage'][st]}", file=sys.stderr, flush=True)
         s.close()
         torch.cuda.empty_cache()
+    return out
+
+
+def time_slabs(n_slabs: int, steps: int = 100, storage: str = "f32"):
+    """The large domain cut into n_slabs x-slabs on this one GPU (a halo exchange
+    over every cut, then one batched step of all slabs) against the whole
+    domain; and one slab alone, closed on itself through its own halo exchange:
+    the share one GPU of n_slabs would step, with its exchange."""
+    import torch
+    from paper_1901_08766_amd import inputs, lbvp
+
+    prob = inputs.large_domain()
+    nodes = prob.nx * prob.ny
+    w = prob.nx // n_slabs
+    widths = [w] * (n_slabs - 1) + [prob.nx - w * (n_slabs - 1)]
+    out = {"workload": f"large single domain {prob.nx}x{prob.ny} in {n_slabs} x-slabs of {w}", "storage": storage}
+    whole = lbvp.Solver(prob, storage=storage, force_every=1, force_capacity=steps + 16)
+    whole.step(5)
+    whole.forces()
+    out["whole_ms_per_step"] = round(_timed(whole.stream, lambda: whole.step(steps)) / steps, 4)
+    whole.forces()
+    whole.close()
+    torch.cuda.empty_cache()
+    slabs_p, x0s = inputs.split_x(prob, widths)
+    slabs = lbvp.Slabs(slabs_p, x0s, storage=storage, force_every=1, force_capacity=steps + 16)
+    slabs.step(5)
+    slabs.forces()
+    ms = _timed(slabs.stream, lambda: slabs.step(steps)) / steps
+    slabs.forces()
+    out["slabs_ms_per_step"] = round(ms, 4)
+    out["slabs_MLUPS"] = round(nodes / (ms * 1e-3) / 1e6, 1)
+    out["overhead_vs_whole"] = round(ms / out["whole_ms_per_step"] - 1.0, 4)
+    ex = _timed(slabs.stream, lambda: [slabs.exchange() for _ in range(steps)]) / steps
+    out["exchange_us_per_step"] = round(ex * 1e3, 2)
+    out["bytes_per_cut_per_step"] = 2 * 3 * prob.ny * STORAGE_BYTES[storage]
+    slabs.close()
+    torch.cuda.empty_cache()
+    # one slab, closed on itself: its halo exchange stands in for the transfer
+    one = inputs.split_x(dataclasses.replace(prob, nx=w, bc=("periodic", "periodic", "periodic", "periodic"),
+                                             mask=prob.mask[:, :w].copy(), rho_init=None, ux_init=None,
+                                             uy_init=None), [w])[0]
+    alone = lbvp.Slabs(one, [0], storage=storage, force_every=1, force_capacity=steps + 16)
+    alone.step(5)
+    alone.forces()
+    ms1 = _timed(alone.stream, lambda: alone.step(steps)) / steps
+    alone.forces()
+    alone.close()
+    out["one_slab_ms_per_step"] = round(ms1, 4)
+    out["one_slab_MLUPS"] = round(w * prob.ny / (ms1 * 1e-3) / 1e6, 1)
+    out["projected_n_gpu_MLUPS"] = round(n_slabs * w * prob.ny / (ms1 * 1e-3) / 1e6, 1)
     return out
 
 
@@ -496,6 +547,8 @@ def main():
                     help="timed steps of the D3Q19 sphere domain (0: skip it)")
     ap.add_argument("--d3q19-storages", default="f32,f16,f64")
     ap.add_argument("--d3q19-only", action="store_true", help="only run the D3Q19 timing leg")
+    ap.add_argument("--slabs", type=int, default=0, metavar="N",
+                    help="only time the large domain as N x-slabs on this GPU (halo exchange + batched step)")
     ap.add_argument("--lattice", default="d2q9", choices=sorted(LATTICES),
                     help="the step kernel --summarize-counters describes")
     ap.add_argument("--serve-requests", type=int, default=100,
@@ -526,6 +579,9 @@ def main():
     if a.summarize_counters:
         sf, sw, cf, cw, cb, kern, md, cmd = a.summarize_counters
         summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, md, cmd, a.lattice)
+        return
+    if a.slabs:
+        print(json.dumps(time_slabs(a.slabs, storage=a.storage)), flush=True)
         return
     if a.d3q19_only:
         print(json.dumps(time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, 5)), flush=True)

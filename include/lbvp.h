@@ -55,7 +55,12 @@ typedef enum lbvp_status {
 typedef enum lbvp_bc {
     LBVP_BC_PERIODIC = 0,
     LBVP_BC_INFLOW_EQ = 1,
-    LBVP_BC_OUTFLOW_ZERO_GRAD = 2
+    LBVP_BC_OUTFLOW_ZERO_GRAD = 2,
+    /* a cut through one larger domain (slab decomposition along x): the
+     * populations entering through this side are the neighbouring slab's
+     * post-collision boundary column, delivered by lbvp_halo_exchange before
+     * each step. Not with LBVP_LAYOUT_AA or LBVP_MOVING_BODIES. */
+    LBVP_BC_NEIGHBOR = 3
 } lbvp_bc;
 
 /* Storage type of the nine populations in device memory. All types store the
@@ -248,6 +253,13 @@ lbvp_status lbvp_batch_create(lbvp_ctx* const* members, int32_t n, int32_t vec, 
 lbvp_status lbvp_batch_step(lbvp_batch* batch, int64_t n_steps, uint32_t flags);
 lbvp_status lbvp_batch_destroy(lbvp_batch* batch);
 const char* lbvp_batch_last_error(const lbvp_batch* batch);
+/* The slabs of one decomposed domain as members of a batch: before every step,
+ * lbvp_batch_step exchanges the halo columns of the n cuts (member west[i]'s east
+ * side to member east[i]'s west side, as lbvp_halo_exchange does) in one kernel,
+ * so a run of steps needs one call. n = 0 removes the cuts; replacing the
+ * members removes them too. E_ARG (n > 32, an index out of range, a linked side
+ * that is not LBVP_BC_NEIGHBOR, unequal ny). */
+lbvp_status lbvp_batch_set_halo(lbvp_batch* batch, const int32_t* west, const int32_t* east, int32_t n);
 
 /* ---- Tuner ----------------------------------------------------------------------
  * Times the step kernel for every launch shape (vec x block) and, with
@@ -351,6 +363,20 @@ const char* lbvp_pool_last_error(const lbvp_pool* pool);
  * (asynchronous). Its rate is the copy bandwidth the step is compared with.
  * E_ARG on misaligned pointers or sizes, E_DEVICE on a launch failure. */
 lbvp_status lbvp_device_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
+
+/* Slab decomposition of one domain along x (the decomposition the method's
+ * two-lattice streaming, eq. streaming, allows: per step only the populations
+ * crossing a cut move). For each i, link i joins west[i]'s east side to
+ * east[i]'s west side (both LBVP_BC_NEIGHBOR; west[i] == east[i] closes one slab
+ * on itself): east[i]'s west halo column receives west[i]'s current populations
+ * with e_x = +1 at its column nx - 1, and west[i]'s east halo column receives
+ * east[i]'s populations with e_x = -1 at its column 0. Call it before every step
+ * of the slabs; one kernel, enqueued on west[0]'s stream, which must be the
+ * stream of every slab (one device: the slabs stand for the shares of several
+ * GPUs, where this is the halo transfer over xGMI). Linked slabs need equal ny
+ * and storage type. Errors: E_ARG (NULL, n < 1 or > 32, a side that is not
+ * LBVP_BC_NEIGHBOR, unequal ny, storage or stream), E_DEVICE. */
+lbvp_status lbvp_halo_exchange(lbvp_ctx* const* west, lbvp_ctx* const* east, int32_t n);
 
 /* Number of steps taken since the last lbvp_init_equilibrium. */
 int64_t lbvp_step_count(const lbvp_ctx* ctx);

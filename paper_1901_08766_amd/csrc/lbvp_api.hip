@@ -130,8 +130,13 @@ std::string validate(const lbvp_params* p)
     const double vals[] = {p->rho_in, p->u_in[0], p->u_in[1], p->body_force[0], p->body_force[1]};
     for (double v : vals)
         if (!std::isfinite(v)) return "non-finite inflow state or body force";
-    auto side_ok = [](int32_t s) { return s == LBVP_BC_PERIODIC || s == LBVP_BC_INFLOW_EQ || s == LBVP_BC_OUTFLOW_ZERO_GRAD; };
+    auto side_ok = [](int32_t s) {
+        return s == LBVP_BC_PERIODIC || s == LBVP_BC_INFLOW_EQ || s == LBVP_BC_OUTFLOW_ZERO_GRAD || s == LBVP_BC_NEIGHBOR;
+    };
     if (!side_ok(p->bc_west) || !side_ok(p->bc_east)) return "unknown x side";
+    const bool cut = p->bc_west == LBVP_BC_NEIGHBOR || p->bc_east == LBVP_BC_NEIGHBOR;
+    if (cut && (p->flags & (LBVP_LAYOUT_AA | LBVP_MOVING_BODIES)))
+        return "LBVP_BC_NEIGHBOR sides need the two-lattice layout and a fixed mask";
     if ((p->bc_west == LBVP_BC_PERIODIC) != (p->bc_east == LBVP_BC_PERIODIC))
         return "x sides must be both periodic or both non-periodic";
     if (p->bc_south != LBVP_BC_PERIODIC || p->bc_north != LBVP_BC_PERIODIC) return "y sides must be periodic";
@@ -673,6 +678,7 @@ struct lbvp_batch {
     PinnedRing ring;
     GraphCache graphs;
     uint64_t gen = 0;                    // bumped whenever the members or the block change
+    std::vector<int32_t> halo_w, halo_e; // cuts between members (lbvp_batch_set_halo)
     std::string err;
 
     lbvp_status fail(lbvp_status st, const std::string& m) { err = m; return st; }
@@ -760,6 +766,8 @@ lbvp_status batch_assign(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
     std::memcpy(b->image.data() + b->off_tile_domain, tile_domain.data(), tile_domain.size() * sizeof(int32_t));
     std::memcpy(b->image.data() + b->off_tile_start, tile_start.data(), n * sizeof(int32_t));
     b->members = m;
+    b->halo_w.clear();   // member indices no longer mean the same contexts
+    b->halo_e.clear();
     b->total_tiles = (int32_t)tile_domain.size();
     b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
     b->graphs.clear(b->stream);
@@ -826,6 +834,19 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
         L.fin_buf = pending ? pending_buf : -1;
         L.n_domains = (int32_t)b->members.size();
         L.n_fin = L.fin_buf >= 0 ? (L.n_domains + N_XCD - 1) / N_XCD * N_XCD : 0;
+        if (!b->halo_w.empty()) {   // the cuts' halo columns for this step
+            BatchHalo H{};
+            H.n_links = (int32_t)b->halo_w.size();
+            H.ny = b->members[0]->p.ny;
+            H.flip = L.flip;
+            H.args = b->dev;
+            for (int32_t i = 0; i < H.n_links; ++i) {
+                H.w[i] = b->halo_w[i];
+                H.e[i] = b->halo_e[i];
+            }
+            hipError_t he = launch_halo_batch(b->storage, H, b->stream);
+            if (he != hipSuccess) return b->hip_fail(he, "halo exchange launch");
+        }
         hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, L, b->stream);
         if (e != hipSuccess) return b->hip_fail(e, "batched step launch");
         pending = record;
@@ -1120,6 +1141,11 @@ lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* 
         LBVP_HIP(c, launch_init(p.storage, c->at<char>(L.lat[0]), c->at<char>(L.fields), a, s));
     }
     LBVP_HIP(c, refresh_aa_ghosts(c));
+    if (p.bc_west == LBVP_BC_NEIGHBOR || p.bc_east == LBVP_BC_NEIGHBOR) {
+        // halo columns at rest (zero deviation) until the first lbvp_halo_exchange
+        LBVP_HIP(c, hipMemsetAsync(c->at<char>(L.ghost_w), 0, 3 * (size_t)p.ny * c->esize(), s));
+        LBVP_HIP(c, hipMemsetAsync(c->at<char>(L.ghost_e), 0, 3 * (size_t)p.ny * c->esize(), s));
+    }
     LBVP_HIP(c, launch_set_i64(c->fin.rec_count, 0, s));
     LBVP_HIP(c, hipStreamSynchronize(s));
     c->cur = 0;
@@ -1446,6 +1472,38 @@ lbvp_status lbvp_get_launch(const lbvp_ctx* c, int32_t* vec, int32_t* block)
     return LBVP_OK;
 }
 
+lbvp_status lbvp_halo_exchange(lbvp_ctx* const* west, lbvp_ctx* const* east, int32_t n)
+{
+    if (!west || !east || n < 1 || n > MAX_HALO_LINKS || !west[0]) return LBVP_E_ARG;
+    lbvp_ctx* c0 = west[0];
+    HaloArgs h{};
+    h.n_links = n;
+    h.ny = c0->p.ny;
+    for (int32_t i = 0; i < n; ++i) {
+        lbvp_ctx* w = west[i];
+        lbvp_ctx* e = east[i];
+        if (!w || !e) return c0->fail(LBVP_E_ARG, "lbvp_halo_exchange: NULL context");
+        if (w->p.bc_east != LBVP_BC_NEIGHBOR || e->p.bc_west != LBVP_BC_NEIGHBOR)
+            return c0->fail(LBVP_E_ARG, "lbvp_halo_exchange: linked sides must be LBVP_BC_NEIGHBOR");
+        if (w->p.ny != h.ny || e->p.ny != h.ny || w->p.storage != c0->p.storage || e->p.storage != c0->p.storage)
+            return c0->fail(LBVP_E_ARG, "lbvp_halo_exchange: linked slabs need equal ny and storage type");
+        if (w->stream != c0->stream || e->stream != c0->stream)
+            return c0->fail(LBVP_E_ARG, "lbvp_halo_exchange: all slabs must share one stream");
+        HaloLink& L = h.link[i];
+        L.w_lat = w->at<char>(w->L.lat[w->cur]);
+        L.e_lat = e->at<char>(e->L.lat[e->cur]);
+        L.e_halo_w = e->at<char>(e->L.ghost_w);
+        L.w_halo_e = w->at<char>(w->L.ghost_e);
+        L.w_lstride = w->L.lstride;
+        L.w_plane = w->L.plane;
+        L.e_lstride = e->L.lstride;
+        L.e_plane = e->L.plane;
+        L.w_nx = w->p.nx;
+    }
+    LBVP_HIP(c0, launch_halo(c0->p.storage, h, c0->stream));
+    return LBVP_OK;
+}
+
 int64_t lbvp_step_count(const lbvp_ctx* c) { return c ? c->step : -1; }
 
 lbvp_status lbvp_device_copy(const void* src, void* dst, size_t bytes, void* hip_stream)
@@ -1577,6 +1635,29 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
         c->rec_head += recs;
         if (keep) c->fields_valid = true;
     }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_batch_set_halo(lbvp_batch* b, const int32_t* west, const int32_t* east, int32_t n)
+{
+    if (!b) return LBVP_E_ARG;
+    if (n < 0 || n > MAX_HALO_LINKS || (n > 0 && (!west || !east)))
+        return b->fail(LBVP_E_ARG, "lbvp_batch_set_halo: 0..32 links with both index arrays");
+    const int32_t nm = (int32_t)b->members.size();
+    for (int32_t i = 0; i < n; ++i) {
+        if (west[i] < 0 || west[i] >= nm || east[i] < 0 || east[i] >= nm)
+            return b->fail(LBVP_E_ARG, "lbvp_batch_set_halo: member index out of range");
+        const lbvp_ctx* w = b->members[west[i]];
+        const lbvp_ctx* e = b->members[east[i]];
+        if (w->p.bc_east != LBVP_BC_NEIGHBOR || e->p.bc_west != LBVP_BC_NEIGHBOR)
+            return b->fail(LBVP_E_ARG, "lbvp_batch_set_halo: linked sides must be LBVP_BC_NEIGHBOR");
+        if (w->p.ny != b->members[0]->p.ny || e->p.ny != b->members[0]->p.ny)
+            return b->fail(LBVP_E_ARG, "lbvp_batch_set_halo: linked members need equal ny");
+    }
+    b->halo_w.assign(west, west + n);
+    b->halo_e.assign(east, east + n);
+    b->graphs.clear(b->stream);
+    b->gen += 1;
     return LBVP_OK;
 }
 

@@ -23,7 +23,7 @@ constexpr int MAX_MOVING = 8;       // bodies of a domain with moving masks
 constexpr int POSE_STRIDE = 8;      // doubles per body pose row
 constexpr int POSE_ROWS = 1024;     // time levels per uploaded pose table
 
-enum Side : int32_t { SIDE_PERIODIC = 0, SIDE_INFLOW_EQ = 1, SIDE_OUTFLOW = 2 };
+enum Side : int32_t { SIDE_PERIODIC = 0, SIDE_INFLOW_EQ = 1, SIDE_OUTFLOW = 2, SIDE_NEIGHBOR = 3 };
 
 // Storage codes (match lbvp_storage).
 enum Storage : int32_t { ST_F64 = 0, ST_F32 = 1, ST_F16 = 2, ST_BF16 = 3 };
@@ -102,6 +102,32 @@ struct BatchLaunch {
     const void* args;               // StepArgs<R>[n_domains]
 };
 
+// One cut between two slabs (lbvp_halo_exchange): west's column nx - 1
+// populations with e_x = +1 into east's west halo, east's column 0 populations
+// with e_x = -1 into west's east halo; halos are [3][ny] of the storage type.
+struct HaloLink {
+    const void* w_lat;
+    const void* e_lat;
+    void* e_halo_w;
+    void* w_halo_e;
+    int64_t w_lstride, w_plane, e_lstride, e_plane;
+    int32_t w_nx;
+};
+constexpr int MAX_HALO_LINKS = 32;   // HaloArgs stays within the 4 KB of kernel arguments
+struct HaloArgs {
+    int32_t n_links, ny;
+    HaloLink link[MAX_HALO_LINKS];
+};
+
+// The cuts of a batch (lbvp_batch_set_halo): member indices of each link; the
+// lattices, halos and strides come from the members' step arguments in the
+// batch's device block, with the lattice parity `flip` of the coming step.
+struct BatchHalo {
+    int32_t n_links, ny, flip;
+    int32_t w[MAX_HALO_LINKS], e[MAX_HALO_LINKS];
+    const void* args;   // StepArgs<R>[members]
+};
+
 struct GhostArgs {
     int32_t nx, ny;
     int32_t west_outflow, east_outflow;
@@ -144,6 +170,8 @@ hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hi
 hipError_t launch_encode(int32_t storage, void* lat, const ConvArgs& a, hipStream_t s);
 hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s);
+hipError_t launch_halo(int32_t storage, const HaloArgs& h, hipStream_t s);
+hipError_t launch_halo_batch(int32_t storage, const BatchHalo& h, hipStream_t s);
 
 // host-side pieces the serving pool builds on (lbvp_api.hip)
 // An empty batch of the given kind on a stream; members come with batch_set_members.

@@ -186,7 +186,9 @@ enum Mode { PULL = 0, AA_PUSH = 1, AA_LOCAL = 2 };
 
 // Population q pulled from column c (-1 and nx are outside the domain) of plane
 // `plane_q` in the row starting at row_off (row index `row`): the domain sides
-// are resolved here. Ghost populations are values of the storage type, like
+// are resolved here. A NEIGHBOR side (a cut of a slab decomposition) reads the
+// halo column that lbvp_halo_exchange filled, in the ghost-column buffers the
+// AA layout uses for its outflow sides (the two never meet). Ghost populations are values of the storage type, like
 // every other population (the AA push step stores the inflow ones in the
 // lattice), so the inflow equilibrium is rounded to it.
 template <int MODE, typename S, typename R>
@@ -195,12 +197,12 @@ __device__ __forceinline__ R pull_column(const S* src, int q, int plane_q, int64
 {
     if (c < 0) {
         if (a.west == SIDE_INFLOW_EQ) return dec(enc<S>(a.feq_in[q]));
-        if (MODE == AA_PUSH && a.west == SIDE_OUTFLOW)
+        if (a.west == SIDE_NEIGHBOR || (MODE == AA_PUSH && a.west == SIDE_OUTFLOW))
             return dec(static_cast<const S*>(a.ghost_w)[(q == 1 ? 0 : q == 5 ? 1 : 2) * (int64_t)a.ny + row]);
         c = (a.west == SIDE_PERIODIC) ? a.nx - 1 : 0;
     } else if (c >= a.nx) {
         if (a.east == SIDE_INFLOW_EQ) return dec(enc<S>(a.feq_in[q]));
-        if (MODE == AA_PUSH && a.east == SIDE_OUTFLOW)
+        if (a.east == SIDE_NEIGHBOR || (MODE == AA_PUSH && a.east == SIDE_OUTFLOW))
             return dec(static_cast<const S*>(a.ghost_e)[(q == 3 ? 0 : q == 6 ? 1 : 2) * (int64_t)a.ny + row]);
         c = (a.east == SIDE_PERIODIC) ? 0 : a.nx - 1;
     }
@@ -727,6 +729,51 @@ __global__ void __launch_bounds__(256) k_aa_ghosts(const S* lat, GhostArgs a)
     }
 }
 
+// The halo columns of every cut of a slab decomposition (one thread per row and
+// direction of each link): plain copies of the storage values, so that a
+// decomposed domain steps bitwise like the whole one.
+template <typename S>
+__global__ void __launch_bounds__(256) k_halo(HaloArgs h)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_link = 3 * (int64_t)h.ny;
+    if (k >= per_link * h.n_links) return;
+    const int l = (int)(k / per_link);
+    const int r = (int)(k - (int64_t)l * per_link);
+    const int m = r / h.ny, j = r - m * h.ny;
+    const HaloLink& L = h.link[l];
+    const int q_in = m == 0 ? 1 : (m == 1 ? 5 : 8);    // e_x = +1 (1, 5, 8): leave west through its east side
+    const int q_out = m == 0 ? 3 : (m == 1 ? 6 : 7);   // e_x = -1 (3, 6, 7): leave east through its west side
+    static_cast<S*>(L.e_halo_w)[(int64_t)m * h.ny + j] =
+        static_cast<const S*>(L.w_lat)[j * L.w_lstride + q_in * L.w_plane + (L.w_nx - 1)];
+    static_cast<S*>(L.w_halo_e)[(int64_t)m * h.ny + j] =
+        static_cast<const S*>(L.e_lat)[j * L.e_lstride + q_out * L.e_plane];
+}
+
+// The same for the cuts of a batch, before one of its steps: each member's
+// current lattice is read from its step arguments (so a captured graph replays
+// correctly whatever the members' lattice parity when it is launched).
+template <typename S>
+__global__ void __launch_bounds__(256) k_halo_batch(BatchHalo h)
+{
+    using R = typename Arith<S>::R;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per_link = 3 * (int64_t)h.ny;
+    if (k >= per_link * h.n_links) return;
+    const int l = (int)(k / per_link);
+    const int r = (int)(k - (int64_t)l * per_link);
+    const int m = r / h.ny, j = r - m * h.ny;
+    const StepArgs<R>* args = static_cast<const StepArgs<R>*>(h.args);
+    const StepArgs<R>& aw = args[h.w[l]];
+    const StepArgs<R>& ae = args[h.e[l]];
+    const S* wl = static_cast<const S*>((aw.cur ^ h.flip) ? aw.lat1 : aw.lat0);
+    const S* el = static_cast<const S*>((ae.cur ^ h.flip) ? ae.lat1 : ae.lat0);
+    const int q_in = m == 0 ? 1 : (m == 1 ? 5 : 8);
+    const int q_out = m == 0 ? 3 : (m == 1 ? 6 : 7);
+    static_cast<S*>(ae.ghost_w)[(int64_t)m * h.ny + j] = wl[j * aw.lstride + q_in * aw.plane + (aw.nx - 1)];
+    static_cast<S*>(aw.ghost_e)[(int64_t)m * h.ny + j] = el[j * ae.lstride + q_out * ae.plane];
+}
+
 template <typename R>
 size_t record_lds_bytes(int v, int block)
 {
@@ -960,6 +1007,34 @@ hipError_t launch_copy16(const void* src, void* dst, int64_t n16, hipStream_t s)
     if (per_xcd * N_XCD > (int64_t(1) << 31) - 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_copy16, dim3((unsigned)(per_xcd * N_XCD)), dim3(256), 0, s,
                        static_cast<const u32x4_t*>(src), static_cast<u32x4_t*>(dst), n16, (int)per_xcd);
+    return hipGetLastError();
+}
+
+hipError_t launch_halo(int32_t storage, const HaloArgs& h, hipStream_t s)
+{
+    const int64_t n = 3 * (int64_t)h.ny * h.n_links;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    switch (storage) {
+    case ST_F64: hipLaunchKernelGGL(k_halo<double>, g, b, 0, s, h); break;
+    case ST_F32: hipLaunchKernelGGL(k_halo<float>, g, b, 0, s, h); break;
+    case ST_F16: hipLaunchKernelGGL(k_halo<_Float16>, g, b, 0, s, h); break;
+    case ST_BF16: hipLaunchKernelGGL(k_halo<__bf16>, g, b, 0, s, h); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_halo_batch(int32_t storage, const BatchHalo& h, hipStream_t s)
+{
+    const int64_t n = 3 * (int64_t)h.ny * h.n_links;
+    const dim3 g((unsigned)((n + 255) / 256)), b(256);
+    switch (storage) {
+    case ST_F64: hipLaunchKernelGGL(k_halo_batch<double>, g, b, 0, s, h); break;
+    case ST_F32: hipLaunchKernelGGL(k_halo_batch<float>, g, b, 0, s, h); break;
+    case ST_F16: hipLaunchKernelGGL(k_halo_batch<_Float16>, g, b, 0, s, h); break;
+    case ST_BF16: hipLaunchKernelGGL(k_halo_batch<__bf16>, g, b, 0, s, h); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -436,3 +436,34 @@ def random_state_problem(nx: int, ny: int, seed, n_disks: int = 3, bc=(INFLOW_EQ
     return Problem(name=f"random{nx}x{ny}", nx=nx, ny=ny, tau_plus=tau_plus, magic_lambda=magic_lambda,
                    eta=eta, bc=tuple(bc), rho_in=1.0, u_in=(u, 0.0), body_force=body_force,
                    mask=mask, bodies=bodies, rho_init=rho, ux_init=ux, uy_init=uy, u_ref=u, l_ref=1.0)
+
+
+def split_x(p: Problem, widths: Sequence[int]) -> Tuple[List[Problem], List[int]]:
+    """The slabs of a domain cut along x into consecutive column ranges of the
+    given widths (summing to nx): each slab keeps its columns of the mask and of
+    the initial fields and every body row with its centre moved to slab
+    coordinates (cx - x0); cut sides become "neighbor", the domain's own x sides
+    stay at the two ends (a periodic domain is cut there too). Returns the slab
+    problems and their first columns x0."""
+    if sum(widths) != p.nx or min(widths) < 3:
+        raise ValueError("slab widths must be >= 3 and sum to nx")
+    periodic = p.bc[0] == PERIODIC
+    slabs, x0s = [], []
+    x0 = 0
+    for k, w in enumerate(widths):
+        cols = slice(x0, x0 + w)
+        west = "neighbor" if (k > 0 or periodic) else p.bc[0]
+        east = "neighbor" if (k < len(widths) - 1 or periodic) else p.bc[1]
+        b = p.bodies_or_empty().copy()
+        b[:, 0] -= x0
+
+        def cut(a):
+            return None if a is None else np.ascontiguousarray(a[:, cols])
+
+        slabs.append(dataclasses.replace(
+            p, name=f"{p.name}_x{x0}+{w}", nx=w, bc=(west, east, p.bc[2], p.bc[3]), mask=cut(p.mask_or_empty()),
+            bodies=b if b.shape[0] else None, rho_init=cut(p.rho_init), ux_init=cut(p.ux_init),
+            uy_init=cut(p.uy_init)))
+        x0s.append(x0)
+        x0 += w
+    return slabs, x0s

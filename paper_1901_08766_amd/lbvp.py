@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(PKG, "liblbvp.so")
 
 OK, E_ARG, E_NOMEM, E_BUSY, E_DEVICE, E_STATE, E_UNSTABLE = range(7)
 STATUS_NAMES = ["OK", "E_ARG", "E_NOMEM", "E_BUSY", "E_DEVICE", "E_STATE", "E_UNSTABLE"]
-BC = {"periodic": 0, "inflow_eq": 1, "outflow_zero_grad": 2}
+BC = {"periodic": 0, "inflow_eq": 1, "outflow_zero_grad": 2, "neighbor": 3}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 LAYOUT_AA = 0x1
 MOVING_BODIES = 0x2
@@ -41,7 +41,7 @@ SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_eq
            "lbvp_pool_create", "lbvp_pool_admit", "lbvp_pool_run_epoch", "lbvp_pool_poll",
            "lbvp_pool_forces", "lbvp_pool_read_fields", "lbvp_pool_release", "lbvp_pool_get_stats",
            "lbvp_pool_destroy", "lbvp_pool_last_error", "lbvp_save_state", "lbvp_load_state",
-           "lbvp_device_copy"]
+           "lbvp_device_copy", "lbvp_halo_exchange", "lbvp_batch_set_halo"]
 NO_STATUS = ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error",
              "lbvp_tune_last_error", "lbvp_pool_last_error")
 
@@ -116,6 +116,8 @@ def _load():
     L.lbvp_batch_last_error.restype = C.c_char_p
     L.lbvp_batch_last_error.argtypes = [vp]
     L.lbvp_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
+    L.lbvp_halo_exchange.argtypes = [C.POINTER(vp), C.POINTER(vp), i32]
+    L.lbvp_batch_set_halo.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), i32]
     L.lbvp_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbvp_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbvp_tune.argtypes = [C.POINTER(vp), i32, i32, u32, C.POINTER(lbvp_tune_row), i32, C.POINTER(i32),
@@ -230,6 +232,14 @@ def lbvp_device_copy(src: int, dst: int, nbytes: int, stream: Optional[int] = No
         raise LbvpError(st, "lbvp_device_copy: pointers and size must be multiples of 16 bytes")
 
 
+def lbvp_halo_exchange(west, east):
+    """One halo exchange over the links (west[i], east[i]) (see lbvp_halo_exchange)."""
+    n = len(west)
+    w = (C.c_void_p * n)(*west)
+    e = (C.c_void_p * n)(*east)
+    _check(west[0] if n else None, _L.lbvp_halo_exchange(w, e, n))
+
+
 def lbvp_save_state(ctx) -> np.ndarray:
     """The context's state as a byte array (see lbvp_save_state)."""
     size = C.c_size_t()
@@ -285,6 +295,13 @@ def lbvp_batch_create(ctxs, vec: int = 0, block: int = 0):
     out = C.c_void_p()
     _check_batch(None, _L.lbvp_batch_create(arr, len(ctxs), int(vec), int(block), C.byref(out)))
     return out.value
+
+
+def lbvp_batch_set_halo(batch, west, east):
+    n = len(west)
+    w = (C.c_int32 * max(n, 1))(*west)
+    e = (C.c_int32 * max(n, 1))(*east)
+    _check_batch(batch, _L.lbvp_batch_set_halo(batch, w, e, n))
 
 
 def lbvp_batch_step(batch, n_steps: int, flags: int = 0):
@@ -593,3 +610,66 @@ class Pool:
             self.close()
         except Exception:
             pass
+
+
+class Slabs:
+    """One domain decomposed along x into slabs (``inputs.split_x``), each its own
+    context with LBVP_BC_NEIGHBOR sides at the cuts, all on one stream. Every
+    step is a halo exchange over all cuts, then one step of every slab: batched,
+    both run inside lbvp_batch_step (lbvp_batch_set_halo); unbatched, one
+    lbvp_halo_exchange and one launch per slab per step. On several GPUs each
+    slab would be one GPU's share and the exchange its xGMI transfer; here they
+    share one."""
+
+    def __init__(self, slab_problems, x0s, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
+                 batched: bool = True, launch: Optional[Tuple[int, int]] = None,
+                 stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda"):
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
+        self.solvers = [Solver(p, storage=storage, force_every=force_every, force_capacity=force_capacity,
+                               stream=self.stream, device=device) for p in slab_problems]
+        if launch is not None:
+            for s in self.solvers:
+                s.set_launch(*launch)
+        self.x0s = list(x0s)
+        n = len(self.solvers)
+        # cut k joins slab k's east side to slab k + 1's west side; a periodic
+        # domain also joins the last slab to the first
+        self.links = [(k, k + 1) for k in range(n - 1)]
+        if slab_problems[0].bc[0] == "neighbor":
+            self.links.append((n - 1, 0))
+        self.batch = Batch(self.solvers, *(launch or (0, 0))) if batched else None
+        if self.batch is not None and self.links:   # the exchange runs inside every batched step
+            lbvp_batch_set_halo(self.batch.handle, [w for w, _ in self.links], [e for _, e in self.links])
+
+    def exchange(self):
+        if self.links:
+            lbvp_halo_exchange([self.solvers[w].ctx for w, _ in self.links],
+                               [self.solvers[e].ctx for _, e in self.links])
+
+    def step(self, n: int, keep_fields: bool = False, graph: bool = False):
+        if self.batch is not None:
+            self.batch.step(n, keep_fields=keep_fields, graph=graph)
+            return
+        for k in range(n):
+            self.exchange()
+            for s in self.solvers:
+                s.step(1, keep_fields=keep_fields and k == n - 1)
+
+    def populations(self) -> np.ndarray:
+        return np.concatenate([s.populations() for s in self.solvers], axis=2)
+
+    def fields(self) -> Dict[str, np.ndarray]:
+        parts = [s.fields() for s in self.solvers]
+        return {k: np.concatenate([p[k] for p in parts], axis=1) for k in parts[0]}
+
+    def forces(self):
+        """(force on each body summed over the slabs [records][n_bodies][2],
+        mass summed over the slabs [records])."""
+        recs = [s.forces() for s in self.solvers]
+        return sum(r[0] for r in recs), sum(r[1] for r in recs)
+
+    def close(self):
+        if self.batch is not None:
+            self.batch.close()
+        for s in self.solvers:
+            s.close()

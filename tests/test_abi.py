@@ -133,3 +133,21 @@ def test_moving_bodies_limit(lbvp):
     out = C.c_void_p()
     assert lbvp.lib().lbvp_create(C.byref(p), None, None, 0, C.byref(out)) == lbvp.E_ARG
     assert "moving" in lbvp.lbvp_last_error(None)
+
+
+def test_neighbor_sides_validation(lbvp):
+    """A cut side needs the two-lattice layout and a fixed mask; with one
+    periodic x side it is rejected like any other mixed pair; the exchange
+    rejects NULL links before any device call."""
+    nb = lbvp.BC["neighbor"]
+    assert lbvp.lbvp_footprint_bytes(_params(lbvp, bc_west=nb, bc_east=nb)) > 0
+    assert lbvp.lbvp_footprint_bytes(_params(lbvp, bc_west=1, bc_east=nb)) > 0
+    for kw in ({"bc_west": nb, "bc_east": nb, "flags": lbvp.LAYOUT_AA},
+               {"bc_west": nb, "bc_east": 2, "flags": lbvp.MOVING_BODIES},
+               {"bc_west": nb, "bc_east": 0}, {"bc_west": 4, "bc_east": nb}):
+        assert lbvp.lbvp_footprint_bytes(_params(lbvp, **kw)) == 0, kw
+    L = lbvp.lib()
+    assert L.lbvp_halo_exchange(None, None, 1) == lbvp.E_ARG
+    arr = (C.c_void_p * 1)(None)
+    assert L.lbvp_halo_exchange(arr, arr, 1) == lbvp.E_ARG
+    assert L.lbvp_halo_exchange(arr, arr, 0) == lbvp.E_ARG
