@@ -137,8 +137,8 @@ lbvp_status lbvp3_read_populations(lbvp3_ctx* ctx, int32_t z0, int32_t n_planes,
  * step counter. Synchronizes the stream. */
 lbvp_status lbvp3_write_populations(lbvp3_ctx* ctx, int32_t z0, int32_t n_planes, const double* g);
 
-/* Launch configuration of the step kernel: vec nodes per thread (1, 2 or 4;
- * 1 for F16_DEV and BF16_DEV; 1 or 2 for F64) and block threads per workgroup
+/* Launch configuration of the step kernel: vec nodes per thread (1, 2 or 4 for
+ * F32; 1 or 2 for F64; 1, 4 or 8 for F16_DEV and BF16_DEV) and block threads per workgroup
  * (64, 128 or 256). Results are bitwise independent of it, except the order in
  * which force and mass records are summed. E_ARG for other values. */
 lbvp_status lbvp3_set_launch(lbvp3_ctx* ctx, int32_t vec, int32_t block);

@@ -58,17 +58,21 @@ Launch3 make_launch(int32_t nx, int64_t rows, int32_t vec, int32_t block)
     return l;
 }
 
-// Default: one node per thread, which measures fastest for every storage type on
-// a 512 x 256 x 256 domain (the 19 loads of a node already keep enough bytes in
-// flight, and the narrow form keeps ~70 VGPRs and 7 waves per SIMD, against ~150
-// VGPRs and 3 waves for four nodes per thread); 256-thread blocks for FP32, 128 for
-// FP64, 64 for the 2-byte types, and 64 on grids too small to fill the chip.
+// Defaults measured on a 512 x 256 x 256 domain: one node per thread for FP32
+// (256-thread blocks) and FP64 (128): the 19 loads of a node already keep enough
+// bytes in flight, and the narrow form keeps ~70 VGPRs and 7 waves per SIMD,
+// against ~150 VGPRs and 3 waves for 16-byte vectors. The 2-byte types take four
+// nodes per thread (8-byte loads, lane shuffles) in 256-thread blocks, 7% ahead
+// of single 2-byte elements. Grids too small to fill the chip: one node per
+// thread, 64-thread blocks.
 Launch3 default_launch(const lbvp3_params& p)
 {
     const int64_t rows = (int64_t)p.ny * p.nz, n = rows * p.nx;
-    const int32_t wide = p.storage == LBVP_F32 ? 256 : p.storage == LBVP_F64 ? 128 : 64;
-    const int32_t block = n / 64 >= 4096 ? wide : 64;
-    return make_launch(p.nx, rows, 1, block);
+    const bool two_byte = p.storage == LBVP_F16_DEV || p.storage == LBVP_BF16_DEV;
+    const int32_t vec = two_byte && n / (64 * 4) >= 8 * 1024 ? 4 : 1;
+    const int32_t wide = p.storage == LBVP_F64 ? 128 : 256;
+    const int32_t block = n / (64 * vec) >= 4096 ? wide : 64;
+    return make_launch(p.nx, rows, vec, block);
 }
 
 std::string validate(const lbvp3_params* p)

@@ -27,10 +27,12 @@
 // The step is bound by HBM traffic: 19 loads, 19 stores and a mask byte per node
 // against ~350 flops. Each thread owns V consecutive nodes of a row and moves
 // each population with one V-wide access; the directions with an x component
-// load V elements one element off alignment (a single dword-aligned vector load).
+// load V elements one element off alignment (a single dword-aligned vector
+// load), or, for 2-byte vectors, aligned with the end element from a lane shuffle.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "lbvp3_internal.h"
 #include "lbvp_device.h"
@@ -39,6 +41,7 @@ namespace lbvp3 {
 namespace {
 
 using lbvp::Arith;
+using lbvp::as_lv;
 using lbvp::block_sum;
 using lbvp::collide_pair;
 using lbvp::dec;
@@ -215,32 +218,66 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
         s0 = a.tile_slot_ptr[t];
         s1 = a.tile_slot_ptr[t + 1];
     }
-    R v[Q][V];
+    // Dword-or-wider elements (and single nodes) fetch the x-shifted directions
+    // as one vector access one element off alignment. 2-byte vectors load aligned
+    // and take the missing end element from the neighbouring lane (lanes that
+    // start or end a wavefront or a tile row load it themselves), keeping the
+    // loaded values packed in the storage type until each node's collision.
+    constexpr bool kShifted = sizeof(S) >= 4 || V == 1;
+    using LV = typename std::conditional<kShifted, R, S>::type;
+    const int lane = (int)(threadIdx.x & 63);
+    LV v[Q][V];
     int body[V];
     if (act) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             S raw[V];
             const S* p = src + src_row[q] + (int64_t)q * a.pitch;
-            if (CX[q] == 1) load_vec_shifted<S, V>(p + (i0 - 1), raw);
-            else if (CX[q] == -1) load_vec_shifted<S, V>(p + (i0 + 1), raw);
-            else load_vec<S, V>(p + i0, raw);
+            if constexpr (kShifted) {
+                if (CX[q] == 1) load_vec_shifted<S, V>(p + (i0 - 1), raw);
+                else if (CX[q] == -1) load_vec_shifted<S, V>(p + (i0 + 1), raw);
+                else load_vec<S, V>(p + i0, raw);
+            } else {
+                load_vec<S, V>(p + i0, raw);
+            }
 #pragma unroll
-            for (int e = 0; e < V; ++e) v[q][e] = dec(raw[e]);
+            for (int e = 0; e < V; ++e) v[q][e] = as_lv<LV>(raw[e]);
         }
         load_mask<V>(a.mask + r0 + i0, body);
-        if (i0 == 0) {   // the west side: column -1 lies outside
+        if constexpr (kShifted) {
+            if (i0 == 0) {   // the west side: column -1 lies outside
 #pragma unroll
-            for (int q = 0; q < Q; ++q)
-                if (CX[q] == 1) v[q][0] = pull_col<S, R>(src, q, src_row[q], -1, a);
+                for (int q = 0; q < Q; ++q)
+                    if (CX[q] == 1) v[q][0] = pull_col<S, R>(src, q, src_row[q], -1, a);
+            }
         }
     } else {
 #pragma unroll
         for (int q = 0; q < Q; ++q)
 #pragma unroll
-            for (int e = 0; e < V; ++e) v[q][e] = R(0);
+            for (int e = 0; e < V; ++e) v[q][e] = LV{};
 #pragma unroll
         for (int e = 0; e < V; ++e) body[e] = 0;
+    }
+
+    // the end elements of the x-shifted directions (lane-shuffle form only)
+    R left[Q], right[Q];
+    if constexpr (!kShifted) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            if (CX[q] == 1) left[q] = __shfl_up(dec(v[q][V - 1]), 1, 64);
+            if (CX[q] == -1) right[q] = __shfl_down(dec(v[q][0]), 1, 64);
+        }
+        if (act && (lane == 0 || lc == 0)) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (CX[q] == 1) left[q] = pull_col<S, R>(src, q, src_row[q], i0 - 1, a);
+        }
+        if (act && (lane == 63 || lc == tpr - 1)) {
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (CX[q] == -1) right[q] = pull_col<S, R>(src, q, src_row[q], i0 + V, a);
+        }
     }
 
     R fl[7][V];
@@ -250,7 +287,15 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     for (int e = 0; e < V; ++e) {
         R f[Q];
 #pragma unroll
-        for (int q = 0; q < Q; ++q) f[q] = v[q][e];
+        for (int q = 0; q < Q; ++q) {
+            if constexpr (kShifted) {
+                f[q] = v[q][e];
+            } else {
+                if (CX[q] == 1) f[q] = (e == 0) ? left[q] : dec(v[q][e > 0 ? e - 1 : 0]);
+                else if (CX[q] == -1) f[q] = (e == V - 1) ? right[q] : dec(v[q][e < V - 1 ? e + 1 : 0]);
+                else f[q] = dec(v[q][e]);
+            }
+        }
         const int i = i0 + e;
         if (i == a.nx - 1) {   // the east side: column nx lies outside
 #pragma unroll
@@ -505,6 +550,10 @@ hipError_t step_typed(bool record, bool fields, const void* src, void* dst, cons
     if constexpr (sizeof(S) == 4) {
         if (a.vec == 4) return step_v<S, 4>(record, fields, in, out, a, s);
     }
+    if constexpr (sizeof(S) == 2) {   // lane-shuffle forms: 8 and 16 bytes per thread
+        if (a.vec == 4) return step_v<S, 4>(record, fields, in, out, a, s);
+        if (a.vec == 8) return step_v<S, 8>(record, fields, in, out, a, s);
+    }
     return hipErrorInvalidValue;
 }
 
@@ -518,7 +567,7 @@ bool vec_supported(int32_t storage, int32_t vec)
     case LBVP_F64: return vec == 1 || vec == 2;
     case LBVP_F32: return vec == 1 || vec == 2 || vec == 4;
     case LBVP_F16_DEV:
-    case LBVP_BF16_DEV: return vec == 1;
+    case LBVP_BF16_DEV: return vec == 1 || vec == 4 || vec == 8;
     default: return false;
     }
 }

@@ -146,7 +146,8 @@ def test_reduced_storage_error(lbvp3, ref3, case, storage, bar):
 @pytest.mark.parametrize("storage,launches", [
     ("f32", [(1, 64), (2, 256), (4, 256), (4, 128), (4, 64), (1, 256)]),
     ("f64", [(1, 64), (2, 256), (2, 128)]),
-    ("f16", [(1, 64), (1, 256)]),
+    ("f16", [(1, 64), (1, 256), (4, 128), (4, 64), (8, 256)]),
+    ("bf16", [(1, 64), (4, 256), (8, 64)]),
 ])
 def test_launch_shapes_bitwise_equal(lbvp3, storage, launches):
     prob = inputs3.random_state_problem3(150, 21, 9, seed=31, n_spheres=4)
