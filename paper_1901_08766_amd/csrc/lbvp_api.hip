@@ -154,7 +154,9 @@ Layout make_layout(const lbvp_params* p)
 {
     Layout L;
     const size_t es = storage_bytes(p->storage), rs = arith_bytes(p->storage);
-    L.pitch = (int64_t)align_up((size_t)p->nx, 64);
+    // a cut side keeps its halo column in the lattice's padding: room for two
+    const bool cut = p->bc_west == LBVP_BC_NEIGHBOR || p->bc_east == LBVP_BC_NEIGHBOR;
+    L.pitch = (int64_t)align_up((size_t)p->nx + (cut ? 2 : 0), 64);
     L.plane = L.pitch;          // population rows of a lattice row back to back
     L.lstride = 9 * L.pitch;
     L.plane_f = (int64_t)p->ny * L.pitch;
@@ -1054,6 +1056,18 @@ lbvp_status lbvp_create(const lbvp_params* p, void* hip_stream, void* dev_mem, s
     c->fin.rec_count = c->at<int64_t>(c->L.rec_count);
     fill_step_args(c, c->a64);
     fill_step_args(c, c->a32);
+    if (p->bc_west == LBVP_BC_NEIGHBOR || p->bc_east == LBVP_BC_NEIGHBOR) {
+        // the halo columns (lattice padding) hold zero deviations, the state at
+        // rest, until the first halo exchange
+        const size_t lat_bytes = (size_t)p->ny * (size_t)c->L.lstride * c->esize();
+        hipError_t e = hipMemsetAsync(c->at<char>(c->L.lat[0]), 0, lat_bytes, c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->at<char>(c->L.lat[1]), 0, lat_bytes, c->stream);
+        if (e != hipSuccess) {
+            g_create_error = std::string("hipMemsetAsync: ") + hipGetErrorString(e);
+            lbvp_destroy(c);
+            return LBVP_E_DEVICE;
+        }
+    }
     // empty mask, fluid at rest
     std::vector<uint8_t> zero((size_t)p->nx * p->ny, 0);
     lbvp_status s = lbvp_set_mask(c, zero.data(), 0, nullptr);
@@ -1141,11 +1155,6 @@ lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* 
         LBVP_HIP(c, launch_init(p.storage, c->at<char>(L.lat[0]), c->at<char>(L.fields), a, s));
     }
     LBVP_HIP(c, refresh_aa_ghosts(c));
-    if (p.bc_west == LBVP_BC_NEIGHBOR || p.bc_east == LBVP_BC_NEIGHBOR) {
-        // halo columns at rest (zero deviation) until the first lbvp_halo_exchange
-        LBVP_HIP(c, hipMemsetAsync(c->at<char>(L.ghost_w), 0, 3 * (size_t)p.ny * c->esize(), s));
-        LBVP_HIP(c, hipMemsetAsync(c->at<char>(L.ghost_e), 0, 3 * (size_t)p.ny * c->esize(), s));
-    }
     LBVP_HIP(c, launch_set_i64(c->fin.rec_count, 0, s));
     LBVP_HIP(c, hipStreamSynchronize(s));
     c->cur = 0;
@@ -1490,14 +1499,13 @@ lbvp_status lbvp_halo_exchange(lbvp_ctx* const* west, lbvp_ctx* const* east, int
         if (w->stream != c0->stream || e->stream != c0->stream)
             return c0->fail(LBVP_E_ARG, "lbvp_halo_exchange: all slabs must share one stream");
         HaloLink& L = h.link[i];
-        L.w_lat = w->at<char>(w->L.lat[w->cur]);
-        L.e_lat = e->at<char>(e->L.lat[e->cur]);
-        L.e_halo_w = e->at<char>(e->L.ghost_w);
-        L.w_halo_e = w->at<char>(w->L.ghost_e);
+        L.w_lat = L.w_lat_w = w->at<char>(w->L.lat[w->cur]);
+        L.e_lat = L.e_lat_w = e->at<char>(e->L.lat[e->cur]);
         L.w_lstride = w->L.lstride;
         L.w_plane = w->L.plane;
         L.e_lstride = e->L.lstride;
         L.e_plane = e->L.plane;
+        L.e_pitch = e->L.pitch;
         L.w_nx = w->p.nx;
     }
     LBVP_HIP(c0, launch_halo(c0->p.storage, h, c0->stream));

@@ -103,14 +103,15 @@ struct BatchLaunch {
 };
 
 // One cut between two slabs (lbvp_halo_exchange): west's column nx - 1
-// populations with e_x = +1 into east's west halo, east's column 0 populations
-// with e_x = -1 into west's east halo; halos are [3][ny] of the storage type.
+// populations with e_x = +1 into east's west halo (its lattice's column
+// pitch - 1), east's column 0 populations with e_x = -1 into west's east halo
+// (column nx); both in the slabs' current lattices.
 struct HaloLink {
     const void* w_lat;
     const void* e_lat;
-    void* e_halo_w;
-    void* w_halo_e;
-    int64_t w_lstride, w_plane, e_lstride, e_plane;
+    void* e_lat_w;      // = e_lat, written
+    void* w_lat_w;      // = w_lat, written
+    int64_t w_lstride, w_plane, e_lstride, e_plane, e_pitch;
     int32_t w_nx;
 };
 constexpr int MAX_HALO_LINKS = 32;   // HaloArgs stays within the 4 KB of kernel arguments

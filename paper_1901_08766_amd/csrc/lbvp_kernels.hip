@@ -187,8 +187,10 @@ enum Mode { PULL = 0, AA_PUSH = 1, AA_LOCAL = 2 };
 // Population q pulled from column c (-1 and nx are outside the domain) of plane
 // `plane_q` in the row starting at row_off (row index `row`): the domain sides
 // are resolved here. A NEIGHBOR side (a cut of a slab decomposition) reads the
-// halo column that lbvp_halo_exchange filled, in the ghost-column buffers the
-// AA layout uses for its outflow sides (the two never meet). Ghost populations are values of the storage type, like
+// halo column that lbvp_halo_exchange wrote into the current lattice's padding
+// (column nx for the east side, pitch - 1 for the west; a context with a cut has
+// pitch >= nx + 2), so it is one more column choice, like a periodic side, with
+// the same single load. Ghost populations are values of the storage type, like
 // every other population (the AA push step stores the inflow ones in the
 // lattice), so the inflow equilibrium is rounded to it.
 template <int MODE, typename S, typename R>
@@ -197,14 +199,16 @@ __device__ __forceinline__ R pull_column(const S* src, int q, int plane_q, int64
 {
     if (c < 0) {
         if (a.west == SIDE_INFLOW_EQ) return dec(enc<S>(a.feq_in[q]));
-        if (a.west == SIDE_NEIGHBOR || (MODE == AA_PUSH && a.west == SIDE_OUTFLOW))
+        if (MODE == AA_PUSH && a.west == SIDE_OUTFLOW)
             return dec(static_cast<const S*>(a.ghost_w)[(q == 1 ? 0 : q == 5 ? 1 : 2) * (int64_t)a.ny + row]);
-        c = (a.west == SIDE_PERIODIC) ? a.nx - 1 : 0;
+        // a cut's west halo lives in the row's last padding column
+        c = (a.west == SIDE_PERIODIC) ? a.nx - 1 : (a.west == SIDE_NEIGHBOR ? (int)a.pitch - 1 : 0);
     } else if (c >= a.nx) {
         if (a.east == SIDE_INFLOW_EQ) return dec(enc<S>(a.feq_in[q]));
-        if (a.east == SIDE_NEIGHBOR || (MODE == AA_PUSH && a.east == SIDE_OUTFLOW))
+        if (MODE == AA_PUSH && a.east == SIDE_OUTFLOW)
             return dec(static_cast<const S*>(a.ghost_e)[(q == 3 ? 0 : q == 6 ? 1 : 2) * (int64_t)a.ny + row]);
-        c = (a.east == SIDE_PERIODIC) ? 0 : a.nx - 1;
+        // a cut's east halo lives in column nx, the first padding column
+        c = (a.east == SIDE_PERIODIC) ? 0 : (a.east == SIDE_NEIGHBOR ? a.nx : a.nx - 1);
     }
     return dec(src[(int64_t)plane_q * a.plane + row_off + c]);
 }
@@ -339,16 +343,28 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
             left[m] = __shfl_up(dec(v[EXP[m]][V - 1]), 1, 64);
             right[m] = __shfl_down(dec(v[EXM[m]][0]), 1, 64);
         }
-        // lanes that start a wavefront or a tile row load the end element themselves
+        // lanes that start a wavefront or a tile row load the end element
+        // themselves: a plain load inside the domain, the side resolution only
+        // where the column lies outside it
         if (act && (lane == 0 || lc == 0)) {
+            if (i0 > 0) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
-                left[m] = pull_column<MODE, S, R>(src, EXP[m], EXP[m], row_of[EXP[m]], row_idx[EXP[m]], i0 - 1, a);
+                for (int m = 0; m < 3; ++m) left[m] = dec(src[EXP[m] * P + row_of[EXP[m]] + (i0 - 1)]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    left[m] = pull_column<MODE, S, R>(src, EXP[m], EXP[m], row_of[EXP[m]], row_idx[EXP[m]], -1, a);
+            }
         }
         if (act && (lane == 63 || lc == tpr - 1)) {
+            if (i0 + V < a.nx) {
 #pragma unroll
-            for (int m = 0; m < 3; ++m)
-                right[m] = pull_column<MODE, S, R>(src, EXM[m], EXM[m], row_of[EXM[m]], row_idx[EXM[m]], i0 + V, a);
+                for (int m = 0; m < 3; ++m) right[m] = dec(src[EXM[m] * P + row_of[EXM[m]] + (i0 + V)]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    right[m] = pull_column<MODE, S, R>(src, EXM[m], EXM[m], row_of[EXM[m]], row_idx[EXM[m]], i0 + V, a);
+            }
         }
     } else {
         if (MODE != AA_LOCAL && act && i0 == 0) {  // the west side: column -1 is outside
@@ -744,10 +760,12 @@ __global__ void __launch_bounds__(256) k_halo(HaloArgs h)
     const HaloLink& L = h.link[l];
     const int q_in = m == 0 ? 1 : (m == 1 ? 5 : 8);    // e_x = +1 (1, 5, 8): leave west through its east side
     const int q_out = m == 0 ? 3 : (m == 1 ? 6 : 7);   // e_x = -1 (3, 6, 7): leave east through its west side
-    static_cast<S*>(L.e_halo_w)[(int64_t)m * h.ny + j] =
-        static_cast<const S*>(L.w_lat)[j * L.w_lstride + q_in * L.w_plane + (L.w_nx - 1)];
-    static_cast<S*>(L.w_halo_e)[(int64_t)m * h.ny + j] =
-        static_cast<const S*>(L.e_lat)[j * L.e_lstride + q_out * L.e_plane];
+    const S* wl = static_cast<const S*>(L.w_lat);
+    const S* el = static_cast<const S*>(L.e_lat);
+    // east slab's west halo: its last padding column; west slab's east halo: column nx
+    static_cast<S*>(L.e_lat_w)[j * L.e_lstride + q_in * L.e_plane + (L.e_pitch - 1)] =
+        wl[j * L.w_lstride + q_in * L.w_plane + (L.w_nx - 1)];
+    static_cast<S*>(L.w_lat_w)[j * L.w_lstride + q_out * L.w_plane + L.w_nx] = el[j * L.e_lstride + q_out * L.e_plane];
 }
 
 // The same for the cuts of a batch, before one of its steps: each member's
@@ -766,12 +784,12 @@ __global__ void __launch_bounds__(256) k_halo_batch(BatchHalo h)
     const StepArgs<R>* args = static_cast<const StepArgs<R>*>(h.args);
     const StepArgs<R>& aw = args[h.w[l]];
     const StepArgs<R>& ae = args[h.e[l]];
-    const S* wl = static_cast<const S*>((aw.cur ^ h.flip) ? aw.lat1 : aw.lat0);
-    const S* el = static_cast<const S*>((ae.cur ^ h.flip) ? ae.lat1 : ae.lat0);
+    S* wl = static_cast<S*>((aw.cur ^ h.flip) ? aw.lat1 : aw.lat0);
+    S* el = static_cast<S*>((ae.cur ^ h.flip) ? ae.lat1 : ae.lat0);
     const int q_in = m == 0 ? 1 : (m == 1 ? 5 : 8);
     const int q_out = m == 0 ? 3 : (m == 1 ? 6 : 7);
-    static_cast<S*>(ae.ghost_w)[(int64_t)m * h.ny + j] = wl[j * aw.lstride + q_in * aw.plane + (aw.nx - 1)];
-    static_cast<S*>(aw.ghost_e)[(int64_t)m * h.ny + j] = el[j * ae.lstride + q_out * ae.plane];
+    el[j * ae.lstride + q_in * ae.plane + (ae.pitch - 1)] = wl[j * aw.lstride + q_in * aw.plane + (aw.nx - 1)];
+    wl[j * aw.lstride + q_out * aw.plane + aw.nx] = el[j * ae.lstride + q_out * ae.plane];
 }
 
 template <typename R>
