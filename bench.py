@@ -405,9 +405,10 @@ def steady_wake(res=(20.0, 40.0), steps: int = 60000, storages=("f32", "f64")):
     return out
 
 
-def copy_bandwidth(nbytes: int = 1207959552, reps: int = 20) -> float:
-    """GB/s (bytes read + written) of the library's 16-byte non-temporal device
-    copy over nbytes, the access pattern of the step kernels."""
+def copy_bandwidth(nbytes: int = 2415919104, reps: int = 20) -> float:
+    """GB/s (bytes read + written) of the library's device copy (one 16-byte
+    non-temporal load and store per thread, the fastest copy form measured) over
+    nbytes each way, about what one 8192x4096 FP32 step moves."""
     import torch
     from paper_1901_08766_amd import lbvp
 
@@ -644,7 +645,7 @@ def main():
                      "traffic": traffic},
         "variants": extra,
         "copy": {"GBps": round(copy_gbps, 1), "step_frac_of_copy": round(achieved / copy_gbps, 4),
-                 "kernel": "16-byte non-temporal device copy (lbvp_device_copy), 1.2 GB"},
+                 "kernel": "device copy, one 16-byte non-temporal load and store per thread (lbvp_device_copy), 2.4 GB each way"},
     }
     if a.ensemble_steps > 0:
         out["ensemble"] = {}
