@@ -86,9 +86,10 @@ def time_gpu(storage: str, steps: int, warmup: int, prob):
     ms = start.elapsed_time(stop)
     forces, mass, _ = solver.forces()
     ok = bool((mass == mass).all()) and len(mass) == steps
+    launch = {"vec": solver.launch[0], "block": solver.launch[1], "tile_band": solver.tile_band}
     solver.close()
     torch.cuda.empty_cache()
-    return ms / steps, ok
+    return ms / steps, ok, launch
 
 
 BYTES_PER_NODE_3D = {"f64": 305, "f32": 153, "f16": 77, "bf16": 77}
@@ -112,7 +113,7 @@ def time_d3q19(storages, steps: int, warmup: int):
         ms = _timed(s.stream, lambda: s.step(steps)) / steps
         _, mass, _ = s.forces()
         gbps = BYTES_PER_NODE_3D[st] * n / (ms * 1e-3) / 1e9
-        out["per_storage"][st] = {"launch": list(s.launch), "ms_per_step": round(ms, 4),
+        out["per_storage"][st] = {"launch": list(s.launch), "tile_band": s.tile_band, "ms_per_step": round(ms, 4),
                                   "MLUPS": round(n / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbps, 1),
                                   "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
                                   "traffic": measured_traffic(st, n, "d3q19"),
@@ -585,7 +586,7 @@ def main():
         print(json.dumps(time_slabs(a.slabs, storage=a.storage)), flush=True)
         return
     if a.d3q19_only:
-        print(json.dumps(time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, 5)), flush=True)
+        print(json.dumps(time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, a.warmup)), flush=True)
         return
     if a.precision_study:
         print(json.dumps(precision_study()), flush=True)
@@ -608,7 +609,7 @@ def main():
     nodes = prob.nx * prob.ny
     print(f"# workload {prob.name}: {nodes} nodes, {prob.n_bodies} bodies, storage {a.storage}", file=sys.stderr,
           flush=True)
-    ms, ok = time_gpu(a.storage, a.steps, a.warmup, prob)
+    ms, ok, launch = time_gpu(a.storage, a.steps, a.warmup, prob)
     if not ok:
         raise SystemExit("non-finite mass during the timed run")
     mlups = nodes / (ms * 1e-3) / 1e6
@@ -616,10 +617,11 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     extra = {}
     for v in [s for s in a.variants.split(",") if s and s != a.storage]:
-        vms, vok = time_gpu(v, a.steps, a.warmup, prob)
+        vms, vok, vlaunch = time_gpu(v, a.steps, a.warmup, prob)
         vb = BYTES_PER_NODE[v] * nodes / (vms * 1e-3) / 1e9
         extra[v] = {"MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
-                    "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok}
+                    "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok,
+                    "launch": vlaunch}
         print(f"# {v}: {extra[v]}", file=sys.stderr, flush=True)
     traffic = measured_traffic(a.storage, nodes)
     copy_gbps = copy_bandwidth()
@@ -640,6 +642,7 @@ def main():
                                f"tandem pair, NACA-0012), Re=200, U=0.04",
                    "nx": prob.nx, "ny": prob.ny, "storage": a.storage, "layout": "two-lattice pull",
                    "force_every": 1},
+        "launch": launch,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic},
@@ -653,7 +656,7 @@ def main():
             out["ensemble"][st] = time_ensemble(st, a.ensemble_steps, max(20, a.ensemble_steps // 5))
             print(f"# ensemble {st}: {out['ensemble'][st]}", file=sys.stderr, flush=True)
     if a.d3q19_steps > 0:
-        out["d3q19"] = time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, 5)
+        out["d3q19"] = time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, a.warmup)
     if a.serve_requests > 0:
         out["serving"] = run_serving(a.serve_storage, a.serve_rate, a.serve_requests)
         print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)

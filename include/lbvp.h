@@ -230,6 +230,21 @@ lbvp_status lbvp_load_state(lbvp_ctx* ctx, const void* buf, size_t size);
 lbvp_status lbvp_set_launch(lbvp_ctx* ctx, int32_t vec, int32_t block);
 lbvp_status lbvp_get_launch(const lbvp_ctx* ctx, int32_t* vec, int32_t* block);
 
+/* Order in which the step kernel's workgroups take the tiles of the domain (a
+ * tile is the vec * block nodes one workgroup updates, in row order). The GPU
+ * deals workgroups to its 8 XCDs round robin, and each XCD has its own L2.
+ *   band = 0: each XCD sweeps one contiguous eighth of the tiles;
+ *   band = 2^k (1 .. 65536): the tiles form groups of 8 bands of `band`
+ *     consecutive tiles and each XCD takes one band of every group, so the
+ *     chip moves through a window of 8 * band tiles at a time (band = 1 is
+ *     plain dispatch order).
+ * Populations, fields and force and mass records do not depend on it. A default
+ * is chosen with the launch shape at lbvp_create; lbvp_set_launch keeps the
+ * band. Batches have their own (lbvp_batch_set_tile_band); the pool uses 0.
+ * Errors: E_ARG (other values). */
+lbvp_status lbvp_set_tile_band(lbvp_ctx* ctx, int32_t band);
+lbvp_status lbvp_get_tile_band(const lbvp_ctx* ctx, int32_t* band);
+
 /* ---- Batches: many contexts advanced by one launch per step -------------------
  * A batch holds contexts of one storage type and layout on one stream. Each step
  * of lbvp_batch_step is a single launch over the tiles of every member (block ->
@@ -260,6 +275,12 @@ const char* lbvp_batch_last_error(const lbvp_batch* batch);
  * members removes them too. E_ARG (n > 32, an index out of range, a linked side
  * that is not LBVP_BC_NEIGHBOR, unequal ny). */
 lbvp_status lbvp_batch_set_halo(lbvp_batch* batch, const int32_t* west, const int32_t* east, int32_t n);
+/* Block -> tile order of the batch's step launches over the members' tiles, taken
+ * in member order, as lbvp_set_tile_band states it (0 at lbvp_batch_create; the
+ * members' own bands do not apply to batch steps). Results and records do not
+ * depend on it. E_ARG for values other than 0 and powers of two up to 65536. */
+lbvp_status lbvp_batch_set_tile_band(lbvp_batch* batch, int32_t band);
+lbvp_status lbvp_batch_get_tile_band(const lbvp_batch* batch, int32_t* band);
 
 /* ---- Tuner ----------------------------------------------------------------------
  * Times the step kernel for every launch shape (vec x block) and, with

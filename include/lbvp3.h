@@ -144,6 +144,13 @@ lbvp_status lbvp3_write_populations(lbvp3_ctx* ctx, int32_t z0, int32_t n_planes
 lbvp_status lbvp3_set_launch(lbvp3_ctx* ctx, int32_t vec, int32_t block);
 lbvp_status lbvp3_get_launch(const lbvp3_ctx* ctx, int32_t* vec, int32_t* block);
 
+/* Order in which the step kernel's workgroups take the tiles, as lbvp_set_tile_band
+ * states it for the 2-D step (a tile is vec * block nodes of consecutive lattice
+ * rows r = k * ny + j). Results and records do not depend on it; lbvp3_set_launch
+ * keeps the band. E_ARG for values other than 0 and powers of two up to 65536. */
+lbvp_status lbvp3_set_tile_band(lbvp3_ctx* ctx, int32_t band);
+lbvp_status lbvp3_get_tile_band(const lbvp3_ctx* ctx, int32_t* band);
+
 /* Steps taken since the last init; -1 for a NULL context. */
 int64_t lbvp3_step_count(const lbvp3_ctx* ctx);
 

@@ -13,6 +13,7 @@ constexpr int Q = 19;
 constexpr int N_XCD = 8;
 constexpr int FIN_THREADS = 256;
 constexpr int N_LEAD = 32;   // blocks that sum one record, a multiple of the 8 XCDs
+constexpr int MAX_TILE_BAND = 1 << 16;
 
 // Velocity components of the 19 directions in the interface order: rest, the
 // faces +x -x +y -y +z -z, then the edges as (opposite) pairs in the xy, xz and
@@ -52,6 +53,7 @@ struct Step3Args {
     int32_t nx, ny, nz;
     int32_t vec, block, tile_w, tile_rows;
     int32_t tiles_x, n_tiles, tiles_per_xcd;
+    int32_t band_log2;              // block -> tile order (xcd_tile): -1 eighths, else bands of 2^band_log2 tiles
     int32_t west, east;             // lbvp_bc of the x sides
     int64_t pitch;                  // elements per population row, mask row and field row
     int64_t lstride;                // elements between lattice rows r and r + 1 (= 19 pitch)

@@ -435,7 +435,7 @@ k_step3(const S* __restrict__ src, S* __restrict__ dst, Step3Args<typename Arith
         finalize3(a.fin, a.fin_buf, (int)blockIdx.x, lds, &last);
         return;
     }
-    const int t = xcd_tile(a.tiles_per_xcd, lead);
+    const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;   // whole block
     step3_body<S, V, RECORD, FIELDS>(src, dst, a, t, lds);
 }

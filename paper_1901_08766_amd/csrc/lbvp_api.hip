@@ -58,7 +58,21 @@ struct Layout {
 struct Launch {
     int32_t vec = 1, block = MAX_BLOCK, tile_w = MAX_BLOCK, tile_rows = 1;
     int32_t tiles_x = 0, n_tiles = 0, tiles_per_xcd = 0;
+    int32_t band = 0;   // block -> tile order: 0 = one eighth per XCD, else bands of `band` tiles
 };
+
+// band_log2 of the kernel arguments: -1 for eighths, else log2(band).
+int32_t band_log2(int32_t band)
+{
+    int32_t k = -1;
+    while (band > 0) {
+        band >>= 1;
+        ++k;
+    }
+    return k;
+}
+
+bool band_allowed(int32_t band) { return band >= 0 && band <= MAX_TILE_BAND && (band & (band - 1)) == 0; }
 
 int32_t pow2_ceil(int32_t v)
 {
@@ -101,20 +115,30 @@ bool vec_allowed(int32_t storage, uint32_t flags, int32_t vec)
     return false;
 }
 
-// Default launch: the vector form (16 bytes; 8 bytes and 128-thread blocks for
-// 2-byte types, which measure fastest there) when it still gives at least 8
-// wavefronts per SIMD (1024 SIMDs: 256 CUs x 4), else one node per thread;
-// small grids use 64-thread blocks to spread over more CUs.
+// Default launch: the 16-byte vector form (for 2-byte types 8 bytes if 16 are
+// too many) when it still gives at least 8 wavefronts per SIMD (1024 SIMDs:
+// 256 CUs x 4), else one node per thread; small grids use 64-thread blocks to
+// spread over more CUs. Vector launches of the pull layout take tiles in bands
+// (lbvp_set_tile_band). The shapes and bands are the fastest measured on MI355X
+// for an 8192 x 4096 domain, recording every step: FP32 128 threads, bands of 8
+// tiles (0.399 ms against 0.407 for 256 threads and one eighth per XCD); FP64
+// 128 threads, bands of 2 (0.792 against 0.812); FP16 and BF16 256 threads of 8
+// nodes, bands of 2 (0.216 ms against 0.228 for the best shape with eighths),
+// or of 4 nodes, bands of 16 (0.218).
 Launch default_launch(int32_t nx, int32_t ny, int32_t storage, uint32_t flags)
 {
     const int64_t n = (int64_t)nx * ny;
     const bool two_byte = storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV;
-    const int wide = two_byte ? 4 : vector_width(storage);
-    const int vw = vec_allowed(storage, flags, wide) ? wide : 1;
-    const int vec = (n / (64 * vw) >= 8 * 1024) ? vw : 1;
+    int32_t vec = 1;
+    for (int32_t v : {vector_width(storage), two_byte ? 4 : 1})
+        if (vec == 1 && v > 1 && vec_allowed(storage, flags, v) && n / (64 * v) >= 8 * 1024) vec = v;
     const int64_t waves = n / (64 * vec);
-    const int block = waves >= 4096 ? (two_byte ? 128 : MAX_BLOCK) : MIN_BLOCK;
-    return make_launch(nx, ny, vec, block);
+    int32_t block = two_byte ? 128 : MAX_BLOCK;
+    if (waves < 4096) block = MIN_BLOCK;
+    else if (vec > 1) block = two_byte ? MAX_BLOCK : 128;
+    Launch l = make_launch(nx, ny, vec, block);
+    if (vec > 1 && !(flags & LBVP_LAYOUT_AA)) l.band = storage == LBVP_F32 ? 8 : (two_byte && vec == 4) ? 16 : 2;
+    return l;
 }
 
 // Returns an empty string if the parameters are valid.
@@ -395,6 +419,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.tiles_x = l.tiles_x;
     a.n_tiles = l.n_tiles;
     a.tiles_per_xcd = l.tiles_per_xcd;
+    a.band_log2 = band_log2(l.band);
     a.west = p.bc_west;
     a.east = p.bc_east;
     a.pitch = L.pitch;
@@ -675,6 +700,7 @@ struct lbvp_batch {
     size_t dev_cap = 0;
     size_t arg_size = 0, off_fins = 0, off_tile_domain = 0, off_tile_start = 0, bytes = 0;
     int32_t total_tiles = 0, tiles_per_xcd = 0;
+    int32_t band = 0;                    // block -> tile order over the concatenated tiles (lbvp_batch_set_tile_band)
     std::vector<char> image;             // host image of the device block
     std::vector<char> uploaded;          // the image as last enqueued for upload
     PinnedRing ring;
@@ -821,6 +847,7 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
     BatchLaunch L{};
     L.total_tiles = b->total_tiles;
     L.tiles_per_xcd = b->tiles_per_xcd;
+    L.band_log2 = band_log2(b->band);
     L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_domain);
     L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_start);
     L.args = b->dev;
@@ -1470,7 +1497,9 @@ lbvp_status lbvp_set_launch(lbvp_ctx* c, int32_t vec, int32_t block)
     if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");
     LBVP_HIP(c, hipStreamSynchronize(c->stream));
     c->graphs.clear(c->stream);
-    return apply_launch(c, make_launch(c->p.nx, c->p.ny, vec, block));
+    Launch l = make_launch(c->p.nx, c->p.ny, vec, block);
+    l.band = c->launch.band;
+    return apply_launch(c, l);
 }
 
 lbvp_status lbvp_get_launch(const lbvp_ctx* c, int32_t* vec, int32_t* block)
@@ -1478,6 +1507,25 @@ lbvp_status lbvp_get_launch(const lbvp_ctx* c, int32_t* vec, int32_t* block)
     if (!c || !vec || !block) return LBVP_E_ARG;
     *vec = c->launch.vec;
     *block = c->launch.block;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_set_tile_band(lbvp_ctx* c, int32_t band)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    if (!band_allowed(band)) return c->fail(LBVP_E_ARG, "band must be 0 or a power of two up to 65536");
+    if (c->launch.band == band) return LBVP_OK;
+    c->launch.band = band;
+    c->gen += 1;   // captured graphs hold the old kernel arguments
+    fill_step_args(c, c->a64);
+    fill_step_args(c, c->a32);
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_get_tile_band(const lbvp_ctx* c, int32_t* band)
+{
+    if (!c || !band) return LBVP_E_ARG;
+    *band = c->launch.band;
     return LBVP_OK;
 }
 
@@ -1666,6 +1714,23 @@ lbvp_status lbvp_batch_set_halo(lbvp_batch* b, const int32_t* west, const int32_
     b->halo_e.assign(east, east + n);
     b->graphs.clear(b->stream);
     b->gen += 1;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_batch_set_tile_band(lbvp_batch* b, int32_t band)
+{
+    if (!b) return LBVP_E_ARG;
+    if (!band_allowed(band)) return b->fail(LBVP_E_ARG, "band must be 0 or a power of two up to 65536");
+    if (b->band == band) return LBVP_OK;
+    b->band = band;
+    b->gen += 1;   // captured graphs hold the old launch arguments
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_batch_get_tile_band(const lbvp_batch* b, int32_t* band)
+{
+    if (!b || !band) return LBVP_E_ARG;
+    *band = b->band;
     return LBVP_OK;
 }
 

@@ -316,13 +316,25 @@ __device__ __forceinline__ double tree_sum(double* s)
     return r;
 }
 
-// Workgroups are dealt to the 8 XCDs round-robin by block id: block b (counted
-// from first_block) takes tile (b % 8) * per_xcd + b / 8, so each XCD sweeps a
-// contiguous run of tiles.
-__device__ __forceinline__ int xcd_tile(int per_xcd, int first_block)
+// Block -> tile order. Workgroups are dealt to the 8 XCDs round-robin by block
+// id, and each XCD has its own L2. Counting blocks from first_block:
+//  - band_log2 < 0: block b takes tile (b % 8) * per_xcd + b / 8, so each XCD
+//    sweeps one contiguous eighth of the tiles;
+//  - band_log2 = k >= 0: the tiles form groups of 8 bands of 2^k consecutive
+//    tiles, and XCD x takes band x of every group: each XCD still sweeps runs
+//    of neighbouring tiles, while the chip as a whole moves through a window of
+//    8 * 2^k tiles (k = 0 is plain dispatch order). Blocks past the last whole
+//    group keep dispatch order.
+// Either way the map is a permutation of [0, 8 per_xcd); a block whose tile is
+// past the domain's last one has nothing to do.
+__device__ __forceinline__ int xcd_tile(int per_xcd, int band_log2, int first_block)
 {
     const int blk = (int)blockIdx.x - first_block;   // first_block is a multiple of 8
-    return (blk % N_XCD_DEV) * per_xcd + blk / N_XCD_DEV;
+    if (band_log2 < 0) return (blk % N_XCD_DEV) * per_xcd + blk / N_XCD_DEV;
+    const int span = N_XCD_DEV << band_log2;
+    if (blk >= (per_xcd >> band_log2) * span) return blk;
+    const int r = blk & (span - 1);
+    return (blk - r) + ((r % N_XCD_DEV) << band_log2) + r / N_XCD_DEV;
 }
 
 }  // namespace

@@ -12,12 +12,14 @@ namespace lbvp {
 
 // One workgroup of `block` threads updates one tile of block * vec consecutive
 // nodes of a row, vec nodes per thread. Workgroups are dealt to the 8 XCDs
-// round-robin by block id; the launch remaps block b to tile
-// (b % 8) * tiles_per_xcd + b / 8 so that each XCD sweeps a contiguous band of
-// rows and neighbouring tiles share one L2.
+// round-robin by block id; the launch maps blocks to tiles (xcd_tile) so that
+// each XCD sweeps runs of neighbouring tiles, which then share its L2: one
+// contiguous eighth of the domain per XCD (band_log2 = -1) or bands of
+// 2^band_log2 tiles.
 constexpr int N_XCD = 8;
 constexpr int MAX_BLOCK = 256;
 constexpr int MIN_BLOCK = 64;
+constexpr int MAX_TILE_BAND = 1 << 16;
 constexpr int FIN_THREADS = 256;
 constexpr int MAX_MOVING = 8;       // bodies of a domain with moving masks
 constexpr int POSE_STRIDE = 8;      // doubles per body pose row
@@ -52,6 +54,7 @@ struct StepArgs {
     int32_t vec, block;             // nodes per thread, threads per block
     int32_t tile_w, tile_rows;      // a tile: tile_rows rows of tile_w nodes (tile_w * tile_rows = vec * block)
     int32_t tiles_x, n_tiles, tiles_per_xcd;
+    int32_t band_log2;  // block -> tile order (xcd_tile): -1 eighths, else bands of 2^band_log2 tiles
     int32_t west, east;
     int32_t part_buf;   // partial buffer a recording step writes
     int32_t fin_buf;    // partial buffer whose record a leading block of the launch sums, or -1
@@ -92,6 +95,7 @@ struct StepArgs {
 // A launch over many domains (k_step_batch).
 struct BatchLaunch {
     int32_t total_tiles, tiles_per_xcd;
+    int32_t band_log2;              // block -> tile order over all tiles (xcd_tile)
     int32_t flip;                   // lattice parity of this step relative to StepArgs::cur
     int32_t part_buf, fin_buf;      // as in StepArgs, for every domain of the batch
     int32_t n_domains;

@@ -584,7 +584,7 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
         if (blockIdx.x == 0) finalize_record(a.fin, a.fin_buf, lds);
         return;
     }
-    const int t = xcd_tile(a.tiles_per_xcd, lead);
+    const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;  // whole block
     step_body<S, V, PULL, RECORD, FIELDS, MOVING>(src, dst, a, t, a.part_buf, lds);
 }
@@ -599,7 +599,7 @@ __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith
         if (blockIdx.x == 0) finalize_record(a.fin, a.fin_buf, lds);
         return;
     }
-    const int t = xcd_tile(a.tiles_per_xcd, lead);
+    const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;  // whole block
     step_body<S, V, MODE, RECORD, FIELDS, MOVING>(lat, lat, a, t, a.part_buf, lds);
 }
@@ -620,7 +620,7 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
         if ((int)blockIdx.x < b.n_domains) finalize_record(args[blockIdx.x].fin, b.fin_buf, lds);
         return;
     }
-    const int g = xcd_tile(b.tiles_per_xcd, b.n_fin);
+    const int g = xcd_tile(b.tiles_per_xcd, b.band_log2, b.n_fin);
     if (g >= b.total_tiles) return;  // whole block
     const int d = b.tile_domain[g];
     const StepArgs<R>& a = args[d];

@@ -35,13 +35,15 @@ TUNE_FRESH = 0x2
 
 SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_equilibrium",
            "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations",
-           "lbvp_write_populations", "lbvp_set_launch", "lbvp_get_launch", "lbvp_step_count",
+           "lbvp_write_populations", "lbvp_set_launch", "lbvp_get_launch", "lbvp_set_tile_band",
+           "lbvp_get_tile_band", "lbvp_step_count",
            "lbvp_synchronize", "lbvp_destroy", "lbvp_last_error", "lbvp_batch_create", "lbvp_batch_step",
            "lbvp_batch_destroy", "lbvp_batch_last_error", "lbvp_tune", "lbvp_tune_last_error",
            "lbvp_pool_create", "lbvp_pool_admit", "lbvp_pool_run_epoch", "lbvp_pool_poll",
            "lbvp_pool_forces", "lbvp_pool_read_fields", "lbvp_pool_release", "lbvp_pool_get_stats",
            "lbvp_pool_destroy", "lbvp_pool_last_error", "lbvp_save_state", "lbvp_load_state",
-           "lbvp_device_copy", "lbvp_halo_exchange", "lbvp_batch_set_halo"]
+           "lbvp_device_copy", "lbvp_halo_exchange", "lbvp_batch_set_halo", "lbvp_batch_set_tile_band",
+           "lbvp_batch_get_tile_band"]
 NO_STATUS = ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error",
              "lbvp_tune_last_error", "lbvp_pool_last_error")
 
@@ -104,6 +106,8 @@ def _load():
     L.lbvp_write_populations.argtypes = [vp, vp]
     L.lbvp_set_launch.argtypes = [vp, i32, i32]
     L.lbvp_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.lbvp_set_tile_band.argtypes = [vp, i32]
+    L.lbvp_get_tile_band.argtypes = [vp, C.POINTER(i32)]
     L.lbvp_step_count.restype = i64
     L.lbvp_step_count.argtypes = [vp]
     L.lbvp_synchronize.argtypes = [vp]
@@ -118,6 +122,8 @@ def _load():
     L.lbvp_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
     L.lbvp_halo_exchange.argtypes = [C.POINTER(vp), C.POINTER(vp), i32]
     L.lbvp_batch_set_halo.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), i32]
+    L.lbvp_batch_set_tile_band.argtypes = [vp, i32]
+    L.lbvp_batch_get_tile_band.argtypes = [vp, C.POINTER(i32)]
     L.lbvp_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
     L.lbvp_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbvp_tune.argtypes = [C.POINTER(vp), i32, i32, u32, C.POINTER(lbvp_tune_row), i32, C.POINTER(i32),
@@ -267,6 +273,16 @@ def lbvp_get_launch(ctx) -> Tuple[int, int]:
     return v.value, b.value
 
 
+def lbvp_set_tile_band(ctx, band: int):
+    _check(ctx, _L.lbvp_set_tile_band(ctx, int(band)))
+
+
+def lbvp_get_tile_band(ctx) -> int:
+    b = C.c_int32()
+    _check(ctx, _L.lbvp_get_tile_band(ctx, C.byref(b)))
+    return b.value
+
+
 def lbvp_step_count(ctx) -> int:
     return int(_L.lbvp_step_count(ctx))
 
@@ -302,6 +318,16 @@ def lbvp_batch_set_halo(batch, west, east):
     w = (C.c_int32 * max(n, 1))(*west)
     e = (C.c_int32 * max(n, 1))(*east)
     _check_batch(batch, _L.lbvp_batch_set_halo(batch, w, e, n))
+
+
+def lbvp_batch_set_tile_band(batch, band: int):
+    _check_batch(batch, _L.lbvp_batch_set_tile_band(batch, int(band)))
+
+
+def lbvp_batch_get_tile_band(batch) -> int:
+    b = C.c_int32()
+    _check_batch(batch, _L.lbvp_batch_get_tile_band(batch, C.byref(b)))
+    return b.value
 
 
 def lbvp_batch_step(batch, n_steps: int, flags: int = 0):
@@ -504,6 +530,13 @@ class Solver:
     def set_launch(self, vec: int, block: int):
         lbvp_set_launch(self.ctx, vec, block)
 
+    @property
+    def tile_band(self) -> int:
+        return lbvp_get_tile_band(self.ctx)
+
+    def set_tile_band(self, band: int):
+        lbvp_set_tile_band(self.ctx, band)
+
     def synchronize(self):
         lbvp_synchronize(self.ctx)
 
@@ -529,6 +562,13 @@ class Batch:
 
     def step(self, n: int, keep_fields: bool = False, graph: bool = False):
         lbvp_batch_step(self.handle, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0))
+
+    @property
+    def tile_band(self) -> int:
+        return lbvp_batch_get_tile_band(self.handle)
+
+    def set_tile_band(self, band: int):
+        lbvp_batch_set_tile_band(self.handle, band)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -622,7 +662,7 @@ class Slabs:
     share one."""
 
     def __init__(self, slab_problems, x0s, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
-                 batched: bool = True, launch: Optional[Tuple[int, int]] = None,
+                 batched: bool = True, launch: Optional[Tuple[int, int]] = None, tile_band: Optional[int] = None,
                  stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda"):
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.solvers = [Solver(p, storage=storage, force_every=force_every, force_capacity=force_capacity,
@@ -640,6 +680,9 @@ class Slabs:
         self.batch = Batch(self.solvers, *(launch or (0, 0))) if batched else None
         if self.batch is not None and self.links:   # the exchange runs inside every batched step
             lbvp_batch_set_halo(self.batch.handle, [w for w, _ in self.links], [e for _, e in self.links])
+        if tile_band is not None:
+            for s in ([self.batch] if self.batch is not None else self.solvers):
+                s.set_tile_band(tile_band)
 
     def exchange(self):
         if self.links:

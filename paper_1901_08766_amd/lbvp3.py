@@ -20,7 +20,8 @@ Q = 19
 FIELD_NAMES = ("rho", "ux", "uy", "uz", "fx", "fy", "fz")
 SYMBOLS = ["lbvp3_footprint_bytes", "lbvp3_create", "lbvp3_set_mask", "lbvp3_init_equilibrium", "lbvp3_step",
            "lbvp3_forces", "lbvp3_read_fields", "lbvp3_read_populations", "lbvp3_write_populations",
-           "lbvp3_set_launch", "lbvp3_get_launch", "lbvp3_step_count", "lbvp3_synchronize", "lbvp3_destroy",
+           "lbvp3_set_launch", "lbvp3_get_launch", "lbvp3_set_tile_band", "lbvp3_get_tile_band",
+           "lbvp3_step_count", "lbvp3_synchronize", "lbvp3_destroy",
            "lbvp3_last_error"]
 NO_STATUS = ("lbvp3_footprint_bytes", "lbvp3_step_count", "lbvp3_last_error")
 
@@ -54,6 +55,8 @@ def _load():
     L.lbvp3_write_populations.argtypes = [vp, i32, i32, vp]
     L.lbvp3_set_launch.argtypes = [vp, i32, i32]
     L.lbvp3_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
+    L.lbvp3_set_tile_band.argtypes = [vp, i32]
+    L.lbvp3_get_tile_band.argtypes = [vp, C.POINTER(i32)]
     L.lbvp3_step_count.restype = i64
     L.lbvp3_step_count.argtypes = [vp]
     L.lbvp3_synchronize.argtypes = [vp]
@@ -153,6 +156,16 @@ def lbvp3_get_launch(ctx) -> Tuple[int, int]:
     return v.value, b.value
 
 
+def lbvp3_set_tile_band(ctx, band: int):
+    _check(ctx, _L.lbvp3_set_tile_band(ctx, int(band)))
+
+
+def lbvp3_get_tile_band(ctx) -> int:
+    b = C.c_int32()
+    _check(ctx, _L.lbvp3_get_tile_band(ctx, C.byref(b)))
+    return b.value
+
+
 def lbvp3_step_count(ctx) -> int:
     return int(_L.lbvp3_step_count(ctx))
 
@@ -231,6 +244,13 @@ class Solver3:
 
     def set_launch(self, vec: int, block: int):
         lbvp3_set_launch(self.ctx, vec, block)
+
+    @property
+    def tile_band(self) -> int:
+        return lbvp3_get_tile_band(self.ctx)
+
+    def set_tile_band(self, band: int):
+        lbvp3_set_tile_band(self.ctx, band)
 
     def synchronize(self):
         lbvp3_synchronize(self.ctx)
