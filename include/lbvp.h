@@ -197,6 +197,14 @@ lbvp_status lbvp_read_fields(lbvp_ctx* ctx, double* rho, double* ux, double* uy,
  * step count (the lattice then holds streamed, not post-collision, values). */
 lbvp_status lbvp_read_populations(lbvp_ctx* ctx, double* g);
 
+/* lbvp_read_fields and lbvp_read_populations for rows y0 .. y0 + n_rows - 1 only:
+ * each field host [n_rows][nx], populations host [9][n_rows][nx], so that a large
+ * domain can be read a band at a time. E_ARG (a row range outside the grid),
+ * otherwise as the whole-domain calls. */
+lbvp_status lbvp_read_fields_rows(lbvp_ctx* ctx, int32_t y0, int32_t n_rows, double* rho, double* ux,
+                                  double* uy, double* fx, double* fy);
+lbvp_status lbvp_read_populations_rows(lbvp_ctx* ctx, int32_t y0, int32_t n_rows, double* g);
+
 /* Overwrite the populations with host [9][ny][nx] FP64 values g_a (rounded to
  * the storage type). Keeps the step counter. E_STATE in the AA layout after an
  * odd step count. */

@@ -66,7 +66,7 @@ struct Step3Args {
     R fb18[3];                      // 18 F_b: the half step in units of 36 j
     R feq_in[Q];                    // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side
     const uint8_t* mask;            // [ny nz][pitch]
-    const R* bodies;                // [(max_bodies + 1)][9]: c, v, omega; row 0 all zero
+    const double* bodies;           // [(max_bodies + 1)][9]: c, v, omega, FP64 for every storage type; row 0 all zero
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
     double* slot_force;             // [2][fin.slot_stride]

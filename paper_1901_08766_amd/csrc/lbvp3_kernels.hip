@@ -91,12 +91,15 @@ __device__ __forceinline__ Node3<R> collide3(R (&f)[Q], int body, int i, int j, 
 
     R fv[3] = {R(0), R(0), R(0)};
     if (body) {
-        const R* B = a.bodies + 9 * body;
-        const R rx = (R)i - B[0], ry = (R)j - B[1], rz = (R)k - B[2];
+        const double* B = a.bodies + 9 * body;
+        // x - c in FP64, rounded once (a centre rounded to FP32 first would be off by
+        // up to half an FP32 spacing, the same for every node of the body)
+        const R rx = (R)((double)i - B[0]), ry = (R)((double)j - B[1]), rz = (R)((double)k - B[2]);
+        const R w0 = (R)B[6], w1 = (R)B[7], w2 = (R)B[8];
         R uo[3];
-        uo[0] = B[3] + (B[7] * rz - B[8] * ry);
-        uo[1] = B[4] + (B[8] * rx - B[6] * rz);
-        uo[2] = B[5] + (B[6] * ry - B[7] * rx);
+        uo[0] = (R)B[3] + (w1 * rz - w2 * ry);
+        uo[1] = (R)B[4] + (w2 * rx - w0 * rz);
+        uo[2] = (R)B[5] + (w0 * ry - w1 * rx);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const R du = a.vp_c * (uo[d] - u[d]);

@@ -205,7 +205,7 @@ Layout make_layout(const lbvp_params* p)
     L.lat[0] = take(lat_bytes);
     L.lat[1] = aa ? L.lat[0] : take(lat_bytes);   // the AA pattern streams in place
     L.mask = take((size_t)p->ny * L.pitch);
-    L.bodies = take((size_t)(L.max_bodies + 1) * 5 * rs);
+    L.bodies = take((size_t)(L.max_bodies + 1) * 5 * sizeof(double));
     L.fields = take(5 * (size_t)L.plane_f * rs);
     L.mass_part = take(2 * (size_t)L.max_waves * sizeof(double));          // double-buffered
     L.slot_force = take(2 * (size_t)L.slot_cap * 2 * sizeof(double));
@@ -440,7 +440,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     inflow_ghost(p, fin);
     for (int q = 0; q < 9; ++q) a.feq_in[q] = (R)fin[q];
     a.mask = c->at<uint8_t>(L.mask);
-    a.bodies = c->at<R>(L.bodies);
+    a.bodies = c->at<double>(L.bodies);
     a.tile_slot_ptr = c->at<int32_t>(L.tile_slot_ptr);
     a.slot_body = c->at<int32_t>(L.slot_body);
     a.slot_force = c->at<double>(L.slot_force);
@@ -1125,8 +1125,7 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
     for (int64_t k = 0; k < n; ++k)
         if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
 
-    std::vector<char> table = c->is_f64() ? body_table_bytes<double>(bodies, n_bodies, L.max_bodies)
-                                          : body_table_bytes<float>(bodies, n_bodies, L.max_bodies);
+    std::vector<char> table = body_table_bytes<double>(bodies, n_bodies, L.max_bodies);
     if (c->moving() && n_bodies > MAX_MOVING) return c->fail(LBVP_E_ARG, "moving bodies: at most 8");
     c->graphs.clear(c->stream);
     c->mask_host.assign(body_id, body_id + n);
@@ -1288,22 +1287,24 @@ lbvp_status lbvp_forces(lbvp_ctx* c, double* out, double* mass, int64_t cap, int
     return LBVP_OK;
 }
 
-lbvp_status lbvp_read_fields(lbvp_ctx* c, double* rho, double* ux, double* uy, double* fx, double* fy)
+lbvp_status lbvp_read_fields_rows(lbvp_ctx* c, int32_t y0, int32_t n_rows, double* rho, double* ux, double* uy,
+                                  double* fx, double* fy)
 {
     if (check_ctx(c)) return LBVP_E_ARG;
+    const lbvp_params& p = c->p;
+    if (y0 < 0 || n_rows < 1 || n_rows > p.ny - y0) return c->fail(LBVP_E_ARG, "row range outside the grid");
     if (!c->fields_valid) return c->fail(LBVP_E_STATE, "no fields kept since the last init");
     LBVP_HIP(c, hipStreamSynchronize(c->stream));
-    const lbvp_params& p = c->p;
     double* dst[5] = {rho, ux, uy, fx, fy};
     const size_t rs = c->rsize();
-    std::vector<char> tmp((size_t)p.nx * p.ny * rs);
+    const size_t n = (size_t)p.nx * n_rows;
+    std::vector<char> tmp(n * rs);
     for (int q = 0; q < 5; ++q) {
         if (!dst[q]) continue;
-        const char* srcp = c->at<char>(c->L.fields) + (size_t)q * c->L.plane_f * rs;
+        const char* srcp = c->at<char>(c->L.fields) + ((size_t)q * c->L.plane_f + (size_t)y0 * c->L.pitch) * rs;
         LBVP_HIP(c, hipMemcpy2DAsync(tmp.data(), (size_t)p.nx * rs, srcp, (size_t)c->L.pitch * rs,
-                                     (size_t)p.nx * rs, (size_t)p.ny, hipMemcpyDeviceToHost, c->stream));
+                                     (size_t)p.nx * rs, (size_t)n_rows, hipMemcpyDeviceToHost, c->stream));
         LBVP_HIP(c, hipStreamSynchronize(c->stream));
-        const size_t n = (size_t)p.nx * p.ny;
         if (c->is_f64()) std::memcpy(dst[q], tmp.data(), n * sizeof(double));
         else {
             const float* f = reinterpret_cast<const float*>(tmp.data());
@@ -1313,19 +1314,26 @@ lbvp_status lbvp_read_fields(lbvp_ctx* c, double* rho, double* ux, double* uy, d
     return LBVP_OK;
 }
 
-lbvp_status lbvp_read_populations(lbvp_ctx* c, double* g)
+lbvp_status lbvp_read_fields(lbvp_ctx* c, double* rho, double* ux, double* uy, double* fx, double* fy)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    return lbvp_read_fields_rows(c, 0, c->p.ny, rho, ux, uy, fx, fy);
+}
+
+lbvp_status lbvp_read_populations_rows(lbvp_ctx* c, int32_t y0, int32_t n_rows, double* g)
 {
     if (check_ctx(c)) return LBVP_E_ARG;
     if (!g) return c->fail(LBVP_E_ARG, "g is NULL");
+    const lbvp_params& p = c->p;
+    if (y0 < 0 || n_rows < 1 || n_rows > p.ny - y0) return c->fail(LBVP_E_ARG, "row range outside the grid");
     if (c->aa() && c->step % 2)
         return c->fail(LBVP_E_STATE, "the AA layout holds the post-collision populations after an even step count");
-    const lbvp_params& p = c->p;
     hipStream_t s = c->stream;
-    const int32_t rows_per = (int32_t)std::min<int64_t>(p.ny, c->L.stage_rows);
-    const size_t N = (size_t)p.nx * p.ny;
-    for (int32_t r0 = 0; r0 < p.ny; r0 += rows_per) {
-        const int32_t rows = std::min(rows_per, p.ny - r0);
-        ConvArgs a = conv_args(c, r0, rows);
+    const int32_t rows_per = (int32_t)std::min<int64_t>(n_rows, c->L.stage_rows);
+    const size_t N = (size_t)p.nx * n_rows;
+    for (int32_t r0 = 0; r0 < n_rows; r0 += rows_per) {
+        const int32_t rows = std::min(rows_per, n_rows - r0);
+        ConvArgs a = conv_args(c, y0 + r0, rows);
         LBVP_HIP(c, launch_decode(p.storage, c->at<char>(c->L.lat[c->cur]), a, s));
         const size_t nn = (size_t)rows * p.nx;
         for (int q = 0; q < 9; ++q)
@@ -1334,6 +1342,12 @@ lbvp_status lbvp_read_populations(lbvp_ctx* c, double* g)
         LBVP_HIP(c, hipStreamSynchronize(s));
     }
     return LBVP_OK;
+}
+
+lbvp_status lbvp_read_populations(lbvp_ctx* c, double* g)
+{
+    if (check_ctx(c)) return LBVP_E_ARG;
+    return lbvp_read_populations_rows(c, 0, c->p.ny, g);
 }
 
 lbvp_status lbvp_write_populations(lbvp_ctx* c, const double* g)

@@ -70,7 +70,7 @@ struct StepArgs {
     R fbx18, fby18;     // 18 F_b: the body-force half step in units of 36 j
     R feq_in[9];        // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side
     const uint8_t* mask;
-    const R* bodies;    // [(n_bodies + 1)][5]; row 0 is all zero (fluid)
+    const double* bodies;   // [(n_bodies + 1)][5] (cx, cy, vx, vy, omega), FP64 for every storage type; row 0 all zero
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
     double* slot_force;             // [2][n_slots][2]

@@ -79,15 +79,20 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     // volume penalization (eqs. d-V, force-density) on solid nodes only
     R fvx = R(0), fvy = R(0);
     if (body) {
-        const R* B = a.bodies + 5 * body;
-        R bcx = B[0], bcy = B[1];                 // the body's centre, at time t if it moves
+        const double* B = a.bodies + 5 * body;
+        double bcx = B[0], bcy = B[1];            // the body's centre, at time t if it moves
         if constexpr (MOVING) {
             const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
-            bcx = (R)m[2];
-            bcy = (R)m[3];
+            bcx = m[2];
+            bcy = m[3];
         }
-        const R uox = B[2] - B[4] * ((R)j - bcy);
-        const R uoy = B[3] + B[4] * ((R)i - bcx);
+        // the offset from the centre is formed in FP64 and rounded once: a centre
+        // rounded to FP32 first would be off by up to half an FP32 spacing (1/512
+        // node near x = 32768), the same for every node of the body
+        const R rx = (R)((double)i - bcx), ry = (R)((double)j - bcy);
+        const R om = (R)B[4];
+        const R uox = (R)B[2] - om * ry;
+        const R uoy = (R)B[3] + om * rx;
         const R dux = a.vp_c * (uox - ux);
         const R duy = a.vp_c * (uoy - uy);
         fvx = R(2) * rho * dux;

@@ -438,6 +438,57 @@ def random_state_problem(nx: int, ny: int, seed, n_disks: int = 3, bc=(INFLOW_EQ
                    mask=mask, bodies=bodies, rho_init=rho, ux_init=ux, uy_init=uy, u_ref=u, l_ref=1.0)
 
 
+def _paint_disk_window(mask: np.ndarray, cx: float, cy: float, r: float, body_id: int) -> None:
+    """paint_disk evaluated on the disk's bounding box only (large grids)."""
+    ny, nx = mask.shape
+    x0, x1 = max(0, int(math.floor(cx - r)) - 1), min(nx, int(math.ceil(cx + r)) + 2)
+    y0, y1 = max(0, int(math.floor(cy - r)) - 1), min(ny, int(math.ceil(cy + r)) + 2)
+    x = np.arange(x0, x1, dtype=np.float64)[None, :]
+    y = np.arange(y0, y1, dtype=np.float64)[:, None]
+    win = mask[y0:y1, x0:x1]
+    win[(x - cx) ** 2 + (y - cy) ** 2 <= r * r] = body_id
+
+
+def huge_domain(nx: int = 32768, ny: int = 16384, seed: int = 8, n_disks: int = 6, u: float = 0.05,
+                tau_plus: float = 0.6) -> Problem:
+    """A domain at the size where 32-bit element offsets no longer reach: 32768 x
+    16384 nodes, 4.8e9 populations per lattice (past 2^32). Rotating and
+    translating disks, half of them in the last rows and columns; a uniform body
+    force drives every node from rest (no host field arrays: the fluid starts at
+    rho0, u = 0), inflow and zero-gradient outflow x sides."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((ny, nx), dtype=np.uint8)
+    rows = []
+    for k in range(n_disks):
+        r = float(rng.uniform(6.0, 40.0))
+        far = k % 2 == 1
+        cx = float(rng.uniform(nx - 400, nx - 60) if far else rng.uniform(60, nx - 60))
+        cy = float(rng.uniform(ny - 400, ny - 60) if far else rng.uniform(60, ny - 60))
+        _paint_disk_window(mask, cx, cy, r, k + 1)
+        rows.append([cx, cy, float(rng.uniform(-0.3, 0.3)) * u, float(rng.uniform(-0.3, 0.3)) * u,
+                     float(rng.uniform(-1, 1)) * u / r])
+    return Problem(name=f"huge{nx}x{ny}", nx=nx, ny=ny, tau_plus=tau_plus, magic_lambda=0.25, eta=1e-4,
+                   bc=(INFLOW_EQ, OUTFLOW, PERIODIC, PERIODIC), rho_in=1.0, u_in=(u, 0.0),
+                   body_force=(2e-5, -1e-5), mask=mask, bodies=np.array(rows), u_ref=u, l_ref=1.0)
+
+
+def rows_band(p: Problem, j0: int, n: int) -> Problem:
+    """Rows j0 .. j0 + n - 1 (taken modulo ny) of a problem as a problem of their
+    own, periodic along y over the n rows, body centres moved by -j0 along y. A
+    node update in the middle row of a 3-row band reads that band only (the y
+    sides are periodic)."""
+    rs = [(j0 + s) % p.ny for s in range(n)]
+
+    def cut(a):
+        return None if a is None else np.ascontiguousarray(a[rs])
+
+    b = p.bodies_or_empty().copy()
+    b[:, 1] -= j0
+    return dataclasses.replace(p, name=f"{p.name}_rows{j0}+{n}", ny=n, mask=cut(p.mask_or_empty()),
+                               bodies=b if b.shape[0] else None, rho_init=cut(p.rho_init),
+                               ux_init=cut(p.ux_init), uy_init=cut(p.uy_init))
+
+
 def split_x(p: Problem, widths: Sequence[int]) -> Tuple[List[Problem], List[int]]:
     """The slabs of a domain cut along x into consecutive column ranges of the
     given widths (summing to nx): each slab keeps its columns of the mask and of

@@ -83,6 +83,40 @@ def paint_sphere(mask: np.ndarray, cx: float, cy: float, cz: float, r: float, bo
     mask[inside] = body_id
 
 
+def _paint_sphere_window(mask: np.ndarray, cx: float, cy: float, cz: float, r: float, body_id: int) -> None:
+    """paint_sphere evaluated on the sphere's bounding box only (large grids)."""
+    nz, ny, nx = mask.shape
+    lo = [max(0, int(math.floor(c - r)) - 1) for c in (cx, cy, cz)]
+    hi = [min(n, int(math.ceil(c + r)) + 2) for c, n in ((cx, nx), (cy, ny), (cz, nz))]
+    x = np.arange(lo[0], hi[0], dtype=np.float64)[None, None, :]
+    y = np.arange(lo[1], hi[1], dtype=np.float64)[None, :, None]
+    z = np.arange(lo[2], hi[2], dtype=np.float64)[:, None, None]
+    win = mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+    win[(x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r] = body_id
+
+
+def huge_domain3(nx: int = 1024, ny: int = 1024, nz: int = 640, seed: int = 9, n_spheres: int = 4,
+                 u: float = 0.05, tau_plus: float = 0.6) -> Problem3:
+    """A 3-D domain past 32-bit element offsets: 1024 x 1024 x 640 nodes, 1.27e10
+    populations per lattice. Spheres turning about random axes and translating,
+    half of them in the last planes; a uniform body force drives every node from
+    rest (no host field arrays), inflow and zero-gradient outflow x sides."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    mask = np.zeros((nz, ny, nx), dtype=np.uint8)
+    rows = []
+    for k in range(n_spheres):
+        r = float(rng.uniform(5.0, 24.0))
+        far = k % 2 == 1
+        c = [float(rng.uniform(n - 200, n - 40) if far else rng.uniform(40, n - 40)) for n in (nx, ny, nz)]
+        _paint_sphere_window(mask, c[0], c[1], c[2], r, k + 1)
+        v = [float(rng.uniform(-0.3, 0.3)) * u for _ in range(3)]
+        om = [float(rng.uniform(-1, 1)) * u / r for _ in range(3)]
+        rows.append(c + v + om)
+    return Problem3(name=f"huge{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz, tau_plus=tau_plus, magic_lambda=0.25,
+                    eta=1e-4, bc=(INFLOW_EQ, OUTFLOW), rho_in=1.0, u_in=(u, 0.0, 0.0),
+                    body_force=(2e-5, -1e-5, 5e-6), mask=mask, bodies=np.array(rows), u_ref=u, l_ref=1.0)
+
+
 def paint_box(mask: np.ndarray, lo: Tuple[int, int, int], hi: Tuple[int, int, int], body_id: int) -> None:
     """Nodes lo <= (i, j, k) < hi, given as (x, y, z) bounds."""
     mask[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = body_id

@@ -34,7 +34,8 @@ TUNE_LAYOUTS = 0x1
 TUNE_FRESH = 0x2
 
 SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_equilibrium",
-           "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations",
+           "lbvp_step", "lbvp_forces", "lbvp_read_fields", "lbvp_read_populations", "lbvp_read_populations_rows",
+           "lbvp_read_fields_rows",
            "lbvp_write_populations", "lbvp_set_launch", "lbvp_get_launch", "lbvp_set_tile_band",
            "lbvp_get_tile_band", "lbvp_step_count",
            "lbvp_synchronize", "lbvp_destroy", "lbvp_last_error", "lbvp_batch_create", "lbvp_batch_step",
@@ -103,6 +104,8 @@ def _load():
     L.lbvp_forces.argtypes = [vp, vp, vp, i64, C.POINTER(i64), C.POINTER(i64)]
     L.lbvp_read_fields.argtypes = [vp] * 6
     L.lbvp_read_populations.argtypes = [vp, vp]
+    L.lbvp_read_fields_rows.argtypes = [vp, i32, i32] + [vp] * 5
+    L.lbvp_read_populations_rows.argtypes = [vp, i32, i32, vp]
     L.lbvp_write_populations.argtypes = [vp, vp]
     L.lbvp_set_launch.argtypes = [vp, i32, i32]
     L.lbvp_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
@@ -224,6 +227,18 @@ def lbvp_read_fields(ctx, nx: int, ny: int) -> Dict[str, np.ndarray]:
 def lbvp_read_populations(ctx, nx: int, ny: int) -> np.ndarray:
     g = np.zeros((9, ny, nx))
     _check(ctx, _L.lbvp_read_populations(ctx, _ptr(g)))
+    return g
+
+
+def lbvp_read_fields_rows(ctx, nx: int, y0: int, n_rows: int) -> Dict[str, np.ndarray]:
+    out = [np.zeros((n_rows, nx)) for _ in range(5)]
+    _check(ctx, _L.lbvp_read_fields_rows(ctx, int(y0), int(n_rows), *[_ptr(a) for a in out]))
+    return dict(zip(("rho", "ux", "uy", "fx", "fy"), out))
+
+
+def lbvp_read_populations_rows(ctx, nx: int, y0: int, n_rows: int) -> np.ndarray:
+    g = np.zeros((9, n_rows, nx))
+    _check(ctx, _L.lbvp_read_populations_rows(ctx, int(y0), int(n_rows), _ptr(g)))
     return g
 
 
@@ -504,11 +519,15 @@ class Solver:
             done += k
         return np.concatenate(fs) if fs else np.zeros((0, self.n_bodies, 2)), np.concatenate(ms) if ms else np.zeros(0)
 
-    def fields(self) -> Dict[str, np.ndarray]:
-        return lbvp_read_fields(self.ctx, self.nx, self.ny)
+    def fields(self, y0: int = 0, n_rows: Optional[int] = None) -> Dict[str, np.ndarray]:
+        if y0 == 0 and n_rows is None:
+            return lbvp_read_fields(self.ctx, self.nx, self.ny)
+        return lbvp_read_fields_rows(self.ctx, self.nx, y0, self.ny - y0 if n_rows is None else n_rows)
 
-    def populations(self) -> np.ndarray:
-        return lbvp_read_populations(self.ctx, self.nx, self.ny)
+    def populations(self, y0: int = 0, n_rows: Optional[int] = None) -> np.ndarray:
+        if y0 == 0 and n_rows is None:
+            return lbvp_read_populations(self.ctx, self.nx, self.ny)
+        return lbvp_read_populations_rows(self.ctx, self.nx, y0, self.ny - y0 if n_rows is None else n_rows)
 
     def set_populations(self, g: np.ndarray):
         lbvp_write_populations(self.ctx, g)
@@ -544,6 +563,7 @@ class Solver:
         if getattr(self, "ctx", None):
             lbvp_destroy(self.ctx)
             self.ctx = None
+            self.mem = None   # the context borrowed it; torch may reuse it now
 
     def __del__(self):
         try:

@@ -1,0 +1,116 @@
+"""Maximum sizes: domains whose lattices hold more populations than 32-bit
+offsets reach (2-D 32768 x 16384, 4.8e9 per FP32 lattice, ~50 GB on the device;
+3-D 1024 x 1024 x 640, 1.27e10, ~120 GB), in the launch configuration a user
+gets by default. After a few GPU steps the oracle advances the GPU's own state
+by one step at sampled nodes, on bands of rows (planes) cut from the domain
+around them (y and z are periodic, so a node in the interior of a band reads
+that band only), and that must equal the GPU's next state to FP32 rounding:
+the first and last rows or planes, the last columns, and every node of a body
+placed in the far corner, whose recorded force must equal the oracle's sum.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1901_08766_amd import inputs, inputs3
+
+pytestmark = pytest.mark.gpu
+
+
+def _rows(read, lo, n, size):
+    """Rows (planes) lo .. lo + n - 1 modulo size, read in contiguous runs;
+    stacked along axis 1."""
+    idx = [(lo + s) % size for s in range(n)]
+    runs, start = [], 0
+    for s in range(1, n + 1):
+        if s == n or idx[s] != idx[s - 1] + 1:
+            runs.append(read(idx[start], s - start))
+            start = s
+    return np.concatenate(runs, axis=1)
+
+
+FIELDS2 = ("rho", "ux", "uy", "fx", "fy")
+
+
+def _stack(fields):
+    return np.stack([fields[k] for k in FIELDS2])
+
+
+def _body_span(mask_any_rows):
+    hit = np.nonzero(mask_any_rows)[0]
+    return int(hit.min()), int(hit.max())
+
+
+def test_fp32_maximum_size_2d(lbvp, oracle):
+    prob = inputs.huge_domain()
+    nx, ny = prob.nx, prob.ny
+    gpu = lbvp.Solver(prob, storage="f32", force_every=1, force_capacity=64)
+    print(f"case {prob.name} launch={gpu.launch} band={gpu.tile_band} device bytes={gpu.footprint}", flush=True)
+    lo2, hi2 = _body_span((prob.mask == 2).any(axis=1))          # body 2 lies in the far corner
+    bands = [(ny - 1, 3), (ny - 2, 3), (ny // 2 - 1, 3), (lo2 - 1, hi2 - lo2 + 3)]
+    gpu.step(12)
+    gpu.forces()
+    g12 = [_rows(lambda a, n: gpu.populations(a, n), lo, n, ny) for lo, n in bands]
+    gpu.step(1, keep_fields=True)
+    gf, _, first = gpu.forces()
+    assert first == 13
+    rng = np.random.Generator(np.random.PCG64(7))
+    for (lo, n), g0 in zip(bands, g12):
+        band = inputs.rows_band(prob, lo, n)
+        ref = oracle.RefSolver(band)
+        inner = np.arange(1, n - 1)
+        g13 = _rows(lambda a, m: gpu.populations(a, m), lo + 1, n - 2, ny)
+        fl = _rows(lambda a, m: _stack(gpu.fields(a, m)), lo + 1, n - 2, ny)
+        ys_s, xs_s = np.nonzero(band.mask[1:n - 1])
+        xs = np.concatenate([np.array([0, 1, nx - 2, nx - 1] * len(inner)), rng.integers(0, nx, 128), xs_s])
+        ys = np.concatenate([np.repeat(inner - 1, 4), rng.integers(0, n - 2, 128), ys_s])
+        gout, rfl = ref.step_nodes(g0, xs, ys + 1)
+        ref.close()
+        assert np.abs(g13[:, ys, xs].T - gout).max() <= 1e-6, (lo, n)
+        for q, k in enumerate(FIELDS2):
+            assert np.abs(fl[q][ys, xs] - rfl[:, q]).max() <= 2e-6, (lo, n, k)
+        if lo == lo2 - 1:   # every node of body 2: its recorded force
+            solid = slice(len(xs) - len(xs_s), len(xs))
+            sel = band.mask[1:n - 1][ys_s, xs_s] == 2
+            f_ref = -rfl[solid][sel, 3:5].sum(axis=0)
+            mag = np.abs(rfl[solid][sel, 3:5]).sum()
+            assert mag > 0
+            assert np.all(np.abs(gf[0, 1] - f_ref) <= 1e-5 * mag)
+    gpu.close()
+    del gpu
+    torch.cuda.empty_cache()
+
+
+def test_fp32_maximum_size_3d(lbvp3, ref3):
+    prob = inputs3.huge_domain3()
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    gpu = lbvp3.Solver3(prob, storage="f32", force_every=1, force_capacity=64)
+    print(f"case {prob.name} launch={gpu.launch} band={gpu.tile_band} device bytes={gpu.footprint}", flush=True)
+    lo2, hi2 = _body_span((prob.mask == 2).any(axis=(1, 2)))    # sphere 2 lies in the far corner
+    planes = [0, nz - 1, (lo2 + hi2) // 2, lo2, hi2]
+    gpu.step(8)
+    gpu.forces()
+    g8 = {k: _rows(lambda a, n: gpu.populations(a, n), k - 1, 3, nz) for k in planes}
+    gpu.step(1, keep_fields=True)
+    _, _, first = gpu.forces()
+    assert first == 9
+    rng = np.random.Generator(np.random.PCG64(11))
+    n_solid = 0
+    for k in planes:
+        g9 = gpu.populations(k, 1)[:, 0]
+        fl = gpu.fields(k, 1)
+        slab = inputs3.slab(prob, k - 1, 3)
+        ref = ref3.RefSolver3(slab)
+        ys_s, xs_s = np.nonzero(prob.mask[k])
+        n_solid += len(xs_s)
+        xs = np.concatenate([np.array([0, nx - 2, nx - 1] * 16), rng.integers(0, nx, 128), xs_s])
+        ys = np.concatenate([rng.integers(0, ny, 48), rng.integers(0, ny, 128), ys_s])
+        gout, rfl = ref.step_nodes(g8[k], xs, ys, np.ones_like(xs))
+        ref.close()
+        assert np.abs(g9[:, ys, xs].T - gout).max() <= 1e-6, k
+        for q, name in enumerate(("rho", "ux", "uy", "uz", "fx", "fy", "fz")):
+            assert np.abs(fl[name][0, ys, xs] - rfl[:, q]).max() <= 2e-6, (k, name)
+    assert n_solid > 0
+    gpu.close()
+    del gpu
+    torch.cuda.empty_cache()
