@@ -241,7 +241,8 @@ def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 
     defaults = [m.launch for m in members]
     rows, best = lbvp.tune(members, steps=40, layouts=True)
     out = {"domains": n_dom, "nodes": nodes, "storage": storage,
-           "tuned": {"layout": "aa" if best["layout_flags"] else "pull", "vec": best["vec"], "block": best["block"]},
+           "tuned": {"layout": "aa" if best["layout_flags"] else "pull", "vec": best["vec"], "block": best["block"],
+                     "tile_band": best["band"]},
            "tuner_rows": len(rows)}
     # per-domain plain launches (pull layout, each domain's default launch shape)
     for m in members:
@@ -276,6 +277,7 @@ def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 
             m.close()
         members = make(lbvp.LAYOUT_AA)
     batch = lbvp.Batch(members, vec=best["vec"], block=best["block"])
+    batch.set_tile_band(best["band"])
     batch.step(10)
     batch.step(steps, graph=True)             # capture outside the timed region
     stream.synchronize()

@@ -291,8 +291,9 @@ lbvp_status lbvp_batch_set_tile_band(lbvp_batch* batch, int32_t band);
 lbvp_status lbvp_batch_get_tile_band(const lbvp_batch* batch, int32_t* band);
 
 /* ---- Tuner ----------------------------------------------------------------------
- * Times the step kernel for every launch shape (vec x block) and, with
- * LBVP_TUNE_LAYOUTS, in both layouts, on scratch contexts made from the members'
+ * Times the step kernel for every launch shape (vec x block, and for vec > 1 the
+ * tile bands 0, 2 and 16 of lbvp_set_tile_band) and, with LBVP_TUNE_LAYOUTS, in
+ * both layouts, on scratch contexts made from the members'
  * parameters and masks (the members themselves are not stepped; the scratch
  * contexts need as much device memory again). n > 1 members run as one batch, as
  * they would in lbvp_batch_step. Each candidate: steps/4 warm-up steps, then the
@@ -308,6 +309,7 @@ lbvp_status lbvp_batch_get_tile_band(const lbvp_batch* batch, int32_t* band);
 typedef struct lbvp_tune_row {
     uint32_t layout_flags;   /* 0 or LBVP_LAYOUT_AA */
     int32_t vec, block;
+    int32_t band;            /* tile band (lbvp_set_tile_band, lbvp_batch_set_tile_band) */
     double ms_per_step;
     double mlups;            /* million node updates per second over all members */
 } lbvp_tune_row;

@@ -160,7 +160,7 @@ Layout3 make_layout(const lbvp3_params& p)
     L.lat[0] = take(lat_bytes);
     L.lat[1] = take(lat_bytes);
     L.mask = take((size_t)L.rows * L.pitch);
-    L.bodies = take((size_t)(L.max_bodies + 1) * 9 * sizeof(double));
+    L.bodies = take((size_t)(L.max_bodies + 1) * BODY3_STRIDE * rs);
     L.fields = take((size_t)7 * L.plane_f * rs);
     L.mass_part = take((size_t)2 * L.max_waves * 8);       // double-buffered partials
     L.slot_force = take((size_t)2 * L.slot_cap * 3 * 8);
@@ -262,7 +262,7 @@ void fill_args(lbvp3_ctx* c, Step3Args<R>& a)
         a.feq_in[q] = (R)((p.rho_in - p.rho0) + p.rho_in * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
     }
     a.mask = c->at<uint8_t>(L.mask);
-    a.bodies = c->at<double>(L.bodies);
+    a.bodies = c->at<R>(L.bodies);
     a.tile_slot_ptr = c->at<int32_t>(L.tile_slot_ptr);
     a.slot_body = c->at<int32_t>(L.slot_body);
     a.slot_force = c->at<double>(L.slot_force);
@@ -436,21 +436,26 @@ lbvp_status lbvp3_set_mask(lbvp3_ctx* c, const uint8_t* body_id, int32_t n_bodie
     const int64_t n = L.rows * p.nx;
     for (int64_t k = 0; k < n; ++k)
         if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
-    // body table: row 0 all zero (fluid), row b = c, v, omega of body b, in FP64
-    // (the kernel rounds v and omega to the arithmetic type, and forms x - c in FP64)
-    std::vector<double> table((size_t)(L.max_bodies + 1) * 9, 0.0);
+    // body table: row 0 all zero (fluid), row b = c_int, c_frac, v, omega of body
+    // b, in the arithmetic type (the centre's split is exact in FP64)
+    const size_t rs = c->rsize();
+    std::vector<char> table((size_t)(L.max_bodies + 1) * BODY3_STRIDE * rs, 0);
     for (int32_t b = 0; b < n_bodies; ++b)
         for (int d = 0; d < 3; ++d) {
-            const double vals[3] = {bodies[b].c[d], bodies[b].v[d], bodies[b].omega[d]};
-            for (int g = 0; g < 3; ++g) table[(size_t)(b + 1) * 9 + 3 * g + d] = vals[g];
+            const double ci = std::nearbyint(bodies[b].c[d]);
+            const double vals[4] = {ci, bodies[b].c[d] - ci, bodies[b].v[d], bodies[b].omega[d]};
+            for (int g = 0; g < 4; ++g) {
+                const size_t idx = (size_t)(b + 1) * BODY3_STRIDE + 3 * g + d;
+                if (c->is_f64()) reinterpret_cast<double*>(table.data())[idx] = vals[g];
+                else reinterpret_cast<float*>(table.data())[idx] = (float)vals[g];
+            }
         }
     if (body_id != c->mask_host.data()) c->mask_host.assign(body_id, body_id + n);
     c->n_bodies = n_bodies;
     hipStream_t s = c->stream;
     LBVP3_HIP(c, hipMemcpy2DAsync(c->at<uint8_t>(L.mask), (size_t)L.pitch, c->mask_host.data(), (size_t)p.nx,
                                   (size_t)p.nx, (size_t)L.rows, hipMemcpyHostToDevice, s));
-    LBVP3_HIP(c, hipMemcpyAsync(c->at<double>(L.bodies), table.data(), table.size() * sizeof(double),
-                                 hipMemcpyHostToDevice, s));
+    LBVP3_HIP(c, hipMemcpyAsync(c->at<char>(L.bodies), table.data(), table.size(), hipMemcpyHostToDevice, s));
     return apply_launch(c, c->launch);   // synchronizes
 }
 

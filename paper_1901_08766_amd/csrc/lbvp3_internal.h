@@ -14,6 +14,10 @@ constexpr int N_XCD = 8;
 constexpr int FIN_THREADS = 256;
 constexpr int N_LEAD = 32;   // blocks that sum one record, a multiple of the 8 XCDs
 constexpr int MAX_TILE_BAND = 1 << 16;
+// Body table row, in the arithmetic type: the centre split into its nearest
+// integer and the remainder (x - c = (x - c_int) - c_frac, exact up to one
+// rounding of a remainder of at most 1/2), then v and omega.
+constexpr int BODY3_STRIDE = 12;
 
 // Velocity components of the 19 directions in the interface order: rest, the
 // faces +x -x +y -y +z -z, then the edges as (opposite) pairs in the xy, xz and
@@ -66,7 +70,7 @@ struct Step3Args {
     R fb18[3];                      // 18 F_b: the half step in units of 36 j
     R feq_in[Q];                    // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side
     const uint8_t* mask;            // [ny nz][pitch]
-    const double* bodies;           // [(max_bodies + 1)][9]: c, v, omega, FP64 for every storage type; row 0 all zero
+    const R* bodies;                // [(max_bodies + 1)][BODY3_STRIDE]: c_int, c_frac, v, omega; row 0 all zero
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
     double* slot_force;             // [2][fin.slot_stride]

@@ -91,15 +91,14 @@ __device__ __forceinline__ Node3<R> collide3(R (&f)[Q], int body, int i, int j, 
 
     R fv[3] = {R(0), R(0), R(0)};
     if (body) {
-        const double* B = a.bodies + 9 * body;
-        // x - c in FP64, rounded once (a centre rounded to FP32 first would be off by
-        // up to half an FP32 spacing, the same for every node of the body)
-        const R rx = (R)((double)i - B[0]), ry = (R)((double)j - B[1]), rz = (R)((double)k - B[2]);
-        const R w0 = (R)B[6], w1 = (R)B[7], w2 = (R)B[8];
+        const R* B = a.bodies + BODY3_STRIDE * body;
+        // x - c from the split centre (a centre rounded to FP32 whole would be off
+        // by up to half an FP32 spacing, the same for every node of the body)
+        const R rx = ((R)i - B[0]) - B[3], ry = ((R)j - B[1]) - B[4], rz = ((R)k - B[2]) - B[5];
         R uo[3];
-        uo[0] = (R)B[3] + (w1 * rz - w2 * ry);
-        uo[1] = (R)B[4] + (w2 * rx - w0 * rz);
-        uo[2] = (R)B[5] + (w0 * ry - w1 * rx);
+        uo[0] = B[6] + (B[10] * rz - B[11] * ry);
+        uo[1] = B[7] + (B[11] * rx - B[9] * rz);
+        uo[2] = B[8] + (B[9] * ry - B[10] * rx);
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
             const R du = a.vp_c * (uo[d] - u[d]);

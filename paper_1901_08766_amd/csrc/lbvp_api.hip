@@ -205,7 +205,7 @@ Layout make_layout(const lbvp_params* p)
     L.lat[0] = take(lat_bytes);
     L.lat[1] = aa ? L.lat[0] : take(lat_bytes);   // the AA pattern streams in place
     L.mask = take((size_t)p->ny * L.pitch);
-    L.bodies = take((size_t)(L.max_bodies + 1) * 5 * sizeof(double));
+    L.bodies = take((size_t)(L.max_bodies + 1) * BODY_STRIDE * rs);
     L.fields = take(5 * (size_t)L.plane_f * rs);
     L.mass_part = take(2 * (size_t)L.max_waves * sizeof(double));          // double-buffered
     L.slot_force = take(2 * (size_t)L.slot_cap * 2 * sizeof(double));
@@ -440,7 +440,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     inflow_ghost(p, fin);
     for (int q = 0; q < 9; ++q) a.feq_in[q] = (R)fin[q];
     a.mask = c->at<uint8_t>(L.mask);
-    a.bodies = c->at<double>(L.bodies);
+    a.bodies = c->at<R>(L.bodies);
     a.tile_slot_ptr = c->at<int32_t>(L.tile_slot_ptr);
     a.slot_body = c->at<int32_t>(L.slot_body);
     a.slot_force = c->at<double>(L.slot_force);
@@ -481,10 +481,12 @@ void moving_pose(const lbvp_ctx* c, int64_t t_level, double* row)
 template <typename R>
 std::vector<char> body_table_bytes(const lbvp_body* bodies, int32_t n, int32_t max_bodies)
 {
-    std::vector<R> t((size_t)(max_bodies + 1) * 5, R(0));
+    std::vector<R> t((size_t)(max_bodies + 1) * BODY_STRIDE, R(0));
     for (int32_t k = 0; k < n; ++k) {
-        const double v[5] = {bodies[k].cx, bodies[k].cy, bodies[k].vx, bodies[k].vy, bodies[k].omega};
-        for (int q = 0; q < 5; ++q) t[(size_t)(k + 1) * 5 + q] = (R)v[q];
+        const double cxi = std::nearbyint(bodies[k].cx), cyi = std::nearbyint(bodies[k].cy);
+        const double v[BODY_STRIDE] = {cxi, cyi, bodies[k].cx - cxi, bodies[k].cy - cyi,   // exact splits
+                                       bodies[k].vx, bodies[k].vy, bodies[k].omega};
+        for (int q = 0; q < BODY_STRIDE; ++q) t[(size_t)(k + 1) * BODY_STRIDE + q] = (R)v[q];
     }
     std::vector<char> out(t.size() * sizeof(R));
     std::memcpy(out.data(), t.data(), out.size());
@@ -943,6 +945,10 @@ std::string tune_signature(const std::vector<lbvp_ctx*>& m, int32_t steps, uint3
     return o.str();
 }
 
+// Tile bands the tuner tries for vector launches: eighths, and the bands measured
+// fastest for single domains (2 for 2-byte and FP64 storage, 8 to 16 for FP32).
+constexpr int32_t TUNE_BANDS[] = {0, 2, 16};
+
 // Time every launch shape in one layout on scratch copies of the members'
 // problems (parameters, mask, bodies; fluid at rest).
 lbvp_status tune_layout(const std::vector<lbvp_ctx*>& m, uint32_t layout, int32_t steps,
@@ -977,38 +983,46 @@ lbvp_status tune_layout(const std::vector<lbvp_ctx*>& m, uint32_t layout, int32_
         return finish(LBVP_E_DEVICE, "hipEventCreate failed");
     const int32_t storage = m[0]->p.storage;
     for (int32_t vec : vec_options(storage, layout))
-        for (int32_t block : {64, 128, 256}) {
-            lbvp_status st = LBVP_OK;
-            if (s.size() == 1) st = lbvp_set_launch(s[0], vec, block);
-            else st = lbvp_batch_create(s.data(), (int32_t)s.size(), vec, block, &b);
-            if (st != LBVP_OK) return finish(st, "launch shape: " + (s.size() == 1 ? s[0]->err : g_batch_error));
-            auto run = [&](int64_t k) { return b ? lbvp_batch_step(b, k, 0) : lbvp_step(s[0], k, 0); };
-            double best = 1e300;
-            st = run(std::max(2, steps / 4));
-            for (lbvp_ctx* x : s) x->rec_tail = x->rec_head;   // records are not needed
-            for (int rep = 0; rep < 3 && st == LBVP_OK; ++rep) {
-                if (hipEventRecord(e0, stream) != hipSuccess) return finish(LBVP_E_DEVICE, "hipEventRecord");
-                st = run(steps);
-                if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
-                    return finish(LBVP_E_DEVICE, "timing events failed");
-                float ms = 0.0f;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return finish(LBVP_E_DEVICE, "hipEventElapsedTime");
-                best = std::min(best, (double)ms);
+        for (int32_t block : {64, 128, 256})
+            for (int32_t band : TUNE_BANDS) {
+                if (vec == 1 && band != 0) continue;   // one node per thread: eighths only
+                lbvp_status st = LBVP_OK;
+                if (s.size() == 1) {
+                    st = lbvp_set_launch(s[0], vec, block);
+                    if (st == LBVP_OK) st = lbvp_set_tile_band(s[0], band);
+                } else {
+                    st = lbvp_batch_create(s.data(), (int32_t)s.size(), vec, block, &b);
+                    if (st == LBVP_OK) st = lbvp_batch_set_tile_band(b, band);
+                }
+                if (st != LBVP_OK) return finish(st, "launch shape: " + (s.size() == 1 ? s[0]->err : g_batch_error));
+                auto run = [&](int64_t k) { return b ? lbvp_batch_step(b, k, 0) : lbvp_step(s[0], k, 0); };
+                double best = 1e300;
+                st = run(std::max(2, steps / 4));
                 for (lbvp_ctx* x : s) x->rec_tail = x->rec_head;   // records are not needed
+                for (int rep = 0; rep < 3 && st == LBVP_OK; ++rep) {
+                    if (hipEventRecord(e0, stream) != hipSuccess) return finish(LBVP_E_DEVICE, "hipEventRecord");
+                    st = run(steps);
+                    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                        return finish(LBVP_E_DEVICE, "timing events failed");
+                    float ms = 0.0f;
+                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return finish(LBVP_E_DEVICE, "hipEventElapsedTime");
+                    best = std::min(best, (double)ms);
+                    for (lbvp_ctx* x : s) x->rec_tail = x->rec_head;   // records are not needed
+                }
+                if (st != LBVP_OK) return finish(st, "timed steps failed");
+                if (b) {
+                    lbvp_batch_destroy(b);
+                    b = nullptr;
+                }
+                lbvp_tune_row r{};
+                r.layout_flags = layout;
+                r.vec = vec;
+                r.block = block;
+                r.band = band;
+                r.ms_per_step = best / steps;
+                r.mlups = nodes * steps / (best * 1e3);
+                rows.push_back(r);
             }
-            if (st != LBVP_OK) return finish(st, "timed steps failed");
-            if (b) {
-                lbvp_batch_destroy(b);
-                b = nullptr;
-            }
-            lbvp_tune_row r{};
-            r.layout_flags = layout;
-            r.vec = vec;
-            r.block = block;
-            r.ms_per_step = best / steps;
-            r.mlups = nodes * steps / (best * 1e3);
-            rows.push_back(r);
-        }
     return finish(LBVP_OK, "");
 }
 
@@ -1125,7 +1139,8 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
     for (int64_t k = 0; k < n; ++k)
         if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
 
-    std::vector<char> table = body_table_bytes<double>(bodies, n_bodies, L.max_bodies);
+    std::vector<char> table = c->is_f64() ? body_table_bytes<double>(bodies, n_bodies, L.max_bodies)
+                                          : body_table_bytes<float>(bodies, n_bodies, L.max_bodies);
     if (c->moving() && n_bodies > MAX_MOVING) return c->fail(LBVP_E_ARG, "moving bodies: at most 8");
     c->graphs.clear(c->stream);
     c->mask_host.assign(body_id, body_id + n);

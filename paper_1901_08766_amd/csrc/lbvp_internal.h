@@ -20,6 +20,11 @@ constexpr int N_XCD = 8;
 constexpr int MAX_BLOCK = 256;
 constexpr int MIN_BLOCK = 64;
 constexpr int MAX_TILE_BAND = 1 << 16;
+// Body table row: the centre split into its nearest integer and the remainder
+// (cx_int, cy_int, cx_frac, cy_frac), then vx, vy, omega, all in the arithmetic
+// type: x - c is then (x - c_int) - c_frac, exact up to one rounding of a
+// remainder of at most 1/2, at any coordinate below 2^24.
+constexpr int BODY_STRIDE = 7;
 constexpr int FIN_THREADS = 256;
 constexpr int MAX_MOVING = 8;       // bodies of a domain with moving masks
 constexpr int POSE_STRIDE = 8;      // doubles per body pose row
@@ -70,7 +75,7 @@ struct StepArgs {
     R fbx18, fby18;     // 18 F_b: the body-force half step in units of 36 j
     R feq_in[9];        // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side
     const uint8_t* mask;
-    const double* bodies;   // [(n_bodies + 1)][5] (cx, cy, vx, vy, omega), FP64 for every storage type; row 0 all zero
+    const R* bodies;    // [(n_bodies + 1)][BODY_STRIDE] (body_table_bytes); row 0 all zero (fluid)
     const int32_t* tile_slot_ptr;   // [n_tiles + 1]
     const int32_t* slot_body;       // [n_slots]
     double* slot_force;             // [2][n_slots][2]

@@ -79,20 +79,21 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     // volume penalization (eqs. d-V, force-density) on solid nodes only
     R fvx = R(0), fvy = R(0);
     if (body) {
-        const double* B = a.bodies + 5 * body;
-        double bcx = B[0], bcy = B[1];            // the body's centre, at time t if it moves
+        const R* B = a.bodies + BODY_STRIDE * body;
+        // x - c from the split centre (a centre rounded to FP32 whole would be off
+        // by up to half an FP32 spacing, 1/512 node near x = 32768, the same for
+        // every node of the body); a moving body's centre at time t is FP64
+        R rx, ry;
         if constexpr (MOVING) {
             const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
-            bcx = m[2];
-            bcy = m[3];
+            rx = (R)((double)i - m[2]);
+            ry = (R)((double)j - m[3]);
+        } else {
+            rx = ((R)i - B[0]) - B[2];
+            ry = ((R)j - B[1]) - B[3];
         }
-        // the offset from the centre is formed in FP64 and rounded once: a centre
-        // rounded to FP32 first would be off by up to half an FP32 spacing (1/512
-        // node near x = 32768), the same for every node of the body
-        const R rx = (R)((double)i - bcx), ry = (R)((double)j - bcy);
-        const R om = (R)B[4];
-        const R uox = (R)B[2] - om * ry;
-        const R uoy = (R)B[3] + om * rx;
+        const R uox = B[4] - B[6] * ry;
+        const R uoy = B[5] + B[6] * rx;
         const R dux = a.vp_c * (uox - ux);
         const R duy = a.vp_c * (uoy - uy);
         fvx = R(2) * rho * dux;

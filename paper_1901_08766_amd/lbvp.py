@@ -72,7 +72,7 @@ class lbvp_body(C.Structure):
 
 
 class lbvp_tune_row(C.Structure):
-    _fields_ = [("layout_flags", C.c_uint32), ("vec", C.c_int32), ("block", C.c_int32),
+    _fields_ = [("layout_flags", C.c_uint32), ("vec", C.c_int32), ("block", C.c_int32), ("band", C.c_int32),
                 ("ms_per_step", C.c_double), ("mlups", C.c_double)]
 
 
@@ -368,8 +368,8 @@ def lbvp_tune(ctxs, steps: int, flags: int = 0):
     st = _L.lbvp_tune(arr, len(ctxs), int(steps), int(flags), rows, cap, C.byref(n), C.byref(best))
     if st != OK:
         raise LbvpError(st, lbvp_tune_last_error())
-    out = [{"layout_flags": r.layout_flags, "vec": r.vec, "block": r.block, "ms_per_step": r.ms_per_step,
-            "mlups": r.mlups} for r in rows[: min(n.value, cap)]]
+    out = [{"layout_flags": r.layout_flags, "vec": r.vec, "block": r.block, "band": r.band,
+            "ms_per_step": r.ms_per_step, "mlups": r.mlups} for r in rows[: min(n.value, cap)]]
     return out, best.value
 
 

@@ -129,8 +129,10 @@ def test_tuner_measures_every_shape_and_leaves_members_alone(lbvp):
         m.step(5)
     before = [m.populations() for m in members]
     rows, best = lbvp.tune(members, steps=20, layouts=True, fresh=True)
-    shapes = {(r["layout_flags"], r["vec"], r["block"]) for r in rows}
-    assert shapes == {(l, v, b) for l in (0, lbvp.LAYOUT_AA) for v in (1, 4) for b in (64, 128, 256)}
+    shapes = {(r["layout_flags"], r["vec"], r["block"], r["band"]) for r in rows}
+    assert len(shapes) == len(rows)
+    assert shapes == {(l, v, b, t) for l in (0, lbvp.LAYOUT_AA) for v in (1, 4) for b in (64, 128, 256)
+                      for t in ((0,) if v == 1 else (0, 2, 16))}
     assert all(r["ms_per_step"] > 0 and r["mlups"] > 0 for r in rows)
     fastest = min(r["ms_per_step"] for r in rows)
     assert best["ms_per_step"] <= 1.03 * fastest + 1e-12
@@ -141,6 +143,7 @@ def test_tuner_measures_every_shape_and_leaves_members_alone(lbvp):
     for m in members:
         m.forces()                                                  # drained: the shape may change
     batch = lbvp.Batch(members, vec=best["vec"], block=best["block"])
+    batch.set_tile_band(best["band"])
     batch.step(3)
     batch.close()
 
