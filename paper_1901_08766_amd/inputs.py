@@ -472,18 +472,26 @@ def huge_domain(nx: int = 32768, ny: int = 16384, seed: int = 8, n_disks: int = 
                    body_force=(2e-5, -1e-5), mask=mask, bodies=np.array(rows), u_ref=u, l_ref=1.0)
 
 
+def _nearest_image(c: np.ndarray, lo: int, n: int, period: int) -> np.ndarray:
+    """Coordinates c relative to a cut starting at lo, taken at the periodic image
+    nearest the cut's middle (a body past the wrap of the axis keeps its offsets
+    to its own nodes)."""
+    rel = c - lo
+    return rel - period * np.round((rel - 0.5 * (n - 1)) / period)
+
+
 def rows_band(p: Problem, j0: int, n: int) -> Problem:
     """Rows j0 .. j0 + n - 1 (taken modulo ny) of a problem as a problem of their
-    own, periodic along y over the n rows, body centres moved by -j0 along y. A
-    node update in the middle row of a 3-row band reads that band only (the y
-    sides are periodic)."""
+    own, periodic along y over the n rows, each body centre moved to band
+    coordinates at its image nearest the band. A node update in the interior
+    rows of a band reads that band only (the y sides are periodic)."""
     rs = [(j0 + s) % p.ny for s in range(n)]
 
     def cut(a):
         return None if a is None else np.ascontiguousarray(a[rs])
 
     b = p.bodies_or_empty().copy()
-    b[:, 1] -= j0
+    b[:, 1] = _nearest_image(b[:, 1], j0, n, p.ny)
     return dataclasses.replace(p, name=f"{p.name}_rows{j0}+{n}", ny=n, mask=cut(p.mask_or_empty()),
                                bodies=b if b.shape[0] else None, rho_init=cut(p.rho_init),
                                ux_init=cut(p.ux_init), uy_init=cut(p.uy_init))

@@ -262,16 +262,18 @@ def plate_channel(nz: int = 24, nxy: int = 4, wall: int = 2, fx: float = 1e-6, t
 
 def slab(p: Problem3, k0: int, n: int) -> Problem3:
     """Planes k0 .. k0 + n - 1 (taken modulo nz) of a problem as a problem of their
-    own, periodic along z over the n planes, with the body centres moved by -k0
-    along z. A node update in the middle plane of a 3-plane slab reads that slab
-    only. The initial fields are cut the same way."""
+    own, periodic along z over the n planes, with each body centre moved to slab
+    coordinates at its image nearest the slab. A node update in the middle plane
+    of a 3-plane slab reads that slab only. The initial fields are cut the same
+    way."""
     ks = [(k0 + s) % p.nz for s in range(n)]
 
     def cut(a):
         return None if a is None else np.ascontiguousarray(a[ks])
 
     b = p.bodies_or_empty().copy()
-    b[:, 2] -= k0
+    rel = b[:, 2] - k0                                  # the centre's image nearest the slab
+    b[:, 2] = rel - p.nz * np.round((rel - 0.5 * (n - 1)) / p.nz)
     return Problem3(name=f"{p.name}_slab{k0}+{n}", nx=p.nx, ny=p.ny, nz=n, tau_plus=p.tau_plus,
                     magic_lambda=p.magic_lambda, eta=p.eta, rho0=p.rho0, bc=p.bc, rho_in=p.rho_in, u_in=p.u_in,
                     body_force=p.body_force, mask=cut(p.mask_or_empty()), bodies=b if b.shape[0] else None,
