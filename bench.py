@@ -182,6 +182,22 @@ def time_slabs(n_slabs: int, steps: int = 100, storage: str = "f32"):
     best1 = min(ms1, ms1g)
     out["one_slab_MLUPS"] = round(w * prob.ny / (best1 * 1e-3) / 1e6, 1)
     out["projected_n_gpu_MLUPS"] = round(n_slabs * w * prob.ny / (best1 * 1e-3) / 1e6, 1)
+    # weak scaling: every GPU holds a slab as large as the whole domain here, closed
+    # on itself through its own exchange (its two cuts' transfers)
+    big = inputs.split_x(dataclasses.replace(prob, bc=("periodic", "periodic", "periodic", "periodic")),
+                         [prob.nx])[0]
+    full = lbvp.Slabs(big, [0], storage=storage, force_every=1, force_capacity=steps + 16)
+    full.step(5)
+    full.forces()
+    full.step(steps, graph=True)
+    full.forces()
+    msw = _timed(full.stream, lambda: full.step(steps, graph=True)) / steps
+    full.forces()
+    full.close()
+    torch.cuda.empty_cache()
+    out["weak_slab"] = f"{prob.nx}x{prob.ny} per GPU"
+    out["weak_slab_ms_per_step"] = round(msw, 4)
+    out["projected_n_gpu_weak_MLUPS"] = round(n_slabs * nodes / (msw * 1e-3) / 1e6, 1)
     return out
 
 
