@@ -228,6 +228,56 @@ def test_edge_cases(lbvp3):
     assert np.abs(s.populations(1, 1) - h).max() <= 1e-7
 
 
+W19 = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def test_fp16_full_size_sampled(lbvp3, ref3):
+    """The 512 x 256 x 256 sphere domain in the FP16 launch configuration the
+    benchmark times: after 20 GPU steps the oracle advances the GPU's own
+    (decoded) state by one step on 3-plane slabs at sampled nodes. Fields to FP32
+    rounding; stored populations within FP16 rounding of the exact step,
+    |g - g_ref| <= w (|h_ref| u + 2e-6) with u = 2^-11. The inflow column pulls
+    the storage-rounded inflow equilibrium, so there the bounds add the entering
+    populations' rounding carried through the collision, as in the 2-D test
+    (w 8 u max|h_in| for populations, twice S = u sum |f_in,a - w_a rho0| for
+    the fields)."""
+    prob = inputs3.sphere()
+    nx, ny, nz = prob.nx, prob.ny, prob.nz
+    gpu = lbvp3.Solver3(prob, storage="f16", force_every=1, force_capacity=64)
+    print(f"case {prob.name} f16 launch={gpu.launch} band={gpu.tile_band}", flush=True)
+    gpu.step(20)
+    gpu.forces()
+    ks_solid = np.nonzero(prob.mask.any(axis=(1, 2)))[0]
+    planes = [0, nz - 1, int(ks_solid.min()), (int(ks_solid.min()) + int(ks_solid.max())) // 2]
+    g20 = {k: np.concatenate([gpu.populations((k + d) % nz, 1) for d in (-1, 0, 1)], axis=1) for k in planes}
+    gpu.step(1, keep_fields=True)
+    rng = np.random.Generator(np.random.PCG64(97))
+    u = 2.0 ** -11
+    f_in = ref3.feq(prob.rho_in, prob.u_in)
+    h_in = np.abs(f_in / W19 - prob.rho0).max()
+    ex = ref3.lattice()[0]
+    s_in = u * np.abs(f_in - W19 * prob.rho0)[ex == 1].sum()
+    worst = 0.0
+    for k in planes:
+        g21 = gpu.populations(k, 1)[:, 0]
+        fl = gpu.fields(k, 1)
+        ref = ref3.RefSolver3(inputs3.slab(prob, k - 1, 3))
+        ys_s, xs_s = np.nonzero(prob.mask[k])
+        xs = np.concatenate([np.zeros(32, int), np.full(32, nx - 1), rng.integers(0, nx, 256), xs_s])
+        ys = np.concatenate([rng.integers(0, ny, 32), rng.integers(0, ny, 32), rng.integers(0, ny, 256), ys_s])
+        gout, rfl = ref.step_nodes(g20[k], xs, ys, np.ones_like(xs))
+        ref.close()
+        inflow = (xs == 0)[:, None]
+        bound = W19 * (np.abs(gout / W19 - prob.rho0) * u + 2e-6 + np.where(inflow, 8.0 * u * h_in, 0.0))
+        err = np.abs(g21[:, ys, xs].T - gout)
+        worst = max(worst, float((err / bound).max()))
+        assert np.all(err <= bound), (k, float((err / bound).max()))
+        field_tol = 2e-6 + np.where(xs == 0, 2.0 * s_in, 0.0)
+        for q, name in enumerate(("rho", "ux", "uy", "uz", "fx", "fy", "fz")):
+            assert np.all(np.abs(fl[name][0, ys, xs] - rfl[:, q]) <= field_tol), (k, name)
+    print(f"f16: worst population error / bound = {worst:.3f}", flush=True)
+
+
 def test_fp32_full_size_sampled(lbvp3, ref3):
     """The 512 x 256 x 256 sphere domain in the launch configuration the benchmark
     times: after 20 GPU steps the oracle advances the GPU's state by one step at

@@ -165,6 +165,69 @@ def test_fp32_full_size_sampled(lbvp, oracle):
         assert abs(gf[0, b - 1, 0] - fx) <= 1e-5 * mag and abs(gf[0, b - 1, 1] - fy) <= 1e-5 * mag
 
 
+# significand bits of the 2-byte storage types: round-to-nearest-even puts a
+# stored deviation within |h| 2^-(bits+1) of the computed one
+STORAGE_BITS = {"f16": 10, "bf16": 7}
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_reduced_storage_full_size_sampled(lbvp, oracle, storage):
+    """The 8192 x 4096 domain in the launch configuration the benchmark times for
+    the 2-byte storage types: after 20 GPU steps the oracle advances the GPU's
+    own (decoded) state by one step at sampled nodes. The GPU's fields of that
+    step, computed in FP32 from the same stored values, must match to FP32
+    rounding; its stored populations must lie within the storage type's rounding
+    of the exact step: |g - g_ref| <= w (|h_ref| u + 2e-6), with h the
+    weight-normalized deviation g/w - rho0 and u = 2^-(bits+1). Nodes of the
+    inflow column pull the inflow equilibrium rounded to the storage type (the
+    inflow ghost is a stored population like any other), so three of their
+    inputs already differ from the oracle's by up to w_a |h_in| u; the collision
+    carries input errors into each output with a gain below 8 (to first order
+    1 + omega+ on the population itself, plus omega+ + omega- times the
+    equilibrium's sensitivity to rho and j, together < 4.2 here), so there the
+    bound adds w 8 u max|h_in|; and their fields, formed from those inputs, may
+    move by the entering errors' sum S = u sum |f_in,a - w_a rho0| (rho and j;
+    twice that is allowed)."""
+    prob = inputs.large_domain()
+    gpu = lbvp.Solver(prob, storage=storage, force_every=1, force_capacity=64)
+    print(f"case {prob.name} storage={storage} launch={gpu.launch} band={gpu.tile_band}", flush=True)
+    gpu.step(20)
+    gpu.forces()
+    g20 = gpu.populations()
+    gpu.step(1, keep_fields=True)
+    g21 = gpu.populations()
+    fl = gpu.fields()
+    rng = np.random.Generator(np.random.PCG64(98))
+    nx, ny = prob.nx, prob.ny
+    ys_s, xs_s = np.nonzero(prob.mask)
+    pick = rng.choice(len(xs_s), 4096, replace=False)
+    xs = np.concatenate([np.zeros(64, int), np.full(64, nx - 1), rng.integers(0, nx, 64), rng.integers(0, nx, 64),
+                         rng.integers(0, nx, 4096), xs_s[pick]])
+    ys = np.concatenate([rng.integers(0, ny, 64), rng.integers(0, ny, 64), np.zeros(64, int), np.full(64, ny - 1),
+                         rng.integers(0, ny, 4096), ys_s[pick]])
+    ref = oracle.RefSolver(prob)
+    gout, rfl = ref.step_nodes(g20, xs, ys)
+    ref.close()
+    h_ref = gout / W9 - prob.rho0
+    u = 2.0 ** -(STORAGE_BITS[storage] + 1)
+    f_in = oracle.feq(prob.rho_in, *prob.u_in)
+    h_in = np.abs(f_in / W9 - prob.rho0).max()
+    bound = W9 * (np.abs(h_ref) * u + 2e-6 + np.where(xs == 0, 8.0 * u * h_in, 0.0)[:, None])
+    ex = oracle.lattice()[0]
+    s_in = u * np.abs(f_in - W9 * prob.rho0)[ex == 1].sum()
+    field_tol = 2e-6 + np.where(xs == 0, 2.0 * s_in, 0.0)
+    err = np.abs(g21[:, ys, xs].T - gout)
+    ratio = err / bound
+    worst = np.argsort(ratio.max(axis=1))[::-1][:8]
+    print(f"{storage}: worst population error / bound = {ratio.max():.3f} at (x, y, q, ratio) "
+          f"{[(int(xs[n]), int(ys[n]), int(ratio[n].argmax()), round(float(ratio[n].max()), 3)) for n in worst]}",
+          flush=True)
+    assert np.all(err <= bound)
+    for q, k in enumerate(("rho", "ux", "uy", "fx", "fy")):
+        assert np.all(np.abs(fl[k][ys, xs] - rfl[:, q]) <= field_tol), k
+
+
 def test_deterministic_rerun(lbvp):
     """Two runs of the same problem are bitwise identical (fixed-order reductions)."""
     prob = inputs.random_state_problem(300, 77, seed=21, n_disks=4)
