@@ -278,16 +278,23 @@ def test_fp16_full_size_sampled(lbvp3, ref3):
     print(f"f16: worst population error / bound = {worst:.3f}", flush=True)
 
 
-def test_fp32_full_size_sampled(lbvp3, ref3):
+# (populations, fields, force relative to its magnitude) of one step from the GPU's state
+FULL_SIZE_TOL = {"f32": (1e-6, 2e-6, 1e-5), "f64": (1e-13, 1e-13, 1e-11)}
+
+
+@pytest.mark.parametrize("storage", ["f32", "f64"])
+def test_full_size_sampled(lbvp3, ref3, storage):
     """The 512 x 256 x 256 sphere domain in the launch configuration the benchmark
     times: after 20 GPU steps the oracle advances the GPU's state by one step at
     sampled nodes (the periodic z planes 0 and nz - 1, the x sides, every solid
-    node, random fluid nodes), and that must equal the GPU's next state to FP32
-    rounding; the recorded force of that step must equal the oracle's sum."""
+    node, random fluid nodes), and that must equal the GPU's next state to the
+    arithmetic type's rounding; the recorded force of that step must equal the
+    oracle's sum."""
+    tol_g, tol_f, tol_force = FULL_SIZE_TOL[storage]
     prob = inputs3.sphere()
     nx, ny, nz = prob.nx, prob.ny, prob.nz
-    gpu = lbvp3.Solver3(prob, storage="f32", force_every=1, force_capacity=64)
-    print(f"case {prob.name} launch={gpu.launch}", flush=True)
+    gpu = lbvp3.Solver3(prob, storage=storage, force_every=1, force_capacity=64)
+    print(f"case {prob.name} {storage} launch={gpu.launch} band={gpu.tile_band}", flush=True)
     gpu.step(20)
     gpu.forces()
     ks_solid = np.nonzero(prob.mask.any(axis=(1, 2)))[0]
@@ -311,10 +318,10 @@ def test_fp32_full_size_sampled(lbvp3, ref3):
         xs = np.concatenate([np.zeros(32, int), np.full(32, nx - 1), rng.integers(0, nx, 256), xs_s])
         ys = np.concatenate([rng.integers(0, ny, 32), rng.integers(0, ny, 32), rng.integers(0, ny, 256), ys_s])
         gout, rfl = ref.step_nodes(ref.populations(), xs, ys, np.ones_like(xs))
-        assert np.abs(g21[:, ys, xs].T - gout).max() <= 1e-6, k
+        assert np.abs(g21[:, ys, xs].T - gout).max() <= tol_g, k
         for q, name in enumerate(("rho", "ux", "uy", "uz", "fx", "fy", "fz")):
-            assert np.abs(fl[name][0, ys, xs] - rfl[:, q]).max() <= 2e-6, (k, name)
+            assert np.abs(fl[name][0, ys, xs] - rfl[:, q]).max() <= tol_f, (k, name)
         solid = slice(len(xs) - len(xs_s), len(xs))
         fsum -= rfl[solid, 4:7].sum(axis=0)
         fmag += np.abs(rfl[solid, 4:7]).sum()
-    assert np.all(np.abs(gf[0, 0] - fsum) <= 1e-5 * fmag)
+    assert np.all(np.abs(gf[0, 0] - fsum) <= tol_force * fmag)
