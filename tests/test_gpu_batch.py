@@ -143,3 +143,42 @@ def test_ensemble_batch_runs(lbvp):
             assert np.all(np.isfinite(f)) and np.all(np.isfinite(mass))
             assert abs(mass[-1] / (p.nx * p.ny) - 1) < 0.05
         batch.close()
+
+
+@pytest.mark.parametrize("storage,launch,band,tol", [("f32", (4, 64), 2, 1e-6), ("f32", (1, 256), 0, 1e-6),
+                                                     ("f64", (2, 128), 2, 1e-13)],
+                         ids=["f32-v4b64-band2", "f32-v1b256", "f64-v2b128-band2"])
+def test_full_ensemble_sampled(lbvp, oracle, storage, launch, band, tol):
+    """All 256 domains of the ensemble (44.2 M nodes) in one batch, in launch
+    forms the tuner picks for it: after 20 batched steps the oracle advances
+    three members' own states by one step at every node (the smallest, the
+    largest and one in the middle of the tile list), which must equal the
+    batched step to the arithmetic type's rounding, fields included."""
+    probs = inputs.ensemble(256)
+    stream = torch.cuda.Stream()
+    members = [lbvp.Solver(p, storage=storage, force_every=1, force_capacity=64, stream=stream) for p in probs]
+    batch = lbvp.Batch(members, vec=launch[0], block=launch[1])
+    batch.set_tile_band(band)
+    print(f"ensemble {storage} launch={launch} band={band}", flush=True)
+    batch.step(20)
+    sizes = [p.nx * p.ny for p in probs]
+    picks = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), len(probs) // 2})
+    g20 = {d: members[d].populations() for d in picks}
+    batch.step(1, keep_fields=True)
+    for d in picks:
+        p = probs[d]
+        ref = oracle.RefSolver(p)
+        ys, xs = np.meshgrid(np.arange(p.ny), np.arange(p.nx), indexing="ij")
+        xs, ys = xs.ravel(), ys.ravel()
+        gout, rfl = ref.step_nodes(g20[d], xs, ys)
+        ref.close()
+        g21 = members[d].populations()
+        fl = members[d].fields()
+        assert np.abs(g21[:, ys, xs].T - gout).max() <= tol, d
+        for q, k in enumerate(("rho", "ux", "uy", "fx", "fy")):
+            assert np.abs(fl[k][ys, xs] - rfl[:, q]).max() <= 2 * tol, (d, k)
+    batch.close()
+    for m in members:
+        m.forces()
+        m.close()
+    torch.cuda.empty_cache()
