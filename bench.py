@@ -569,7 +569,7 @@ def main():
     ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_NODE))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--variants", default="f16,bf16",
+    ap.add_argument("--variants", default="f16,bf16,f64",
                     help="other storage types to time as extra fields ('' for none)")
     ap.add_argument("--ensemble-steps", type=int, default=300,
                     help="batched steps of the 256-domain ensemble comparison (0: skip it)")
