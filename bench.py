@@ -543,8 +543,19 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
              "algorithmic_read_bytes": alg_read, "algorithmic_write_bytes": alg_write,
              "fetch_over_algorithmic": round(fetch_b / alg_read, 4),
              "write_over_algorithmic": round(write_b / alg_write, 4)}
-    data = {"kernel_source_hash": kernel_source_hash(lattice), "kernel": kernel_part, "per_storage": {storage: entry},
-            "command": command}
+    entry["kernel"] = kernel_part
+    entry["command"] = command
+    # one entry per storage type, kept while they describe the same kernel source
+    try:
+        with open(out_json) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        data = {}
+    if data.get("kernel_source_hash") != kernel_source_hash(lattice):
+        data = {"kernel_source_hash": kernel_source_hash(lattice), "per_storage": {}}
+    data.pop("kernel", None)
+    data.pop("command", None)
+    data.setdefault("per_storage", {})[storage] = entry
     with open(out_json, "w") as f:
         json.dump(data, f, indent=1)
     md = ["# HBM traffic of the step kernel (rocprofv3 PMC)", "", "Command:", "", "```", command, "```", "",
@@ -650,7 +661,7 @@ def main():
         vb = BYTES_PER_NODE[v] * nodes / (vms * 1e-3) / 1e9
         extra[v] = {"MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
                     "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok,
-                    "launch": vlaunch}
+                    "launch": vlaunch, "traffic": measured_traffic(v, nodes)}
         print(f"# {v}: {extra[v]}", file=sys.stderr, flush=True)
     traffic = measured_traffic(a.storage, nodes)
     copy_gbps = copy_bandwidth()
