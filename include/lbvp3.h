@@ -151,6 +151,19 @@ lbvp_status lbvp3_get_launch(const lbvp3_ctx* ctx, int32_t* vec, int32_t* block)
 lbvp_status lbvp3_set_tile_band(lbvp3_ctx* ctx, int32_t band);
 lbvp_status lbvp3_get_tile_band(const lbvp3_ctx* ctx, int32_t* band);
 
+/* Checkpoint and resume, as lbvp_save_state / lbvp_load_state for the 2-D step:
+ * lbvp3_save_state writes the context's exact state (the current lattice as
+ * stored, the mask and bodies, the fields, the step and record counters) into a
+ * caller-allocated host buffer; *size gets the bytes needed, and with buf NULL
+ * or cap too small nothing is written and E_NOMEM is returned. E_STATE if force
+ * records are undrained (call lbvp3_forces first). lbvp3_load_state restores
+ * such a state into a context of the same grid and storage type (launch shape,
+ * tile band and parameters are the context's own): stepping it gives bitwise
+ * the results the saved context would have given. E_ARG for another grid or
+ * storage type, too many bodies, or a damaged blob. Both synchronize the stream. */
+lbvp_status lbvp3_save_state(lbvp3_ctx* ctx, void* buf, size_t cap, size_t* size);
+lbvp_status lbvp3_load_state(lbvp3_ctx* ctx, const void* buf, size_t size);
+
 /* Steps taken since the last init; -1 for a NULL context. */
 int64_t lbvp3_step_count(const lbvp3_ctx* ctx);
 

@@ -194,6 +194,7 @@ struct lbvp3_ctx {
     int32_t n_bodies = 0;
     double tau_minus = 0.0;
     std::vector<uint8_t> mask_host;   // [nz][ny][nx], kept to rebuild the tile tables
+    std::vector<lbvp3_body> bodies_host;   // the bodies as given, kept for checkpoints
     Step3Args<double> a64{};
     Step3Args<float> a32{};
     Fin3Args fin{};
@@ -354,6 +355,47 @@ Conv3Args conv_args(lbvp3_ctx* c, int32_t plane0, int32_t planes)
 
 bool bad_range(const lbvp3_ctx* c, int32_t z0, int32_t n) { return z0 < 0 || n < 0 || (int64_t)z0 + n > c->p.nz; }
 
+// Checkpoint blob: this header, then the current lattice as stored (pitched
+// rows of 19 populations), the mask ([nz][ny][nx] bytes), the bodies, the seven
+// field planes (pitched, as stored).
+struct State3Header {
+    char magic[8];
+    uint32_t version, header_bytes;
+    int32_t nx, ny, nz, storage;
+    int32_t n_bodies, cur, fields_valid, pad;
+    int64_t step, records;
+    uint64_t lat_bytes, mask_bytes, body_bytes, field_bytes;
+};
+constexpr char STATE3_MAGIC[8] = {'L', 'B', 'V', 'P', '3', 'S', 'T', 'A'};
+constexpr uint32_t STATE3_VERSION = 1;
+
+State3Header state3_header(const lbvp3_ctx* c)
+{
+    State3Header h{};
+    std::memcpy(h.magic, STATE3_MAGIC, 8);
+    h.version = STATE3_VERSION;
+    h.header_bytes = sizeof(State3Header);
+    h.nx = c->p.nx;
+    h.ny = c->p.ny;
+    h.nz = c->p.nz;
+    h.storage = c->p.storage;
+    h.n_bodies = c->n_bodies;
+    h.cur = c->cur;
+    h.fields_valid = c->fields_valid ? 1 : 0;
+    h.step = c->step;
+    h.records = c->rec_head;
+    h.lat_bytes = (uint64_t)c->L.rows * (uint64_t)c->L.lstride * storage_bytes(c->p.storage);
+    h.mask_bytes = (uint64_t)c->L.rows * (uint64_t)c->p.nx;
+    h.body_bytes = (uint64_t)c->n_bodies * sizeof(lbvp3_body);
+    h.field_bytes = 7 * (uint64_t)c->L.plane_f * c->rsize();
+    return h;
+}
+
+uint64_t state3_bytes(const State3Header& h)
+{
+    return h.header_bytes + h.lat_bytes + h.mask_bytes + h.body_bytes + h.field_bytes;
+}
+
 }  // namespace
 
 extern "C" {
@@ -451,6 +493,7 @@ lbvp_status lbvp3_set_mask(lbvp3_ctx* c, const uint8_t* body_id, int32_t n_bodie
             }
         }
     if (body_id != c->mask_host.data()) c->mask_host.assign(body_id, body_id + n);
+    c->bodies_host.assign(bodies, bodies + n_bodies);
     c->n_bodies = n_bodies;
     hipStream_t s = c->stream;
     LBVP3_HIP(c, hipMemcpy2DAsync(c->at<uint8_t>(L.mask), (size_t)L.pitch, c->mask_host.data(), (size_t)p.nx,
@@ -698,5 +741,68 @@ lbvp_status lbvp3_destroy(lbvp3_ctx* c)
 }
 
 const char* lbvp3_last_error(const lbvp3_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+lbvp_status lbvp3_save_state(lbvp3_ctx* c, void* buf, size_t cap, size_t* size)
+{
+    if (!c) return LBVP_E_ARG;
+    if (!size) return c->fail(LBVP_E_ARG, "size is NULL");
+    if (c->rec_head != c->rec_tail) return c->fail(LBVP_E_STATE, "drain the force records first");
+    const State3Header h = state3_header(c);
+    *size = (size_t)state3_bytes(h);
+    if (!buf || cap < *size) return c->fail(LBVP_E_NOMEM, "buffer too small for the state (see *size)");
+    hipStream_t s = c->stream;
+    char* o = static_cast<char*>(buf);
+    std::memcpy(o, &h, sizeof(h));
+    o += sizeof(h);
+    LBVP3_HIP(c, hipMemcpyAsync(o, c->at<char>(c->L.lat[c->cur]), h.lat_bytes, hipMemcpyDeviceToHost, s));
+    o += h.lat_bytes;
+    LBVP3_HIP(c, hipMemcpyAsync(o + h.mask_bytes + h.body_bytes, c->at<char>(c->L.fields), h.field_bytes,
+                                hipMemcpyDeviceToHost, s));
+    std::memcpy(o, c->mask_host.data(), h.mask_bytes);
+    o += h.mask_bytes;
+    if (h.body_bytes) std::memcpy(o, c->bodies_host.data(), h.body_bytes);
+    LBVP3_HIP(c, hipStreamSynchronize(s));
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_load_state(lbvp3_ctx* c, const void* buf, size_t size)
+{
+    if (!c) return LBVP_E_ARG;
+    if (!buf || size < sizeof(State3Header)) return c->fail(LBVP_E_ARG, "not a state blob");
+    State3Header h;
+    std::memcpy(&h, buf, sizeof(h));
+    const State3Header mine = state3_header(c);
+    if (std::memcmp(h.magic, STATE3_MAGIC, 8) != 0 || h.version != STATE3_VERSION || h.header_bytes != sizeof(h))
+        return c->fail(LBVP_E_ARG, "not a D3Q19 state blob of this version");
+    if (h.nx != mine.nx || h.ny != mine.ny || h.nz != mine.nz || h.storage != mine.storage)
+        return c->fail(LBVP_E_ARG, "the state is of another grid or storage type");
+    if (h.n_bodies < 0 || h.n_bodies > c->L.max_bodies)
+        return c->fail(LBVP_E_ARG, "the state holds more bodies than max_bodies");
+    if (h.cur < 0 || h.cur > 1 || h.step < 0 || h.records < 0) return c->fail(LBVP_E_ARG, "damaged state counters");
+    if (h.lat_bytes != mine.lat_bytes || h.mask_bytes != mine.mask_bytes ||
+        h.body_bytes != (uint64_t)h.n_bodies * sizeof(lbvp3_body) || h.field_bytes != mine.field_bytes ||
+        size < state3_bytes(h))
+        return c->fail(LBVP_E_ARG, "damaged state sizes");
+    const char* lat = static_cast<const char*>(buf) + sizeof(h);
+    const uint8_t* mask = reinterpret_cast<const uint8_t*>(lat + h.lat_bytes);
+    std::vector<lbvp3_body> bodies((size_t)h.n_bodies);
+    if (h.body_bytes) std::memcpy(bodies.data(), mask + h.mask_bytes, h.body_bytes);
+    const char* fields = reinterpret_cast<const char*>(mask) + h.mask_bytes + h.body_bytes;
+    const lbvp_status st = lbvp3_set_mask(c, mask, h.n_bodies, bodies.data());   // validates, synchronizes
+    if (st != LBVP_OK) return st;
+    hipStream_t s = c->stream;
+    const int64_t records = h.records;
+    LBVP3_HIP(c, hipMemcpyAsync(c->at<char>(c->L.lat[h.cur]), lat, h.lat_bytes, hipMemcpyHostToDevice, s));
+    LBVP3_HIP(c, hipMemcpyAsync(c->at<char>(c->L.fields), fields, h.field_bytes, hipMemcpyHostToDevice, s));
+    LBVP3_HIP(c, hipMemcpyAsync(c->fin.rec_count, &records, sizeof(records), hipMemcpyHostToDevice, s));
+    LBVP3_HIP(c, launch_zero_i64(c->fin.arrivals, s));
+    LBVP3_HIP(c, hipStreamSynchronize(s));
+    c->cur = h.cur;
+    c->step = h.step;
+    c->rec_head = c->rec_tail = h.records;
+    c->pending = false;
+    c->fields_valid = h.fields_valid != 0;
+    return LBVP_OK;
+}
 
 }  // extern "C"

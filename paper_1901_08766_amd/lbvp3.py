@@ -21,7 +21,7 @@ FIELD_NAMES = ("rho", "ux", "uy", "uz", "fx", "fy", "fz")
 SYMBOLS = ["lbvp3_footprint_bytes", "lbvp3_create", "lbvp3_set_mask", "lbvp3_init_equilibrium", "lbvp3_step",
            "lbvp3_forces", "lbvp3_read_fields", "lbvp3_read_populations", "lbvp3_write_populations",
            "lbvp3_set_launch", "lbvp3_get_launch", "lbvp3_set_tile_band", "lbvp3_get_tile_band",
-           "lbvp3_step_count", "lbvp3_synchronize", "lbvp3_destroy",
+           "lbvp3_step_count", "lbvp3_synchronize", "lbvp3_destroy", "lbvp3_save_state", "lbvp3_load_state",
            "lbvp3_last_error"]
 NO_STATUS = ("lbvp3_footprint_bytes", "lbvp3_step_count", "lbvp3_last_error")
 
@@ -56,6 +56,8 @@ def _load():
     L.lbvp3_set_launch.argtypes = [vp, i32, i32]
     L.lbvp3_get_launch.argtypes = [vp, C.POINTER(i32), C.POINTER(i32)]
     L.lbvp3_set_tile_band.argtypes = [vp, i32]
+    L.lbvp3_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
+    L.lbvp3_load_state.argtypes = [vp, vp, C.c_size_t]
     L.lbvp3_get_tile_band.argtypes = [vp, C.POINTER(i32)]
     L.lbvp3_step_count.restype = i64
     L.lbvp3_step_count.argtypes = [vp]
@@ -166,6 +168,23 @@ def lbvp3_get_tile_band(ctx) -> int:
     return b.value
 
 
+def lbvp3_save_state(ctx) -> np.ndarray:
+    """The context's state as a byte array (see lbvp3_save_state)."""
+    size = C.c_size_t()
+    st = _L.lbvp3_save_state(ctx, None, 0, C.byref(size))
+    if st not in (OK, E_NOMEM):
+        _check(ctx, st)
+    buf = np.empty(size.value, dtype=np.uint8)
+    _check(ctx, _L.lbvp3_save_state(ctx, buf.ctypes.data_as(C.c_void_p), buf.nbytes, C.byref(size)))
+    return buf
+
+
+def lbvp3_load_state(ctx, blob):
+    blob = np.ascontiguousarray(np.frombuffer(blob, dtype=np.uint8) if isinstance(blob, (bytes, bytearray)) else blob,
+                                dtype=np.uint8)
+    _check(ctx, _L.lbvp3_load_state(ctx, blob.ctypes.data_as(C.c_void_p), blob.nbytes))
+
+
 def lbvp3_step_count(ctx) -> int:
     return int(_L.lbvp3_step_count(ctx))
 
@@ -244,6 +263,12 @@ class Solver3:
 
     def set_launch(self, vec: int, block: int):
         lbvp3_set_launch(self.ctx, vec, block)
+
+    def save_state(self) -> np.ndarray:
+        return lbvp3_save_state(self.ctx)
+
+    def load_state(self, blob):
+        lbvp3_load_state(self.ctx, blob)
 
     @property
     def tile_band(self) -> int:

@@ -325,3 +325,56 @@ def test_full_size_sampled(lbvp3, ref3, storage):
         fsum -= rfl[solid, 4:7].sum(axis=0)
         fmag += np.abs(rfl[solid, 4:7]).sum()
     assert np.all(np.abs(gf[0, 0] - fsum) <= tol_force * fmag)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_checkpoint_resume_bitwise(lbvp3, storage):
+    """A state saved after 13 steps and loaded into another context of the same
+    problem (one that had stepped elsewhere) continues bitwise like the saved
+    one: fields at the checkpoint, then populations, fields and force and mass
+    records after 11 more steps."""
+    prob = inputs3.random_state_problem3(40, 24, 20, seed=3, n_spheres=3, body_force=(1e-5, 0.0, -2e-6))
+    a = lbvp3.Solver3(prob, storage=storage, force_every=1, force_capacity=64)
+    a.step(13, keep_fields=True)
+    a.forces()
+    fields13 = a.fields()
+    blob = a.save_state()
+    a.step(11, keep_fields=True)
+    ra = a.forces()
+    b = lbvp3.Solver3(prob, storage=storage, force_every=1, force_capacity=64)
+    b.step(5)
+    b.forces()
+    b.load_state(blob)
+    assert b.step_count == 13
+    for k, v in b.fields().items():
+        assert np.array_equal(v, fields13[k]), k
+    b.step(11, keep_fields=True)
+    rb = b.forces()
+    assert np.array_equal(a.populations(), b.populations())
+    fa, fb = a.fields(), b.fields()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+    assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1]) and ra[2] == rb[2] == 14
+    a.close()
+    b.close()
+
+
+def test_checkpoint_rejections(lbvp3):
+    prob = inputs3.random_state_problem3(24, 12, 10, seed=4, n_spheres=1)
+    a = lbvp3.Solver3(prob, storage="f32", force_every=1, force_capacity=64)
+    a.step(3)
+    with pytest.raises(lbvp3.LbvpError) as e:          # undrained records
+        a.save_state()
+    assert e.value.status == lbvp3.E_STATE
+    a.forces()
+    blob = a.save_state()
+    other_grid = lbvp3.Solver3(inputs3.random_state_problem3(25, 12, 10, seed=4, n_spheres=1), storage="f32")
+    other_type = lbvp3.Solver3(prob, storage="f64")
+    for ctx, bad in ((other_grid, blob), (other_type, blob), (a, blob[: len(blob) // 2]), (a, np.zeros_like(blob))):
+        with pytest.raises(lbvp3.LbvpError) as e:
+            ctx.load_state(bad)
+        assert e.value.status == lbvp3.E_ARG
+    a.load_state(blob)                                 # the intact blob still loads
+    assert a.step_count == 3
+    for s in (a, other_grid, other_type):
+        s.close()
