@@ -164,6 +164,26 @@ lbvp_status lbvp3_get_tile_band(const lbvp3_ctx* ctx, int32_t* band);
 lbvp_status lbvp3_save_state(lbvp3_ctx* ctx, void* buf, size_t cap, size_t* size);
 lbvp_status lbvp3_load_state(lbvp3_ctx* ctx, const void* buf, size_t size);
 
+/* Batches: many contexts advanced together, one launch per step over all their
+ * tiles (as lbvp_batch_* for the 2-D step). lbvp3_batch_create: members[n]
+ * (borrowed; they must outlive the batch; same storage type, stream, force_every
+ * and step count), vec / block as in lbvp3_set_launch (0: member 0's), applied
+ * to every member. lbvp3_batch_step: every member advances n_steps (flags as
+ * lbvp3_step); each member's populations, fields and force and mass records are
+ * bitwise those of the member stepped alone with the same launch shape.
+ * Asynchronous, apart from waiting for the batch's previous steps. E_STATE if a
+ * member was stepped alone or given another launch shape since, or a member's
+ * records would overflow its ring. The batch's tile band (lbvp3_batch_set_tile_band,
+ * 0 at creation) orders the tiles of all members together. */
+typedef struct lbvp3_batch lbvp3_batch;
+lbvp_status lbvp3_batch_create(lbvp3_ctx* const* members, int32_t n, int32_t vec, int32_t block,
+                               lbvp3_batch** out);
+lbvp_status lbvp3_batch_step(lbvp3_batch* batch, int64_t n_steps, uint32_t flags);
+lbvp_status lbvp3_batch_set_tile_band(lbvp3_batch* batch, int32_t band);
+lbvp_status lbvp3_batch_get_tile_band(const lbvp3_batch* batch, int32_t* band);
+lbvp_status lbvp3_batch_destroy(lbvp3_batch* batch);
+const char* lbvp3_batch_last_error(const lbvp3_batch* batch);
+
 /* Steps taken since the last init; -1 for a NULL context. */
 int64_t lbvp3_step_count(const lbvp3_ctx* ctx);
 

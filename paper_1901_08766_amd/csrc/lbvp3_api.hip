@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lbvp3.h"
@@ -215,6 +216,40 @@ struct lbvp3_ctx {
     }
 };
 
+// Contexts advanced together, one launch per step over all their tiles. The
+// members stay ordinary contexts (their records, fields and populations are read
+// through the usual calls) and step in lockstep.
+struct lbvp3_batch {
+    std::vector<lbvp3_ctx*> members;
+    hipStream_t stream = nullptr;
+    int32_t storage = 0, vec = 1, block = 256, band = 0;
+    int32_t total_tiles = 0, tiles_per_xcd = 0;
+    char* dev = nullptr;             // owned: [member images | tile_domain | tile_start]
+    size_t member_bytes = 0, off_domain = 0, off_start = 0;
+    std::vector<char> image;         // host image of the member block, as last uploaded
+    std::string err;
+
+    lbvp_status fail(lbvp_status s, const std::string& m)
+    {
+        err = m;
+        return s;
+    }
+    lbvp_status hip_fail(hipError_t e, const char* what)
+    {
+        err = std::string(what) + ": " + hipGetErrorString(e);
+        return LBVP_E_DEVICE;
+    }
+    ~lbvp3_batch()
+    {
+        if (dev) {
+            (void)hipStreamSynchronize(stream);
+            (void)hipFree(dev);
+        }
+    }
+};
+
+thread_local std::string g_batch3_error;
+
 namespace {
 
 #define LBVP3_HIP(ctx, call)                                              \
@@ -354,6 +389,24 @@ Conv3Args conv_args(lbvp3_ctx* c, int32_t plane0, int32_t planes)
 }
 
 bool bad_range(const lbvp3_ctx* c, int32_t z0, int32_t n) { return z0 < 0 || n < 0 || (int64_t)z0 + n > c->p.nz; }
+
+// The member block a batch step reads: each member's step arguments (with its
+// finalize arguments), lattices and current lattice, as now.
+template <typename R>
+void write_member_images(lbvp3_batch* b)
+{
+    for (size_t d = 0; d < b->members.size(); ++d) {
+        lbvp3_ctx* c = b->members[d];
+        Member3<R> m{};
+        if constexpr (std::is_same<R, double>::value) m.a = c->a64;
+        else m.a = c->a32;
+        m.a.fin = c->fin;
+        m.lat0 = c->at<char>(c->L.lat[0]);
+        m.lat1 = c->at<char>(c->L.lat[1]);
+        m.cur = c->cur;
+        std::memcpy(b->image.data() + d * sizeof(Member3<R>), &m, sizeof(m));
+    }
+}
 
 // Checkpoint blob: this header, then the current lattice as stored (pitched
 // rows of 19 populations), the mask ([nz][ny][nx] bytes), the bodies, the seven
@@ -804,5 +857,181 @@ lbvp_status lbvp3_load_state(lbvp3_ctx* c, const void* buf, size_t size)
     c->fields_valid = h.fields_valid != 0;
     return LBVP_OK;
 }
+
+lbvp_status lbvp3_batch_create(lbvp3_ctx* const* members, int32_t n, int32_t vec, int32_t block, lbvp3_batch** out)
+{
+    if (!out || !members || n < 1) {
+        g_batch3_error = "members, n >= 1 and out are required";
+        return LBVP_E_ARG;
+    }
+    *out = nullptr;
+    for (int32_t d = 0; d < n; ++d)
+        if (!members[d]) {
+            g_batch3_error = "a member is NULL";
+            return LBVP_E_ARG;
+        }
+    lbvp3_ctx* c0 = members[0];
+    for (int32_t d = 0; d < n; ++d) {
+        const lbvp3_ctx* c = members[d];
+        if (c->p.storage != c0->p.storage || c->stream != c0->stream || c->p.force_every != c0->p.force_every ||
+            c->step != c0->step || c->rec_head != c0->rec_head) {
+            g_batch3_error = "members differ in storage, stream, force_every or step count";
+            return LBVP_E_ARG;
+        }
+        for (int32_t e = 0; e < d; ++e)
+            if (members[e] == c) {
+                g_batch3_error = "a context appears twice";
+                return LBVP_E_ARG;
+            }
+    }
+    if (vec == 0) vec = c0->launch.vec;
+    if (block == 0) block = c0->launch.block;
+    if (!vec_supported(c0->p.storage, vec) || (block != 64 && block != 128 && block != 256)) {
+        g_batch3_error = "vec or block not built for this storage type (see lbvp3_set_launch)";
+        return LBVP_E_ARG;
+    }
+    for (int32_t d = 0; d < n; ++d) {   // every member tiled for the batch's shape
+        lbvp3_ctx* c = members[d];
+        if (c->launch.vec != vec || c->launch.block != block) {
+            const lbvp_status st = lbvp3_set_launch(c, vec, block);
+            if (st != LBVP_OK) {
+                g_batch3_error = "launch shape: " + c->err;
+                return st;
+            }
+        }
+    }
+    lbvp3_batch* b = new (std::nothrow) lbvp3_batch();
+    if (!b) {
+        g_batch3_error = "host allocation failed";
+        return LBVP_E_NOMEM;
+    }
+    b->members.assign(members, members + n);
+    b->stream = c0->stream;
+    b->storage = c0->p.storage;
+    b->vec = vec;
+    b->block = block;
+    std::vector<int32_t> tile_domain, tile_start((size_t)n);
+    for (int32_t d = 0; d < n; ++d) {
+        tile_start[d] = (int32_t)tile_domain.size();
+        tile_domain.insert(tile_domain.end(), (size_t)members[d]->launch.n_tiles, d);
+    }
+    b->total_tiles = (int32_t)tile_domain.size();
+    b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
+    b->member_bytes = (b->storage == LBVP_F64 ? sizeof(Member3<double>) : sizeof(Member3<float>)) * (size_t)n;
+    b->off_domain = align_up(b->member_bytes, 256);
+    b->off_start = align_up(b->off_domain + tile_domain.size() * 4, 256);
+    const size_t bytes = b->off_start + tile_start.size() * 4;
+    b->image.assign(b->member_bytes, 0);
+    hipError_t e = hipMalloc(&b->dev, bytes);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dev + b->off_domain, tile_domain.data(), tile_domain.size() * 4, hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dev + b->off_start, tile_start.data(), tile_start.size() * 4, hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);   // the host tables go out of scope
+    if (e != hipSuccess) {
+        g_batch3_error = std::string("device tables: ") + hipGetErrorString(e);
+        delete b;
+        return e == hipErrorOutOfMemory ? LBVP_E_NOMEM : LBVP_E_DEVICE;
+    }
+    *out = b;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
+{
+    if (!b) return LBVP_E_ARG;
+    if (n_steps < 0) return b->fail(LBVP_E_ARG, "n_steps < 0");
+    if (flags & ~KNOWN_STEP_FLAGS) return b->fail(LBVP_E_ARG, "unknown step flag");
+    if (n_steps == 0) return LBVP_OK;
+    lbvp3_ctx* c0 = b->members[0];
+    const int64_t fe = c0->p.force_every;
+    for (lbvp3_ctx* c : b->members) {
+        if (c->step != c0->step || c->rec_head != c0->rec_head)
+            return b->fail(LBVP_E_STATE, "members went out of step (one was stepped alone)");
+        if (c->launch.vec != b->vec || c->launch.block != b->block)
+            return b->fail(LBVP_E_STATE, "a member's launch shape was changed after the batch was made");
+        if (fe > 0) {
+            const int64_t new_recs = (c->step + n_steps) / fe - c->step / fe;
+            if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
+                return b->fail(LBVP_E_STATE, "a member's force records would overflow its ring; drain them first");
+        }
+    }
+    // the member block: rewritten once the previous call's steps (which read it) are done
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "hipStreamSynchronize");
+    for (lbvp3_ctx* c : b->members) {
+        c->a64.fin = c->fin;
+        c->a32.fin = c->fin;
+    }
+    if (b->storage == LBVP_F64) write_member_images<double>(b);
+    else write_member_images<float>(b);
+    e = hipMemcpyAsync(b->dev, b->image.data(), b->member_bytes, hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return b->hip_fail(e, "member upload");
+    const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
+    const int32_t n = (int32_t)b->members.size();
+    Batch3Launch L{};
+    L.total_tiles = b->total_tiles;
+    L.tiles_per_xcd = b->tiles_per_xcd;
+    L.band_log2 = band_log2(b->band);
+    L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_domain);
+    L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_start);
+    L.members = b->dev;
+    for (int64_t k = 0; k < n_steps; ++k) {
+        const int64_t next = c0->step + 1;
+        const bool record = fe > 0 && next % fe == 0;
+        const bool keep_here = keep && k == n_steps - 1;
+        const int32_t part_buf = (int32_t)(c0->rec_head & 1);
+        L.flip = (int32_t)(k & 1);
+        L.part_buf = part_buf;
+        L.fin_buf = c0->pending ? c0->pending_buf : -1;
+        L.n_fin = L.fin_buf >= 0 ? n * N_LEAD : 0;
+        e = launch_step3_batch(b->storage, b->vec, b->block, record, keep_here, L, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "batch step kernel launch");
+        for (lbvp3_ctx* c : b->members) {
+            c->pending = record;
+            if (record) {
+                c->pending_buf = part_buf;
+                c->rec_head += 1;
+            }
+            if (keep_here) c->fields_valid = true;
+            c->cur ^= 1;
+            c->step = next;
+        }
+    }
+    for (lbvp3_ctx* c : b->members)
+        if (c->pending) {   // the last record of the call, summed on its own
+            e = launch_finalize3(c->fin, c->pending_buf, b->stream);
+            if (e != hipSuccess) return b->hip_fail(e, "finalize kernel launch");
+            c->pending = false;
+        }
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_batch_set_tile_band(lbvp3_batch* b, int32_t band)
+{
+    if (!b) return LBVP_E_ARG;
+    if (band < 0 || band > MAX_TILE_BAND || (band & (band - 1)) != 0)
+        return b->fail(LBVP_E_ARG, "band must be 0 or a power of two up to 65536");
+    b->band = band;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_batch_get_tile_band(const lbvp3_batch* b, int32_t* band)
+{
+    if (!b || !band) return LBVP_E_ARG;
+    *band = b->band;
+    return LBVP_OK;
+}
+
+lbvp_status lbvp3_batch_destroy(lbvp3_batch* b)
+{
+    if (!b) return LBVP_OK;
+    delete b;
+    return LBVP_OK;
+}
+
+const char* lbvp3_batch_last_error(const lbvp3_batch* b) { return b ? b->err.c_str() : g_batch3_error.c_str(); }
 
 }  // extern "C"

@@ -90,11 +90,36 @@ struct Conv3Args {
     double* pops;        // staged [19][planes][ny][nx]
 };
 
+// A batch member as the batch kernel sees it: its step arguments and lattices,
+// and its current lattice when the batch wrote this image (Batch3Launch::flip
+// gives each step's parity relative to it).
+template <typename R>
+struct Member3 {
+    Step3Args<R> a;
+    void* lat0;
+    void* lat1;
+    int32_t cur;
+};
+
+// One step of every member of a batch: block -> (member, tile) through the tile
+// map (tiles of member d are tile_start[d] .. tile_start[d + 1] - 1).
+struct Batch3Launch {
+    int32_t total_tiles, tiles_per_xcd, band_log2;
+    int32_t flip;                   // this step's lattice parity relative to Member3::cur
+    int32_t part_buf, fin_buf;      // as in Step3Args, for every member
+    int32_t n_fin;                  // N_LEAD leading blocks per member, or 0 if fin_buf < 0
+    const int32_t* tile_domain;     // [total_tiles] member of each tile
+    const int32_t* tile_start;      // [n_members] first tile of each member
+    const void* members;            // Member3<R>[n_members]
+};
+
 // nodes per thread the step kernel is built for, per storage type
 bool vec_supported(int32_t storage, int32_t vec);
 
 hipError_t launch_step3(int32_t storage, bool record, bool fields, const void* src, void* dst, const void* step_args,
                         hipStream_t s);
+hipError_t launch_step3_batch(int32_t storage, int32_t vec, int32_t block, bool record, bool fields,
+                              const Batch3Launch& b, hipStream_t s);
 hipError_t launch_finalize3(const Fin3Args& a, int32_t buf, hipStream_t s);
 hipError_t launch_init3(int32_t storage, void* lat, void* fields, const Conv3Args& a, hipStream_t s);
 hipError_t launch_decode3(int32_t storage, const void* lat, const Conv3Args& a, hipStream_t s);

@@ -186,7 +186,8 @@ __device__ __forceinline__ R* force_lds()
 // Tile t: tile_rows lattice rows of tile_w nodes, V consecutive nodes per thread.
 template <typename S, int V, bool RECORD, bool FIELDS>
 __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restrict__ dst,
-                                           const Step3Args<typename Arith<S>::R>& a, int t, double* lds)
+                                           const Step3Args<typename Arith<S>::R>& a, int t, int part_buf,
+                                           double* lds)
 {
     using R = typename Arith<S>::R;
     const int n_rows = a.ny * a.nz;
@@ -349,8 +350,8 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
         // mass: one partial per wavefront (DPP moves only, no block barrier)
         const int lane = (int)(threadIdx.x & 63);
         const double wm = wave_sum_lane63(tile_drho);
-        double* mass_part = a.mass_part + a.part_buf * a.fin.mass_stride;
-        double* slot_force = a.slot_force + a.part_buf * a.fin.slot_stride;
+        double* mass_part = a.mass_part + part_buf * a.fin.mass_stride;
+        double* slot_force = a.slot_force + part_buf * a.fin.slot_stride;
         if (lane == 63) mass_part[(int64_t)t * (a.block >> 6) + (threadIdx.x >> 6)] = wm;
         if (s1 > s0) {   // tiles that hold solid nodes (uniform across the block)
             const R* fv = force_lds<R>();
@@ -439,7 +440,33 @@ k_step3(const S* __restrict__ src, S* __restrict__ dst, Step3Args<typename Arith
     }
     const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;   // whole block
-    step3_body<S, V, RECORD, FIELDS>(src, dst, a, t, lds);
+    step3_body<S, V, RECORD, FIELDS>(src, dst, a, t, a.part_buf, lds);
+}
+
+// Many domains in one launch: block -> (member, tile) through the tile map; each
+// member's arguments and lattices live in device memory. The members step in
+// lockstep: one step kind, record flag and partial buffer for all; N_LEAD
+// leading blocks per member sum that member's previous record.
+template <typename S, int V, bool RECORD, bool FIELDS>
+__global__ void __launch_bounds__(256) k_step3_batch(Batch3Launch b)
+{
+    using R = typename Arith<S>::R;
+    __shared__ double lds[FIN_LANES];
+    const Member3<R>* m = static_cast<const Member3<R>*>(b.members);
+    if ((int)blockIdx.x < b.n_fin) {
+        __shared__ int last;
+        const int d = (int)blockIdx.x / N_LEAD;
+        finalize3(m[d].a.fin, b.fin_buf, (int)blockIdx.x - d * N_LEAD, lds, &last);
+        return;
+    }
+    const int g = xcd_tile(b.tiles_per_xcd, b.band_log2, b.n_fin);
+    if (g >= b.total_tiles) return;   // whole block
+    const int d = b.tile_domain[g];
+    const Member3<R>& md = m[d];
+    const int cur = md.cur ^ b.flip;
+    const S* src = static_cast<const S*>(cur ? md.lat1 : md.lat0);
+    S* dst = static_cast<S*>(cur ? md.lat0 : md.lat1);
+    step3_body<S, V, RECORD, FIELDS>(src, dst, md.a, g - b.tile_start[d], b.part_buf, lds);
 }
 
 // The last record of an lbvp3_step call, summed on its own (N_LEAD blocks).
@@ -559,6 +586,39 @@ hipError_t step_typed(bool record, bool fields, const void* src, void* dst, cons
     return hipErrorInvalidValue;
 }
 
+template <typename S, int V>
+hipError_t batch_v(bool record, bool fields, const Batch3Launch& b, int32_t block, hipStream_t s)
+{
+    using R = typename Arith<S>::R;
+    const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD + b.n_fin)), blk((unsigned)block);
+    const size_t lds = record ? 3 * (size_t)V * (size_t)block * sizeof(R) : 0;
+    if (record) {
+        if (fields) hipLaunchKernelGGL((k_step3_batch<S, V, true, true>), grid, blk, lds, s, b);
+        else hipLaunchKernelGGL((k_step3_batch<S, V, true, false>), grid, blk, lds, s, b);
+    } else {
+        if (fields) hipLaunchKernelGGL((k_step3_batch<S, V, false, true>), grid, blk, 0, s, b);
+        else hipLaunchKernelGGL((k_step3_batch<S, V, false, false>), grid, blk, 0, s, b);
+    }
+    return hipGetLastError();
+}
+
+template <typename S>
+hipError_t batch_typed(int32_t vec, int32_t block, bool record, bool fields, const Batch3Launch& b, hipStream_t s)
+{
+    if (vec == 1) return batch_v<S, 1>(record, fields, b, block, s);
+    if constexpr (sizeof(S) >= 4) {
+        if (vec == 2) return batch_v<S, 2>(record, fields, b, block, s);
+    }
+    if constexpr (sizeof(S) == 4) {
+        if (vec == 4) return batch_v<S, 4>(record, fields, b, block, s);
+    }
+    if constexpr (sizeof(S) == 2) {
+        if (vec == 4) return batch_v<S, 4>(record, fields, b, block, s);
+        if (vec == 8) return batch_v<S, 8>(record, fields, b, block, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 unsigned conv_blocks(const Conv3Args& a) { return (unsigned)(((int64_t)a.planes * a.ny * a.nx + 255) / 256); }
 
 }  // namespace
@@ -582,6 +642,18 @@ hipError_t launch_step3(int32_t storage, bool record, bool fields, const void* s
     case LBVP_F32: return step_typed<float>(record, fields, src, dst, step_args, s);
     case LBVP_F16_DEV: return step_typed<_Float16>(record, fields, src, dst, step_args, s);
     case LBVP_BF16_DEV: return step_typed<__bf16>(record, fields, src, dst, step_args, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_step3_batch(int32_t storage, int32_t vec, int32_t block, bool record, bool fields,
+                              const Batch3Launch& b, hipStream_t s)
+{
+    switch (storage) {
+    case LBVP_F64: return batch_typed<double>(vec, block, record, fields, b, s);
+    case LBVP_F32: return batch_typed<float>(vec, block, record, fields, b, s);
+    case LBVP_F16_DEV: return batch_typed<_Float16>(vec, block, record, fields, b, s);
+    case LBVP_BF16_DEV: return batch_typed<__bf16>(vec, block, record, fields, b, s);
     default: return hipErrorInvalidValue;
     }
 }

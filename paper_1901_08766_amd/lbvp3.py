@@ -3,7 +3,8 @@ function per entry point with the same name, marshalling only. Every step runs
 in the library's HIP kernels; there is no CPU fallback (importing raises if the
 library is not built).
 
-``Solver3`` wraps a context for a ``Problem3`` (see ``inputs3``) on a torch stream.
+``Solver3`` wraps a context for a ``Problem3`` (see ``inputs3``) on a torch stream;
+``Batch3`` advances several of them together.
 """
 from __future__ import annotations
 
@@ -22,8 +23,9 @@ SYMBOLS = ["lbvp3_footprint_bytes", "lbvp3_create", "lbvp3_set_mask", "lbvp3_ini
            "lbvp3_forces", "lbvp3_read_fields", "lbvp3_read_populations", "lbvp3_write_populations",
            "lbvp3_set_launch", "lbvp3_get_launch", "lbvp3_set_tile_band", "lbvp3_get_tile_band",
            "lbvp3_step_count", "lbvp3_synchronize", "lbvp3_destroy", "lbvp3_save_state", "lbvp3_load_state",
-           "lbvp3_last_error"]
-NO_STATUS = ("lbvp3_footprint_bytes", "lbvp3_step_count", "lbvp3_last_error")
+           "lbvp3_last_error", "lbvp3_batch_create", "lbvp3_batch_step", "lbvp3_batch_set_tile_band",
+           "lbvp3_batch_get_tile_band", "lbvp3_batch_destroy", "lbvp3_batch_last_error"]
+NO_STATUS = ("lbvp3_footprint_bytes", "lbvp3_step_count", "lbvp3_last_error", "lbvp3_batch_last_error")
 
 
 class lbvp3_params(C.Structure):
@@ -65,6 +67,13 @@ def _load():
     L.lbvp3_destroy.argtypes = [vp]
     L.lbvp3_last_error.restype = C.c_char_p
     L.lbvp3_last_error.argtypes = [vp]
+    L.lbvp3_batch_create.argtypes = [C.POINTER(vp), i32, i32, i32, C.POINTER(vp)]
+    L.lbvp3_batch_step.argtypes = [vp, i64, u32]
+    L.lbvp3_batch_set_tile_band.argtypes = [vp, i32]
+    L.lbvp3_batch_get_tile_band.argtypes = [vp, C.POINTER(i32)]
+    L.lbvp3_batch_destroy.argtypes = [vp]
+    L.lbvp3_batch_last_error.restype = C.c_char_p
+    L.lbvp3_batch_last_error.argtypes = [vp]
     for name in SYMBOLS:
         if name not in NO_STATUS:
             getattr(L, name).restype = C.c_int
@@ -198,6 +207,42 @@ def lbvp3_destroy(ctx):
         _check(None, _L.lbvp3_destroy(ctx))
 
 
+def lbvp3_batch_last_error(batch) -> str:
+    msg = _L.lbvp3_batch_last_error(batch)
+    return msg.decode() if msg else ""
+
+
+def _check_batch(batch, status: int):
+    if status != OK:
+        raise LbvpError(status, lbvp3_batch_last_error(batch))
+
+
+def lbvp3_batch_create(ctxs, vec: int = 0, block: int = 0):
+    arr = (C.c_void_p * len(ctxs))(*ctxs)
+    out = C.c_void_p()
+    _check_batch(None, _L.lbvp3_batch_create(arr, len(ctxs), int(vec), int(block), C.byref(out)))
+    return out.value
+
+
+def lbvp3_batch_step(batch, n_steps: int, flags: int = 0):
+    _check_batch(batch, _L.lbvp3_batch_step(batch, int(n_steps), int(flags)))
+
+
+def lbvp3_batch_set_tile_band(batch, band: int):
+    _check_batch(batch, _L.lbvp3_batch_set_tile_band(batch, int(band)))
+
+
+def lbvp3_batch_get_tile_band(batch) -> int:
+    b = C.c_int32()
+    _check_batch(batch, _L.lbvp3_batch_get_tile_band(batch, C.byref(b)))
+    return b.value
+
+
+def lbvp3_batch_destroy(batch):
+    if batch:
+        _check_batch(None, _L.lbvp3_batch_destroy(batch))
+
+
 # ------------------------------------------------------------ convenience --
 
 def params_for(prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
@@ -284,6 +329,36 @@ class Solver3:
         if getattr(self, "ctx", None):
             lbvp3_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch3:
+    """D3Q19 solvers advanced together (one launch per step over all their
+    tiles). The solvers must share one stream (pass the same torch stream)."""
+
+    def __init__(self, solvers, vec: int = 0, block: int = 0):
+        self.solvers = list(solvers)
+        self.handle = lbvp3_batch_create([s.ctx for s in self.solvers], vec, block)
+
+    def step(self, n: int, keep_fields: bool = False):
+        lbvp3_batch_step(self.handle, n, KEEP_FIELDS if keep_fields else 0)
+
+    @property
+    def tile_band(self) -> int:
+        return lbvp3_batch_get_tile_band(self.handle)
+
+    def set_tile_band(self, band: int):
+        lbvp3_batch_set_tile_band(self.handle, band)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lbvp3_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -1,0 +1,137 @@
+"""D3Q19 batches (lbvp3_batch_*): several contexts advanced by one launch per
+step over all their tiles. Every member must end bitwise where it ends when
+stepped alone with the same launch shape: populations, fields and the force and
+mass records (whose sums the batch's leading blocks form per member). Members
+of ragged, uneven sizes with different sides, bodies and relaxation times; each
+storage type; tile bands over the whole batch. FP64 members also match the
+oracle to 1e-12 directly.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_1901_08766_amd import inputs3
+
+pytestmark = pytest.mark.gpu
+
+IO = ("inflow_eq", "outflow_zero_grad")
+
+
+def _members():
+    return [inputs3.random_state_problem3(40, 24, 20, seed=31, n_spheres=3, body_force=(1e-5, 0.0, -2e-6)),
+            inputs3.random_state_problem3(17, 9, 7, seed=32, n_spheres=2, bc=("periodic", "periodic"),
+                                          tau_plus=0.9),
+            inputs3.random_state_problem3(3, 3, 3, seed=33, n_spheres=1, bc=("periodic", "periodic")),
+            inputs3.random_state_problem3(129, 5, 3, seed=34, n_spheres=1, bc=IO, tau_plus=0.55),
+            inputs3.random_state_problem3(70, 33, 9, seed=35, n_spheres=3, bc=("outflow_zero_grad", "inflow_eq"))]
+
+
+CALLS = [(9, False), (1, False), (4, True)]
+
+
+def _alone(lbvp3, prob, storage, launch, force_every):
+    s = lbvp3.Solver3(prob, storage=storage, force_every=force_every, force_capacity=64)
+    s.set_launch(*launch)
+    for n, keep in CALLS:
+        s.step(n, keep_fields=keep)
+    out = (s.populations(), s.fields(), s.forces())
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("storage,launch,force_every,band", [
+    ("f64", (1, 64), 1, 0), ("f64", (2, 128), 3, 8), ("f32", (4, 256), 1, 2), ("f32", (1, 128), 2, 0),
+    ("f16", (4, 64), 1, 16), ("f16", (8, 256), 1, 0), ("bf16", (4, 128), 1, 1)])
+def test_batch_members_step_like_alone(lbvp3, storage, launch, force_every, band):
+    probs = _members()
+    stream = torch.cuda.Stream()
+    members = [lbvp3.Solver3(p, storage=storage, force_every=force_every, force_capacity=64, stream=stream)
+               for p in probs]
+    batch = lbvp3.Batch3(members, *launch)
+    batch.set_tile_band(band)
+    assert batch.tile_band == band and all(m.launch == launch for m in members)
+    print(f"batch3 {storage} launch={launch} force_every={force_every} band={band}", flush=True)
+    for n, keep in CALLS:
+        batch.step(n, keep_fields=keep)
+    for k, (prob, m) in enumerate(zip(probs, members)):
+        assert m.step_count == 14
+        pops, fields, (f, mass, first) = m.populations(), m.fields(), m.forces()
+        a_pops, a_fields, (af, amass, afirst) = _alone(lbvp3, prob, storage, launch, force_every)
+        assert np.array_equal(pops, a_pops), k
+        for name in fields:
+            assert np.array_equal(fields[name], a_fields[name]), (k, name)
+        assert len(mass) == 14 // force_every and first == afirst == force_every, k
+        assert np.array_equal(f, af) and np.array_equal(mass, amass), k
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_batch_fp64_matches_oracle(lbvp3, ref3):
+    probs = _members()[:4]
+    stream = torch.cuda.Stream()
+    members = [lbvp3.Solver3(p, storage="f64", force_every=1, force_capacity=32, stream=stream) for p in probs]
+    batch = lbvp3.Batch3(members, 2, 64)
+    batch.step(6)
+    batch.step(5, keep_fields=True)
+    for prob, m in zip(probs, members):
+        ref = ref3.RefSolver3(prob)
+        rf, rm = ref.step(11, record=True)
+        gf, gm, first = m.forces()
+        assert first == 1 and gf.shape == rf.shape
+        g_ref = ref.populations()
+        assert np.abs(m.populations() - g_ref).max() <= 1e-12 * np.abs(g_ref).max(), prob.name
+        fr = ref.fields()
+        scale = np.array([sum(np.abs(fr[k][prob.mask_or_empty() == b]).sum() for k in ("fx", "fy", "fz")) + 1e-300
+                          for b in range(1, prob.n_bodies + 1)])
+        if prob.n_bodies:
+            assert np.all(np.abs(gf - rf).max(axis=(0, 2)) <= 1e-11 * scale), prob.name
+        assert np.abs(gm - rm).max() <= 1e-13 * rm.max(), prob.name
+        ref.close()
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_batch_rejections(lbvp3):
+    probs = _members()[:3]
+    stream = torch.cuda.Stream()
+    members = [lbvp3.Solver3(p, storage="f32", force_every=1, force_capacity=8, stream=stream) for p in probs]
+    other_type = lbvp3.Solver3(probs[0], storage="f64", stream=stream)
+    other_stream = lbvp3.Solver3(probs[0], storage="f32", stream=torch.cuda.Stream())
+    for bad in ([members[0], other_type], [members[0], other_stream], [members[0], members[0]]):
+        with pytest.raises(lbvp3.LbvpError) as e:
+            lbvp3.Batch3(bad)
+        assert e.value.status == lbvp3.E_ARG
+    with pytest.raises(lbvp3.LbvpError) as e:         # FP32 has no 8-node form
+        lbvp3.Batch3(members, 8, 64)
+    assert e.value.status == lbvp3.E_ARG
+    batch = lbvp3.Batch3(members, 1, 64)
+    for bad in (-1, 3, 1 << 17):
+        with pytest.raises(lbvp3.LbvpError) as e:
+            batch.set_tile_band(bad)
+        assert e.value.status == lbvp3.E_ARG
+    batch.step(5)
+    with pytest.raises(lbvp3.LbvpError) as e:         # 5 + 5 records do not fit a ring of 8
+        batch.step(5)
+    assert e.value.status == lbvp3.E_STATE
+    for m in members:
+        m.forces()
+    batch.step(5)
+    members[1].step(1)                                # stepped alone: the batch is out of step
+    with pytest.raises(lbvp3.LbvpError) as e:
+        batch.step(1)
+    assert e.value.status == lbvp3.E_STATE
+    members[0].step(1)
+    members[2].step(1)
+    for m in members:
+        m.forces()
+    batch.step(2)                                     # back in step
+    members[2].set_launch(2, 64)
+    with pytest.raises(lbvp3.LbvpError) as e:
+        batch.step(1)
+    assert e.value.status == lbvp3.E_STATE
+    assert all(m.step_count == 13 for m in members)
+    batch.close()
+    for s in members + [other_type, other_stream]:
+        s.close()
