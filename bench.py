@@ -124,6 +124,68 @@ def time_d3q19(storages, steps: int, warmup: int):
     return out
 
 
+def time_ensemble3(storage: str, steps: int, n_dom: int = 64):
+    """The D3Q19 ensemble of uneven sphere domains as one batch (one launch per
+    step over all their tiles; the launch shape and band from a short trial of a
+    few candidates) against each domain's own launch per step, round-robin on
+    one stream, at the same storage type."""
+    import torch
+    from paper_1901_08766_amd import inputs3, lbvp3
+
+    probs = inputs3.ensemble3(n=n_dom)
+    nodes = sum(p.n_nodes for p in probs)
+    stream = torch.cuda.Stream()
+    members = [lbvp3.Solver3(p, storage=storage, force_every=1, force_capacity=2 * steps + 64, stream=stream)
+               for p in probs]
+    out = {"workload": f"{n_dom} sphere domains, nx {inputs3.ENSEMBLE3_NX}, ny and nz {inputs3.ENSEMBLE3_NYZ}",
+           "domains": n_dom, "nodes": nodes, "storage": storage}
+
+    def drain():
+        for m in members:
+            m.forces()
+
+    def per_domain():
+        for _ in range(steps):
+            for m in members:
+                m.step(1)
+
+    for m in members:
+        m.step(2)
+    drain()
+    ms = _timed(stream, per_domain)
+    out["per_domain_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
+    drain()
+    shapes = {"f64": [(1, 128), (2, 128)], "f32": [(1, 128), (2, 128), (4, 256)]}.get(storage, [(4, 128), (8, 256)])
+    best = None
+    for vec, block in shapes:
+        for band in (0, 2):
+            batch = lbvp3.Batch3(members, vec, block)
+            batch.set_tile_band(band)
+            batch.step(2)
+            drain()
+            t = _timed(stream, lambda: batch.step(20)) / 20
+            drain()
+            batch.close()
+            if best is None or t < best[0]:
+                best = (t, vec, block, band)
+    _, vec, block, band = best
+    batch = lbvp3.Batch3(members, vec, block)
+    batch.set_tile_band(band)
+    ms = _timed(stream, lambda: batch.step(steps))
+    _, mass, _ = members[0].forces()
+    drain()
+    out.update({"launch": [vec, block], "tile_band": band, "batched_MLUPS": round(nodes * steps / ms / 1e3, 1),
+                "batched_ms_per_step": round(ms / steps, 4),
+                "speedup": round(nodes * steps / ms / 1e3 / max(out["per_domain_MLUPS"], 1e-9), 2),
+                "finite": bool(np.isfinite(mass).all())})
+    batch.close()
+    for m in members:
+        m.close()
+    torch.cuda.empty_cache()
+    print(f"# d3q19 ensemble {storage}: {out}", file=sys.stderr, flush=True)
+    return out
+
+
 def time_slabs(n_slabs: int, steps: int = 100, storage: str = "f32"):
     """The large domain cut into n_slabs x-slabs on this one GPU (a halo exchange
     over every cut, then one batched step of all slabs) against the whole
@@ -588,6 +650,10 @@ def main():
     ap.add_argument("--d3q19-steps", type=int, default=50,
                     help="timed steps of the D3Q19 sphere domain (0: skip it)")
     ap.add_argument("--d3q19-storages", default="f32,f16,f64")
+    ap.add_argument("--d3q19-ensemble-steps", type=int, default=None,
+                    help="timed steps of the D3Q19 ensemble, batched and per domain (0: skip it; "
+                         "default 100, and none with --d3q19-only)")
+    ap.add_argument("--d3q19-ensemble-storages", default="f32,f16")
     ap.add_argument("--d3q19-only", action="store_true", help="only run the D3Q19 timing leg")
     ap.add_argument("--slabs", type=int, default=0, metavar="N",
                     help="only time the large domain as N x-slabs on this GPU (halo exchange + batched step)")
@@ -626,7 +692,12 @@ def main():
         print(json.dumps(time_slabs(a.slabs, storage=a.storage)), flush=True)
         return
     if a.d3q19_only:
-        print(json.dumps(time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, a.warmup)), flush=True)
+        res = time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, a.warmup) \
+            if a.d3q19_steps > 0 else {}
+        if a.d3q19_ensemble_steps:
+            res["ensemble"] = {st: time_ensemble3(st, a.d3q19_ensemble_steps)
+                               for st in a.d3q19_ensemble_storages.split(",") if st}
+        print(json.dumps(res), flush=True)
         return
     if a.precision_study:
         print(json.dumps(precision_study()), flush=True)
@@ -697,6 +768,11 @@ def main():
             print(f"# ensemble {st}: {out['ensemble'][st]}", file=sys.stderr, flush=True)
     if a.d3q19_steps > 0:
         out["d3q19"] = time_d3q19([x for x in a.d3q19_storages.split(",") if x], a.d3q19_steps, a.warmup)
+    if a.d3q19_ensemble_steps is None:
+        a.d3q19_ensemble_steps = 100
+    if a.d3q19_ensemble_steps > 0:
+        out.setdefault("d3q19", {})["ensemble"] = {
+            st: time_ensemble3(st, a.d3q19_ensemble_steps) for st in a.d3q19_ensemble_storages.split(",") if st}
     if a.serve_requests > 0:
         out["serving"] = run_serving(a.serve_storage, a.serve_rate, a.serve_requests)
         print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)

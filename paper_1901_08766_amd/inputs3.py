@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
-from typing import Optional, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -230,6 +230,27 @@ def sphere(nx: int = SPHERE_SHAPE[0], ny: int = SPHERE_SHAPE[1], nz: int = SPHER
                     magic_lambda=magic_lambda, eta=eta, bc=(INFLOW_EQ, OUTFLOW), rho_in=1.0,
                     u_in=(u, 0.0, 0.0), mask=mask, bodies=bodies, ux_init=ux, uy_init=uy, uz_init=uz,
                     steps=steps, u_ref=u, l_ref=d)
+
+
+ENSEMBLE3_NX = (96, 128, 160)
+ENSEMBLE3_NYZ = (32, 48, 64)
+
+
+def ensemble3(n: int = 64, seed: int = 5) -> List[Problem3]:
+    """An ensemble of independent sphere domains of uneven sizes (the 3-D
+    counterpart of the channel ensemble): nx from ENSEMBLE3_NX, ny and nz from
+    ENSEMBLE3_NYZ, sphere diameter ~ U[8, min(ny, nz) / 3] at a random height,
+    Re ~ U[20, 50] (tau+ >= 0.524), each with its own seeded perturbation."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for k in range(n):
+        nx = int(ENSEMBLE3_NX[int(rng.integers(len(ENSEMBLE3_NX)))])
+        ny, nz = (int(ENSEMBLE3_NYZ[int(rng.integers(len(ENSEMBLE3_NYZ)))]) for _ in range(2))
+        d = float(rng.uniform(8.0, min(ny, nz) / 3.0))
+        re = float(rng.uniform(20.0, 50.0))
+        p = sphere(nx, ny, nz, d=d, re=re, seed=int(rng.integers(1 << 31)))
+        out.append(dataclasses.replace(p, name=f"ens3_{k}_{p.name}"))
+    return out
 
 
 def shear_wave(n: int = 32, u0: float = 1e-3, axis_u: int = 0, axis_k: int = 2, tau_plus: float = 0.8,

@@ -135,3 +135,40 @@ def test_batch_rejections(lbvp3):
     batch.close()
     for s in members + [other_type, other_stream]:
         s.close()
+
+
+@pytest.mark.parametrize("storage,launch,band", [("f32", (2, 128), 2), ("f64", (1, 128), 0)])
+def test_whole_ensemble_in_one_batch(lbvp3, ref3, storage, launch, band):
+    """The benchmark's 64-domain sphere ensemble as one batch: three members
+    (first, a middle one, last) bitwise equal to stepping alone; in FP64 the
+    smallest member also matches the oracle to 1e-12."""
+    probs = inputs3.ensemble3()
+    stream = torch.cuda.Stream()
+    members = [lbvp3.Solver3(p, storage=storage, force_every=1, force_capacity=32, stream=stream) for p in probs]
+    batch = lbvp3.Batch3(members, *launch)
+    batch.set_tile_band(band)
+    print(f"ensemble3 {storage} launch={launch} band={band} nodes={sum(p.n_nodes for p in probs)}", flush=True)
+    batch.step(7)
+    batch.step(5, keep_fields=True)
+    for k in (0, 31, 63):
+        s = lbvp3.Solver3(probs[k], storage=storage, force_every=1, force_capacity=32)
+        s.set_launch(*launch)
+        s.step(12, keep_fields=True)
+        assert np.array_equal(s.populations(), members[k].populations()), k
+        fa, fb = s.fields(), members[k].fields()
+        for name in fa:
+            assert np.array_equal(fa[name], fb[name]), (k, name)
+        ra, rb = s.forces(), members[k].forces()
+        assert np.array_equal(ra[0], rb[0]) and np.array_equal(ra[1], rb[1]), k
+        s.close()
+    if storage == "f64":
+        k = int(np.argmin([p.n_nodes for p in probs]))
+        ref = ref3.RefSolver3(probs[k])
+        ref.step(12)
+        g_ref = ref.populations()
+        assert np.abs(members[k].populations() - g_ref).max() <= 1e-12 * np.abs(g_ref).max()
+        ref.close()
+    batch.close()
+    for m in members:
+        m.close()
+    torch.cuda.empty_cache()
