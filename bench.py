@@ -155,7 +155,7 @@ def time_ensemble3(storage: str, steps: int, n_dom: int = 64):
     ms = _timed(stream, per_domain)
     out["per_domain_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
     drain()
-    shapes = {"f64": [(1, 128), (2, 128)], "f32": [(1, 128), (2, 128), (4, 256)]}.get(storage, [(4, 128), (8, 256)])
+    shapes = {"f64": [(1, 128), (2, 128)], "f32": [(1, 128), (2, 128), (4, 256)]}.get(storage, [(4, 64), (4, 128), (8, 256)])
     best = None
     for vec, block in shapes:
         for band in (0, 2):
