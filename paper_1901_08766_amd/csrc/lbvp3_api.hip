@@ -978,6 +978,7 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
     L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_domain);
     L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_start);
     L.members = b->dev;
+    L.n_members = n;
     for (int64_t k = 0; k < n_steps; ++k) {
         const int64_t next = c0->step + 1;
         const bool record = fe > 0 && next % fe == 0;
@@ -986,7 +987,7 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
         L.flip = (int32_t)(k & 1);
         L.part_buf = part_buf;
         L.fin_buf = c0->pending ? c0->pending_buf : -1;
-        L.n_fin = L.fin_buf >= 0 ? n * N_LEAD : 0;
+        L.n_fin = L.fin_buf >= 0 ? (n + N_XCD - 1) / N_XCD * N_XCD : 0;
         e = launch_step3_batch(b->storage, b->vec, b->block, record, keep_here, L, b->stream);
         if (e != hipSuccess) return b->hip_fail(e, "batch step kernel launch");
         for (lbvp3_ctx* c : b->members) {
@@ -1000,12 +1001,12 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
             c->step = next;
         }
     }
-    for (lbvp3_ctx* c : b->members)
-        if (c->pending) {   // the last record of the call, summed on its own
-            e = launch_finalize3(c->fin, c->pending_buf, b->stream);
-            if (e != hipSuccess) return b->hip_fail(e, "finalize kernel launch");
-            c->pending = false;
-        }
+    if (c0->pending) {   // the last record of the call, every member's in one launch
+        L.fin_buf = c0->pending_buf;
+        e = launch_finalize3_members(b->storage, L, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "finalize kernel launch");
+        for (lbvp3_ctx* c : b->members) c->pending = false;
+    }
     return LBVP_OK;
 }
 

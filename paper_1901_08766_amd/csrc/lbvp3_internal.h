@@ -107,7 +107,9 @@ struct Batch3Launch {
     int32_t total_tiles, tiles_per_xcd, band_log2;
     int32_t flip;                   // this step's lattice parity relative to Member3::cur
     int32_t part_buf, fin_buf;      // as in Step3Args, for every member
-    int32_t n_fin;                  // N_LEAD leading blocks per member, or 0 if fin_buf < 0
+    int32_t n_members;
+    int32_t n_fin;                  // leading blocks, one per member (rounded up to a multiple of
+                                    // the 8 XCDs), or 0 if fin_buf < 0
     const int32_t* tile_domain;     // [total_tiles] member of each tile
     const int32_t* tile_start;      // [n_members] first tile of each member
     const void* members;            // Member3<R>[n_members]
@@ -121,6 +123,8 @@ hipError_t launch_step3(int32_t storage, bool record, bool fields, const void* s
 hipError_t launch_step3_batch(int32_t storage, int32_t vec, int32_t block, bool record, bool fields,
                               const Batch3Launch& b, hipStream_t s);
 hipError_t launch_finalize3(const Fin3Args& a, int32_t buf, hipStream_t s);
+// every member's record in partial buffer b.fin_buf summed by one block each
+hipError_t launch_finalize3_members(int32_t storage, const Batch3Launch& b, hipStream_t s);
 hipError_t launch_init3(int32_t storage, void* lat, void* fields, const Conv3Args& a, hipStream_t s);
 hipError_t launch_decode3(int32_t storage, const void* lat, const Conv3Args& a, hipStream_t s);
 hipError_t launch_encode3(int32_t storage, void* lat, const Conv3Args& a, hipStream_t s);

@@ -425,6 +425,44 @@ __device__ __forceinline__ void finalize3(const Fin3Args& f, int buf, int part, 
     }
 }
 
+// The same record by one block: the N_LEAD slice sums of finalize3 formed in
+// turn, each exactly as there, and added in slice order as its last block adds
+// the stage rows, so the result is bitwise the same; no stage rows, fences or
+// arrival counter. For small domains, where the partial lists are short.
+__device__ __forceinline__ void finalize3_serial(const Fin3Args& f, int buf, double* lds)
+{
+    const double* pm = f.mass_part + buf * f.mass_stride;
+    const double* sf = f.slot_force + buf * f.slot_stride;
+    int64_t r = 0;
+    if (threadIdx.x == 0) r = *f.rec_count % f.capacity;
+    double mass = 0.0;
+    for (int part = 0; part < N_LEAD; ++part) {
+        const int m0 = (int)((int64_t)f.n_mass * part / N_LEAD), m1 = (int)((int64_t)f.n_mass * (part + 1) / N_LEAD);
+        for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) lds[v] = lane_sum(pm + m0, m1 - m0, v);
+        mass += tree_sum(lds);
+    }
+    for (int b = 0; b < f.n_bodies; ++b) {
+        const int s0 = f.body_slot_ptr[b], n = f.body_slot_ptr[b + 1] - s0;
+        for (int c = 0; c < 3; ++c) {
+            double x = 0.0;
+            for (int part = 0; part < N_LEAD; ++part) {
+                const int a0 = s0 + (int)((int64_t)n * part / N_LEAD), a1 = s0 + (int)((int64_t)n * (part + 1) / N_LEAD);
+                for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
+                    double y = 0.0;
+                    for (int kk = a0 + v; kk < a1; kk += FIN_LANES) y += sf[3 * f.body_slots[kk] + c];
+                    lds[v] = y;
+                }
+                x += tree_sum(lds);
+            }
+            if (threadIdx.x == 0) f.ring_force[(r * f.max_bodies + b) * 3 + c] = x;
+        }
+    }
+    if (threadIdx.x == 0) {
+        f.ring_mass[r] = f.mass_offset + mass;
+        *f.rec_count += 1;
+    }
+}
+
 // A step launch: when the previous step recorded (fin_buf >= 0), N_LEAD leading
 // blocks sum that record while the other blocks stream their tiles.
 template <typename S, int V, bool RECORD, bool FIELDS>
@@ -445,8 +483,8 @@ k_step3(const S* __restrict__ src, S* __restrict__ dst, Step3Args<typename Arith
 
 // Many domains in one launch: block -> (member, tile) through the tile map; each
 // member's arguments and lattices live in device memory. The members step in
-// lockstep: one step kind, record flag and partial buffer for all; N_LEAD
-// leading blocks per member sum that member's previous record.
+// lockstep: one step kind, record flag and partial buffer for all; one leading
+// block per member sums that member's previous record (finalize3_serial).
 template <typename S, int V, bool RECORD, bool FIELDS>
 __global__ void __launch_bounds__(256) k_step3_batch(Batch3Launch b)
 {
@@ -454,9 +492,7 @@ __global__ void __launch_bounds__(256) k_step3_batch(Batch3Launch b)
     __shared__ double lds[FIN_LANES];
     const Member3<R>* m = static_cast<const Member3<R>*>(b.members);
     if ((int)blockIdx.x < b.n_fin) {
-        __shared__ int last;
-        const int d = (int)blockIdx.x / N_LEAD;
-        finalize3(m[d].a.fin, b.fin_buf, (int)blockIdx.x - d * N_LEAD, lds, &last);
+        if ((int)blockIdx.x < b.n_members) finalize3_serial(m[blockIdx.x].a.fin, b.fin_buf, lds);
         return;
     }
     const int g = xcd_tile(b.tiles_per_xcd, b.band_log2, b.n_fin);
@@ -467,6 +503,15 @@ __global__ void __launch_bounds__(256) k_step3_batch(Batch3Launch b)
     const S* src = static_cast<const S*>(cur ? md.lat1 : md.lat0);
     S* dst = static_cast<S*>(cur ? md.lat0 : md.lat1);
     step3_body<S, V, RECORD, FIELDS>(src, dst, md.a, g - b.tile_start[d], b.part_buf, lds);
+}
+
+// The last record of an lbvp3_batch_step call: one block per member.
+template <typename R>
+__global__ void __launch_bounds__(FIN_THREADS) k_finalize3_members(Batch3Launch b)
+{
+    __shared__ double lds[FIN_LANES];
+    const Member3<R>* m = static_cast<const Member3<R>*>(b.members);
+    finalize3_serial(m[blockIdx.x].a.fin, b.fin_buf, lds);
 }
 
 // The last record of an lbvp3_step call, summed on its own (N_LEAD blocks).
@@ -656,6 +701,13 @@ hipError_t launch_step3_batch(int32_t storage, int32_t vec, int32_t block, bool 
     case LBVP_BF16_DEV: return batch_typed<__bf16>(vec, block, record, fields, b, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_finalize3_members(int32_t storage, const Batch3Launch& b, hipStream_t s)
+{
+    if (storage == LBVP_F64) hipLaunchKernelGGL(k_finalize3_members<double>, dim3(b.n_members), dim3(FIN_THREADS), 0, s, b);
+    else hipLaunchKernelGGL(k_finalize3_members<float>, dim3(b.n_members), dim3(FIN_THREADS), 0, s, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize3(const Fin3Args& a, int32_t buf, hipStream_t s)
