@@ -425,39 +425,81 @@ __device__ __forceinline__ void finalize3(const Fin3Args& f, int buf, int part, 
     }
 }
 
+// tree_sum's binary tree over FIN_LANES virtual lanes, with the same pairwise
+// additions (lane v takes lane v + w, w = FIN_LANES / 2 .. 1), where thread t
+// holds lanes t + k * blockDim in h[k]: levels w >= blockDim inside each thread,
+// levels 64 <= w < blockDim through lds, the last six by wave shuffles. The sum
+// is bitwise tree_sum's and lands in thread 0 only.
+constexpr int SERIAL_H = FIN_LANES / 64;
+__device__ __forceinline__ double serial_tree(double (&h)[SERIAL_H], double* lds)
+{
+    const int bd = (int)blockDim.x, t = (int)threadIdx.x;
+    const int nh = FIN_LANES / bd;
+#pragma unroll
+    for (int k = SERIAL_H / 2; k > 0; k >>= 1)
+        if (k < nh)
+#pragma unroll
+            for (int i = 0; i < k; ++i) h[i] += h[i + k];
+    for (int w = bd / 2; w >= 64; w >>= 1) {
+        __syncthreads();   // lds free from the previous level or sum
+        if (t >= w && t < 2 * w) lds[t - w] = h[0];
+        __syncthreads();
+        if (t < w) h[0] += lds[t];
+    }
+    double v = h[0];
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) v += __shfl_down(v, w, 64);
+    return v;
+}
+
 // The same record by one block: the N_LEAD slice sums of finalize3 formed in
-// turn, each exactly as there, and added in slice order as its last block adds
-// the stage rows, so the result is bitwise the same; no stage rows, fences or
-// arrival counter. For small domains, where the partial lists are short.
+// turn, each with the same virtual lanes and tree, and added in slice order as
+// its last block adds the stage rows, so the result is bitwise the same; no
+// stage rows, fences or arrival counter. For small domains, where the partial
+// lists are short. One pass over a body's slots serves its three components.
 __device__ __forceinline__ void finalize3_serial(const Fin3Args& f, int buf, double* lds)
 {
     const double* pm = f.mass_part + buf * f.mass_stride;
     const double* sf = f.slot_force + buf * f.slot_stride;
+    const int bd = (int)blockDim.x, t = (int)threadIdx.x, nh = FIN_LANES / bd;
     int64_t r = 0;
-    if (threadIdx.x == 0) r = *f.rec_count % f.capacity;
+    if (t == 0) r = *f.rec_count % f.capacity;
     double mass = 0.0;
     for (int part = 0; part < N_LEAD; ++part) {
         const int m0 = (int)((int64_t)f.n_mass * part / N_LEAD), m1 = (int)((int64_t)f.n_mass * (part + 1) / N_LEAD);
-        for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) lds[v] = lane_sum(pm + m0, m1 - m0, v);
-        mass += tree_sum(lds);
+        double h[SERIAL_H];
+#pragma unroll
+        for (int k = 0; k < SERIAL_H; ++k) h[k] = k < nh ? lane_sum(pm + m0, m1 - m0, t + k * bd) : 0.0;
+        mass += serial_tree(h, lds);
     }
     for (int b = 0; b < f.n_bodies; ++b) {
         const int s0 = f.body_slot_ptr[b], n = f.body_slot_ptr[b + 1] - s0;
-        for (int c = 0; c < 3; ++c) {
-            double x = 0.0;
-            for (int part = 0; part < N_LEAD; ++part) {
-                const int a0 = s0 + (int)((int64_t)n * part / N_LEAD), a1 = s0 + (int)((int64_t)n * (part + 1) / N_LEAD);
-                for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
-                    double y = 0.0;
-                    for (int kk = a0 + v; kk < a1; kk += FIN_LANES) y += sf[3 * f.body_slots[kk] + c];
-                    lds[v] = y;
-                }
-                x += tree_sum(lds);
+        double x[3] = {0.0, 0.0, 0.0};
+        for (int part = 0; part < N_LEAD; ++part) {
+            const int a0 = s0 + (int)((int64_t)n * part / N_LEAD), a1 = s0 + (int)((int64_t)n * (part + 1) / N_LEAD);
+            double h[3][SERIAL_H];
+#pragma unroll
+            for (int k = 0; k < SERIAL_H; ++k) {
+                double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+                if (k < nh)
+                    for (int kk = a0 + t + k * bd; kk < a1; kk += FIN_LANES) {
+                        const double* p = sf + 3 * f.body_slots[kk];
+                        y0 += p[0];
+                        y1 += p[1];
+                        y2 += p[2];
+                    }
+                h[0][k] = y0;
+                h[1][k] = y1;
+                h[2][k] = y2;
             }
-            if (threadIdx.x == 0) f.ring_force[(r * f.max_bodies + b) * 3 + c] = x;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) x[c] += serial_tree(h[c], lds);
         }
+        if (t == 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) f.ring_force[(r * f.max_bodies + b) * 3 + c] = x[c];
     }
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         f.ring_mass[r] = f.mass_offset + mass;
         *f.rec_count += 1;
     }
