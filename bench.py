@@ -126,9 +126,9 @@ def time_d3q19(storages, steps: int, warmup: int):
 
 def time_ensemble3(storage: str, steps: int, n_dom: int = 64):
     """The D3Q19 ensemble of uneven sphere domains as one batch (one launch per
-    step over all their tiles; the launch shape and band from a short trial of a
-    few candidates) against each domain's own launch per step, round-robin on
-    one stream, at the same storage type."""
+    step over all their tiles; launch shape and band from lbvp3_tune) against
+    each domain's own launch per step, round-robin on one stream, at the same
+    storage type."""
     import torch
     from paper_1901_08766_amd import inputs3, lbvp3
 
@@ -155,22 +155,13 @@ def time_ensemble3(storage: str, steps: int, n_dom: int = 64):
     ms = _timed(stream, per_domain)
     out["per_domain_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
     drain()
-    shapes = {"f64": [(1, 128), (2, 128)], "f32": [(1, 128), (2, 128), (4, 256)]}.get(storage, [(4, 64), (4, 128), (8, 256)])
-    best = None
-    for vec, block in shapes:
-        for band in (0, 2):
-            batch = lbvp3.Batch3(members, vec, block)
-            batch.set_tile_band(band)
-            batch.step(2)
-            drain()
-            t = _timed(stream, lambda: batch.step(20)) / 20
-            drain()
-            batch.close()
-            if best is None or t < best[0]:
-                best = (t, vec, block, band)
-    _, vec, block, band = best
+    rows, best = lbvp3.tune(members, steps=20)
+    vec, block, band = best["vec"], best["block"], best["band"]
+    out["tuner_rows"] = len(rows)
     batch = lbvp3.Batch3(members, vec, block)
     batch.set_tile_band(band)
+    batch.step(5)
+    drain()
     ms = _timed(stream, lambda: batch.step(steps))
     _, mass, _ = members[0].forces()
     drain()

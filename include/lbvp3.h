@@ -184,6 +184,27 @@ lbvp_status lbvp3_batch_get_tile_band(const lbvp3_batch* batch, int32_t* band);
 lbvp_status lbvp3_batch_destroy(lbvp3_batch* batch);
 const char* lbvp3_batch_last_error(const lbvp3_batch* batch);
 
+/* Tuner: times the step for every launch shape built for the members' storage
+ * (vec x block as in lbvp3_set_launch) and tile bands 0, 2 and 16, on scratch
+ * contexts made from the members' parameters, masks and bodies at rest (the
+ * members themselves are not stepped; the scratch contexts need as much device
+ * memory again). One member runs alone, several as one batch, as lbvp3_step and
+ * lbvp3_batch_step would. Each candidate: steps / 4 warm-up steps, then the best
+ * of three timed runs of `steps` steps (HIP events on the members' stream).
+ * rows[cap] receives one row per candidate and *best the index of the fastest.
+ * Results are cached per process, keyed by storage, record cadence, steps and
+ * the members' grid sizes, unless flags holds LBVP_TUNE_FRESH (no other flag is
+ * known). Errors (message from lbvp3_tune_last_error): E_ARG (NULL or mixed
+ * members), E_NOMEM, E_DEVICE. */
+typedef struct lbvp3_tune_row {
+    int32_t vec, block, band;
+    double ms_per_step;
+    double mlups;            /* million node updates per second over all members */
+} lbvp3_tune_row;
+lbvp_status lbvp3_tune(lbvp3_ctx* const* members, int32_t n, int32_t steps, uint32_t flags, lbvp3_tune_row* rows,
+                       int32_t cap, int32_t* n_rows, int32_t* best);
+const char* lbvp3_tune_last_error(void);
+
 /* Steps taken since the last init; -1 for a NULL context. */
 int64_t lbvp3_step_count(const lbvp3_ctx* ctx);
 

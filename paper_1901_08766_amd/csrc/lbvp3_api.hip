@@ -5,6 +5,8 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -249,6 +251,9 @@ struct lbvp3_batch {
 };
 
 thread_local std::string g_batch3_error;
+thread_local std::string g_tune3_error;
+std::mutex g_tune3_mu;
+std::map<std::string, std::pair<std::vector<lbvp3_tune_row>, int32_t>> g_tune3_cache;
 
 namespace {
 
@@ -1034,5 +1039,135 @@ lbvp_status lbvp3_batch_destroy(lbvp3_batch* b)
 }
 
 const char* lbvp3_batch_last_error(const lbvp3_batch* b) { return b ? b->err.c_str() : g_batch3_error.c_str(); }
+
+
+// Scratch contexts of the members' parameters, masks and bodies (fluid at rest),
+// destroyed with this object.
+struct Tune3Scratch {
+    std::vector<lbvp3_ctx*> ctx;
+    ~Tune3Scratch()
+    {
+        for (lbvp3_ctx* c : ctx) (void)lbvp3_destroy(c);
+    }
+};
+
+lbvp_status tune3_fail(lbvp_status st, const std::string& m)
+{
+    g_tune3_error = m;
+    return st;
+}
+
+lbvp_status lbvp3_tune(lbvp3_ctx* const* members, int32_t n, int32_t steps, uint32_t flags, lbvp3_tune_row* rows,
+                       int32_t cap, int32_t* n_rows, int32_t* best)
+{
+    if (!members || n < 1 || steps < 1 || cap < 0 || (cap > 0 && !rows) || !n_rows || !best ||
+        (flags & ~LBVP_TUNE_FRESH))
+        return tune3_fail(LBVP_E_ARG, "members, n >= 1, steps >= 1, rows[cap], n_rows, best and known flags are required");
+    for (int32_t d = 0; d < n; ++d)
+        if (!members[d]) return tune3_fail(LBVP_E_ARG, "a member is NULL");
+    const lbvp3_ctx* c0 = members[0];
+    std::string key = std::to_string(c0->p.storage) + "/" + std::to_string(c0->p.force_every) + "/" +
+                      std::to_string(steps);
+    for (int32_t d = 0; d < n; ++d) {
+        const lbvp3_ctx* c = members[d];
+        if (c->p.storage != c0->p.storage || c->stream != c0->stream || c->p.force_every != c0->p.force_every)
+            return tune3_fail(LBVP_E_ARG, "members differ in storage, stream or force_every");
+        key += "/" + std::to_string(c->p.nx) + "x" + std::to_string(c->p.ny) + "x" + std::to_string(c->p.nz);
+    }
+    std::vector<lbvp3_tune_row> table;
+    int32_t pick = 0;
+    bool cached = false;
+    if (!(flags & LBVP_TUNE_FRESH)) {
+        std::lock_guard<std::mutex> g(g_tune3_mu);
+        auto it = g_tune3_cache.find(key);
+        if (it != g_tune3_cache.end()) {
+            table = it->second.first;
+            pick = it->second.second;
+            cached = true;
+        }
+    }
+    if (!cached) {
+        hipStream_t stream = c0->stream;
+        const int64_t warm = std::max(1, steps / 4), per_run = warm + 3 * (int64_t)steps;
+        Tune3Scratch sc;
+        int64_t nodes = 0;
+        for (int32_t d = 0; d < n; ++d) {
+            const lbvp3_ctx* c = members[d];
+            lbvp3_params p = c->p;
+            p.force_capacity = p.force_every > 0 ? per_run / p.force_every + 16 : 0;
+            lbvp3_ctx* s = nullptr;
+            lbvp_status st = lbvp3_create(&p, stream, &s);
+            if (st != LBVP_OK) return tune3_fail(st, "scratch context: " + g_create_error);
+            sc.ctx.push_back(s);
+            if (!c->mask_host.empty())   // else all fluid, as the member
+                st = lbvp3_set_mask(s, c->mask_host.data(), c->n_bodies,
+                                    c->bodies_host.empty() ? nullptr : c->bodies_host.data());
+            if (st == LBVP_OK) st = lbvp3_init_equilibrium(s, nullptr, nullptr, nullptr, nullptr);
+            if (st != LBVP_OK) return tune3_fail(st, "scratch context: " + s->err);
+            nodes += (int64_t)p.nx * p.ny * p.nz;
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return tune3_fail(LBVP_E_DEVICE, "hipEventCreate failed");
+        }
+        lbvp_status st = LBVP_OK;
+        for (int32_t vec : {1, 2, 4, 8}) {
+            if (!vec_supported(c0->p.storage, vec)) continue;
+            for (int32_t block : BLOCKS)
+                for (int32_t band : {0, 2, 16}) {
+                    lbvp3_batch* b = nullptr;
+                    for (lbvp3_ctx* s : sc.ctx) {
+                        if (st == LBVP_OK) st = lbvp3_set_launch(s, vec, block);
+                        if (st == LBVP_OK && n == 1) st = lbvp3_set_tile_band(s, band);
+                    }
+                    if (st == LBVP_OK && n > 1) {
+                        st = lbvp3_batch_create(sc.ctx.data(), n, vec, block, &b);
+                        if (st == LBVP_OK) st = lbvp3_batch_set_tile_band(b, band);
+                    }
+                    auto run = [&](int64_t k) {
+                        return n > 1 ? lbvp3_batch_step(b, k, 0) : lbvp3_step(sc.ctx[0], k, 0);
+                    };
+                    float best_ms = 0.0f;
+                    if (st == LBVP_OK) st = run(warm);
+                    for (int rep = 0; rep < 3 && st == LBVP_OK; ++rep) {
+                        float ms = 0.0f;
+                        if (hipEventRecord(e0, stream) != hipSuccess) st = LBVP_E_DEVICE;
+                        if (st == LBVP_OK) st = run(steps);
+                        if (st == LBVP_OK && (hipEventRecord(e1, stream) != hipSuccess ||
+                                              hipEventSynchronize(e1) != hipSuccess ||
+                                              hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                            st = LBVP_E_DEVICE;
+                        if (st == LBVP_OK && (rep == 0 || ms < best_ms)) best_ms = ms;
+                    }
+                    if (b) (void)lbvp3_batch_destroy(b);
+                    for (lbvp3_ctx* s : sc.ctx)   // drain the records of this candidate
+                        if (st == LBVP_OK) {
+                            int64_t got = 0, first = 0;
+                            const lbvp_status fs = lbvp3_forces(s, nullptr, nullptr, per_run, &got, &first);
+                            if (fs != LBVP_OK && fs != LBVP_E_UNSTABLE) st = fs;
+                        }
+                    if (st != LBVP_OK) break;
+                    const double ms_step = (double)best_ms / steps;
+                    table.push_back(lbvp3_tune_row{vec, block, band, ms_step, (double)nodes / (ms_step * 1e3)});
+                }
+            if (st != LBVP_OK) break;
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (st != LBVP_OK) return tune3_fail(st, "tuning run failed");
+        for (int32_t i = 1; i < (int32_t)table.size(); ++i)
+            if (table[i].ms_per_step < table[pick].ms_per_step) pick = i;
+        std::lock_guard<std::mutex> g(g_tune3_mu);
+        g_tune3_cache[key] = {table, pick};
+    }
+    const int32_t k = std::min<int32_t>(cap, (int32_t)table.size());
+    for (int32_t i = 0; i < k; ++i) rows[i] = table[i];
+    *n_rows = (int32_t)table.size();
+    *best = pick;
+    return LBVP_OK;
+}
+
+const char* lbvp3_tune_last_error(void) { return g_tune3_error.c_str(); }
 
 }  // extern "C"

@@ -24,8 +24,10 @@ SYMBOLS = ["lbvp3_footprint_bytes", "lbvp3_create", "lbvp3_set_mask", "lbvp3_ini
            "lbvp3_set_launch", "lbvp3_get_launch", "lbvp3_set_tile_band", "lbvp3_get_tile_band",
            "lbvp3_step_count", "lbvp3_synchronize", "lbvp3_destroy", "lbvp3_save_state", "lbvp3_load_state",
            "lbvp3_last_error", "lbvp3_batch_create", "lbvp3_batch_step", "lbvp3_batch_set_tile_band",
-           "lbvp3_batch_get_tile_band", "lbvp3_batch_destroy", "lbvp3_batch_last_error"]
-NO_STATUS = ("lbvp3_footprint_bytes", "lbvp3_step_count", "lbvp3_last_error", "lbvp3_batch_last_error")
+           "lbvp3_batch_get_tile_band", "lbvp3_batch_destroy", "lbvp3_batch_last_error", "lbvp3_tune",
+           "lbvp3_tune_last_error"]
+NO_STATUS = ("lbvp3_footprint_bytes", "lbvp3_step_count", "lbvp3_last_error", "lbvp3_batch_last_error",
+             "lbvp3_tune_last_error")
 
 
 class lbvp3_params(C.Structure):
@@ -35,6 +37,11 @@ class lbvp3_params(C.Structure):
                 ("rho_in", C.c_double), ("u_in", C.c_double * 3), ("body_force", C.c_double * 3),
                 ("storage", C.c_int32), ("force_every", C.c_int32), ("force_capacity", C.c_int64),
                 ("max_bodies", C.c_int32), ("flags", C.c_uint32)]
+
+
+class lbvp3_tune_row(C.Structure):
+    _fields_ = [("vec", C.c_int32), ("block", C.c_int32), ("band", C.c_int32),
+                ("ms_per_step", C.c_double), ("mlups", C.c_double)]
 
 
 class lbvp3_body(C.Structure):
@@ -74,6 +81,10 @@ def _load():
     L.lbvp3_batch_destroy.argtypes = [vp]
     L.lbvp3_batch_last_error.restype = C.c_char_p
     L.lbvp3_batch_last_error.argtypes = [vp]
+    L.lbvp3_tune.argtypes = [C.POINTER(vp), i32, i32, u32, C.POINTER(lbvp3_tune_row), i32, C.POINTER(i32),
+                             C.POINTER(i32)]
+    L.lbvp3_tune_last_error.restype = C.c_char_p
+    L.lbvp3_tune_last_error.argtypes = []
     for name in SYMBOLS:
         if name not in NO_STATUS:
             getattr(L, name).restype = C.c_int
@@ -243,6 +254,21 @@ def lbvp3_batch_destroy(batch):
         _check_batch(None, _L.lbvp3_batch_destroy(batch))
 
 
+def lbvp3_tune(ctxs, steps: int = 20, flags: int = 0):
+    """(rows as dicts, index of the fastest row)."""
+    arr = (C.c_void_p * len(ctxs))(*ctxs)
+    cap = 64
+    rows = (lbvp3_tune_row * cap)()
+    n_rows, best = C.c_int32(), C.c_int32()
+    st = _L.lbvp3_tune(arr, len(ctxs), int(steps), int(flags), rows, cap, C.byref(n_rows), C.byref(best))
+    if st != OK:
+        msg = _L.lbvp3_tune_last_error()
+        raise LbvpError(st, msg.decode() if msg else "")
+    out = [{"vec": r.vec, "block": r.block, "band": r.band, "ms_per_step": r.ms_per_step, "mlups": r.mlups}
+           for r in rows[:min(n_rows.value, cap)]]
+    return out, best.value
+
+
 # ------------------------------------------------------------ convenience --
 
 def params_for(prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
@@ -365,3 +391,11 @@ class Batch3:
             self.close()
         except Exception:
             pass
+
+
+def tune(solvers, steps: int = 20, fresh: bool = False):
+    """Time every launch shape and band for these solvers (run together as a
+    batch when there are several); returns (rows, best row). The solvers are not
+    stepped."""
+    rows, best = lbvp3_tune([s.ctx for s in solvers], steps, _base.TUNE_FRESH if fresh else 0)
+    return rows, rows[best]

@@ -172,3 +172,36 @@ def test_whole_ensemble_in_one_batch(lbvp3, ref3, storage, launch, band):
     for m in members:
         m.close()
     torch.cuda.empty_cache()
+
+
+def test_tuner(lbvp3):
+    """lbvp3_tune: one row per built shape and band, the pick is the fastest, the
+    members are not stepped, a repeated call returns the cached rows, one member
+    is timed alone; mixed members are rejected."""
+    probs = _members()[:3]
+    stream = torch.cuda.Stream()
+    members = [lbvp3.Solver3(p, storage="f16", force_every=1, force_capacity=16, stream=stream) for p in probs]
+    members[0].step(3)
+    before = members[0].populations()
+    rows, best = lbvp3.tune(members, steps=4, fresh=True)
+    print(f"tuner rows {len(rows)} best {best}", flush=True)
+    assert {(r["vec"], r["block"], r["band"]) for r in rows} == \
+        {(v, b, band) for v in (1, 4, 8) for b in (64, 128, 256) for band in (0, 2, 16)}
+    assert best["ms_per_step"] == min(r["ms_per_step"] for r in rows) and all(r["mlups"] > 0 for r in rows)
+    assert members[0].step_count == 3 and np.array_equal(members[0].populations(), before)
+    assert lbvp3.tune(members, steps=4)[0] == rows
+    for m in members[1:]:
+        m.step(3)
+    batch = lbvp3.Batch3(members, best["vec"], best["block"])
+    batch.set_tile_band(best["band"])
+    batch.step(2)
+    assert all(m.step_count == 5 for m in members)
+    batch.close()
+    alone, _ = lbvp3.tune([members[1]], steps=4, fresh=True)
+    assert len(alone) == len(rows)
+    other = lbvp3.Solver3(probs[0], storage="f32", stream=stream)
+    with pytest.raises(lbvp3.LbvpError) as e:
+        lbvp3.tune([members[0], other], steps=4)
+    assert e.value.status == lbvp3.E_ARG
+    for s in members + [other]:
+        s.close()
