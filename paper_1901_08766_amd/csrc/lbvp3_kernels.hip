@@ -409,16 +409,23 @@ __device__ __forceinline__ void finalize3(const Fin3Args& f, int buf, int part, 
     __syncthreads();
     if (!*flag) return;
     __threadfence();   // the other blocks' rows are visible from here on
+    // each column of the N_LEAD rows fetched at once into lds, then added in
+    // row order by one thread
+    int64_t r = 0;
+    if (threadIdx.x == 0) r = *f.rec_count % f.capacity;
+    double mass = 0.0;
+    for (int col = 0; col < 1 + 3 * f.n_bodies; ++col) {
+        __syncthreads();   // lds free from the previous column
+        if ((int)threadIdx.x < N_LEAD) lds[threadIdx.x] = f.stage[(int64_t)threadIdx.x * row_len + col];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double x = 0.0;
+            for (int p = 0; p < N_LEAD; ++p) x += lds[p];
+            if (col == 0) mass = x;
+            else f.ring_force[(r * f.max_bodies + (col - 1) / 3) * 3 + (col - 1) % 3] = x;
+        }
+    }
     if (threadIdx.x == 0) {
-        const int64_t r = *f.rec_count % f.capacity;
-        double mass = 0.0;
-        for (int p = 0; p < N_LEAD; ++p) mass += f.stage[(int64_t)p * row_len];
-        for (int b = 0; b < f.n_bodies; ++b)
-            for (int c = 0; c < 3; ++c) {
-                double x = 0.0;
-                for (int p = 0; p < N_LEAD; ++p) x += f.stage[(int64_t)p * row_len + 1 + 3 * b + c];
-                f.ring_force[(r * f.max_bodies + b) * 3 + c] = x;
-            }
         f.ring_mass[r] = f.mass_offset + mass;
         *f.rec_count += 1;
         *f.arrivals = 0;
