@@ -374,33 +374,76 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     }
 }
 
+// tree_sum's binary tree over FIN_LANES virtual lanes, with the same pairwise
+// additions (lane v takes lane v + w, w = FIN_LANES / 2 .. 1), where thread t
+// holds lanes t + k * blockDim in h[k]: levels w >= blockDim inside each thread,
+// levels 64 <= w < blockDim through lds, the last six by wave shuffles. The sum
+// is bitwise tree_sum's and lands in thread 0 only.
+constexpr int SERIAL_H = FIN_LANES / 64;
+__device__ __forceinline__ double serial_tree(double (&h)[SERIAL_H], double* lds)
+{
+    const int bd = (int)blockDim.x, t = (int)threadIdx.x;
+    const int nh = FIN_LANES / bd;
+#pragma unroll
+    for (int k = SERIAL_H / 2; k > 0; k >>= 1)
+        if (k < nh)
+#pragma unroll
+            for (int i = 0; i < k; ++i) h[i] += h[i + k];
+    for (int w = bd / 2; w >= 64; w >>= 1) {
+        __syncthreads();   // lds free from the previous level or sum
+        if (t >= w && t < 2 * w) lds[t - w] = h[0];
+        __syncthreads();
+        if (t < w) h[0] += lds[t];
+    }
+    double v = h[0];
+#pragma unroll
+    for (int w = 32; w > 0; w >>= 1) v += __shfl_down(v, w, 64);
+    return v;
+}
+
 // One record: mass and the force on each body, each summed in an order fixed by
 // the partials alone, so that neither the block size of the launch that runs it
 // nor the way steps are split over calls changes a record by one bit. Block
 // `part` of N_LEAD sums its fixed slice of every partial list (FIN_LANES virtual
-// lanes, then a binary tree in lds, which holds FIN_LANES doubles) into its stage
-// row; the last block to arrive adds the N_LEAD rows in block order.
+// lanes, then their binary tree, serial_tree) into its stage row; the last
+// block to arrive adds the N_LEAD rows in block order.
 __device__ __forceinline__ void finalize3(const Fin3Args& f, int buf, int part, double* lds, int* flag)
 {
     const double* pm = f.mass_part + buf * f.mass_stride;
     const double* sf = f.slot_force + buf * f.slot_stride;
     const int row_len = 1 + 3 * f.max_bodies;
     double* row = f.stage + (int64_t)part * row_len;
+    const int bd = (int)blockDim.x, t = (int)threadIdx.x, nh = FIN_LANES / bd;
     const int m0 = (int)((int64_t)f.n_mass * part / N_LEAD), m1 = (int)((int64_t)f.n_mass * (part + 1) / N_LEAD);
-    for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) lds[v] = lane_sum(pm + m0, m1 - m0, v);
-    const double m = tree_sum(lds);
-    if (threadIdx.x == 0) row[0] = m;
-    for (int b = 0; b < f.n_bodies; ++b) {
+    {
+        double h[SERIAL_H];
+#pragma unroll
+        for (int k = 0; k < SERIAL_H; ++k) h[k] = k < nh ? lane_sum(pm + m0, m1 - m0, t + k * bd) : 0.0;
+        const double m = serial_tree(h, lds);
+        if (t == 0) row[0] = m;
+    }
+    for (int b = 0; b < f.n_bodies; ++b) {   // one pass over the slice serves three components
         const int s0 = f.body_slot_ptr[b], n = f.body_slot_ptr[b + 1] - s0;
         const int a0 = s0 + (int)((int64_t)n * part / N_LEAD), a1 = s0 + (int)((int64_t)n * (part + 1) / N_LEAD);
+        double h[3][SERIAL_H];
+#pragma unroll
+        for (int k = 0; k < SERIAL_H; ++k) {
+            double y0 = 0.0, y1 = 0.0, y2 = 0.0;
+            if (k < nh)
+                for (int kk = a0 + t + k * bd; kk < a1; kk += FIN_LANES) {
+                    const double* p = sf + 3 * f.body_slots[kk];
+                    y0 += p[0];
+                    y1 += p[1];
+                    y2 += p[2];
+                }
+            h[0][k] = y0;
+            h[1][k] = y1;
+            h[2][k] = y2;
+        }
+#pragma unroll
         for (int c = 0; c < 3; ++c) {
-            for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
-                double x = 0.0;
-                for (int kk = a0 + v; kk < a1; kk += FIN_LANES) x += sf[3 * f.body_slots[kk] + c];
-                lds[v] = x;
-            }
-            const double X = tree_sum(lds);
-            if (threadIdx.x == 0) row[1 + 3 * b + c] = X;
+            const double X = serial_tree(h[c], lds);
+            if (t == 0) row[1 + 3 * b + c] = X;
         }
     }
     __threadfence();   // publish the row before counting in
@@ -430,33 +473,6 @@ __device__ __forceinline__ void finalize3(const Fin3Args& f, int buf, int part, 
         *f.rec_count += 1;
         *f.arrivals = 0;
     }
-}
-
-// tree_sum's binary tree over FIN_LANES virtual lanes, with the same pairwise
-// additions (lane v takes lane v + w, w = FIN_LANES / 2 .. 1), where thread t
-// holds lanes t + k * blockDim in h[k]: levels w >= blockDim inside each thread,
-// levels 64 <= w < blockDim through lds, the last six by wave shuffles. The sum
-// is bitwise tree_sum's and lands in thread 0 only.
-constexpr int SERIAL_H = FIN_LANES / 64;
-__device__ __forceinline__ double serial_tree(double (&h)[SERIAL_H], double* lds)
-{
-    const int bd = (int)blockDim.x, t = (int)threadIdx.x;
-    const int nh = FIN_LANES / bd;
-#pragma unroll
-    for (int k = SERIAL_H / 2; k > 0; k >>= 1)
-        if (k < nh)
-#pragma unroll
-            for (int i = 0; i < k; ++i) h[i] += h[i + k];
-    for (int w = bd / 2; w >= 64; w >>= 1) {
-        __syncthreads();   // lds free from the previous level or sum
-        if (t >= w && t < 2 * w) lds[t - w] = h[0];
-        __syncthreads();
-        if (t < w) h[0] += lds[t];
-    }
-    double v = h[0];
-#pragma unroll
-    for (int w = 32; w > 0; w >>= 1) v += __shfl_down(v, w, 64);
-    return v;
 }
 
 // The same record by one block: the N_LEAD slice sums of finalize3 formed in
