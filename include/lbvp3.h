@@ -105,9 +105,13 @@ lbvp_status lbvp3_init_equilibrium(lbvp3_ctx* ctx, const double* rho, const doub
                                    const double* uz);
 
 /* Enqueue n_steps time steps. flags: LBVP_KEEP_FIELDS (store rho, u, F_VP of the
- * call's last step). Asynchronous. Errors: E_ARG (n_steps < 0, unknown flag),
- * E_STATE (the records this call would produce do not fit the undrained ring),
- * E_DEVICE. */
+ * call's last step); LBVP_GRAPH (as for lbvp_step: each run of up to 512 steps is
+ * captured once per distinct launch sequence, at most 8 kept per context, and
+ * replayed; bitwise the plain call's results; a new launch shape, tile band,
+ * mask or loaded state drops the kept graphs; needs a stream other than the
+ * null stream). Asynchronous. Errors: E_ARG (n_steps < 0, unknown flag, graph on
+ * the null stream), E_STATE (the records this call would produce do not fit the
+ * undrained ring), E_DEVICE. */
 lbvp_status lbvp3_step(lbvp3_ctx* ctx, int64_t n_steps, uint32_t flags);
 
 /* Drain the force records produced since the last call, oldest first.

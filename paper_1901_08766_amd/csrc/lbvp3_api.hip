@@ -14,6 +14,7 @@
 
 #include "lbvp3.h"
 #include "lbvp3_internal.h"
+#include "lbvp_graph.h"
 
 using namespace lbvp3;
 
@@ -24,7 +25,8 @@ constexpr size_t STAGE_MIN_BYTES = size_t(64) << 20;
 constexpr int64_t DEFAULT_CAPACITY = 4096;
 constexpr int32_t DEFAULT_MAX_BODIES = 8;
 constexpr int32_t MAX_BODIES = 255;
-constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS;
+constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS | LBVP_GRAPH;
+constexpr int64_t GRAPH_CHUNK = 512;   // steps per captured graph; longer calls replay it
 constexpr int32_t VECS[3] = {1, 2, 4};
 constexpr int32_t BLOCKS[3] = {64, 128, 256};
 
@@ -201,9 +203,17 @@ struct lbvp3_ctx {
     Step3Args<double> a64{};
     Step3Args<float> a32{};
     Fin3Args fin{};
+    lbvp_host::GraphCache graphs;   // captured chunks of steps (LBVP_GRAPH)
+    uint64_t gen = 0;               // kernel-argument generation (graph keys)
     std::string err;
 
     template <typename T> T* at(size_t off) { return reinterpret_cast<T*>(mem + off); }
+    // captured graphs hold the old kernel arguments
+    void args_changed()
+    {
+        graphs.clear(stream);
+        gen += 1;
+    }
     bool is_f64() const { return p.storage == LBVP_F64; }
     size_t rsize() const { return arith_bytes(p.storage); }
     lbvp_status fail(lbvp_status s, const std::string& m)
@@ -528,6 +538,7 @@ lbvp_status lbvp3_set_mask(lbvp3_ctx* c, const uint8_t* body_id, int32_t n_bodie
     const Layout3& L = c->L;
     if (!body_id) return c->fail(LBVP_E_ARG, "body_id is NULL");
     if (n_bodies < 0 || n_bodies > L.max_bodies) return c->fail(LBVP_E_ARG, "n_bodies out of range (see max_bodies)");
+    c->args_changed();   // the body count and tables the graphs hold change
     if (n_bodies > 0 && !bodies) return c->fail(LBVP_E_ARG, "bodies is NULL");
     for (int32_t b = 0; b < n_bodies; ++b)
         for (int d = 0; d < 3; ++d)
@@ -614,29 +625,95 @@ lbvp_status lbvp3_step(lbvp3_ctx* c, int64_t n_steps, uint32_t flags)
     const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
     c->a64.fin = c->fin;
     c->a32.fin = c->fin;
-    for (int64_t k = 0; k < n_steps; ++k) {
-        const int64_t next = c->step + 1;
-        const bool record = fe > 0 && next % fe == 0;
-        const bool keep_here = keep && k == n_steps - 1;
-        const int32_t part_buf = (int32_t)(c->rec_head & 1);
-        c->a64.part_buf = c->a32.part_buf = part_buf;
-        c->a64.fin_buf = c->a32.fin_buf = c->pending ? c->pending_buf : -1;
-        hipError_t e = launch_step3(c->p.storage, record, keep_here, c->at<char>(c->L.lat[c->cur]),
-                                    c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
-        if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
-        c->pending = record;
-        if (record) {
-            c->pending_buf = part_buf;
-            c->rec_head += 1;
+    // n steps, the last keeping the fields if asked, and the call's last record summed
+    auto enqueue = [&](int64_t n, bool keep_last) -> lbvp_status {
+        for (int64_t k = 0; k < n; ++k) {
+            const int64_t next = c->step + 1;
+            const bool record = fe > 0 && next % fe == 0;
+            const bool keep_here = keep_last && k == n - 1;
+            const int32_t part_buf = (int32_t)(c->rec_head & 1);
+            c->a64.part_buf = c->a32.part_buf = part_buf;
+            c->a64.fin_buf = c->a32.fin_buf = c->pending ? c->pending_buf : -1;
+            hipError_t e = launch_step3(c->p.storage, record, keep_here, c->at<char>(c->L.lat[c->cur]),
+                                        c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "step kernel launch");
+            c->pending = record;
+            if (record) {
+                c->pending_buf = part_buf;
+                c->rec_head += 1;
+            }
+            if (keep_here) c->fields_valid = true;
+            c->cur ^= 1;
+            c->step = next;
         }
-        if (keep_here) c->fields_valid = true;
-        c->cur ^= 1;
-        c->step = next;
-    }
-    if (c->pending) {   // the last record of the call is summed on its own
-        hipError_t e = launch_finalize3(c->fin, c->pending_buf, c->stream);
-        if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
-        c->pending = false;
+        if (c->pending) {   // the last record of the call is summed on its own
+            hipError_t e = launch_finalize3(c->fin, c->pending_buf, c->stream);
+            if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
+            c->pending = false;
+        }
+        return LBVP_OK;
+    };
+    if (!(flags & LBVP_GRAPH)) return enqueue(n_steps, keep);
+    if (!c->stream) return c->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
+    for (int64_t done = 0; done < n_steps;) {
+        const int64_t n = std::min(GRAPH_CHUNK, n_steps - done);
+        const bool keep_here = keep && done + n == n_steps;
+        lbvp_host::GraphKey key;   // every call starts with its records summed
+        key.n = n;
+        key.keep = keep_here;
+        key.cur = c->cur;
+        key.phase = fe > 0 ? c->step % fe : 0;
+        key.rec = (int32_t)(c->rec_head & 1);
+        key.gen = c->gen;
+        hipGraphExec_t x = c->graphs.find(key);
+        if (x) {
+            LBVP3_HIP(c, hipGraphLaunch(x, c->stream));
+            // advance the host bookkeeping exactly as the captured launches did
+            const int cur0 = c->cur;
+            const int64_t step0 = c->step, head0 = c->rec_head;
+            const int64_t recs = fe > 0 ? (step0 + n) / fe - step0 / fe : 0;
+            c->cur = (int)((cur0 + n) & 1);
+            c->step = step0 + n;
+            c->rec_head = head0 + recs;
+            c->pending = false;
+            if (recs > 0) c->pending_buf = (int32_t)((c->rec_head - 1) & 1);
+            if (keep_here) c->fields_valid = true;
+        } else {
+            const int cur0 = c->cur;
+            const int64_t step0 = c->step, head0 = c->rec_head;
+            const bool pend0 = c->pending, fields0 = c->fields_valid;
+            const int32_t buf0 = c->pending_buf;
+            auto restore = [&]() {
+                c->cur = cur0;
+                c->step = step0;
+                c->rec_head = head0;
+                c->pending = pend0;
+                c->fields_valid = fields0;
+                c->pending_buf = buf0;
+            };
+            LBVP3_HIP(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            const lbvp_status st = enqueue(n, keep_here);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(c->stream, &g);
+            if (st != LBVP_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                restore();
+                return st != LBVP_OK ? st : c->hip_fail(e, "hipStreamEndCapture");
+            }
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                restore();
+                return c->hip_fail(e, "hipGraphInstantiate");
+            }
+            c->graphs.put(key, x, c->stream);
+            e = hipGraphLaunch(x, c->stream);
+            if (e != hipSuccess) {
+                restore();
+                return c->hip_fail(e, "hipGraphLaunch");
+            }
+        }
+        done += n;
     }
     return LBVP_OK;
 }
@@ -751,6 +828,7 @@ lbvp_status lbvp3_set_launch(lbvp3_ctx* c, int32_t vec, int32_t block)
     LBVP3_HIP(c, hipStreamSynchronize(c->stream));   // running steps still read the old tables
     Launch3 l = make_launch(c->p.nx, c->L.rows, vec, block);
     l.band = c->launch.band;
+    c->args_changed();
     return apply_launch(c, l);
 }
 
@@ -770,6 +848,7 @@ lbvp_status lbvp3_set_tile_band(lbvp3_ctx* c, int32_t band)
     c->launch.band = band;
     fill_args(c, c->a64);
     fill_args(c, c->a32);
+    c->args_changed();
     return LBVP_OK;
 }
 
@@ -948,7 +1027,7 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
 {
     if (!b) return LBVP_E_ARG;
     if (n_steps < 0) return b->fail(LBVP_E_ARG, "n_steps < 0");
-    if (flags & ~KNOWN_STEP_FLAGS) return b->fail(LBVP_E_ARG, "unknown step flag");
+    if (flags & ~LBVP_KEEP_FIELDS) return b->fail(LBVP_E_ARG, "unknown step flag (batches take LBVP_KEEP_FIELDS only)");
     if (n_steps == 0) return LBVP_OK;
     lbvp3_ctx* c0 = b->members[0];
     const int64_t fe = c0->p.force_every;

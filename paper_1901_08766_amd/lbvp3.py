@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import lbvp as _base
-from .lbvp import BC, E_ARG, E_DEVICE, E_NOMEM, E_STATE, E_UNSTABLE, KEEP_FIELDS, OK, STORAGE, LbvpError  # noqa: F401
+from .lbvp import BC, E_ARG, E_DEVICE, E_NOMEM, E_STATE, E_UNSTABLE, GRAPH, KEEP_FIELDS, OK, STORAGE, LbvpError  # noqa: F401
 
 Q = 19
 FIELD_NAMES = ("rho", "ux", "uy", "uz", "fx", "fy", "fz")
@@ -309,8 +309,8 @@ class Solver3:
     def footprint(self) -> int:
         return lbvp3_footprint_bytes(self.params)
 
-    def step(self, n: int, keep_fields: bool = False):
-        lbvp3_step(self.ctx, n, KEEP_FIELDS if keep_fields else 0)
+    def step(self, n: int, keep_fields: bool = False, graph: bool = False):
+        lbvp3_step(self.ctx, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0))
 
     def forces(self, cap: Optional[int] = None):
         return lbvp3_forces(self.ctx, self.n_bodies, cap or (self.params.force_capacity or 4096))

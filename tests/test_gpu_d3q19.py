@@ -378,3 +378,40 @@ def test_checkpoint_rejections(lbvp3):
     assert a.step_count == 3
     for s in (a, other_grid, other_type):
         s.close()
+
+
+@pytest.mark.parametrize("storage,force_every", [("f32", 1), ("f64", 3), ("f16", 2)])
+def test_graph_steps_bitwise_equal(lbvp3, storage, force_every):
+    """LBVP_GRAPH: the same calls through captured graphs give bitwise the plain
+    calls' populations, fields and records. Each chunk shape is replayed several
+    times with plain steps, reads and synchronizations between the replays, and
+    every replay is checked; a new band and launch shape drop the graphs."""
+    prob = inputs3.random_state_problem3(40, 24, 20, seed=8, n_spheres=3, body_force=(1e-5, 0.0, -2e-6))
+    plan = ([(7, False, True)] * 4 + [(4, False, False), (7, True, True)] + [(7, False, True)] * 2 +
+            [(1, False, False), (7, True, True), ("band", 8)] + [(7, False, True)] * 3 +
+            [("launch", (1, 64))] + [(7, True, True)] * 3)
+    runs = []
+    for use_graph in (False, True):
+        s = lbvp3.Solver3(prob, storage=storage, force_every=force_every, force_capacity=128)
+        checks = []
+        for item in plan:
+            if item[0] == "band":
+                s.set_tile_band(item[1])
+                continue
+            if item[0] == "launch":
+                s.set_launch(*item[1])
+                continue
+            n, keep, graphed = item
+            print(f"graph={use_graph} {storage} n={n} keep={keep} graphed={graphed}", flush=True)
+            s.step(n, keep_fields=keep, graph=use_graph and graphed)
+            f, m, first = s.forces()
+            checks.append((s.step_count, s.populations(), s.fields() if keep else None, f, m, first))
+        runs.append(checks)
+        s.close()
+    for k, (a, b) in enumerate(zip(*runs)):
+        assert a[0] == b[0], k
+        assert np.array_equal(a[1], b[1]), k
+        if a[2] is not None:
+            for name in a[2]:
+                assert np.array_equal(a[2][name], b[2][name]), (k, name)
+        assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]) and a[5] == b[5], k
