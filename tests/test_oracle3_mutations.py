@@ -44,6 +44,10 @@ MUTANTS = [
     ("reported velocity before the correction", "fields[1 + d] = u[d];", "fields[1 + d] = u[d] - c * 0.5 * fvp[d] / fields[0];"),
     ("outflow from wrong column", "si = si < 0 ? 0 : nx - 1;", "si = si < 0 ? 0 : nx - 2;"),
     ("inflow at rho0", "return feq3_one(a, c->p.rho_in, c->p.u_in);", "return feq3_one(a, c->p.rho0, c->p.u_in);"),
+    ("sampled step in the first plane", "node3_update(c, g, xs[k], ys[k], zs[k], gout + Q3 * k, fl);",
+     "node3_update(c, g, xs[k], ys[k], 0, gout + Q3 * k, fl);"),
+    ("sampled step with x and y swapped", "node3_update(c, g, xs[k], ys[k], zs[k], gout + Q3 * k, fl);",
+     "node3_update(c, g, ys[k] % c->p.nx, xs[k] % c->p.ny, zs[k], gout + Q3 * k, fl);"),
 ]
 
 
@@ -61,7 +65,8 @@ def _run_mutant(case, tmpdir):
                     "-o", so_path, c_path, "-lm"], check=True)
     env = dict(os.environ, LBVP3_REF_LIB=so_path, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        "-m", "not slow", os.path.join(ROOT, "tests", "test_oracle3.py")],
+                        "-m", "not slow", os.path.join(ROOT, "tests", "test_oracle3.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_step_nodes.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 

@@ -46,6 +46,10 @@ MUTANTS = [
     ("moving mask one step behind", "const double t = (double)(c->step + 1);", "const double t = (double)(c->step);"),
     ("moving mask rounded down", "const double ir = floor(xr + 0.5), jr = floor(yr + 0.5);",
      "const double ir = floor(xr), jr = floor(yr);"),
+    ("sampled step one time level behind",
+     "node_update(c, g, xs[k], ys[k], (double)(c->step + 1), gout + Q * k, fl);",
+     "node_update(c, g, xs[k], ys[k], (double)(c->step), gout + Q * k, fl);"),
+    ("sampled step fields at the wrong stride", "fields[5 * k + q] = fl[q];", "fields[4 * k + q] = fl[q];"),
 ]
 
 
@@ -66,7 +70,8 @@ def _run_mutant(case, tmpdir):
                         "-m", "not slow",
                         os.path.join(ROOT, "tests", "test_oracle_node.py"),
                         os.path.join(ROOT, "tests", "test_oracle_grid.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_moving.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_moving.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_step_nodes.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return name, r.returncode
 

@@ -1,0 +1,101 @@
+"""The oracle's sampled single-node step (``step_nodes``), which every sampled
+check of a large or maximum-size GPU run rests on, must compute exactly what the
+whole-domain step computes (Sec. 2.2, steps (2)-(6)): stepping every node of a
+small domain from the current populations gives, bitwise, the populations and
+fields of one ``step`` call. The cases cover fixed masks with rotating and
+translating surfaces, inflow/outflow and periodic sides, a body force, moving
+masks (whose membership and obstacle velocity depend on the time level of the
+step) and the D3Q19 twin; the grids are not square, so swapped coordinates
+show up too.
+"""
+import numpy as np
+import pytest
+
+from paper_1901_08766_amd import inputs, inputs3
+
+IO = ("inflow_eq", "outflow_zero_grad", "periodic", "periodic")
+OI = ("outflow_zero_grad", "inflow_eq", "periodic", "periodic")
+
+CASES_2D = [
+    ("io_rotating", lambda: inputs.random_state_problem(23, 17, seed=31, n_disks=3, bc=IO,
+                                                         body_force=(1e-5, -4e-6)), 3),
+    ("reversed_sides", lambda: inputs.random_state_problem(19, 26, seed=32, n_disks=2, bc=OI), 2),
+    ("periodic", lambda: inputs.random_state_problem(21, 13, seed=33, n_disks=2, bc=("periodic",) * 4), 4),
+    ("moving_bodies", lambda: inputs.moving_bodies(nx=160, ny=96, seed=7), 5),
+    ("moving_bodies_io", lambda: inputs.moving_bodies(nx=160, ny=96, seed=8, bc=IO, u_in=0.03), 1),
+]
+
+
+def _all_nodes_2d(nx, ny):
+    ys, xs = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    return xs.ravel(), ys.ravel()
+
+
+@pytest.mark.parametrize("name,make,pre", CASES_2D, ids=[c[0] for c in CASES_2D])
+def test_step_nodes_equals_the_whole_step(oracle, name, make, pre):
+    p = make()
+    s = oracle.RefSolver(p)
+    s.step(pre)
+    g = s.populations()
+    xs, ys = _all_nodes_2d(p.nx, p.ny)
+    got, fl = s.step_nodes(g, xs, ys)
+    assert s.step_count == pre                      # the context's own state is untouched
+    assert np.array_equal(s.populations(), g)
+    s.step(1)
+    want = s.populations().reshape(9, -1).T         # [node][q], node = j nx + i
+    assert np.array_equal(got, want), name
+    fields = s.fields()
+    for q, key in enumerate(("rho", "ux", "uy", "fx", "fy")):
+        assert np.array_equal(fl[:, q], fields[key].ravel()), (name, key)
+    if name.startswith("moving"):
+        # the step is taken at the time level it produces: its membership is
+        # chi(x, t + 1), which differs from chi(x, t) somewhere once bodies move
+        solid = fields["fx"] != 0.0
+        t1 = np.array([[s.body_at(i, j, pre + 1) > 0 for i in range(p.nx)] for j in range(p.ny)])
+        assert np.array_equal(solid, t1)
+    s.close()
+
+
+def test_step_nodes_of_a_subset_in_any_order(oracle):
+    p = inputs.random_state_problem(29, 11, seed=34, n_disks=3, bc=IO)
+    s = oracle.RefSolver(p)
+    s.step(2)
+    g = s.populations()
+    rng = np.random.Generator(np.random.PCG64(35))
+    xs = rng.integers(0, p.nx, 40)
+    ys = rng.integers(0, p.ny, 40)
+    got, _ = s.step_nodes(g, xs, ys)
+    s.step(1)
+    whole = s.populations()
+    assert np.array_equal(got, whole[:, ys, xs].T)
+    with pytest.raises(ValueError):
+        s.step_nodes(g, [p.nx], [0])
+    s.close()
+
+
+CASES_3D = [
+    ("io_turning", lambda: inputs3.random_state_problem3(13, 9, 7, seed=36, n_spheres=3,
+                                                          body_force=(1e-5, 0.0, -3e-6)), 2),
+    ("reversed_sides", lambda: inputs3.random_state_problem3(9, 11, 6, seed=37, n_spheres=2,
+                                                              bc=("outflow_zero_grad", "inflow_eq")), 3),
+    ("periodic", lambda: inputs3.random_state_problem3(8, 7, 10, seed=38, n_spheres=2,
+                                                        bc=("periodic", "periodic")), 1),
+]
+
+
+@pytest.mark.parametrize("name,make,pre", CASES_3D, ids=[c[0] for c in CASES_3D])
+def test_step_nodes3_equals_the_whole_step(ref3, name, make, pre):
+    p = make()
+    s = ref3.RefSolver3(p)
+    s.step(pre)
+    g = s.populations()
+    zs, ys, xs = np.meshgrid(np.arange(p.nz), np.arange(p.ny), np.arange(p.nx), indexing="ij")
+    got, fl = s.step_nodes(g, xs.ravel(), ys.ravel(), zs.ravel())
+    assert np.array_equal(s.populations(), g)
+    s.step(1)
+    want = s.populations().reshape(19, -1).T
+    assert np.array_equal(got, want), name
+    fields = s.fields()
+    for q, key in enumerate(("rho", "ux", "uy", "uz", "fx", "fy", "fz")):
+        assert np.array_equal(fl[:, q], fields[key].ravel()), (name, key)
+    s.close()
