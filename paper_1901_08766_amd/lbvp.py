@@ -475,7 +475,10 @@ class Solver:
     """A context for one ``Problem``; device memory from torch, stream from torch."""
 
     def __init__(self, prob, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
-                 flags: int = 0, stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda"):
+                 flags: int = 0, stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda",
+                 mem_fill: Optional[int] = None):
+        """mem_fill: a byte value written over the whole device allocation before
+        the context is created (0xFF makes every unwritten element a NaN)."""
         self.prob = prob
         self.nx, self.ny = prob.nx, prob.ny
         self.n_bodies = prob.n_bodies
@@ -485,6 +488,9 @@ class Solver:
             raise LbvpError(E_ARG, "invalid parameters")
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.mem = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        if mem_fill is not None:
+            self.mem.fill_(int(mem_fill))
+            torch.cuda.current_stream(self.mem.device).synchronize()
         base = self.mem.data_ptr()
         aligned = (base + 255) // 256 * 256
         self.ctx = lbvp_create(self.params, self.stream.cuda_stream, aligned, nbytes)
@@ -683,10 +689,10 @@ class Slabs:
 
     def __init__(self, slab_problems, x0s, storage: str = "f32", force_every: int = 1, force_capacity: int = 0,
                  batched: bool = True, launch: Optional[Tuple[int, int]] = None, tile_band: Optional[int] = None,
-                 stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda"):
+                 stream: Optional["torch.cuda.Stream"] = None, device: str = "cuda", mem_fill: Optional[int] = None):
         self.stream = stream if stream is not None else torch.cuda.Stream(device=device)
         self.solvers = [Solver(p, storage=storage, force_every=force_every, force_capacity=force_capacity,
-                               stream=self.stream, device=device) for p in slab_problems]
+                               stream=self.stream, device=device, mem_fill=mem_fill) for p in slab_problems]
         if launch is not None:
             for s in self.solvers:
                 s.set_launch(*launch)

@@ -1,0 +1,237 @@
+"""Failure isolation. The step and the VP force of a node use only that node's
+and its neighbours' variables (Sec. 2.2), and the solves of a batch or a pool
+share launches but no data. So:
+
+- a solve that goes unstable inside a batch or a pool (a NaN in its initial
+  velocity; or tau+ = 1/2 + 1e-6 at U = 0.3, which the FP64 oracle also drives
+  to non-finite values within 500 steps) reports E_UNSTABLE from lbvp_forces /
+  lbvp_pool_forces, and every other member is bitwise its solo run;
+- device memory filled with NaN bytes before a context is created (row padding,
+  the halo columns of slab cuts, AA ghost columns, partial-sum buffers, unused
+  arena space) changes no bit of any result: no step reads memory it has not
+  written;
+- an FP64 pool solve equals the oracle to 1e-12 (the pool's results reach the
+  oracle directly, not only through single-context runs).
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1901_08766_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+IO = ("inflow_eq", "outflow_zero_grad", "periodic", "periodic")
+PER = ("periodic",) * 4
+VW = {"f64": 2, "f32": 4, "f16": 8, "bf16": 8}
+STEPS = 600
+
+
+def _nan_start():
+    p = inputs.random_state_problem(96, 40, seed=121, n_disks=2, bc=IO)
+    ux = p.ux_init.copy()
+    ux[20, 30] = np.nan
+    return dataclasses.replace(p, ux_init=ux, name="nan_start")
+
+
+def _near_inviscid():
+    p = inputs.random_state_problem(96, 40, seed=122, n_disks=2, bc=IO, u=0.3, tau_plus=0.5 + 1e-6)
+    return dataclasses.replace(p, name="tau_half_plus_1e-6")
+
+
+def _good():
+    return [
+        inputs.random_state_problem(67, 45, seed=123, n_disks=3, bc=IO, tau_plus=0.6),
+        inputs.random_state_problem(256, 24, seed=124, n_disks=2, bc=PER, body_force=(1e-5, 0.0)),
+        inputs.random_state_problem(130, 64, seed=125, n_disks=4, bc=IO, tau_plus=0.9),
+    ]
+
+
+def test_the_bad_members_are_unstable_in_the_oracle(oracle):
+    for p in (_nan_start(), _near_inviscid()):
+        r = oracle.RefSolver(p)
+        _, m = r.step(STEPS, record=True)
+        assert not np.isfinite(m[-1]), p.name
+        r.close()
+
+
+def _alone(lbvp, p, storage, flags, vec, block, steps=STEPS):
+    s = lbvp.Solver(p, storage=storage, force_every=1, force_capacity=steps + 1, flags=flags)
+    s.set_launch(vec, block)
+    s.step(steps, keep_fields=True)
+    f, m, first = s.forces()
+    out = (f, m, first, s.fields(), s.populations())
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("storage,aa", [("f32", False), ("f16", False), ("f64", True)])
+def test_unstable_members_of_a_batch_leave_the_others_unchanged(lbvp, storage, aa):
+    flags = lbvp.LAYOUT_AA if aa else 0
+    vec, block = VW[storage], 256
+    good = _good()
+    probs = [good[0], _nan_start(), good[1], _near_inviscid(), good[2]]
+    bad = {1, 3}
+    stream = torch.cuda.Stream()
+    members = [lbvp.Solver(p, storage=storage, force_every=1, force_capacity=STEPS + 1, flags=flags, stream=stream)
+               for p in probs]
+    batch = lbvp.Batch(members, vec=vec, block=block)
+    print(f"isolation batch {storage} aa={aa}: {len(members)} members, {STEPS} steps", flush=True)
+    batch.step(STEPS, keep_fields=True)
+    for k, (p, m) in enumerate(zip(probs, members)):
+        if k in bad:
+            with pytest.raises(lbvp.LbvpError) as e:
+                m.forces()
+            assert e.value.status == lbvp.E_UNSTABLE, p.name
+            continue
+        f, mass, first = m.forces()
+        fa, ma, firsta, fla, ga = _alone(lbvp, p, storage, flags, vec, block)
+        assert first == firsta == 1 and np.all(np.isfinite(mass))
+        assert np.array_equal(f, fa) and np.array_equal(mass, ma), p.name
+        fl = m.fields()
+        for key in fl:
+            assert np.array_equal(fl[key], fla[key]), (p.name, key)
+        assert np.array_equal(m.populations(), ga), p.name
+    batch.close()
+    for m in members:
+        m.close()
+
+
+def test_unstable_solves_of_a_pool_leave_the_others_unchanged(lbvp):
+    storage, vec, block = "f32", 4, 128
+    good = _good()
+    reqs = [(good[0], 300), (_nan_start(), STEPS), (good[1], 450), (_near_inviscid(), STEPS), (good[2], 520)]
+    bad = {1, 3}
+    pool = lbvp.Pool(storage=storage, cap_bytes=1 << 30, max_slots=3, vec=vec, block=block,
+                     chunk_bytes=64 << 20, max_in_flight=2)
+    pending, slot_of, results = list(range(len(reqs))), {}, {}
+    epochs = 0
+    while pending or slot_of:
+        while pending:
+            slot = pool.admit(reqs[pending[0]][0], reqs[pending[0]][1])
+            if slot is None:
+                break
+            slot_of[slot] = pending.pop(0)
+        ran = pool.run_epoch(64)
+        epochs += 1
+        for slot in pool.poll(wait=(ran == 0)):
+            k = slot_of.pop(slot)
+            try:
+                results[k] = pool.forces(slot) + (pool.fields(slot),)
+            except lbvp.LbvpError as e:
+                results[k] = e.status
+            pool.release(slot)
+        assert epochs < 1000
+    pool.close()
+    for k, (p, steps) in enumerate(reqs):
+        print(f"isolation pool request {k} {p.name} {steps} steps", flush=True)
+        if k in bad:
+            assert results[k] == lbvp.E_UNSTABLE, p.name
+            continue
+        f, m, first, fl = results[k]
+        fa, ma, firsta, fla, _ = _alone(lbvp, p, storage, 0, vec, block, steps)
+        assert np.array_equal(f, fa) and np.array_equal(m, ma), p.name
+        for key in fl:
+            assert np.array_equal(fl[key], fla[key]), (p.name, key)
+
+
+POISON_CASES = [
+    # (storage, AA layout, launch)
+    ("f32", False, (4, 128)),
+    ("f32", True, (4, 256)),
+    ("f32", False, (1, 64)),
+    ("f16", False, (8, 256)),
+    ("f16", False, (4, 256)),
+    ("bf16", True, (1, 256)),
+    ("f64", False, (2, 128)),
+    ("f64", True, (1, 64)),
+]
+
+
+@pytest.mark.parametrize("storage,aa,launch", POISON_CASES,
+                         ids=[f"{s}-{'aa' if a else 'pull'}-v{l[0]}b{l[1]}" for s, a, l in POISON_CASES])
+def test_nan_filled_memory_changes_nothing(lbvp, storage, aa, launch):
+    flags = lbvp.LAYOUT_AA if aa else 0
+    # ragged widths (padding columns inside every row), outflow sides (AA ghost
+    # columns), reversed sides, a fully periodic domain
+    probs = [inputs.random_state_problem(67, 45, seed=131, n_disks=3, bc=IO, body_force=(1e-5, -2e-6)),
+             inputs.random_state_problem(131, 9, seed=132, n_disks=2,
+                                         bc=("outflow_zero_grad", "outflow_zero_grad", "periodic", "periodic")),
+             inputs.random_state_problem(61, 37, seed=133, n_disks=2, bc=PER)]
+    for p in probs:
+        runs = []
+        for fill in (0x00, 0xFF):
+            s = lbvp.Solver(p, storage=storage, force_every=1, force_capacity=64, flags=flags, mem_fill=fill)
+            s.set_launch(*launch)
+            s.step(23)
+            s.step(9, keep_fields=True)          # an even count: AA populations are readable
+            f, m, _ = s.forces()
+            runs.append((f, m, s.fields(), s.populations()))
+            s.close()
+        (f0, m0, fl0, g0), (f1, m1, fl1, g1) = runs
+        print(f"poison {storage} aa={aa} launch={launch} {p.name}", flush=True)
+        assert np.all(np.isfinite(m1)) and np.array_equal(f0, f1) and np.array_equal(m0, m1), p.name
+        for key in fl0:
+            assert np.array_equal(fl0[key], fl1[key]), (p.name, key)
+        assert np.array_equal(g0, g1), p.name
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_nan_filled_memory_in_batches_and_slabs(lbvp, storage):
+    """Batch members and slabs (whose cut halos live in the row padding) on
+    NaN-filled memory step bitwise like the same on zeroed memory."""
+    p = inputs.random_state_problem(300, 37, seed=134, n_disks=3, bc=IO, body_force=(1e-5, -2e-6))
+    p.bodies[:, :2] = np.round(p.bodies[:, :2] * 8.0) / 8.0
+    slabs_p, x0s = inputs.split_x(p, [70, 100, 130])
+    out = []
+    for fill in (0x00, 0xFF):
+        slabs = lbvp.Slabs(slabs_p, x0s, storage=storage, force_every=1, force_capacity=64, mem_fill=fill)
+        slabs.step(20, keep_fields=True)
+        f, m = slabs.forces()
+        out.append((f, m, slabs.fields(), slabs.populations()))
+        slabs.close()
+    (f0, m0, fl0, g0), (f1, m1, fl1, g1) = out
+    assert np.array_equal(f0, f1) and np.array_equal(m0, m1)
+    for key in fl0:
+        assert np.array_equal(fl0[key], fl1[key]), key
+    assert np.array_equal(g0, g1)
+
+
+def test_fp64_pool_solves_match_the_oracle(lbvp, oracle):
+    reqs = [(inputs.random_state_problem(67, 45, seed=141, n_disks=3, bc=IO, body_force=(1e-5, -2e-6)), 40),
+            (inputs.random_state_problem(128, 32, seed=142, n_disks=2, bc=PER), 25),
+            (inputs.random_state_problem(40, 61, seed=143, n_disks=1,
+                                         bc=("outflow_zero_grad", "inflow_eq", "periodic", "periodic")), 33)]
+    pool = lbvp.Pool(storage="f64", cap_bytes=1 << 30, max_slots=2, vec=2, block=128, chunk_bytes=32 << 20)
+    pending, slot_of, results = list(range(len(reqs))), {}, {}
+    while pending or slot_of:
+        while pending:
+            slot = pool.admit(*reqs[pending[0]])
+            if slot is None:
+                break
+            slot_of[slot] = pending.pop(0)
+        ran = pool.run_epoch(16)
+        for slot in pool.poll(wait=(ran == 0)):
+            k = slot_of.pop(slot)
+            results[k] = pool.forces(slot) + (pool.fields(slot),)
+            pool.release(slot)
+    pool.close()
+    for k, (p, steps) in enumerate(reqs):
+        f, m, first, fl = results[k]
+        r = oracle.RefSolver(p)
+        rf, rm = r.step(steps, record=True)
+        fr = r.fields()
+        r.close()
+        num = np.sum((fl["ux"] - fr["ux"]) ** 2 + (fl["uy"] - fr["uy"]) ** 2)
+        den = np.sum(fr["ux"] ** 2 + fr["uy"] ** 2)
+        print(f"pool f64 request {k}: velocity rel-L2 {np.sqrt(num / den):.2e}", flush=True)
+        assert np.sqrt(num / den) <= 1e-12
+        for key in ("rho", "fx", "fy"):
+            assert np.abs(fl[key] - fr[key]).max() <= 1e-12 * max(np.abs(fr[key]).max(), 1e-30), (k, key)
+        assert first == 1 and f.shape == rf.shape and np.abs(m - rm).max() <= 1e-13 * rm.max()
+        if p.n_bodies:
+            scale = np.array([np.abs(fr["fx"][p.mask == b]).sum() + np.abs(fr["fy"][p.mask == b]).sum() + 1e-300
+                              for b in range(1, p.n_bodies + 1)])
+            assert np.all(np.abs(f - rf).max(axis=(0, 2)) <= 1e-11 * scale), k
