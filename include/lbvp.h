@@ -290,6 +290,27 @@ lbvp_status lbvp_batch_set_halo(lbvp_batch* batch, const int32_t* west, const in
 lbvp_status lbvp_batch_set_tile_band(lbvp_batch* batch, int32_t band);
 lbvp_status lbvp_batch_get_tile_band(const lbvp_batch* batch, int32_t* band);
 
+/* ---- A batched step that allocates nothing ---------------------------------------
+ * For callers that cannot allocate device or pinned host memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid it): one call of
+ * lbvp_batch_create + lbvp_batch_step + lbvp_batch_destroy on members[n]
+ * (borrowed contexts, as for a batch), with the batch's tables (each member's step
+ * and finalize arguments and the tile map) kept in a file-scope device array of
+ * 4 MiB (one copy per GPU, held until the process ends) instead of memory the
+ * library allocates. The same kernels run in the same order, so populations,
+ * fields and force records are bitwise those of lbvp_batch_step at band 0.
+ * Members must share the first member's launch shape (set beforehand with
+ * lbvp_set_launch, which may allocate) and the conditions of lbvp_batch_create.
+ * The tables go up with one host-to-device copy on the members' stream from a
+ * pageable staging block; the call returns without waiting for the steps.
+ * Every call on a GPU shares its array and rewrites all of the tables it uses,
+ * so calls that overlap on one GPU (other streams, other host threads) race.
+ * flags: LBVP_KEEP_FIELDS (LBVP_GRAPH is rejected: instantiating a graph
+ * allocates). E_ARG (tables larger than 4 MiB, with the size in the message; NULL
+ * members; mixed storage, layout, stream, cadence, phase or launch shape),
+ * E_STATE (a ring would overflow), E_DEVICE. Messages: lbvp_batch_last_error(NULL). */
+lbvp_status lbvp_batch_step_static(lbvp_ctx* const* members, int32_t n, int64_t n_steps, uint32_t flags);
+
 /* ---- Tuner ----------------------------------------------------------------------
  * Times the step kernel for every launch shape (vec x block, and for vec > 1 the
  * tile bands 0, 2 and 16 of lbvp_set_tile_band) and, with LBVP_TUNE_LAYOUTS, in

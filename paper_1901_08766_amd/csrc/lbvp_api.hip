@@ -694,16 +694,11 @@ std::string batch_consistency(const lbvp_batch* b, const std::vector<lbvp_ctx*>&
     return "";
 }
 
-// Adopt a member list: launch shapes, the tile map in the host image and a
-// device block large enough for it.
-lbvp_status batch_assign(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
+// The member list's tables in the host image: offsets of the argument blocks,
+// the finalize arguments and the tile map, and the tile map itself. The members
+// must already have the batch's launch shape. No device memory is touched.
+void batch_layout(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
 {
-    const std::string why = batch_consistency(b, m);
-    if (!why.empty()) return b->fail(LBVP_E_ARG, why);
-    for (lbvp_ctx* c : m) {
-        const lbvp_status st = lbvp_set_launch(c, b->vec, b->block);
-        if (st != LBVP_OK) return b->fail(st, std::string("setting a member's launch shape: ") + c->err);
-    }
     const size_t n = m.size();
     std::vector<int32_t> tile_start(n), tile_domain;
     for (size_t d = 0; d < n; ++d) {
@@ -718,6 +713,28 @@ lbvp_status batch_assign(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
     b->off_tile_domain = take(std::max<size_t>(tile_domain.size(), 1) * sizeof(int32_t));
     b->off_tile_start = take(std::max<size_t>(n, 1) * sizeof(int32_t));
     b->bytes = o;
+    b->image.assign(b->bytes, 0);
+    b->uploaded.clear();
+    std::memcpy(b->image.data() + b->off_tile_domain, tile_domain.data(), tile_domain.size() * sizeof(int32_t));
+    std::memcpy(b->image.data() + b->off_tile_start, tile_start.data(), n * sizeof(int32_t));
+    b->members = m;
+    b->halo_w.clear();   // member indices no longer mean the same contexts
+    b->halo_e.clear();
+    b->total_tiles = (int32_t)tile_domain.size();
+    b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
+}
+
+// Adopt a member list: launch shapes, the tables in the host image and a
+// device block large enough for them.
+lbvp_status batch_assign(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
+{
+    const std::string why = batch_consistency(b, m);
+    if (!why.empty()) return b->fail(LBVP_E_ARG, why);
+    for (lbvp_ctx* c : m) {
+        const lbvp_status st = lbvp_set_launch(c, b->vec, b->block);
+        if (st != LBVP_OK) return b->fail(st, std::string("setting a member's launch shape: ") + c->err);
+    }
+    batch_layout(b, m);
     if (b->bytes > b->dev_cap) {   // rare: grow, after the stream has finished with the old block
         b->graphs.clear(b->stream);
         if (b->dev) {
@@ -733,23 +750,14 @@ lbvp_status batch_assign(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
         b->dev = static_cast<char*>(d);
         b->dev_cap = want;
     }
-    b->image.assign(b->bytes, 0);
-    b->uploaded.clear();
-    std::memcpy(b->image.data() + b->off_tile_domain, tile_domain.data(), tile_domain.size() * sizeof(int32_t));
-    std::memcpy(b->image.data() + b->off_tile_start, tile_start.data(), n * sizeof(int32_t));
-    b->members = m;
-    b->halo_w.clear();   // member indices no longer mean the same contexts
-    b->halo_e.clear();
-    b->total_tiles = (int32_t)tile_domain.size();
-    b->tiles_per_xcd = (b->total_tiles + N_XCD - 1) / N_XCD;
     b->graphs.clear(b->stream);
     b->gen += 1;
     return LBVP_OK;
 }
 
 // The members' step and finalize arguments as of now (lattice parity, record
-// tables), uploaded if they differ from what the device block holds.
-lbvp_status batch_refresh_args(lbvp_batch* b)
+// tables) in the host image.
+void batch_fill_args(lbvp_batch* b)
 {
     for (size_t d = 0; d < b->members.size(); ++d) {
         lbvp_ctx* c = b->members[d];
@@ -776,6 +784,12 @@ lbvp_status batch_refresh_args(lbvp_batch* b)
         }
         std::memcpy(b->image.data() + b->off_fins + d * sizeof(FinalizeArgs), &c->fin, sizeof(FinalizeArgs));
     }
+}
+
+// The same, uploaded if they differ from what the device block holds.
+lbvp_status batch_refresh_args(lbvp_batch* b)
+{
+    batch_fill_args(b);
     if (b->image == b->uploaded) return LBVP_OK;
     LBVP_HIP(b, b->ring.upload(b->dev, b->image.data(), b->bytes, b->stream));
     b->uploaded = b->image;
@@ -834,6 +848,66 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
         if (e != hipSuccess) return b->hip_fail(e, "batched finalize launch");
     }
     return LBVP_OK;
+}
+
+// After a run of n_steps: the members' step counts, lattice parity, records
+// and fields, as lbvp_step would leave them.
+void batch_advance_members(lbvp_batch* b, int64_t n_steps, int64_t recs, bool keep)
+{
+    for (lbvp_ctx* c : b->members) {
+        c->step += n_steps;
+        if (!c->aa() && (n_steps & 1)) c->cur ^= 1;
+        c->rec_head += recs;
+        if (keep) c->fields_valid = true;
+    }
+}
+
+// ---- the static device array of lbvp_batch_step_static
+// For callers that cannot allocate device memory, the batch tables (argument
+// blocks, finalize arguments, tile map) of that call live in this array, one
+// copy per GPU, held until the process ends. Host code never passes the array's
+// name to a kernel or a copy: it is a host-side stand-in there. Each device's
+// address comes from hipGetSymbolAddress, taken once with that device current.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(4) << 20;
+__device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+
+struct StaticScratch {
+    char* dev = nullptr;                 // this device's copy of `scratch`
+    std::vector<char> host;              // pageable staging of the tables, STATIC_SCRATCH_BYTES
+    hipEvent_t copied = nullptr;         // recorded after the last upload from `host`
+};
+constexpr int MAX_STATIC_DEVICES = 64;
+std::mutex g_static_mu;
+StaticScratch g_static[MAX_STATIC_DEVICES];
+
+// The current device's entry, set up on its first use; "" or the reason it failed.
+std::string static_scratch(StaticScratch** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return std::string("hipGetDevice: ") + hipGetErrorString(e);
+    if (dev < 0 || dev >= MAX_STATIC_DEVICES) return "device index beyond the static table";
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    StaticScratch& s = g_static[dev];
+    if (!s.dev) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+        if (!s.copied) {
+            e = hipEventCreateWithFlags(&s.copied, hipEventDisableTiming);
+            if (e != hipSuccess) return std::string("hipEventCreate: ") + hipGetErrorString(e);
+        }
+        s.host.assign(STATIC_SCRATCH_BYTES, 0);
+        s.dev = static_cast<char*>(p);
+    }
+    *out = &s;
+    return "";
+}
+
+lbvp_status batch_static_fail(lbvp_status st, const std::string& why)
+{
+    g_batch_error = "lbvp_batch_step_static: " + why;
+    return st;
 }
 
 }  // namespace
@@ -1656,12 +1730,72 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
             k0 += n;
         }
     }
-    for (lbvp_ctx* c : b->members) {
-        c->step += n_steps;
-        if (!c->aa() && (n_steps & 1)) c->cur ^= 1;
-        c->rec_head += recs;
-        if (keep) c->fields_valid = true;
+    batch_advance_members(b, n_steps, recs, keep);
+    return LBVP_OK;
+}
+
+lbvp_status lbvp_batch_step_static(lbvp_ctx* const* members, int32_t n, int64_t n_steps, uint32_t flags)
+{
+    g_batch_error.clear();
+    if (!members || n < 1) return batch_static_fail(LBVP_E_ARG, "members[n] with n >= 1 required");
+    if (n_steps < 0) return batch_static_fail(LBVP_E_ARG, "n_steps < 0");
+    if (flags & ~KNOWN_STEP_FLAGS) return batch_static_fail(LBVP_E_ARG, "unknown step flag");
+    if (flags & LBVP_GRAPH) return batch_static_fail(LBVP_E_ARG, "LBVP_GRAPH instantiates graphs, which allocates");
+    for (int32_t i = 0; i < n; ++i)
+        if (check_ctx(members[i])) return batch_static_fail(LBVP_E_ARG, "a member is NULL or not a context");
+    const lbvp_ctx* c0 = members[0];
+    for (int32_t i = 0; i < n; ++i)
+        if (members[i]->launch.vec != c0->launch.vec || members[i]->launch.block != c0->launch.block)
+            return batch_static_fail(LBVP_E_ARG, "members need the first member's launch shape (lbvp_set_launch)");
+    // a batch object on the host only: its device block is the static array
+    lbvp_batch b;
+    b.stream = c0->stream;
+    b.storage = c0->p.storage;
+    b.aa = c0->aa();
+    b.force_every = c0->p.force_every;
+    b.vec = c0->launch.vec;
+    b.block = c0->launch.block;
+    const std::vector<lbvp_ctx*> m(members, members + n);
+    const std::string why = batch_consistency(&b, m);
+    if (!why.empty()) return batch_static_fail(LBVP_E_ARG, why);
+    if (n_steps == 0) return LBVP_OK;
+    const int64_t fe = b.force_every;
+    const int64_t step0 = c0->step;
+    const int64_t new_recs = fe > 0 ? (step0 + n_steps) / fe - step0 / fe : 0;
+    for (lbvp_ctx* c : m)
+        if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
+            return batch_static_fail(LBVP_E_STATE, "a member's force ring would overflow; drain it with lbvp_forces first");
+    batch_layout(&b, m);
+    if (b.bytes > STATIC_SCRATCH_BYTES) {
+        std::ostringstream os;
+        os << "the members' tables need " << b.bytes << " bytes, more than the " << STATIC_SCRATCH_BYTES
+           << "-byte static array (fewer members, or fewer tiles: a wider launch shape)";
+        return batch_static_fail(LBVP_E_ARG, os.str());
     }
+    StaticScratch* sc = nullptr;
+    const std::string setup = static_scratch(&sc);
+    if (!setup.empty()) return batch_static_fail(LBVP_E_DEVICE, setup);
+    batch_fill_args(&b);
+    // the previous call's copy must have read the host staging block before it
+    // is overwritten; every byte of the tables is rewritten, none is left over
+    hipError_t e = hipSuccess;
+    {
+        std::lock_guard<std::mutex> lock(g_static_mu);
+        e = hipEventSynchronize(sc->copied);
+        if (e == hipSuccess) {
+            std::memcpy(sc->host.data(), b.image.data(), b.bytes);
+            e = hipMemcpyAsync(sc->dev, sc->host.data(), b.bytes, hipMemcpyHostToDevice, b.stream);
+        }
+        if (e == hipSuccess) e = hipEventRecord(sc->copied, b.stream);
+    }
+    if (e != hipSuccess) return batch_static_fail(LBVP_E_DEVICE, std::string("uploading the tables: ") + hipGetErrorString(e));
+    b.dev = sc->dev;
+    b.dev_cap = STATIC_SCRATCH_BYTES;
+    int64_t recs = 0;
+    const lbvp_status st = batch_run(&b, step0, 0, n_steps, (flags & LBVP_KEEP_FIELDS) != 0, &recs);
+    b.dev = nullptr;   // not the batch's to free
+    if (st != LBVP_OK) return batch_static_fail(st, b.err);
+    batch_advance_members(&b, n_steps, recs, (flags & LBVP_KEEP_FIELDS) != 0);
     return LBVP_OK;
 }
 

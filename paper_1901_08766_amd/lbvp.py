@@ -44,7 +44,7 @@ SYMBOLS = ["lbvp_footprint_bytes", "lbvp_create", "lbvp_set_mask", "lbvp_init_eq
            "lbvp_pool_forces", "lbvp_pool_read_fields", "lbvp_pool_release", "lbvp_pool_get_stats",
            "lbvp_pool_destroy", "lbvp_pool_last_error", "lbvp_save_state", "lbvp_load_state",
            "lbvp_device_copy", "lbvp_halo_exchange", "lbvp_batch_set_halo", "lbvp_batch_set_tile_band",
-           "lbvp_batch_get_tile_band"]
+           "lbvp_batch_get_tile_band", "lbvp_batch_step_static"]
 NO_STATUS = ("lbvp_footprint_bytes", "lbvp_step_count", "lbvp_last_error", "lbvp_batch_last_error",
              "lbvp_tune_last_error", "lbvp_pool_last_error")
 
@@ -125,6 +125,7 @@ def _load():
     L.lbvp_device_copy.argtypes = [vp, vp, C.c_size_t, vp]
     L.lbvp_halo_exchange.argtypes = [C.POINTER(vp), C.POINTER(vp), i32]
     L.lbvp_batch_set_halo.argtypes = [vp, C.POINTER(i32), C.POINTER(i32), i32]
+    L.lbvp_batch_step_static.argtypes = [C.POINTER(vp), i32, i64, u32]
     L.lbvp_batch_set_tile_band.argtypes = [vp, i32]
     L.lbvp_batch_get_tile_band.argtypes = [vp, C.POINTER(i32)]
     L.lbvp_save_state.argtypes = [vp, vp, C.c_size_t, C.POINTER(C.c_size_t)]
@@ -347,6 +348,11 @@ def lbvp_batch_get_tile_band(batch) -> int:
 
 def lbvp_batch_step(batch, n_steps: int, flags: int = 0):
     _check_batch(batch, _L.lbvp_batch_step(batch, int(n_steps), int(flags)))
+
+
+def lbvp_batch_step_static(ctxs, n_steps: int, flags: int = 0):
+    arr = (C.c_void_p * max(len(ctxs), 1))(*ctxs)
+    _check_batch(None, _L.lbvp_batch_step_static(arr, len(ctxs), int(n_steps), int(flags)))
 
 
 def lbvp_batch_destroy(batch):
