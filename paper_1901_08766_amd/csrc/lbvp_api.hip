@@ -374,6 +374,19 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.k_p = (R)(1.0 - 0.5 / p.tau_plus);
     a.k_m = (R)(1.0 - 0.5 / c->tau_minus);
     a.vp_c = (R)(1.0 / (2.0 * p.eta + 1.0));
+    {
+        const double om_p = 1.0 / p.tau_plus, om_m = 1.0 / c->tau_minus;
+        const double k_p = 1.0 - 0.5 / p.tau_plus, k_m = 1.0 - 0.5 / c->tau_minus;
+        a.c1 = (R)(1.0 - 0.5 * (om_p + om_m));
+        a.c2 = (R)(0.5 * (om_m - om_p));
+        a.om_p1 = (R)(1.0 - om_p);
+        a.om_p45 = (R)(4.5 * om_p);
+        a.om_p15 = (R)(1.5 * om_p);
+        a.om_m3 = (R)(3.0 * om_m);
+        a.k_p9 = (R)(9.0 * k_p);
+        a.k_p3 = (R)(3.0 * k_p);
+        a.k_m3 = (R)(3.0 * k_m);
+    }
     a.fbx = (R)p.body_force[0];
     a.fby = (R)p.body_force[1];
     a.fbx18 = (R)(18.0 * p.body_force[0]);

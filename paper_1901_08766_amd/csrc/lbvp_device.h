@@ -30,6 +30,31 @@ __device__ __forceinline__ LV as_lv(S x)
 template <typename S, typename R>
 __device__ __forceinline__ S enc(R v) { return (S)v; }  // round to nearest even
 
+// Two values of a 2-byte storage type from one packed conversion (round to
+// nearest even, as enc), written to out[0], out[1]. The values are first pinned
+// as FP32 results (an empty register constraint, no instruction): otherwise the
+// compiler may fuse a conversion with the multiply-add that produced its value
+// into one mixed-precision operation that rounds once, straight to FP16, which
+// rounds some values differently from FP32-then-FP16 and would make launch
+// forms of one step disagree bitwise.
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+template <typename S>
+__device__ __forceinline__ void enc2(float a, float b, S* out)
+{
+    static_assert(sizeof(S) == 2, "packed conversion of 2-byte storage types");
+    asm("" : "+v"(a), "+v"(b));
+    const f32x2_t v = {a, b};
+    if constexpr (std::is_same<S, _Float16>::value) {
+        const f16x2_t h = __builtin_convertvector(v, f16x2_t);
+        __builtin_memcpy(out, &h, 4);
+    } else {
+        const bf16x2_t h = __builtin_convertvector(v, bf16x2_t);
+        __builtin_memcpy(out, &h, 4);
+    }
+}
+
 template <typename S> struct Arith { using R = float; };
 template <> struct Arith<double> { using R = double; };
 

@@ -71,6 +71,13 @@ struct StepArgs {
     R om_p, om_m;       // 1/tau_plus, 1/tau_minus
     R k_p, k_m;         // 1 - 1/(2 tau_plus), 1 - 1/(2 tau_minus)
     R vp_c;             // 1 / (2 eta + 1): the chi = 1 value of chi / (2 eta + chi)
+    // the collision of the 2-byte storage types, regrouped per population pair
+    // (collide_node_lowp): g_a = c1 h_a + c2 h_opp(a) + E+ + E-
+    R c1, c2;           // 1 - (om_p + om_m) / 2, (om_m - om_p) / 2
+    R om_p1;            // 1 - om_p
+    R om_p45, om_p15;   // 9/2 om_p, 3/2 om_p
+    R om_m3;            // 3 om_m
+    R k_p9, k_p3, k_m3; // 9 k_p, 3 k_p, 3 k_m
     R fbx, fby;         // body force
     R fbx18, fby18;     // 18 F_b: the body-force half step in units of 36 j
     R feq_in[9];        // (f^eq(rho_in, u_in) - w rho0) / w of an INFLOW_EQ side

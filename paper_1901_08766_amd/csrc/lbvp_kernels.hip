@@ -134,6 +134,76 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
     return {drho, rho, ux, uy, fvx, fvy};
 }
 
+// The same steps for the 2-byte storage types, whose stored values carry a
+// rounding error (~1e-3 relative) far above any FP32 arithmetic detail, in the
+// fewest operations: 1/36 and 1/rho as single roundings, the odd equilibrium as
+// (3 rho) e.u, and each pair's two relaxations regrouped into
+//   g_a     = c1 h_a + c2 h_opp + (E+ + E-),
+//   g_opp   = c2 h_a + c1 h_opp + (E+ - E-),
+//   E+ = om_p h^eq+ + k_p F+/w = eu (9/2 om_p rho eu + 9 k_p eF) + B,
+//   E- = om_m h^eq- + k_m F-/w = 3 om_m rho eu + 3 k_m eF,
+//   B  = om_p (drho - 3/2 rho u.u) - 3 k_p u.F,
+// with c1 = 1 - (om_p + om_m)/2, c2 = (om_m - om_p)/2 (algebraically the
+// relaxation of collide_pair); the rest population is g_0 = (1 - om_p) h_0 + B.
+// About 85 operations per node instead of about 125.
+template <typename R, bool MOVING = false>
+__device__ __forceinline__ NodeResult<R> collide_node_lowp(R (&f)[9], int body, int i, int j, const StepArgs<R>& a)
+{
+    const R s36 = R(16) * f[0] + (R(4) * ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+    const R drho = s36 * R(1.0 / 36.0);
+    const R rho = a.rho0 + drho;
+    const R d57 = f[5] - f[7], d86 = f[8] - f[6];
+    const R inv_36rho = __builtin_amdgcn_rcpf(R(36) * rho);
+    const R jx36 = R(4) * (f[1] - f[3]) + (d57 + d86) + a.fbx18;
+    const R jy36 = R(4) * (f[2] - f[4]) + (d57 - d86) + a.fby18;
+    R ux = jx36 * inv_36rho;
+    R uy = jy36 * inv_36rho;
+    R fvx = R(0), fvy = R(0);
+    if (body) {
+        const R* B = a.bodies + BODY_STRIDE * body;
+        R rx, ry;
+        if constexpr (MOVING) {
+            const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
+            rx = (R)((double)i - m[2]);
+            ry = (R)((double)j - m[3]);
+        } else {
+            rx = ((R)i - B[0]) - B[2];
+            ry = ((R)j - B[1]) - B[3];
+        }
+        const R uox = B[4] - B[6] * ry;
+        const R uoy = B[5] + B[6] * rx;
+        const R dux = a.vp_c * (uox - ux);
+        const R duy = a.vp_c * (uoy - uy);
+        fvx = R(2) * rho * dux;
+        fvy = R(2) * rho * duy;
+        ux += dux;
+        uy += duy;
+    }
+    const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
+    const R uu = ux * ux + uy * uy;
+    const R uF = ux * Fx + uy * Fy;
+    const R B0 = a.om_p * drho - (a.om_p15 * (rho * uu) + a.k_p3 * uF);
+    const R a1 = a.om_p45 * rho;
+    const R r3m = a.om_m3 * rho;
+    const R g0 = a.om_p1 * f[0] + B0;
+    auto pair = [&](R& ha, R& hb, R eu, R eF) {
+        const R t = a1 * eu + a.k_p9 * eF;
+        const R ep = eu * t + B0;
+        const R em = r3m * eu + a.k_m3 * eF;
+        const R sum = ep + em, dif = ep - em;
+        const R ga = a.c1 * ha + (a.c2 * hb + sum);
+        const R gb = a.c2 * ha + (a.c1 * hb + dif);
+        ha = ga;
+        hb = gb;
+    };
+    pair(f[1], f[3], ux, Fx);
+    pair(f[2], f[4], uy, Fy);
+    pair(f[5], f[7], ux + uy, Fx + Fy);
+    pair(f[6], f[8], uy - ux, Fy - Fx);
+    f[0] = g0;
+    return {drho, rho, ux, uy, fvx, fvy};
+}
+
 // Moving masks: the body occupying node (i, j) at the step's time level. Node
 // x belongs to body b when the reference (t = 0) mask holds b at the node
 // nearest to R(-th) (x - c(t)) + c(0), the node carried back by the body's
@@ -272,8 +342,8 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         s1 = a.tile_slot_ptr[t + 1];
     }
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
-    const int tpr = a.tile_w / V;                       // threads per tile row
-    const int lr = (int)threadIdx.x / tpr, lc = (int)threadIdx.x - lr * tpr;
+    const int tpr = a.tile_w / V;                       // threads per tile row (tile_w and V are powers of two)
+    const int lr = (int)threadIdx.x >> __builtin_ctz((unsigned)tpr), lc = (int)threadIdx.x & (tpr - 1);
     const int j = min(ty * a.tile_rows + lr, a.ny - 1); // rows past ny idle (clamped for addressing)
     const int i0 = tx * a.tile_w + lc * V;
     const int lane = (int)(threadIdx.x & 63);
@@ -307,20 +377,25 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     using LV = typename std::conditional<kShifted, R, S>::type;
     LV v[9][V];
     int body[V];
-    if (act) {
+    // Threads without a node of their own (past the last column or row) load
+    // column 0 of their (clamped) row instead: every access stays inside the
+    // lattice, no branch or register clearing is needed, and their results are
+    // never stored, summed or shuffled into an owned node.
+    const int il = act ? i0 : 0;
+    if (sizeof(S) >= 4 || act) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             S raw[V];
             if constexpr (MODE == AA_LOCAL) {
-                load_vec<S, V>(src + q * P + l0 + i0, raw);
+                load_vec<S, V>(src + q * P + l0 + il, raw);
             } else {
                 const int pq = (MODE == AA_PUSH) ? OPP[q] : q;
                 if constexpr (kShifted) {
-                    if (EXQ[q] == 1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (i0 - 1), raw);
-                    else if (EXQ[q] == -1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (i0 + 1), raw);
-                    else load_vec<S, V>(src + pq * P + row_of[q] + i0, raw);
+                    if (EXQ[q] == 1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il - 1), raw);
+                    else if (EXQ[q] == -1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il + 1), raw);
+                    else load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
                 } else {
-                    load_vec<S, V>(src + pq * P + row_of[q] + i0, raw);
+                    load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
                 }
             }
 #pragma unroll
@@ -330,7 +405,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
             for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, i0 + k, j) : 0;
         } else {
-            load_mask<V>(a.mask + r0 + i0, body);
+            load_mask<V>(a.mask + r0 + il, body);
         }
     } else {
 #pragma unroll
@@ -385,6 +460,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     R fl_rho[V], fl_ux[V], fl_uy[V], fl_fx[V], fl_fy[V];
     double tile_drho = 0.0;
     S out[9][V];
+    R prev[9];   // 2-byte storage: the even node's results, converted with the odd node's
 #pragma unroll
     for (int k = 0; k < V; ++k) {
         R f[9];
@@ -405,9 +481,35 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 f[q] = pull_column<MODE, S, R>(src, q, MODE == AA_PUSH ? OPP[q] : q, row_of[q], row_idx[q], a.nx, a);
             }
         }
-        const NodeResult<R> n = collide_node<R, MOVING, (sizeof(S) >= 4)>(f, body[k], i, j, a);
+        NodeResult<R> n;
+        if constexpr (sizeof(S) == 2) {
+            n = collide_node_lowp<R, MOVING>(f, body[k], i, j, a);
+            if constexpr (V >= 2) {
+                // two nodes' populations at a time, one packed conversion each
+                if (k & 1) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) out[q][k] = enc<S>(f[q]);
+                    for (int q = 0; q < 9; ++q) enc2<S>(prev[q], f[q], &out[q][k - 1]);
+                } else {
+#pragma unroll
+                    for (int q = 0; q < 9; ++q) prev[q] = f[q];
+                }
+            } else {
+                // the packed conversion here too: a scalar one may be fused with
+                // the collision's last multiply-add into a single rounding to the
+                // storage type, which rounds some values differently from the
+                // two roundings (to FP32, then to storage) of the vector forms
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    S two[2];
+                    enc2<S>(f[q], R(0), two);
+                    out[q][k] = two[0];
+                }
+            }
+        } else {
+            n = collide_node<R, MOVING, true>(f, body[k], i, j, a);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) out[q][k] = enc<S>(f[q]);
+        }
         fl_rho[k] = n.rho;
         fl_ux[k] = n.ux;
         fl_uy[k] = n.uy;

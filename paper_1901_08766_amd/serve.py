@@ -23,12 +23,17 @@ from . import lbvp
 
 @dataclass
 class ServeReport:
-    latencies: Dict[int, float] = field(default_factory=dict)   # request id -> seconds
-    node_updates: int = 0
+    """Latencies and node updates count valid results only: a solve whose mass
+    went non-finite (E_UNSTABLE) delivered no usable result, so its latency and
+    its node updates are kept apart."""
+    latencies: Dict[int, float] = field(default_factory=dict)   # request id -> seconds (valid results)
+    node_updates: int = 0                                       # of valid results
     wall_s: float = 0.0
     epochs: int = 0
     max_resident: int = 0
     unstable: List[int] = field(default_factory=list)           # ids whose mass went non-finite
+    unstable_latencies: Dict[int, float] = field(default_factory=dict)
+    unstable_node_updates: int = 0
 
     def percentile(self, q: float) -> float:
         v = np.array(sorted(self.latencies.values()))
@@ -42,7 +47,8 @@ class ServeReport:
         return {"requests": len(self.latencies), "p50_s": round(self.percentile(50), 4),
                 "p99_s": round(self.percentile(99), 4), "mean_s": round(float(np.mean(list(self.latencies.values()))), 4)
                 if self.latencies else None, "MLUPS": round(self.mlups, 1), "wall_s": round(self.wall_s, 3),
-                "epochs": self.epochs, "max_resident": self.max_resident, "unstable": len(self.unstable)}
+                "epochs": self.epochs, "max_resident": self.max_resident, "unstable": len(self.unstable),
+                "unstable_node_updates": self.unstable_node_updates}
 
 
 def serve(requests, pool, max_epoch_steps: int = 256, fields: bool = False,
@@ -73,6 +79,7 @@ def serve(requests, pool, max_epoch_steps: int = 256, fields: bool = False,
         done = pool.poll(wait=(ran == 0 and bool(resident)))
         for slot in done:
             r = resident.pop(slot)
+            ok = True
             try:
                 forces, mass, _ = pool.forces(slot)
             except lbvp.LbvpError as e:       # reported, not fatal: the solve itself diverged
@@ -80,9 +87,16 @@ def serve(requests, pool, max_epoch_steps: int = 256, fields: bool = False,
                     raise
                 forces, mass, _ = e.data
                 rep.unstable.append(r.rid)
+                ok = False
             flds = pool.fields(slot) if fields else None
-            rep.latencies[r.rid] = time.perf_counter() - t0 - r.arrival
-            rep.node_updates += r.problem.nx * r.problem.ny * r.problem.steps
+            latency = time.perf_counter() - t0 - r.arrival
+            work = r.problem.nx * r.problem.ny * r.problem.steps
+            if ok:
+                rep.latencies[r.rid] = latency
+                rep.node_updates += work
+            else:
+                rep.unstable_latencies[r.rid] = latency
+                rep.unstable_node_updates += work
             if on_result is not None:
                 on_result(r, forces, mass, flds)
             pool.release(slot)

@@ -235,3 +235,29 @@ def test_fp64_pool_solves_match_the_oracle(lbvp, oracle):
             scale = np.array([np.abs(fr["fx"][p.mask == b]).sum() + np.abs(fr["fy"][p.mask == b]).sum() + 1e-300
                               for b in range(1, p.n_bodies + 1)])
             assert np.all(np.abs(f - rf).max(axis=(0, 2)) <= 1e-11 * scale), k
+
+
+def test_served_stream_keeps_unstable_results_apart(lbvp):
+    """The serving loop counts only valid results in its latencies and node
+    updates: a diverging request is listed as unstable, with its work and
+    latency reported on their own, and the other results still equal their solo
+    runs."""
+    from paper_1901_08766_amd import serve
+
+    reqs = inputs.request_stream(rate=400.0, n=6, seed=12, step_lo=20, step_hi=200, sizes=[(128, 64), (96, 48)])
+    bad = dataclasses.replace(_near_inviscid(), steps=STEPS)
+    reqs[2] = inputs.Request(rid=2, arrival=reqs[2].arrival, problem=bad)
+    pool = lbvp.Pool(storage="f32", cap_bytes=1 << 30, max_slots=3, vec=4, block=256, chunk_bytes=32 << 20)
+    got = {}
+    rep = serve.serve(reqs, pool, max_epoch_steps=64,
+                      on_result=lambda r, f, m, fl: got.__setitem__(r.rid, (f, m)))
+    pool.close()
+    assert rep.unstable == [2] and sorted(rep.latencies) == [0, 1, 3, 4, 5] and list(rep.unstable_latencies) == [2]
+    assert rep.unstable_node_updates == bad.nx * bad.ny * bad.steps
+    assert rep.node_updates == sum(r.problem.nx * r.problem.ny * r.problem.steps for r in reqs if r.rid != 2)
+    assert rep.summary()["requests"] == 5 and rep.summary()["unstable"] == 1
+    for r in reqs:
+        if r.rid == 2:
+            continue
+        fa, ma, _, _, _ = _alone(lbvp, r.problem, "f32", 0, 4, 256, r.problem.steps)
+        assert np.array_equal(got[r.rid][0], fa) and np.array_equal(got[r.rid][1], ma), r.rid
