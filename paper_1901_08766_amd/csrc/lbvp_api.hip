@@ -124,16 +124,16 @@ bool vec_allowed(int32_t storage, uint32_t flags, int32_t vec)
 // spread over more CUs. Vector launches of the pull layout take tiles in bands
 // (lbvp_set_tile_band). The shapes and bands are the fastest measured on MI355X
 // for an 8192 x 4096 domain, recording every step: FP32 128 threads, bands of 8
-// tiles (0.399 ms against 0.407 for 256 threads and one eighth per XCD); FP64
-// 128 threads, bands of 2 (0.792 against 0.812); FP16 and BF16 256 threads of 8
-// nodes, bands of 2 (0.216 ms against 0.228 for the best shape with eighths),
-// or of 4 nodes, bands of 16 (0.218).
+// tiles (0.394-0.399 ms against 0.407 for 256 threads and one eighth per XCD);
+// FP64 128 threads, bands of 2 (0.789-0.792 against 0.812); FP16 and BF16 256
+// threads of 4 nodes (8-byte accesses), bands of 16 (FP16 0.208 ms, BF16 0.209,
+// against 0.210 and 0.213 for 8 nodes in bands of 2 and 0.221 for 128 threads).
 Launch default_launch(int32_t nx, int32_t ny, int32_t storage, uint32_t flags)
 {
     const int64_t n = (int64_t)nx * ny;
     const bool two_byte = storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV;
     int32_t vec = 1;
-    for (int32_t v : {vector_width(storage), two_byte ? 4 : 1})
+    for (int32_t v : {two_byte ? 4 : vector_width(storage), two_byte ? vector_width(storage) : 1})
         if (vec == 1 && v > 1 && vec_allowed(storage, flags, v) && n / (64 * v) >= 8 * 1024) vec = v;
     const int64_t waves = n / (64 * vec);
     int32_t block = two_byte ? 128 : MAX_BLOCK;

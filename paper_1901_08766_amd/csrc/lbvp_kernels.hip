@@ -55,13 +55,67 @@ struct NodeResult {
     R drho, rho, ux, uy, fvx, fvy;
 };
 
+// One row of the body table (see StepArgs::bodies): the centre split into its
+// nearest integer and the remainder, then V and omega.
+template <typename R>
+struct BodyRow {
+    R cxi, cyi, cxf, cyf, vx, vy, om;
+};
+
+template <typename R>
+__device__ __forceinline__ BodyRow<R> body_row(const R* B)
+{
+    return {B[0], B[1], B[2], B[3], B[4], B[5], B[6]};
+}
+
+// Where a solid node finds its body's row: `uniform` when every solid node of
+// the tile belongs to one body, whose row was then read once per tile (scalar
+// loads, before any store); otherwise each node reads its own row.
+template <typename R>
+struct BodySource {
+    bool uniform;
+    BodyRow<R> row;
+};
+
+// Volume penalization of a solid node (eqs. d-V, force-density): U_O = V +
+// omega z x (x - c), du = (U_O - u*) / (2 eta + 1), F_VP = 2 rho du, u = u* + du.
+// x - c comes from the split centre (a centre rounded to FP32 whole would be off
+// by up to half an FP32 spacing, 1/512 node near x = 32768, the same for every
+// node of the body); a moving body's centre at time t is FP64.
+template <typename R, bool MOVING>
+__device__ __forceinline__ void penalize(const BodySource<R>& src, int body, int i, int j, const StepArgs<R>& a,
+                                         R rho, R& ux, R& uy, R& fvx, R& fvy)
+{
+    BodyRow<R> B;
+    if (src.uniform) B = src.row;
+    else B = body_row(a.bodies + BODY_STRIDE * body);
+    R rx, ry;
+    if constexpr (MOVING) {
+        const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
+        rx = (R)((double)i - m[2]);
+        ry = (R)((double)j - m[3]);
+    } else {
+        rx = ((R)i - B.cxi) - B.cxf;
+        ry = ((R)j - B.cyi) - B.cyf;
+    }
+    const R uox = B.vx - B.om * ry;
+    const R uoy = B.vy + B.om * rx;
+    const R dux = a.vp_c * (uox - ux);
+    const R duy = a.vp_c * (uoy - uy);
+    fvx = R(2) * rho * dux;
+    fvy = R(2) * rho * duy;
+    ux += dux;
+    uy += duy;
+}
+
 // Steps (4)-(6) of the algorithm at node (i, j) with streamed populations f;
 // overwrites f with the post-collision populations.
 // EXACT_MOM: the odd equilibrium from the momentum (momentum3); the 2-byte
 // storage types take 3 rho u as (3 rho) u instead, whose ~1e-8 momentum bias is
 // far below their own rounding, for two fewer quotients per node.
 template <typename R, bool MOVING = false, bool EXACT_MOM = true>
-__device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i, int j, const StepArgs<R>& a)
+__device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i, int j, const StepArgs<R>& a,
+                                                    const BodySource<R>& bs)
 {
     // moments with the integers 36 w_a = 16, 4, 1 (sum w_a rho0 = rho0 and
     // sum e_a w_a = 0 drop out); 1/36 and 1/rho through div36 / recip
@@ -78,29 +132,7 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
 
     // volume penalization (eqs. d-V, force-density) on solid nodes only
     R fvx = R(0), fvy = R(0);
-    if (body) {
-        const R* B = a.bodies + BODY_STRIDE * body;
-        // x - c from the split centre (a centre rounded to FP32 whole would be off
-        // by up to half an FP32 spacing, 1/512 node near x = 32768, the same for
-        // every node of the body); a moving body's centre at time t is FP64
-        R rx, ry;
-        if constexpr (MOVING) {
-            const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
-            rx = (R)((double)i - m[2]);
-            ry = (R)((double)j - m[3]);
-        } else {
-            rx = ((R)i - B[0]) - B[2];
-            ry = ((R)j - B[1]) - B[3];
-        }
-        const R uox = B[4] - B[6] * ry;
-        const R uoy = B[5] + B[6] * rx;
-        const R dux = a.vp_c * (uox - ux);
-        const R duy = a.vp_c * (uoy - uy);
-        fvx = R(2) * rho * dux;
-        fvy = R(2) * rho * duy;
-        ux += dux;
-        uy += duy;
-    }
+    if (body) penalize<R, MOVING>(bs, body, i, j, a, rho, ux, uy, fvx, fvy);
     const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
     R px, py;   // 3 rho u
     if constexpr (EXACT_MOM) {
@@ -147,7 +179,8 @@ __device__ __forceinline__ NodeResult<R> collide_node(R (&f)[9], int body, int i
 // relaxation of collide_pair); the rest population is g_0 = (1 - om_p) h_0 + B.
 // About 85 operations per node instead of about 125.
 template <typename R, bool MOVING = false>
-__device__ __forceinline__ NodeResult<R> collide_node_lowp(R (&f)[9], int body, int i, int j, const StepArgs<R>& a)
+__device__ __forceinline__ NodeResult<R> collide_node_lowp(R (&f)[9], int body, int i, int j, const StepArgs<R>& a,
+                                                         const BodySource<R>& bs)
 {
     const R s36 = R(16) * f[0] + (R(4) * ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
     const R drho = s36 * R(1.0 / 36.0);
@@ -159,26 +192,7 @@ __device__ __forceinline__ NodeResult<R> collide_node_lowp(R (&f)[9], int body, 
     R ux = jx36 * inv_36rho;
     R uy = jy36 * inv_36rho;
     R fvx = R(0), fvy = R(0);
-    if (body) {
-        const R* B = a.bodies + BODY_STRIDE * body;
-        R rx, ry;
-        if constexpr (MOVING) {
-            const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
-            rx = (R)((double)i - m[2]);
-            ry = (R)((double)j - m[3]);
-        } else {
-            rx = ((R)i - B[0]) - B[2];
-            ry = ((R)j - B[1]) - B[3];
-        }
-        const R uox = B[4] - B[6] * ry;
-        const R uoy = B[5] + B[6] * rx;
-        const R dux = a.vp_c * (uox - ux);
-        const R duy = a.vp_c * (uoy - uy);
-        fvx = R(2) * rho * dux;
-        fvy = R(2) * rho * duy;
-        ux += dux;
-        uy += duy;
-    }
+    if (body) penalize<R, MOVING>(bs, body, i, j, a, rho, ux, uy, fvx, fvy);
     const R Fx = a.fbx + fvx, Fy = a.fby + fvy;
     const R uu = ux * ux + uy * uy;
     const R uF = ux * Fx + uy * Fy;
@@ -337,9 +351,17 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 {
     using R = typename Arith<S>::R;
     int s0 = 0, s1 = 0;          // this tile's (tile, body) force slots
+    BodySource<R> bs;
+    bs.uniform = false;
     if constexpr (RECORD) {
         s0 = a.tile_slot_ptr[t];
         s1 = a.tile_slot_ptr[t + 1];
+        // the slots list every body with a node in the tile: with one, its row
+        // serves every solid node of the tile (read here, before any store)
+        if (s1 - s0 == 1) {
+            bs.uniform = true;
+            bs.row = body_row(a.bodies + BODY_STRIDE * a.slot_body[s0]);
+        }
     }
     const int ty = t / a.tiles_x, tx = t - ty * a.tiles_x;
     const int tpr = a.tile_w / V;                       // threads per tile row (tile_w and V are powers of two)
@@ -483,7 +505,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         }
         NodeResult<R> n;
         if constexpr (sizeof(S) == 2) {
-            n = collide_node_lowp<R, MOVING>(f, body[k], i, j, a);
+            n = collide_node_lowp<R, MOVING>(f, body[k], i, j, a, bs);
             if constexpr (V >= 2) {
                 // two nodes' populations at a time, one packed conversion each
                 if (k & 1) {
@@ -506,7 +528,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 }
             }
         } else {
-            n = collide_node<R, MOVING, true>(f, body[k], i, j, a);
+            n = collide_node<R, MOVING, true>(f, body[k], i, j, a, bs);
 #pragma unroll
             for (int q = 0; q < 9; ++q) out[q][k] = enc<S>(f[q]);
         }
@@ -520,8 +542,8 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
             // only), summed per body after the stores
             if (s1 > s0) {
                 R* fv = dyn_lds<R>();
-                fv[k * (int)blockDim.x + (int)threadIdx.x] = n.fvx;
-                fv[(V + k) * (int)blockDim.x + (int)threadIdx.x] = n.fvy;
+                fv[k * a.block + (int)threadIdx.x] = n.fvx;
+                fv[(V + k) * a.block + (int)threadIdx.x] = n.fvy;
             }
         }
         if (k < n_own) tile_drho += (double)n.drho;
@@ -643,39 +665,55 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 load_mask<V>(a.mask + r0 + i0, bid);
             }
         }
+        // each (tile, body) slot: every wavefront sums its lanes with DPP moves
+        // into lane 63, which parks the sum in LDS; after one barrier per batch
+        // of slots the block's first threads add the wavefronts in order
         const R* fv = dyn_lds<R>();
-        for (int s = s0; s < s1; ++s) {
-            const int b = a.slot_body[s];
-            if constexpr (MOVING) {
-                // slots are dense (every tile, every body): skip bodies whose radius
-                // misses this tile's rectangle (uniform across the block)
-                const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (b - 1)) * POSE_STRIDE;
-                const double x0 = (double)(tx * a.tile_w), x1 = x0 + (double)(a.tile_w - 1);
-                const double y0 = (double)(ty * a.tile_rows), y1 = y0 + (double)(a.tile_rows - 1);
-                const double ex = m[2] < x0 ? x0 - m[2] : (m[2] > x1 ? m[2] - x1 : 0.0);
-                const double ey = m[3] < y0 ? y0 - m[3] : (m[3] > y1 ? m[3] - y1 : 0.0);
-                if (ex * ex + ey * ey > m[6]) {
-                    if (threadIdx.x == 0) {
-                        slot_force[2 * s] = 0.0;
-                        slot_force[2 * s + 1] = 0.0;
-                    }
-                    continue;
+        const int nw = a.block >> 6, wid = (int)threadIdx.x >> 6;
+        const int per_pass = FIN_LANES / nw;          // slots whose wave sums fit lds[2 FIN_LANES]
+        for (int c0 = s0; c0 < s1; c0 += per_pass) {
+            const int c1 = min(s1, c0 + per_pass);
+            for (int s = c0; s < c1; ++s) {
+                const int b = a.slot_body[s];
+                bool skip = false;
+                if constexpr (MOVING) {
+                    // slots are dense (every tile, every body): a body whose radius
+                    // misses this tile's rectangle adds nothing (uniform across the block)
+                    const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (b - 1)) * POSE_STRIDE;
+                    const double x0 = (double)(tx * a.tile_w), x1 = x0 + (double)(a.tile_w - 1);
+                    const double y0 = (double)(ty * a.tile_rows), y1 = y0 + (double)(a.tile_rows - 1);
+                    const double ex = m[2] < x0 ? x0 - m[2] : (m[2] > x1 ? m[2] - x1 : 0.0);
+                    const double ey = m[3] < y0 ? y0 - m[3] : (m[3] > y1 ? m[3] - y1 : 0.0);
+                    skip = ex * ex + ey * ey > m[6];
                 }
-            }
-            double px = 0.0, py = 0.0;
+                double px = 0.0, py = 0.0;
+                if (!skip) {
 #pragma unroll
-            for (int k = 0; k < V; ++k) {
-                if (k < n_own && bid[k] == b) {
-                    px -= (double)fv[k * (int)blockDim.x + (int)threadIdx.x];
-                    py -= (double)fv[(V + k) * (int)blockDim.x + (int)threadIdx.x];
+                    for (int k = 0; k < V; ++k) {
+                        if (k < n_own && bid[k] == b) {
+                            px -= (double)fv[k * a.block + (int)threadIdx.x];
+                            py -= (double)fv[(V + k) * a.block + (int)threadIdx.x];
+                        }
+                    }
+                }
+                const double wx = wave_sum_lane63(px);
+                const double wy = wave_sum_lane63(py);
+                if (lane == 63) {
+                    lds[2 * ((s - c0) * nw + wid)] = wx;
+                    lds[2 * ((s - c0) * nw + wid) + 1] = wy;
                 }
             }
-            const double sx = block_sum(px, lds);
-            const double sy = block_sum(py, lds);
-            if (threadIdx.x == 0) {
-                slot_force[2 * s] = sx;
-                slot_force[2 * s + 1] = sy;
+            __syncthreads();
+            for (int s = c0 + (int)threadIdx.x; s < c1; s += a.block) {
+                double x = 0.0, y = 0.0;
+                for (int w = 0; w < nw; ++w) {
+                    x += lds[2 * ((s - c0) * nw + w)];
+                    y += lds[2 * ((s - c0) * nw + w) + 1];
+                }
+                slot_force[2 * s] = x;
+                slot_force[2 * s + 1] = y;
             }
+            __syncthreads();   // lds is reused by the next batch of slots
         }
     }
 }

@@ -1,7 +1,8 @@
 """Cylindrical Couette (Sec. 3.1) on the GPU in FP64: the TRT-vs-SRT accuracy
 comparison and its grid convergence at 64^2, 128^2, 256^2 (geometry scaled,
 steps scaled with the diffusion time), against u = A r + B / r (reading R12).
-At 64^2 the GPU's error equals the oracle's (the arithmetic matches to 1e-12)."""
+At 64^2 and 128^2 the GPU's error equals the oracle's run of the same case
+(the arithmetic matches to 1e-12)."""
 import numpy as np
 import pytest
 
@@ -38,12 +39,20 @@ def _gpu_error(lbvp, n, tau, lam):
     return e
 
 
-def test_couette_gpu_equals_oracle_at_64(lbvp, oracle):
-    p, scale, steps = _problem(64, 0.8, 0.25)
+@pytest.mark.parametrize("n,tau,lam", [(64, 0.8, 0.25), (128, 0.8, 0.25), (128, 1.5, 0.25), (128, 1.5, 1.0)],
+                         ids=["64-trt", "128-trt", "128-trt-tau1.5", "128-srt-tau1.5"])
+def test_couette_gpu_equals_oracle(lbvp, oracle, n, tau, lam):
+    """The grid study's points against the oracle's own run: the GPU's error
+    against the closed form equals the oracle's (FP64 arithmetic to 1e-12), at
+    64^2 and at 128^2, TRT and SRT (Lambda = (tau+ - 1/2)^2)."""
+    p, scale, steps = _problem(n, tau, lam)
     r = oracle.RefSolver(p)
     r.step(steps)
-    e_ref = _error(r.fields(), 64, scale)
-    assert abs(_gpu_error(lbvp, 64, 0.8, 0.25) - e_ref) <= 1e-9 * e_ref
+    e_ref = _error(r.fields(), n, scale)
+    r.close()
+    e_gpu = _gpu_error(lbvp, n, tau, lam)
+    print(f"couette n={n} tau+={tau} Lambda={lam}: oracle {e_ref:.6%} GPU {e_gpu:.6%}", flush=True)
+    assert abs(e_gpu - e_ref) <= 1e-9 * e_ref
 
 
 def test_couette_trt_vs_srt_convergence(lbvp):
