@@ -66,7 +66,10 @@ def measured_traffic(storage: str, nodes: int, lattice: str = "d2q9"):
     return entry.get("hbm_bytes_per_launch")
 
 
-def time_gpu(storage: str, steps: int, warmup: int, prob):
+def time_gpu(storage: str, steps: int, warmup: int, prob, repeats: int = 1):
+    """ms per step of `steps` steps after `warmup` untimed ones (HIP events on the
+    solver's stream); with repeats > 1 the timed run is repeated and the median
+    taken (every repeat's time is returned too)."""
     import torch
     from paper_1901_08766_amd import lbvp
 
@@ -75,21 +78,25 @@ def time_gpu(storage: str, steps: int, warmup: int, prob):
     solver.step(warmup)
     solver.synchronize()
     solver.forces()
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    solver.step(steps)
-    stop.record(stream)
-    stop.synchronize()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    forces, mass, _ = solver.forces()
-    ok = bool((mass == mass).all()) and len(mass) == steps
+    runs, ok = [], True
+    for _ in range(repeats):
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record(stream)
+        solver.step(steps)
+        stop.record(stream)
+        stop.synchronize()
+        torch.cuda.synchronize()
+        runs.append(start.elapsed_time(stop) / steps)
+        forces, mass, _ = solver.forces()
+        ok = ok and bool((mass == mass).all()) and len(mass) == steps
     launch = {"vec": solver.launch[0], "block": solver.launch[1], "tile_band": solver.tile_band}
     solver.close()
     torch.cuda.empty_cache()
-    return ms / steps, ok, launch
+    if repeats == 1:
+        return runs[0], ok, launch
+    return float(np.median(runs)), ok, launch, runs
 
 
 BYTES_PER_NODE_3D = {"f64": 305, "f32": 153, "f16": 77, "bf16": 77}
@@ -155,6 +162,19 @@ def time_ensemble3(storage: str, steps: int, n_dom: int = 64):
     ms = _timed(stream, per_domain)
     out["per_domain_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
     drain()
+    # the stronger per-domain forms: captured graphs of `chunk` steps per domain,
+    # and each domain's whole run as one call in turn
+    chunk = min(20, steps)
+    for m in members:
+        m.step(chunk, graph=True)             # capture outside the timed region
+    drain()
+    ms = _timed(stream, lambda: [m.step(chunk, graph=True) for _ in range(steps // chunk) for m in members])
+    out["per_domain_graph_MLUPS"] = round(nodes * (steps // chunk) * chunk / ms / 1e3, 1)
+    drain()
+    ms = _timed(stream, lambda: [m.step(steps) for m in members])
+    out["per_domain_whole_run_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
+    drain()
+    best_per_domain = max(out["per_domain_MLUPS"], out["per_domain_graph_MLUPS"], out["per_domain_whole_run_MLUPS"])
     rows, best = lbvp3.tune(members, steps=20)
     vec, block, band = best["vec"], best["block"], best["band"]
     out["tuner_rows"] = len(rows)
@@ -168,6 +188,7 @@ def time_ensemble3(storage: str, steps: int, n_dom: int = 64):
     out.update({"launch": [vec, block], "tile_band": band, "batched_MLUPS": round(nodes * steps / ms / 1e3, 1),
                 "batched_ms_per_step": round(ms / steps, 4),
                 "speedup": round(nodes * steps / ms / 1e3 / max(out["per_domain_MLUPS"], 1e-9), 2),
+                "speedup_vs_best_per_domain": round(nodes * steps / ms / 1e3 / max(best_per_domain, 1e-9), 2),
                 "finite": bool(np.isfinite(mass).all())})
     batch.close()
     for m in members:
@@ -254,13 +275,28 @@ def time_slabs(n_slabs: int, steps: int = 100, storage: str = "f32"):
     return out
 
 
-def cpu_baseline(prob, budget_s: float = 15.0):
-    """The FP64 oracle on this host's cores, on the same domain, for as many
-    whole steps as fit in about ``budget_s`` seconds (at least one); then one
-    step on a single thread for the per-core rate."""
-    from oracle import ref
+def _host_cpu():
+    """CPU model name and processor counts of this host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable}
 
-    cores = ref.num_threads()
+
+def _oracle_rate(ref, prob, budget_s: float, threads: int):
+    """Whole FP64 steps of prob on `threads` threads for about budget_s seconds
+    (at least one): (MLUPS, steps, seconds)."""
+    ref.set_num_threads(threads)
     r = ref.RefSolver(prob)
     t0 = time.perf_counter()
     r.step(1)
@@ -270,18 +306,31 @@ def cpu_baseline(prob, budget_s: float = 15.0):
     if n_more:
         r.step(n_more)
     total = one + (time.perf_counter() - t1)
-    steps = 1 + n_more
-    ref.set_num_threads(1)
-    t2 = time.perf_counter()
-    r.step(1)
-    single = time.perf_counter() - t2
-    ref.set_num_threads(cores)
     r.close()
-    n = prob.nx * prob.ny
-    return {"value": round(n * steps / total / 1e6, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "single_thread_MLUPS": round(n / single / 1e6, 3),
+    steps = 1 + n_more
+    return prob.nx * prob.ny * steps / total / 1e6, steps, total
+
+
+def cpu_baseline(prob, budget_s: float = 15.0):
+    """The FP64 oracle on this host's cores, on the same domain, for as many
+    whole steps as fit in about ``budget_s`` seconds (at least one); then one
+    step on a single thread for the per-core rate; then the 1024 x 512 cylinder
+    (the shedding case) on all threads for about a third of the budget."""
+    from oracle import ref
+    from paper_1901_08766_amd import inputs
+
+    cores = ref.num_threads()
+    mlups, steps, total = _oracle_rate(ref, prob, budget_s, cores)
+    single, _, single_s = _oracle_rate(ref, prob, 0.0, 1)
+    c2 = inputs.cylinder()
+    c2_mlups, c2_steps, c2_s = _oracle_rate(ref, c2, budget_s / 3.0, cores)
+    ref.set_num_threads(cores)
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "single_thread_MLUPS": round(single, 3), **_host_cpu(),
+            "cylinder_1024x512_MLUPS": round(c2_mlups, 3),
             "sample": f"{steps} FP64 steps of the full {prob.nx}x{prob.ny} domain on {cores} threads "
-                      f"({total:.1f} s), then 1 step on 1 thread ({single:.1f} s)"}
+                      f"({total:.1f} s), then 1 step on 1 thread ({single_s:.1f} s), then {c2_steps} steps of the "
+                      f"1024x512 cylinder on {cores} threads ({c2_s:.1f} s)"}
 
 
 def _timed(stream, fn):
@@ -368,6 +417,13 @@ def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 
     drain(members)
     ms = _timed(stream, lambda: batch.step(steps, graph=True))
     out["batched_graph_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
+    if not best["layout_flags"]:
+        # the same steps as one cooperative launch with a grid barrier per step
+        drain(members)
+        batch.step(10, persistent=True)
+        drain(members)
+        ms = _timed(stream, lambda: batch.step(steps, persistent=True))
+        out["batched_persistent_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
     _, mass, _ = members[0].forces()
     out["finite"] = bool(np.isfinite(mass).all())
     drain(members)
@@ -719,9 +775,12 @@ def main():
     achieved = alg_bytes / (ms * 1e-3) / 1e9
     extra = {}
     for v in [s for s in a.variants.split(",") if s and s != a.storage]:
-        vms, vok, vlaunch = time_gpu(v, a.steps, a.warmup, prob)
+        # median of 5 repeats of the requested steps (the first absorbs the
+        # clock ramp after the set-up of the variant's context)
+        vms, vok, vlaunch, vruns = time_gpu(v, a.steps, a.warmup, prob, repeats=5)
         vb = BYTES_PER_NODE[v] * nodes / (vms * 1e-3) / 1e9
         extra[v] = {"MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
+                    "ms_per_step_runs": [round(x, 4) for x in vruns], "timing": "median of 5 repeats",
                     "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok,
                     "launch": vlaunch, "traffic": measured_traffic(v, nodes)}
         print(f"# {v}: {extra[v]}", file=sys.stderr, flush=True)
@@ -767,6 +826,12 @@ def main():
     if a.serve_requests > 0:
         out["serving"] = run_serving(a.serve_storage, a.serve_rate, a.serve_requests)
         print(f"# serving: {out['serving']}", file=sys.stderr, flush=True)
+        # a sub-capacity point and one more loaded point, fewer requests each
+        out["serving_sweep"] = []
+        for rate in (20.0, 200.0):
+            row = run_serving(a.serve_storage, rate, max(10, a.serve_requests // 2))
+            out["serving_sweep"].append(row)
+            print(f"# serving {rate:g} req/s: {row}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, a.cpu_budget)
     print(json.dumps(out), flush=True)

@@ -196,10 +196,13 @@ const char* lbvp3_batch_last_error(const lbvp3_batch* batch);
  * lbvp3_batch_step would. Each candidate: steps / 4 warm-up steps, then the best
  * of three timed runs of `steps` steps (HIP events on the members' stream).
  * rows[cap] receives one row per candidate and *best the index of the fastest.
- * Results are cached per process, keyed by storage, record cadence, steps and
- * the members' grid sizes, unless flags holds LBVP_TUNE_FRESH (no other flag is
- * known). Errors (message from lbvp3_tune_last_error): E_ARG (NULL or mixed
- * members), E_NOMEM, E_DEVICE. */
+ * A candidate that a member's grid does not admit (lbvp3_set_launch or
+ * lbvp3_batch_create answers E_ARG) is skipped, and lbvp3_tune_last_error lists
+ * it with the reason. Results are cached per process, keyed by storage, record
+ * cadence, steps and each member's grid size, body count and mask, unless flags
+ * holds LBVP_TUNE_FRESH (no other flag is known). Errors (message from
+ * lbvp3_tune_last_error): E_ARG (NULL or mixed members, or no candidate admitted
+ * by every member), E_NOMEM, E_DEVICE. */
 typedef struct lbvp3_tune_row {
     int32_t vec, block, band;
     double ms_per_step;

@@ -538,7 +538,6 @@ lbvp_status lbvp3_set_mask(lbvp3_ctx* c, const uint8_t* body_id, int32_t n_bodie
     const Layout3& L = c->L;
     if (!body_id) return c->fail(LBVP_E_ARG, "body_id is NULL");
     if (n_bodies < 0 || n_bodies > L.max_bodies) return c->fail(LBVP_E_ARG, "n_bodies out of range (see max_bodies)");
-    c->args_changed();   // the body count and tables the graphs hold change
     if (n_bodies > 0 && !bodies) return c->fail(LBVP_E_ARG, "bodies is NULL");
     for (int32_t b = 0; b < n_bodies; ++b)
         for (int d = 0; d < 3; ++d)
@@ -547,6 +546,9 @@ lbvp_status lbvp3_set_mask(lbvp3_ctx* c, const uint8_t* body_id, int32_t n_bodie
     const int64_t n = L.rows * p.nx;
     for (int64_t k = 0; k < n; ++k)
         if (body_id[k] > n_bodies) return c->fail(LBVP_E_ARG, "body_id larger than n_bodies");
+    // accepted: from here the body count and the tables the graphs hold change
+    // (a rejected call above leaves the context, its stream and its graphs alone)
+    c->args_changed();
     // body table: row 0 all zero (fluid), row b = c_int, c_frac, v, omega of body
     // b, in the arithmetic type (the centre's split is exact in FP64)
     const size_t rs = c->rsize();
@@ -1151,7 +1153,12 @@ lbvp_status lbvp3_tune(lbvp3_ctx* const* members, int32_t n, int32_t steps, uint
         const lbvp3_ctx* c = members[d];
         if (c->p.storage != c0->p.storage || c->stream != c0->stream || c->p.force_every != c0->p.force_every)
             return tune3_fail(LBVP_E_ARG, "members differ in storage, stream or force_every");
-        key += "/" + std::to_string(c->p.nx) + "x" + std::to_string(c->p.ny) + "x" + std::to_string(c->p.nz);
+        // the pick is kept per grid shape, body count and mask (FNV-1a of the
+        // body ids): members with other solids may tune differently
+        uint64_t h = 1469598103934665603ull;
+        for (uint8_t v : c->mask_host) h = (h ^ v) * 1099511628211ull;
+        key += "/" + std::to_string(c->p.nx) + "x" + std::to_string(c->p.ny) + "x" + std::to_string(c->p.nz) + ":" +
+               std::to_string(c->n_bodies) + ":" + std::to_string(h);
     }
     std::vector<lbvp3_tune_row> table;
     int32_t pick = 0;
@@ -1191,18 +1198,29 @@ lbvp_status lbvp3_tune(lbvp3_ctx* const* members, int32_t n, int32_t steps, uint
             return tune3_fail(LBVP_E_DEVICE, "hipEventCreate failed");
         }
         lbvp_status st = LBVP_OK;
+        std::string skipped;   // candidates a member's grid does not admit
         for (int32_t vec : {1, 2, 4, 8}) {
             if (!vec_supported(c0->p.storage, vec)) continue;
             for (int32_t block : BLOCKS)
                 for (int32_t band : {0, 2, 16}) {
                     lbvp3_batch* b = nullptr;
+                    std::string why;
                     for (lbvp3_ctx* s : sc.ctx) {
                         if (st == LBVP_OK) st = lbvp3_set_launch(s, vec, block);
                         if (st == LBVP_OK && n == 1) st = lbvp3_set_tile_band(s, band);
+                        if (st != LBVP_OK && why.empty()) why = s->err;
                     }
                     if (st == LBVP_OK && n > 1) {
                         st = lbvp3_batch_create(sc.ctx.data(), n, vec, block, &b);
                         if (st == LBVP_OK) st = lbvp3_batch_set_tile_band(b, band);
+                        if (st != LBVP_OK) why = lbvp3_batch_last_error(b);
+                    }
+                    if (st == LBVP_E_ARG) {   // not a failure of the run: skip the candidate
+                        if (b) (void)lbvp3_batch_destroy(b);
+                        skipped += " (" + std::to_string(vec) + ", " + std::to_string(block) + ", " +
+                                   std::to_string(band) + "): " + why + ";";
+                        st = LBVP_OK;
+                        continue;
                     }
                     auto run = [&](int64_t k) {
                         return n > 1 ? lbvp3_batch_step(b, k, 0) : lbvp3_step(sc.ctx[0], k, 0);
@@ -1235,6 +1253,8 @@ lbvp_status lbvp3_tune(lbvp3_ctx* const* members, int32_t n, int32_t steps, uint
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (st != LBVP_OK) return tune3_fail(st, "tuning run failed");
+        if (table.empty()) return tune3_fail(LBVP_E_ARG, "no launch shape admitted by every member:" + skipped);
+        g_tune3_error = skipped.empty() ? "" : "skipped:" + skipped;
         for (int32_t i = 1; i < (int32_t)table.size(); ++i)
             if (table[i].ms_per_step < table[pick].ms_per_step) pick = i;
         std::lock_guard<std::mutex> g(g_tune3_mu);

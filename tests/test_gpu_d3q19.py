@@ -415,3 +415,43 @@ def test_graph_steps_bitwise_equal(lbvp3, storage, force_every):
             for name in a[2]:
                 assert np.array_equal(a[2][name], b[2][name]), (k, name)
         assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]) and a[5] == b[5], k
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_graph_long_calls_and_state_changes(lbvp3, storage):
+    """LBVP_GRAPH on calls longer than one captured chunk (512 steps): a 600-step
+    call replays a full chunk and then a shorter one, records every step and keeps
+    the fields of the last step only; between replays a new mask (set_mask) and a
+    restored checkpoint (load_state) drop the graphs. Every call's populations,
+    fields and records are bitwise those of the plain calls."""
+    prob = inputs3.random_state_problem3(24, 16, 12, seed=17, n_spheres=2, body_force=(1e-5, 0.0, 0.0))
+    other = inputs3.random_state_problem3(24, 16, 12, seed=18, n_spheres=3)
+    runs = []
+    for use_graph in (False, True):
+        s = lbvp3.Solver3(prob, storage=storage, force_every=1, force_capacity=1300)
+        out = []
+
+        def call(n, keep):
+            s.step(n, keep_fields=keep, graph=use_graph)
+            f, m, first = s.forces()
+            out.append((s.step_count, s.populations(), s.fields() if keep else None, f, m, first))
+
+        print(f"d3q19 long graph calls {storage} graph={use_graph}", flush=True)
+        call(600, True)
+        blob = s.save_state()
+        call(600, True)
+        lbvp3.lbvp3_set_mask(s.ctx, other.mask_or_empty(), other.bodies_or_empty())
+        call(30, True)
+        s.load_state(blob)
+        call(600, False)
+        call(5, True)
+        runs.append(out)
+        s.close()
+    for k, (a, b) in enumerate(zip(*runs)):
+        assert a[0] == b[0], k
+        assert np.array_equal(a[1], b[1]), k
+        if a[2] is not None:
+            for name in a[2]:
+                assert np.array_equal(a[2][name], b[2][name]), (k, name)
+        assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]) and a[5] == b[5], k
+        assert len(a[4]) == (600 if k in (0, 1, 3) else (30 if k == 2 else 5))
