@@ -417,13 +417,6 @@ def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 
     drain(members)
     ms = _timed(stream, lambda: batch.step(steps, graph=True))
     out["batched_graph_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
-    if not best["layout_flags"]:
-        # the same steps as one cooperative launch with a grid barrier per step
-        drain(members)
-        batch.step(10, persistent=True)
-        drain(members)
-        ms = _timed(stream, lambda: batch.step(steps, persistent=True))
-        out["batched_persistent_MLUPS"] = round(nodes * steps / ms / 1e3, 1)
     _, mass, _ = members[0].forces()
     out["finite"] = bool(np.isfinite(mass).all())
     drain(members)

@@ -100,14 +100,6 @@ typedef enum lbvp_storage {
  * bitwise those of the plain call. Needs a stream other than the null stream. */
 #define LBVP_KEEP_FIELDS 0x1u
 #define LBVP_GRAPH 0x2u
-/* LBVP_PERSISTENT (lbvp_batch_step only): the whole call as one cooperative
- * launch whose resident workgroups sweep the batch's tile map once per step and
- * meet at a grid barrier between steps (the batched form of the paper's
- * per-node step, Sec. 2.2, with no launch per step). Pull layout, no slab cuts,
- * not with LBVP_GRAPH. Bitwise the results of the plain call. The call waits for
- * the launch; E_DEVICE if a barrier did not complete (every workgroup polls a
- * bounded number of times, so the launch always ends). */
-#define LBVP_PERSISTENT 0x4u
 
 /* The problem statement (paper Sec. 2): grid, relaxation, penalization and sides.
  *   tau_plus      symmetric relaxation time tau_s (> 1/2); the viscosity is

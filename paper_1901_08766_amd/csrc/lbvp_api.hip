@@ -34,8 +34,7 @@ constexpr int64_t DEFAULT_CAPACITY = 16384;
 constexpr int32_t DEFAULT_MAX_BODIES = 8;
 constexpr int32_t MAX_BODIES = 255;
 constexpr uint32_t KNOWN_PARAM_FLAGS = LBVP_LAYOUT_AA | LBVP_MOVING_BODIES;
-constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS | LBVP_GRAPH | LBVP_PERSISTENT;
-constexpr int32_t PERSISTENT_SPIN_LIMIT = 1 << 20;   // barrier polls (about a second) before a launch gives up
+constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS | LBVP_GRAPH;
 constexpr int64_t GRAPH_CHUNK = 512;   // steps per captured graph; longer calls replay it
 
 thread_local std::string g_create_error;
@@ -656,7 +655,7 @@ struct lbvp_batch {
     int32_t force_every = 0;
     char* dev = nullptr;                 // owned: [step args | finalize args | tile map]
     size_t dev_cap = 0;
-    size_t arg_size = 0, off_fins = 0, off_tile_domain = 0, off_tile_start = 0, off_bar = 0, bytes = 0;
+    size_t arg_size = 0, off_fins = 0, off_tile_domain = 0, off_tile_start = 0, bytes = 0;
     int32_t total_tiles = 0, tiles_per_xcd = 0;
     int32_t band = 0;                    // block -> tile order over the concatenated tiles (lbvp_batch_set_tile_band)
     std::vector<char> image;             // host image of the device block
@@ -726,7 +725,6 @@ void batch_layout(lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
     b->off_fins = take(sizeof(FinalizeArgs) * std::max<size_t>(n, 1));
     b->off_tile_domain = take(std::max<size_t>(tile_domain.size(), 1) * sizeof(int32_t));
     b->off_tile_start = take(std::max<size_t>(n, 1) * sizeof(int32_t));
-    b->off_bar = take(4 * sizeof(uint32_t));   // grid barrier of LBVP_PERSISTENT
     b->bytes = o;
     b->image.assign(b->bytes, 0);
     b->uploaded.clear();
@@ -923,37 +921,6 @@ lbvp_status batch_static_fail(lbvp_status st, const std::string& why)
 {
     g_batch_error = "lbvp_batch_step_static: " + why;
     return st;
-}
-
-// A run of n steps as one cooperative launch (LBVP_PERSISTENT); waits for it,
-// then checks that every grid barrier completed.
-lbvp_status batch_run_persistent(lbvp_batch* b, int64_t step0, int64_t n, bool keep_last)
-{
-    PersistentLaunch P{};
-    P.b.total_tiles = b->total_tiles;
-    P.b.tiles_per_xcd = b->tiles_per_xcd;
-    P.b.band_log2 = band_log2(b->band);
-    P.b.n_domains = (int32_t)b->members.size();
-    P.b.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_domain);
-    P.b.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_start);
-    P.b.args = b->dev;
-    P.n_steps = n;
-    P.step0 = step0;
-    P.force_every = b->force_every;
-    P.keep_last = keep_last ? 1 : 0;
-    P.spin_limit = PERSISTENT_SPIN_LIMIT;
-    P.bar = reinterpret_cast<uint32_t*>(b->dev + b->off_bar);
-    int64_t* bar64 = reinterpret_cast<int64_t*>(P.bar);
-    LBVP_HIP(b, launch_set_i64(bar64, 0, b->stream));
-    LBVP_HIP(b, launch_set_i64(bar64 + 1, 0, b->stream));
-    int32_t grid = 0;
-    hipError_t e = launch_step_persistent(b->storage, b->vec, b->block, P, b->stream, &grid);
-    if (e != hipSuccess) return b->hip_fail(e, "persistent batched step launch");
-    LBVP_HIP(b, hipStreamSynchronize(b->stream));
-    uint32_t failed = 0;
-    LBVP_HIP(b, hipMemcpy(&failed, P.bar + 2, sizeof(failed), hipMemcpyDeviceToHost));
-    if (failed) return b->fail(LBVP_E_DEVICE, "a grid barrier of the persistent launch did not complete");
-    return LBVP_OK;
 }
 
 }  // namespace
@@ -1273,7 +1240,6 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
     if (check_ctx(c)) return LBVP_E_ARG;
     if (n_steps < 0) return c->fail(LBVP_E_ARG, "n_steps < 0");
     if (flags & ~KNOWN_STEP_FLAGS) return c->fail(LBVP_E_ARG, "unknown step flag");
-    if (flags & LBVP_PERSISTENT) return c->fail(LBVP_E_ARG, "LBVP_PERSISTENT is a flag of lbvp_batch_step");
     const int64_t fe = c->p.force_every;
     if (fe > 0) {
         const int64_t new_recs = (c->step + n_steps) / fe - c->step / fe;
@@ -1735,20 +1701,11 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
         if (c->rec_head + new_recs - c->rec_tail > c->L.capacity)
             return b->fail(LBVP_E_STATE, "a member's force ring would overflow; drain it with lbvp_forces first");
     }
-    if (flags & LBVP_PERSISTENT) {
-        if (flags & LBVP_GRAPH) return b->fail(LBVP_E_ARG, "LBVP_PERSISTENT and LBVP_GRAPH exclude each other");
-        if (b->aa) return b->fail(LBVP_E_ARG, "LBVP_PERSISTENT runs the two-lattice pull layout only");
-        if (!b->halo_w.empty()) return b->fail(LBVP_E_ARG, "LBVP_PERSISTENT does not run slab cuts");
-    }
     const lbvp_status up = batch_refresh_args(b);
     if (up != LBVP_OK) return up;
     const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
     int64_t recs = 0;
-    if (flags & LBVP_PERSISTENT) {
-        const lbvp_status st = batch_run_persistent(b, step0, n_steps, keep);
-        if (st != LBVP_OK) return st;
-        recs = new_recs;
-    } else if (!(flags & LBVP_GRAPH)) {
+    if (!(flags & LBVP_GRAPH)) {
         const lbvp_status st = batch_run(b, step0, 0, n_steps, keep, &recs);
         if (st != LBVP_OK) return st;
     } else {
@@ -1797,7 +1754,6 @@ lbvp_status lbvp_batch_step_static(lbvp_ctx* const* members, int32_t n, int64_t 
     if (n_steps < 0) return batch_static_fail(LBVP_E_ARG, "n_steps < 0");
     if (flags & ~KNOWN_STEP_FLAGS) return batch_static_fail(LBVP_E_ARG, "unknown step flag");
     if (flags & LBVP_GRAPH) return batch_static_fail(LBVP_E_ARG, "LBVP_GRAPH instantiates graphs, which allocates");
-    if (flags & LBVP_PERSISTENT) return batch_static_fail(LBVP_E_ARG, "LBVP_PERSISTENT is not offered here");
     for (int32_t i = 0; i < n; ++i)
         if (check_ctx(members[i])) return batch_static_fail(LBVP_E_ARG, "a member is NULL or not a context");
     const lbvp_ctx* c0 = members[0];

@@ -352,15 +352,6 @@ __device__ __forceinline__ double tree_sum(double* s)
 //    group keep dispatch order.
 // Either way the map is a permutation of [0, 8 per_xcd); a block whose tile is
 // past the domain's last one has nothing to do.
-__device__ __forceinline__ int xcd_tile_of(int blk, int per_xcd, int band_log2)
-{
-    if (band_log2 < 0) return (blk % N_XCD_DEV) * per_xcd + blk / N_XCD_DEV;
-    const int span = N_XCD_DEV << band_log2;
-    if (blk >= (per_xcd >> band_log2) * span) return blk;
-    const int r = blk & (span - 1);
-    return (blk - r) + ((r % N_XCD_DEV) << band_log2) + r / N_XCD_DEV;
-}
-
 __device__ __forceinline__ int xcd_tile(int per_xcd, int band_log2, int first_block)
 {
     const int blk = (int)blockIdx.x - first_block;   // first_block is a multiple of 8

@@ -118,22 +118,6 @@ struct BatchLaunch {
     const void* args;               // StepArgs<R>[n_domains]
 };
 
-// A whole run of batched steps in one cooperative launch (LBVP_PERSISTENT):
-// the resident workgroups sweep the tile map once per step (workgroup w takes
-// map positions w, w + grid, ...; grid is a multiple of 8, so positions keep
-// their XCD) and meet at a grid barrier between steps. Records are summed by
-// the workgroups after the barrier that ends their step, one domain each, as
-// the leading blocks of a per-step launch do.
-struct PersistentLaunch {
-    BatchLaunch b;                  // flip, part_buf, fin_buf and n_fin are not used
-    int64_t n_steps;
-    int64_t step0;                  // the members' step count before the run
-    int32_t force_every;
-    int32_t keep_last;              // LBVP_KEEP_FIELDS on the run's last step
-    int32_t spin_limit;             // barrier polls before a workgroup gives up
-    uint32_t* bar;                  // [4]: arrivals, generation, failure flag, unused (zero at launch)
-};
-
 // One cut between two slabs (lbvp_halo_exchange): west's column nx - 1
 // populations with e_x = +1 into east's west halo (its lattice's column
 // pitch - 1), east's column 0 populations with e_x = -1 into west's east halo
@@ -197,9 +181,6 @@ hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a
 hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_t mode, bool record, bool fields,
                              const BatchLaunch& b, hipStream_t s);
 hipError_t launch_finalize_batch(const FinalizeArgs* fin_dev, int32_t n, int32_t buf, hipStream_t s);
-// the persistent form (pull layout); *grid: workgroups launched
-hipError_t launch_step_persistent(int32_t storage, int32_t vec, int32_t block, const PersistentLaunch& p,
-                                  hipStream_t s, int32_t* grid);
 hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s);
 hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs& a, hipStream_t s);
 hipError_t launch_decode(int32_t storage, const void* lat, const ConvArgs& a, hipStream_t s);

@@ -777,90 +777,6 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
     step_body<S, V, MODE, RECORD, FIELDS>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, lds);
 }
 
-// Grid barrier of a cooperative launch (every workgroup resident): the last of
-// `n` workgroups to arrive resets the arrival count and bumps the generation
-// the others poll. Release before arriving and acquire after leaving, at device
-// scope, make every step's stores visible to the next step's loads on any XCD.
-// A workgroup that polls more than spin_limit times (or sees another's failure)
-// raises the failure flag and returns false, so a barrier that cannot complete
-// ends the launch instead of hanging it.
-__device__ bool grid_barrier(uint32_t* bar, uint32_t n, uint32_t gen, int32_t spin_limit)
-{
-    __shared__ int ok;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        ok = 1;
-        __threadfence();
-        const uint32_t arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (arrived == n - 1) {
-            __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-            // relaxed polls (an acquiring poll would invalidate the XCD's L2 on
-            // every iteration, under the feet of the workgroups still streaming);
-            // the one acquire after the loop orders what follows
-            int32_t polls = 0;
-            while (__hip_atomic_load(&bar[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-                if (++polls > spin_limit ||
-                    __hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                    __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-            }
-        }
-        __threadfence();
-    }
-    __syncthreads();
-    return ok != 0;
-}
-
-// A run of batched pull steps in one launch (PersistentLaunch).
-template <typename S, int V>
-__global__ void __launch_bounds__(256) k_step_persistent(PersistentLaunch p)
-{
-    using R = typename Arith<S>::R;
-    __shared__ double lds[2 * FIN_LANES];
-    const BatchLaunch& b = p.b;
-    const StepArgs<R>* args = static_cast<const StepArgs<R>*>(b.args);
-    const int positions = N_XCD_DEV * b.tiles_per_xcd;
-    int pending = -1;        // partial buffer of the record waiting for its sum
-    int64_t recs = 0;        // records of the run so far (their parity picks the buffer)
-    for (int64_t k = 0; k < p.n_steps; ++k) {
-        const int64_t next = p.step0 + k + 1;
-        const bool record = p.force_every > 0 && next % p.force_every == 0;
-        const bool keep = p.keep_last && k == p.n_steps - 1;
-        const int flip = (int)(k & 1);
-        const int part_buf = (int)(recs & 1);
-        if (pending >= 0)
-            for (int d = (int)blockIdx.x; d < b.n_domains; d += (int)gridDim.x)
-                finalize_record(args[d].fin, pending, lds);
-        for (int m = (int)blockIdx.x; m < positions; m += (int)gridDim.x) {
-            const int g = xcd_tile_of(m, b.tiles_per_xcd, b.band_log2);
-            if (g >= b.total_tiles) continue;   // whole block
-            const int d = b.tile_domain[g];
-            const StepArgs<R>& a = args[d];
-            const int t = g - b.tile_start[d];
-            const int cur = a.cur ^ flip;
-            const S* src = static_cast<const S*>(cur ? a.lat1 : a.lat0);
-            S* dst = static_cast<S*>(cur ? a.lat0 : a.lat1);
-            if (record) {
-                if (keep) step_body<S, V, PULL, true, true>(src, dst, a, t, part_buf, lds);
-                else step_body<S, V, PULL, true, false>(src, dst, a, t, part_buf, lds);
-            } else {
-                if (keep) step_body<S, V, PULL, false, true>(src, dst, a, t, part_buf, lds);
-                else step_body<S, V, PULL, false, false>(src, dst, a, t, part_buf, lds);
-            }
-        }
-        pending = record ? part_buf : -1;
-        if (record) ++recs;
-        if (!grid_barrier(p.bar, gridDim.x, (uint32_t)k, p.spin_limit)) return;
-    }
-    if (pending >= 0)
-        for (int d = (int)blockIdx.x; d < b.n_domains; d += (int)gridDim.x) finalize_record(args[d].fin, pending, lds);
-}
-
 // The last record of an lbvp_step call, summed on its own.
 __global__ void __launch_bounds__(FIN_THREADS) k_finalize(FinalizeArgs a, int32_t buf)
 {
@@ -1173,53 +1089,6 @@ hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_
     case ST_F32: return batch_typed<float>(vec, mode, record, fields, b, block, s);
     case ST_F16: return batch_typed<_Float16>(vec, mode, record, fields, b, block, s);
     case ST_BF16: return batch_typed<__bf16>(vec, mode, record, fields, b, block, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-template <typename S, int V>
-hipError_t persistent_v(const PersistentLaunch& p, int32_t block, hipStream_t s, int32_t* grid_out)
-{
-    using R = typename Arith<S>::R;
-    const size_t lds = record_lds_bytes<R>(V, block);
-    int per_cu = 0, dev = 0, cus = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_persistent<S, V>, block, lds);
-    if (e == hipSuccess) e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    // every workgroup resident at once (the barrier needs it), a multiple of 8
-    // (map positions keep their XCD), no more than there are map positions
-    int64_t grid = std::min<int64_t>((int64_t)per_cu * cus, (int64_t)N_XCD * p.b.tiles_per_xcd);
-    grid = grid / N_XCD * N_XCD;
-    if (grid < N_XCD) return hipErrorInvalidConfiguration;
-    PersistentLaunch q = p;
-    void* kargs[] = {&q};
-    e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_step_persistent<S, V>), dim3((unsigned)grid),
-                                   dim3((unsigned)block), kargs, (unsigned)lds, s);
-    *grid_out = (int32_t)grid;
-    return e;
-}
-
-template <typename S>
-hipError_t persistent_typed(int32_t vec, const PersistentLaunch& p, int32_t block, hipStream_t s, int32_t* grid)
-{
-    constexpr int VW = 16 / (int)sizeof(S);
-    if (vec == VW) return persistent_v<S, VW>(p, block, s, grid);
-    if (vec == 1) return persistent_v<S, 1>(p, block, s, grid);
-    if constexpr (sizeof(S) == 2) {
-        if (vec == 4) return persistent_v<S, 4>(p, block, s, grid);
-    }
-    return hipErrorInvalidValue;
-}
-
-hipError_t launch_step_persistent(int32_t storage, int32_t vec, int32_t block, const PersistentLaunch& p,
-                                  hipStream_t s, int32_t* grid)
-{
-    switch (storage) {
-    case ST_F64: return persistent_typed<double>(vec, p, block, s, grid);
-    case ST_F32: return persistent_typed<float>(vec, p, block, s, grid);
-    case ST_F16: return persistent_typed<_Float16>(vec, p, block, s, grid);
-    case ST_BF16: return persistent_typed<__bf16>(vec, p, block, s, grid);
     default: return hipErrorInvalidValue;
     }
 }

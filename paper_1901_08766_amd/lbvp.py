@@ -30,7 +30,6 @@ LAYOUT_AA = 0x1
 MOVING_BODIES = 0x2
 KEEP_FIELDS = 0x1
 GRAPH = 0x2
-PERSISTENT = 0x4
 TUNE_LAYOUTS = 0x1
 TUNE_FRESH = 0x2
 
@@ -593,9 +592,8 @@ class Batch:
         self.solvers = list(solvers)
         self.handle = lbvp_batch_create([s.ctx for s in self.solvers], vec, block)
 
-    def step(self, n: int, keep_fields: bool = False, graph: bool = False, persistent: bool = False):
-        lbvp_batch_step(self.handle, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0)
-                        | (PERSISTENT if persistent else 0))
+    def step(self, n: int, keep_fields: bool = False, graph: bool = False):
+        lbvp_batch_step(self.handle, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0))
 
     @property
     def tile_band(self) -> int:
