@@ -88,8 +88,13 @@ typedef enum lbvp_storage {
  * c_b(t) = c_b + V_b t and turned by omega_b t (t = k), and node x belongs to it
  * when the mask given to lbvp_set_mask (the bodies at t = 0) holds b at the node
  * nearest to R(-omega_b t)(x - c_b(t)) + c_b (first such body wins); U_O uses
- * c_b(t). At most 8 bodies; one node per thread; not with LBVP_GRAPH, batches,
- * the pool or the tuner, which cannot carry a per-step time. */
+ * c_b(t). At most 8 bodies. Every launch shape, LBVP_GRAPH, batches (moving
+ * and fixed members mixed), the pool and the tuner take such contexts: the
+ * poses are evaluated on the host in double for up to 1024 coming time levels
+ * at a time and read on the device at a row that the device itself advances
+ * after each run, so a captured graph replays correctly at any later time.
+ * Results are bitwise equal across launch shapes, alone or in a batch, plain or
+ * through graphs. */
 #define LBVP_MOVING_BODIES 0x2u
 
 /* lbvp_step / lbvp_batch_step flags

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -36,6 +37,7 @@ constexpr int32_t MAX_BODIES = 255;
 constexpr uint32_t KNOWN_PARAM_FLAGS = LBVP_LAYOUT_AA | LBVP_MOVING_BODIES;
 constexpr uint32_t KNOWN_STEP_FLAGS = LBVP_KEEP_FIELDS | LBVP_GRAPH;
 constexpr int64_t GRAPH_CHUNK = 512;   // steps per captured graph; longer calls replay it
+static_assert(GRAPH_CHUNK <= POSE_ROWS, "a captured chunk reads one pose table");
 
 thread_local std::string g_create_error;
 
@@ -54,7 +56,7 @@ struct Layout {
     int64_t stage_rows = 0;
     size_t lat[2] = {0, 0}, mask = 0, bodies = 0, fields = 0, mass_part = 0, slot_force = 0,
            tile_slot_ptr = 0, slot_body = 0, body_slot_ptr = 0, body_slots = 0, ring_force = 0,
-           ring_mass = 0, rec_count = 0, stage = 0, ghost_w = 0, ghost_e = 0, pose = 0, total = 0;
+           ring_mass = 0, rec_count = 0, stage = 0, ghost_w = 0, ghost_e = 0, pose = 0, pose_base = 0, total = 0;
 };
 
 // Launch configuration of the step kernel and the tiling it implies.
@@ -104,7 +106,6 @@ Launch make_launch(int32_t nx, int32_t ny, int32_t vec, int32_t block)
 // (its push step moves single elements).
 std::vector<int32_t> vec_options(int32_t storage, uint32_t flags)
 {
-    if (flags & LBVP_MOVING_BODIES) return {1};   // moving masks run one node per thread
     const bool two_byte = storage == LBVP_F16_DEV || storage == LBVP_BF16_DEV;
     if (two_byte && (flags & LBVP_LAYOUT_AA)) return {1};
     if (two_byte) return {1, 4, vector_width(storage)};
@@ -223,6 +224,7 @@ Layout make_layout(const lbvp_params* p)
     L.ghost_e = take(3 * (size_t)p->ny * es);
     L.stage = take(stage_bytes);
     L.pose = take((p->flags & LBVP_MOVING_BODIES) ? (size_t)POSE_ROWS * MAX_MOVING * POSE_STRIDE * sizeof(double) : 0);
+    L.pose_base = take((p->flags & LBVP_MOVING_BODIES) ? sizeof(int64_t) : 0);
     L.total = o;
     return L;
 }
@@ -406,8 +408,9 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.ghost_w = c->at<char>(L.ghost_w);
     a.ghost_e = c->at<char>(L.ghost_e);
     a.fin = c->fin;
-    a.n_moving = 0;
-    a.pose_row = 0;
+    a.n_moving = c->moving() ? c->n_bodies : 0;
+    a.pose_k = 0;
+    a.pose_base = c->at<int64_t>(L.pose_base);
     a.pose = c->at<double>(L.pose);
 }
 
@@ -577,11 +580,33 @@ void restore_clock(lbvp_ctx* c, const CtxClock& k)
     c->pending = k.pending;
     c->fields_valid = k.fields_valid;
     c->pending_buf = k.pending_buf;
+    c->pose_first = -1;   // a failed run may have left the device pose row anywhere
+}
+
+// Moving bodies: make the device pose table hold the time levels next .. next +
+// n - 1 (n <= POSE_ROWS; next is the count after the coming step). If it does
+// not, the table is refilled from `next` on and the device base row reset to 0;
+// either way the base row is then the coming step's (every run advances it by
+// its length when it ends).
+lbvp_status pose_window(lbvp_ctx* c, int64_t next, int64_t n)
+{
+    if (c->pose_first >= 0 && next >= c->pose_first && next + n <= c->pose_first + POSE_ROWS) return LBVP_OK;
+    // the previous upload must have been read from its host buffer first
+    LBVP_HIP(c, hipStreamSynchronize(c->stream));
+    const size_t row = (size_t)MAX_MOVING * POSE_STRIDE;
+    c->pose_host.assign(row * POSE_ROWS, 0.0);
+    for (int32_t r = 0; r < POSE_ROWS; ++r) moving_pose(c, next + r, c->pose_host.data() + r * row);
+    LBVP_HIP(c, hipMemcpyAsync(c->at<double>(c->L.pose), c->pose_host.data(), c->pose_host.size() * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+    LBVP_HIP(c, launch_set_i64(c->at<int64_t>(c->L.pose_base), 0, c->stream));
+    c->pose_first = next;
+    return LBVP_OK;
 }
 
 // n steps from the current state, one launch each, then the standalone sum of
 // the last record. With launch == false only the bookkeeping advances (the
-// same launches were replayed from a graph).
+// same launches were replayed from a graph). Moving bodies: the pose table
+// must hold the run's time levels (pose_window).
 lbvp_status enqueue_steps(lbvp_ctx* c, int64_t n_steps, bool keep_last, bool launch)
 {
     const int64_t fe = c->p.force_every;
@@ -599,21 +624,8 @@ lbvp_status enqueue_steps(lbvp_ctx* c, int64_t n_steps, bool keep_last, bool lau
             const void* args = c->is_f64() ? (const void*)&c->a64 : (const void*)&c->a32;
             const int32_t mode = !c->aa() ? MODE_PULL : (c->step % 2 == 0 ? MODE_AA_PUSH : MODE_AA_LOCAL);
             hipError_t e;
-            if (c->moving()) {   // the bodies' poses at the time level this step computes
-                if (c->pose_first < 0 || next < c->pose_first || next >= c->pose_first + POSE_ROWS) {
-                    // a new table of poses from this time level on; the previous
-                    // upload must have been read from its host buffer first
-                    LBVP_HIP(c, hipStreamSynchronize(c->stream));
-                    const size_t row = (size_t)MAX_MOVING * POSE_STRIDE;
-                    c->pose_host.assign(row * POSE_ROWS, 0.0);
-                    for (int32_t r = 0; r < POSE_ROWS; ++r) moving_pose(c, next + r, c->pose_host.data() + r * row);
-                    LBVP_HIP(c, hipMemcpyAsync(c->at<double>(c->L.pose), c->pose_host.data(),
-                                               c->pose_host.size() * sizeof(double), hipMemcpyHostToDevice,
-                                               c->stream));
-                    c->pose_first = next;
-                }
-                c->a64.n_moving = c->a32.n_moving = c->n_bodies;
-                c->a64.pose_row = c->a32.pose_row = (int32_t)(next - c->pose_first);
+            if (c->moving()) {   // row *pose_base + k: the poses at the time level this step computes
+                c->a64.pose_k = c->a32.pose_k = (int32_t)k;
                 e = launch_step_moving(c->p.storage, mode, record, keep, c->at<char>(c->L.lat[c->cur]),
                                        c->at<char>(c->L.lat[c->cur ^ 1]), args, c->stream);
             } else {
@@ -637,6 +649,10 @@ lbvp_status enqueue_steps(lbvp_ctx* c, int64_t n_steps, bool keep_last, bool lau
             if (e != hipSuccess) return c->hip_fail(e, "finalize kernel launch");
         }
         c->pending = false;
+    }
+    if (launch && c->moving() && n_steps > 0) {   // the next run's first pose row
+        hipError_t e = launch_pose_advance(c->at<int64_t>(c->L.pose_base), n_steps, c->stream);
+        if (e != hipSuccess) return c->hip_fail(e, "pose advance launch");
     }
     return LBVP_OK;
 }
@@ -686,6 +702,15 @@ namespace {
 
 thread_local std::string g_batch_error;
 
+// Some member has moving bodies: the batch runs the kernels that evaluate a
+// moving mask (members with fixed masks take their mask as usual).
+bool batch_moving(const lbvp_batch* b)
+{
+    for (const lbvp_ctx* c : b->members)
+        if (c->moving()) return true;
+    return false;
+}
+
 // The batch requires one step kind, one record cadence and one stream for all
 // its members at every call.
 std::string batch_consistency(const lbvp_batch* b, const std::vector<lbvp_ctx*>& m)
@@ -702,7 +727,6 @@ std::string batch_consistency(const lbvp_batch* b, const std::vector<lbvp_ctx*>&
         const int64_t fe = c->p.force_every;
         if (fe > 1 && (c->step % fe) != (c0->step % fe)) return "members must be at the same force-record phase";
         if (c->pending) return "a member has an unsummed record";
-        if (c->moving()) return "members with moving bodies run alone";
     }
     return "";
 }
@@ -834,6 +858,7 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
         L.fin_buf = pending ? pending_buf : -1;
         L.n_domains = (int32_t)b->members.size();
         L.n_fin = L.fin_buf >= 0 ? (L.n_domains + N_XCD - 1) / N_XCD * N_XCD : 0;
+        L.pose_k = (int32_t)(k - k0);
         if (!b->halo_w.empty()) {   // the cuts' halo columns for this step
             BatchHalo H{};
             H.n_links = (int32_t)b->halo_w.size();
@@ -847,7 +872,8 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
             hipError_t he = launch_halo_batch(b->storage, H, b->stream);
             if (he != hipSuccess) return b->hip_fail(he, "halo exchange launch");
         }
-        hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, L, b->stream);
+        hipError_t e = launch_step_batch(b->storage, b->vec, b->block, mode, record, keep, batch_moving(b), L,
+                                         b->stream);
         if (e != hipSuccess) return b->hip_fail(e, "batched step launch");
         pending = record;
         if (record) {
@@ -860,8 +886,37 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
                                              (int32_t)b->members.size(), pending_buf, b->stream);
         if (e != hipSuccess) return b->hip_fail(e, "batched finalize launch");
     }
+    if (batch_moving(b) && n > 0) {   // the moving members' next pose rows
+        hipError_t e = launch_pose_advance_batch(b->storage, b->dev, (int32_t)b->members.size(), n, b->stream);
+        if (e != hipSuccess) return b->hip_fail(e, "pose advance launch");
+    }
     return LBVP_OK;
 }
+
+// Moving members: every one's pose table holds the time levels of the call's
+// steps k0 + 1 .. k0 + n, counted from the member's own step count (outside any
+// capture; n <= POSE_ROWS).
+lbvp_status batch_pose_windows(lbvp_batch* b, int64_t k0, int64_t n)
+{
+    for (lbvp_ctx* c : b->members)
+        if (c->moving()) {
+            const lbvp_status st = pose_window(c, c->step + k0 + 1, n);
+            if (st != LBVP_OK) return b->fail(st, "pose table of a moving member: " + c->err);
+        }
+    return LBVP_OK;
+}
+
+// Until disarmed, forgets the members' pose windows when it goes out of scope:
+// a run that failed part way may have left their device pose rows anywhere.
+struct PoseWindowGuard {
+    const std::vector<lbvp_ctx*>& members;
+    bool armed = true;
+    ~PoseWindowGuard()
+    {
+        if (armed)
+            for (lbvp_ctx* c : members) c->pose_first = -1;
+    }
+};
 
 // After a run of n_steps: the members' step counts, lattice parity, records
 // and fields, as lbvp_step would leave them.
@@ -963,14 +1018,15 @@ std::map<std::string, std::pair<std::vector<lbvp_tune_row>, int32_t>> g_tune_cac
 
 std::string tune_signature(const std::vector<lbvp_ctx*>& m, int32_t steps, uint32_t flags)
 {
-    std::vector<std::pair<int32_t, int32_t>> shapes;
-    for (const lbvp_ctx* c : m) shapes.emplace_back(c->p.nx, c->p.ny);
+    // a domain's size and whether it runs the moving-body kernels
+    std::vector<std::array<int32_t, 3>> shapes;
+    for (const lbvp_ctx* c : m) shapes.push_back({c->p.nx, c->p.ny, c->moving() ? c->n_bodies : 0});
     std::sort(shapes.begin(), shapes.end());
     std::ostringstream o;
     const lbvp_ctx* c0 = m[0];
     o << c0->p.storage << '/' << (c0->p.flags & LBVP_LAYOUT_AA) << '/' << c0->p.force_every << '/' << steps << '/'
       << (flags & LBVP_TUNE_LAYOUTS);
-    for (auto& x : shapes) o << ';' << x.first << 'x' << x.second;
+    for (auto& x : shapes) o << ';' << x[0] << 'x' << x[1] << (x[2] ? "m" + std::to_string(x[2]) : "");
     return o.str();
 }
 
@@ -1176,6 +1232,7 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
     c->bodies_host.assign(bodies, bodies + n_bodies);
     c->mov_r2.assign((size_t)n_bodies, 0.0);
     c->pose_first = -1;   // the poses follow the new bodies
+    c->a64.n_moving = c->a32.n_moving = c->moving() ? n_bodies : 0;
     if (c->moving()) {   // reach of each body about its centre: farthest node + 1
         std::vector<double> rmax((size_t)n_bodies, 0.0);
         for (int32_t j = 0; j < p.ny; ++j)
@@ -1229,6 +1286,7 @@ lbvp_status lbvp_init_equilibrium(lbvp_ctx* c, const double* rho, const double* 
     LBVP_HIP(c, hipStreamSynchronize(s));
     c->cur = 0;
     c->step = 0;
+    c->pose_first = -1;   // the step count starts again: so do the poses
     c->rec_head = c->rec_tail = 0;
     c->pending = false;
     c->fields_valid = true;
@@ -1247,12 +1305,25 @@ lbvp_status lbvp_step(lbvp_ctx* c, int64_t n_steps, uint32_t flags)
             return c->fail(LBVP_E_STATE, "force records would overflow the device ring; call lbvp_forces first");
     }
     const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
-    if (!(flags & LBVP_GRAPH)) return enqueue_steps(c, n_steps, keep, true);
-    if (c->moving()) return c->fail(LBVP_E_ARG, "LBVP_GRAPH cannot carry the per-step poses of moving bodies");
+    if (!(flags & LBVP_GRAPH)) {
+        if (!c->moving()) return enqueue_steps(c, n_steps, keep, true);
+        for (int64_t done = 0; done < n_steps;) {   // runs that fit the pose table
+            const int64_t n = std::min<int64_t>(POSE_ROWS, n_steps - done);
+            lbvp_status st = pose_window(c, c->step + 1, n);
+            if (st == LBVP_OK) st = enqueue_steps(c, n, keep && done + n == n_steps, true);
+            if (st != LBVP_OK) return st;
+            done += n;
+        }
+        return LBVP_OK;
+    }
     if (!c->stream) return c->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
     for (int64_t done = 0; done < n_steps;) {
         const int64_t n = std::min(GRAPH_CHUNK, n_steps - done);
         const bool keep_here = keep && done + n == n_steps;
+        if (c->moving()) {   // outside any capture: the chunk's poses on the device
+            const lbvp_status st = pose_window(c, c->step + 1, n);
+            if (st != LBVP_OK) return st;
+        }
         GraphKey key;
         key.n = n;
         key.keep = keep_here;
@@ -1533,6 +1604,7 @@ lbvp_status lbvp_load_state(lbvp_ctx* c, const void* buf, size_t size)
     c->graphs.clear(s);
     c->cur = h.cur;
     c->step = h.step;
+    c->pose_first = -1;
     c->rec_head = c->rec_tail = h.records;
     c->pending = false;
     c->fields_valid = h.fields_valid != 0;
@@ -1705,14 +1777,27 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
     if (up != LBVP_OK) return up;
     const bool keep = (flags & LBVP_KEEP_FIELDS) != 0;
     int64_t recs = 0;
+    const bool moving = batch_moving(b);
+    PoseWindowGuard guard{b->members};
     if (!(flags & LBVP_GRAPH)) {
-        const lbvp_status st = batch_run(b, step0, 0, n_steps, keep, &recs);
-        if (st != LBVP_OK) return st;
+        // one run, or runs that fit the moving members' pose tables
+        const int64_t seg = moving ? (int64_t)POSE_ROWS : n_steps;
+        for (int64_t k0 = 0; k0 < n_steps;) {
+            const int64_t n = std::min(seg, n_steps - k0);
+            lbvp_status st = moving ? batch_pose_windows(b, k0, n) : LBVP_OK;
+            if (st == LBVP_OK) st = batch_run(b, step0, k0, n, keep && k0 + n == n_steps, &recs);
+            if (st != LBVP_OK) return st;
+            k0 += n;
+        }
     } else {
         if (!b->stream) return b->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
         for (int64_t k0 = 0; k0 < n_steps;) {
             const int64_t n = std::min(GRAPH_CHUNK, n_steps - k0);
             const bool keep_here = keep && k0 + n == n_steps;
+            if (moving) {   // outside any capture: the chunk's poses on the device
+                const lbvp_status st = batch_pose_windows(b, k0, n);
+                if (st != LBVP_OK) return st;
+            }
             GraphKey key;
             key.n = n;
             key.keep = keep_here;
@@ -1743,6 +1828,7 @@ lbvp_status lbvp_batch_step(lbvp_batch* b, int64_t n_steps, uint32_t flags)
             k0 += n;
         }
     }
+    guard.armed = false;
     batch_advance_members(b, n_steps, recs, keep);
     return LBVP_OK;
 }
@@ -1805,9 +1891,20 @@ lbvp_status lbvp_batch_step_static(lbvp_ctx* const* members, int32_t n, int64_t 
     b.dev = sc->dev;
     b.dev_cap = STATIC_SCRATCH_BYTES;
     int64_t recs = 0;
-    const lbvp_status st = batch_run(&b, step0, 0, n_steps, (flags & LBVP_KEEP_FIELDS) != 0, &recs);
+    lbvp_status st = LBVP_OK;
+    const bool moving = batch_moving(&b);
+    const int64_t seg = moving ? (int64_t)POSE_ROWS : n_steps;
+    for (int64_t k0 = 0; k0 < n_steps && st == LBVP_OK;) {
+        const int64_t n = std::min(seg, n_steps - k0);
+        if (moving) st = batch_pose_windows(&b, k0, n);
+        if (st == LBVP_OK) st = batch_run(&b, step0, k0, n, (flags & LBVP_KEEP_FIELDS) != 0 && k0 + n == n_steps, &recs);
+        k0 += n;
+    }
     b.dev = nullptr;   // not the batch's to free
-    if (st != LBVP_OK) return batch_static_fail(st, b.err);
+    if (st != LBVP_OK) {
+        for (lbvp_ctx* c : m) c->pose_first = -1;   // the device pose rows may be anywhere
+        return batch_static_fail(st, b.err);
+    }
     batch_advance_members(&b, n_steps, recs, (flags & LBVP_KEEP_FIELDS) != 0);
     return LBVP_OK;
 }
@@ -1882,10 +1979,6 @@ lbvp_status lbvp_tune(lbvp_ctx* const* members, int32_t n, int32_t steps, uint32
         }
     const lbvp_ctx* c0 = m[0];
     for (const lbvp_ctx* c : m) {
-        if (c->moving()) {
-            g_tune_error = "members with moving bodies run alone, one node per thread: nothing to tune";
-            return LBVP_E_ARG;
-        }
         if (c->p.storage != c0->p.storage || c->aa() != c0->aa() || c->stream != c0->stream ||
             c->p.force_every != c0->p.force_every) {
             g_tune_error = "members differ in storage, layout, stream or force_every";

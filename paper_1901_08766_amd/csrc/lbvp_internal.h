@@ -94,13 +94,17 @@ struct StepArgs {
     void* lat1;                     // current (two-lattice pull; the AA layout uses lat0 only)
     int32_t cur;
     FinalizeArgs fin;
-    // moving bodies: pose[(pose_row * MAX_MOVING + b) * POSE_STRIDE + k] holds body
-    // b's pose at this step's time level t, k = 0..6: cos th, sin th, cx(t),
+    // moving bodies: pose[(row * MAX_MOVING + b) * POSE_STRIDE + k] holds body b's
+    // pose at the time level of table row `row`, k = 0..6: cos th, sin th, cx(t),
     // cy(t), cx(0), cy(0) with th = omega t, c(t) = c(0) + V t, and the square
-    // of a radius about c(t) outside which no node can belong to the body;
+    // of a radius about c(t) outside which no node can belong to the body. A
+    // launch that is the k-th step of a run takes row *pose_base + k, with k =
+    // pose_k (single-domain launches) or BatchLaunch::pose_k; the device value
+    // pose_base is advanced after every run, so captured runs replay correctly.
     // n_moving = 0 for fixed masks
     int32_t n_moving;
-    int32_t pose_row;
+    int32_t pose_k;
+    const int64_t* pose_base;
     const double* pose;
 };
 
@@ -113,6 +117,7 @@ struct BatchLaunch {
     int32_t n_domains;
     int32_t n_fin;                  // leading blocks that sum the fin_buf records: n_domains
                                     // rounded up to a multiple of 8, or 0 if fin_buf < 0
+    int32_t pose_k;                 // this launch's step within the run (moving bodies)
     const int32_t* tile_domain;     // [total_tiles] domain of each tile
     const int32_t* tile_start;      // [n_domains] first tile of each domain
     const void* args;               // StepArgs<R>[n_domains]
@@ -179,7 +184,11 @@ hipError_t launch_step_moving(int32_t storage, int32_t mode, bool record, bool f
                               const void* step_args, hipStream_t s);
 hipError_t launch_aa_ghosts(int32_t storage, const void* lat, const GhostArgs& a, hipStream_t s);
 hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_t mode, bool record, bool fields,
-                             const BatchLaunch& b, hipStream_t s);
+                             bool moving, const BatchLaunch& b, hipStream_t s);
+// moving bodies: advance the pose table row of a context (base) or of every
+// moving member of a batch (their StepArgs in args) by n steps
+hipError_t launch_pose_advance(int64_t* base, int64_t n, hipStream_t s);
+hipError_t launch_pose_advance_batch(int32_t storage, const void* args, int32_t n_domains, int64_t n, hipStream_t s);
 hipError_t launch_finalize_batch(const FinalizeArgs* fin_dev, int32_t n, int32_t buf, hipStream_t s);
 hipError_t launch_finalize(const FinalizeArgs& a, int32_t buf, hipStream_t s);
 hipError_t launch_init(int32_t storage, void* lat, void* fields, const ConvArgs& a, hipStream_t s);

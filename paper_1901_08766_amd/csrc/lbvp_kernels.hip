@@ -75,6 +75,7 @@ template <typename R>
 struct BodySource {
     bool uniform;
     BodyRow<R> row;
+    const double* pose;   // moving bodies: the poses at this step's time level, else null
 };
 
 // Volume penalization of a solid node (eqs. d-V, force-density): U_O = V +
@@ -90,8 +91,8 @@ __device__ __forceinline__ void penalize(const BodySource<R>& src, int body, int
     if (src.uniform) B = src.row;
     else B = body_row(a.bodies + BODY_STRIDE * body);
     R rx, ry;
-    if constexpr (MOVING) {
-        const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (body - 1)) * POSE_STRIDE;
+    if (MOVING && src.pose) {
+        const double* m = src.pose + (body - 1) * POSE_STRIDE;
         rx = (R)((double)i - m[2]);
         ry = (R)((double)j - m[3]);
     } else {
@@ -225,9 +226,8 @@ __device__ __forceinline__ NodeResult<R> collide_node_lowp(R (&f)[9], int body, 
 // operation per statement (no fused multiply-adds), so that membership does
 // not depend on the storage type. Nodes outside a body's radius skip it.
 template <typename R>
-__device__ __forceinline__ int moving_body(const StepArgs<R>& a, int i, int j)
+__device__ __forceinline__ int moving_body(const StepArgs<R>& a, const double* row, int i, int j)
 {
-    const double* row = a.pose + (int64_t)a.pose_row * MAX_MOVING * POSE_STRIDE;
     for (int b = 0; b < a.n_moving; ++b) {
         const double* m = row + b * POSE_STRIDE;
         const double dx = (double)i - m[2];
@@ -347,12 +347,16 @@ __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, 
 // lds: the kernel's 2 FIN_LANES doubles.
 template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false>
 __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a, int t,
-                                          int part_buf, double* lds)
+                                          int part_buf, double* lds, int pose_k = 0)
 {
     using R = typename Arith<S>::R;
     int s0 = 0, s1 = 0;          // this tile's (tile, body) force slots
     BodySource<R> bs;
     bs.uniform = false;
+    bs.pose = nullptr;
+    if constexpr (MOVING) {      // the poses at this step's time level (a domain with moving bodies)
+        if (a.n_moving > 0) bs.pose = a.pose + (*a.pose_base + pose_k) * (int64_t)(MAX_MOVING * POSE_STRIDE);
+    }
     if constexpr (RECORD) {
         s0 = a.tile_slot_ptr[t];
         s1 = a.tile_slot_ptr[t + 1];
@@ -423,9 +427,9 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
             for (int k = 0; k < V; ++k) v[q][k] = as_lv<LV>(raw[k]);
         }
-        if constexpr (MOVING) {
+        if (MOVING && bs.pose) {
 #pragma unroll
-            for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, i0 + k, j) : 0;
+            for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, bs.pose, i0 + k, j) : 0;
         } else {
             load_mask<V>(a.mask + r0 + il, body);
         }
@@ -658,9 +662,9 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 #pragma unroll
         for (int k = 0; k < V; ++k) bid[k] = 0;
         if (s1 > s0 && act) {
-            if constexpr (MOVING) {
+            if (MOVING && bs.pose) {
 #pragma unroll
-                for (int k = 0; k < V; ++k) bid[k] = (k < n_own) ? moving_body(a, i0 + k, j) : 0;
+                for (int k = 0; k < V; ++k) bid[k] = (k < n_own) ? moving_body(a, bs.pose, i0 + k, j) : 0;
             } else {
                 load_mask<V>(a.mask + r0 + i0, bid);
             }
@@ -676,10 +680,10 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
             for (int s = c0; s < c1; ++s) {
                 const int b = a.slot_body[s];
                 bool skip = false;
-                if constexpr (MOVING) {
+                if (MOVING && bs.pose) {
                     // slots are dense (every tile, every body): a body whose radius
                     // misses this tile's rectangle adds nothing (uniform across the block)
-                    const double* m = a.pose + ((int64_t)a.pose_row * MAX_MOVING + (b - 1)) * POSE_STRIDE;
+                    const double* m = bs.pose + (b - 1) * POSE_STRIDE;
                     const double x0 = (double)(tx * a.tile_w), x1 = x0 + (double)(a.tile_w - 1);
                     const double y0 = (double)(ty * a.tile_rows), y1 = y0 + (double)(a.tile_rows - 1);
                     const double ex = m[2] < x0 ? x0 - m[2] : (m[2] > x1 ? m[2] - x1 : 0.0);
@@ -732,7 +736,7 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     }
     const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, PULL, RECORD, FIELDS, MOVING>(src, dst, a, t, a.part_buf, lds);
+    step_body<S, V, PULL, RECORD, FIELDS, MOVING>(src, dst, a, t, a.part_buf, lds, a.pose_k);
 }
 
 // One lattice, read and written in place (no restrict).
@@ -747,13 +751,13 @@ __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith
     }
     const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, MODE, RECORD, FIELDS, MOVING>(lat, lat, a, t, a.part_buf, lds);
+    step_body<S, V, MODE, RECORD, FIELDS, MOVING>(lat, lat, a, t, a.part_buf, lds, a.pose_k);
 }
 
 // Many domains in one launch: block -> (domain, tile) through the tile map;
 // every domain's arguments (geometry, parameters, lattices) live in device
 // memory. All domains take the same step kind, record flag and partial buffers.
-template <typename S, int V, int MODE, bool RECORD, bool FIELDS>
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false>
 __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
 {
     using R = typename Arith<S>::R;
@@ -774,7 +778,8 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
     const int cur = a.cur ^ b.flip;
     S* lat_cur = static_cast<S*>(cur ? a.lat1 : a.lat0);
     S* lat_next = static_cast<S*>(cur ? a.lat0 : a.lat1);
-    step_body<S, V, MODE, RECORD, FIELDS>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, lds);
+    step_body<S, V, MODE, RECORD, FIELDS, MOVING>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, lds,
+                                                  b.pose_k);
 }
 
 // The last record of an lbvp_step call, summed on its own.
@@ -789,6 +794,16 @@ __global__ void __launch_bounds__(FIN_THREADS) k_finalize_batch(const FinalizeAr
 {
     __shared__ double lds[2 * FIN_LANES];
     finalize_record(fins[blockIdx.x], buf, lds);
+}
+
+// Moving bodies: after a run of n steps, the pose table row of the next step.
+__global__ void k_pose_advance(int64_t* base, int64_t n) { *base += n; }
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_pose_advance_batch(const StepArgs<R>* args, int32_t n_domains, int64_t n)
+{
+    const int d = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (d < n_domains && args[d].n_moving > 0) *const_cast<int64_t*>(args[d].pose_base) += n;
 }
 
 // ------------------------------------------------------------ conversions --
@@ -1000,46 +1015,55 @@ hipError_t step_typed_moving(int mode, bool record, bool fields, const void* src
 {
     using R = typename Arith<S>::R;
     const StepArgs<R>& a = *static_cast<const StepArgs<R>*>(args_v);
-    if (a.vec != 1) return hipErrorInvalidValue;   // moving masks run one node per thread
-    return step_v<S, 1, true>(mode, record, fields, static_cast<const S*>(src), static_cast<S*>(dst), a, s);
+    const S* in = static_cast<const S*>(src);
+    S* out = static_cast<S*>(dst);
+    constexpr int VW = 16 / (int)sizeof(S);
+    if (a.vec == VW) return step_v<S, VW, true>(mode, record, fields, in, out, a, s);
+    if (a.vec == 1) return step_v<S, 1, true>(mode, record, fields, in, out, a, s);
+    if constexpr (sizeof(S) == 2) {
+        if (a.vec == 4) return step_v<S, 4, true>(mode, record, fields, in, out, a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
-template <typename S, int V, int MODE>
+template <typename S, int V, int MODE, bool MOVING>
 hipError_t batch_mode(bool record, bool fields, const BatchLaunch& b, int32_t block, hipStream_t s)
 {
     const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD + b.n_fin)), blk((unsigned)block);
     const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, block);
     if (record) {
-        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true>), grid, blk, lds, s, b);
-        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false>), grid, blk, lds, s, b);
+        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true, MOVING>), grid, blk, lds, s, b);
+        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false, MOVING>), grid, blk, lds, s, b);
     } else {
-        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, true>), grid, blk, 0, s, b);
-        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, false>), grid, blk, 0, s, b);
+        if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, true, MOVING>), grid, blk, 0, s, b);
+        else hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, false, MOVING>), grid, blk, 0, s, b);
     }
     return hipGetLastError();
 }
 
-template <typename S, int V>
+template <typename S, int V, bool MOVING>
 hipError_t batch_v(int32_t mode, bool record, bool fields, const BatchLaunch& b, int32_t block, hipStream_t s)
 {
-    if (mode == PULL) return batch_mode<S, V, PULL>(record, fields, b, block, s);
+    if (mode == PULL) return batch_mode<S, V, PULL, MOVING>(record, fields, b, block, s);
     if constexpr (sizeof(S) >= 4 || V == 1) {
-        if (mode == AA_PUSH) return batch_mode<S, V, AA_PUSH>(record, fields, b, block, s);
-        return batch_mode<S, V, AA_LOCAL>(record, fields, b, block, s);
+        if (mode == AA_PUSH) return batch_mode<S, V, AA_PUSH, MOVING>(record, fields, b, block, s);
+        return batch_mode<S, V, AA_LOCAL, MOVING>(record, fields, b, block, s);
     } else {
         return hipErrorInvalidValue;
     }
 }
 
-template <typename S>
+// moving: some member has moving bodies (every member then runs the kernel
+// that evaluates a moving mask where a domain has one)
+template <typename S, bool MOVING>
 hipError_t batch_typed(int32_t vec, int32_t mode, bool record, bool fields, const BatchLaunch& b, int32_t block,
                        hipStream_t s)
 {
     constexpr int VW = 16 / (int)sizeof(S);
-    if (vec == VW) return batch_v<S, VW>(mode, record, fields, b, block, s);
-    if (vec == 1) return batch_v<S, 1>(mode, record, fields, b, block, s);
+    if (vec == VW) return batch_v<S, VW, MOVING>(mode, record, fields, b, block, s);
+    if (vec == 1) return batch_v<S, 1, MOVING>(mode, record, fields, b, block, s);
     if constexpr (sizeof(S) == 2) {
-        if (vec == 4) return batch_v<S, 4>(mode, record, fields, b, block, s);
+        if (vec == 4) return batch_v<S, 4, MOVING>(mode, record, fields, b, block, s);
     }
     return hipErrorInvalidValue;
 }
@@ -1082,15 +1106,42 @@ hipError_t launch_step_moving(int32_t storage, int32_t mode, bool record, bool f
 }
 
 hipError_t launch_step_batch(int32_t storage, int32_t vec, int32_t block, int32_t mode, bool record, bool fields,
-                             const BatchLaunch& b, hipStream_t s)
+                             bool moving, const BatchLaunch& b, hipStream_t s)
 {
+    if (moving) {
+        switch (storage) {
+        case ST_F64: return batch_typed<double, true>(vec, mode, record, fields, b, block, s);
+        case ST_F32: return batch_typed<float, true>(vec, mode, record, fields, b, block, s);
+        case ST_F16: return batch_typed<_Float16, true>(vec, mode, record, fields, b, block, s);
+        case ST_BF16: return batch_typed<__bf16, true>(vec, mode, record, fields, b, block, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (storage) {
-    case ST_F64: return batch_typed<double>(vec, mode, record, fields, b, block, s);
-    case ST_F32: return batch_typed<float>(vec, mode, record, fields, b, block, s);
-    case ST_F16: return batch_typed<_Float16>(vec, mode, record, fields, b, block, s);
-    case ST_BF16: return batch_typed<__bf16>(vec, mode, record, fields, b, block, s);
+    case ST_F64: return batch_typed<double, false>(vec, mode, record, fields, b, block, s);
+    case ST_F32: return batch_typed<float, false>(vec, mode, record, fields, b, block, s);
+    case ST_F16: return batch_typed<_Float16, false>(vec, mode, record, fields, b, block, s);
+    case ST_BF16: return batch_typed<__bf16, false>(vec, mode, record, fields, b, block, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_pose_advance(int64_t* base, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pose_advance, dim3(1), dim3(1), 0, s, base, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_pose_advance_batch(int32_t storage, const void* args, int32_t n_domains, int64_t n, hipStream_t s)
+{
+    const dim3 g((unsigned)((n_domains + 255) / 256)), b(256);
+    if (storage == ST_F64)
+        hipLaunchKernelGGL(k_pose_advance_batch<double>, g, b, 0, s, static_cast<const StepArgs<double>*>(args),
+                           n_domains, n);
+    else
+        hipLaunchKernelGGL(k_pose_advance_batch<float>, g, b, 0, s, static_cast<const StepArgs<float>*>(args),
+                           n_domains, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize_batch(const FinalizeArgs* fin_dev, int32_t n, int32_t buf, hipStream_t s)

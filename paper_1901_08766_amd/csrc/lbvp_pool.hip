@@ -287,7 +287,6 @@ lbvp_status lbvp_pool_admit(lbvp_pool* p, const lbvp_params* prm, const uint8_t*
     if (n_steps > (int64_t(1) << 26)) return p->fail(LBVP_E_ARG, "n_steps larger than the force ring allows");
     if (prm->storage != p->cfg.storage || (prm->flags & LBVP_LAYOUT_AA) != p->cfg.layout_flags)
         return p->fail(LBVP_E_ARG, "the solve's storage and layout must be the pool's");
-    if (prm->flags & LBVP_MOVING_BODIES) return p->fail(LBVP_E_ARG, "solves with moving bodies run alone");
     if (prm->bc_west == LBVP_BC_NEIGHBOR || prm->bc_east == LBVP_BC_NEIGHBOR)
         return p->fail(LBVP_E_ARG, "a slab of a decomposed domain needs its halo exchanges: step it outside the pool");
     if (n_bodies < 0 || n_bodies > 255) return p->fail(LBVP_E_ARG, "n_bodies must be in 0..255");

@@ -83,20 +83,217 @@ def test_bodies_at_rest_equal_the_fixed_mask(lbvp):
     assert np.abs(fa - fb).max() <= 1e-14 * max(np.abs(fb).max(), 1e-300) * 10
 
 
-def test_moving_rejections(lbvp):
+VW = {"f64": 2, "f32": 4, "f16": 8, "bf16": 8}
+
+
+def _solver(lbvp, p, storage, steps, launch=None, band=None, stream=None, flags=0):
+    s = lbvp.Solver(p, storage=storage, force_every=1, force_capacity=steps + 8, flags=flags, stream=stream)
+    if launch:
+        s.set_launch(*launch)
+    if band is not None:
+        s.set_tile_band(band)
+    return s
+
+
+def _state(s):
+    f, m, first = s.forces()
+    return s.populations(), s.fields(), f, m, first
+
+
+def _assert_same(a, b, what):
+    assert np.array_equal(a[0], b[0]), what
+    for k in a[1]:
+        assert np.array_equal(a[1][k], b[1][k]), (what, k)
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[3], b[3]) and a[4] == b[4], what
+
+
+def _mixed_members():
+    """Two moving problems (different sides, sizes and seeds) and a fixed-mask one."""
+    return [inputs.moving_bodies(bc=SIDES_IO, u_in=0.03),
+            inputs.moving_bodies(nx=197, ny=101, seed=9),
+            inputs.random_state_problem(130, 70, seed=61, n_disks=3, bc=SIDES_IO)]
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_launch_shapes_agree(lbvp, storage):
+    """The per-node arithmetic does not depend on the launch shape: populations
+    and fields are bitwise those of one node per thread; the force records are
+    sums over a different tiling (last bits), and bitwise across tile bands."""
+    p = inputs.moving_bodies(bc=SIDES_IO, u_in=0.03)
+    steps = 37
+    shapes = [(1, 64), (VW[storage], 256), (VW[storage], 64)] + ([(4, 256)] if storage in ("f16", "bf16") else [])
+    ref = None
+    for launch in shapes:
+        for band in ((0, 16) if launch[0] > 1 else (0,)):
+            print(f"moving {storage} launch={launch} band={band}", flush=True)
+            s = _solver(lbvp, p, storage, steps, launch, band)
+            s.step(steps, keep_fields=True)
+            got = _state(s)
+            s.close()
+            if ref is None:
+                ref = got
+                continue
+            assert np.array_equal(ref[0], got[0]), (launch, band)
+            for k in ref[1]:
+                assert np.array_equal(ref[1][k], got[1][k]), (launch, band, k)
+            # bound: the per-node force magnitudes that the sums add up
+            scale = np.abs(ref[1]["fx"]).sum() + np.abs(ref[1]["fy"]).sum()
+            tol = 1e-13 if storage == "f64" else 1e-6
+            assert np.abs(ref[2] - got[2]).max() <= tol * scale, (launch, band)
+            assert np.abs(ref[3] - got[3]).max() <= tol * np.abs(ref[3]).max(), (launch, band)
+            if band:
+                _assert_same(band0, got, (launch, band))
+            band0 = got
+
+
+@pytest.mark.parametrize("aa", [False, True], ids=["pull", "aa"])
+def test_graph_equals_plain(lbvp, aa):
+    """Graph replays read the poses at a device-side row: the same captured
+    chunk replayed at later times, across pose-table refills (1024 time levels)
+    and graph chunks (512 steps), is bitwise the plain run."""
     p = inputs.moving_bodies()
-    s = lbvp.Solver(p, storage="f32", force_every=1, force_capacity=64, stream=torch.cuda.Stream())
-    with pytest.raises(lbvp.LbvpError) as e:
-        s.step(2, graph=True)
-    assert e.value.status == lbvp.E_ARG
-    with pytest.raises(lbvp.LbvpError):
-        s.set_launch(4, 256)
-    q = inputs.random_state_problem(64, 32, seed=5, n_disks=1)
-    other = lbvp.Solver(q, storage="f32", force_every=1, force_capacity=64, stream=s.stream)
-    with pytest.raises(lbvp.LbvpError):
-        lbvp.Batch([s, other])
-    pool = lbvp.Pool(storage="f32", cap_bytes=1 << 28, max_slots=2, stream=s.stream)
-    params = lbvp.params_for(p, "f32", 1, 0)
-    with pytest.raises(lbvp.LbvpError):
-        lbvp.lbvp_pool_admit(pool.handle, params, p.mask_or_empty(), p.bodies_or_empty(), n_steps=3)
+    flags = lbvp.LAYOUT_AA if aa else 0
+    calls = [100] * 6 + [700, 150, 2]
+    total = sum(calls)
+    stream = torch.cuda.Stream()
+    g = _solver(lbvp, p, "f32", total, stream=stream, flags=flags)
+    for k, n in enumerate(calls):
+        print(f"moving graph aa={aa} call {k}: {n} steps", flush=True)
+        g.step(n, graph=True, keep_fields=(k == len(calls) - 1))
+    a = _solver(lbvp, p, "f32", total, launch=g.launch, band=g.tile_band, flags=flags)
+    a.step(total, keep_fields=True)
+    assert g.step_count == a.step_count == total
+    _assert_same(_state(a), _state(g), "graph")     # an even count: AA populations readable
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f64"])
+def test_batch_equals_alone(lbvp, storage):
+    """Moving and fixed members in one batch, at different step counts, through a
+    pose-table refill, plain and through graphs: each member bitwise as alone."""
+    probs = _mixed_members()
+    vec = VW[storage]
+    stream = torch.cuda.Stream()
+    total = 1200
+    members = [_solver(lbvp, q, storage, total + 40, (vec, 256), stream=stream) for q in probs]
+    members[1].step(7)                  # a member ahead of the others
+    members[1].forces()
+    batch = lbvp.Batch(members, vec=vec, block=256)
+    print(f"moving batch {storage}: {len(members)} members", flush=True)
+    batch.step(600)
+    batch.step(300, graph=True)
+    batch.step(300, graph=True, keep_fields=True)
+    batch.close()
+    for k, (q, m) in enumerate(zip(probs, members)):
+        ahead = 7 if k == 1 else 0
+        a = _solver(lbvp, q, storage, total + 40, (vec, 256))
+        a.step(ahead)
+        a.forces()
+        a.step(total, keep_fields=True)
+        assert m.step_count == a.step_count == total + ahead
+        _assert_same(_state(a), _state(m), (storage, k))
+        a.close()
+        m.close()
+
+
+def test_batch_fp64_matches_oracle(lbvp, oracle):
+    """A moving member of a batch against the oracle's own run (FP64 to 1e-12)."""
+    probs = _mixed_members()
+    stream = torch.cuda.Stream()
+    steps = 60
+    members = [_solver(lbvp, q, "f64", steps, (2, 128), stream=stream) for q in probs]
+    batch = lbvp.Batch(members, vec=2, block=128)
+    batch.step(steps, keep_fields=True)
+    batch.close()
+    for q, m in zip(probs[:2], members[:2]):
+        r = oracle.RefSolver(q)
+        rf, rm = r.step(steps, record=True)
+        gf, gm, first = m.forces()
+        assert _rel(m.populations(), r.populations()) <= 1e-12
+        scale = np.abs(rf).max()
+        assert first == 1 and np.abs(gf - rf).max() <= 1e-11 * scale
+        assert np.abs(gm - rm).max() <= 1e-13 * rm.max()
+        r.close()
+
+
+def test_pool_results_equal_alone(lbvp):
+    """Moving solves in the serving pool, admitted at different epochs next to
+    fixed ones: every result bitwise that of the solve stepped alone."""
+    reqs = [(inputs.moving_bodies(bc=SIDES_IO, u_in=0.03), 90, 0),
+            (inputs.random_state_problem(96, 64, seed=71, n_disks=2, bc=SIDES_IO), 40, 0),
+            (inputs.moving_bodies(nx=150, ny=90, seed=3), 1100, 1),
+            (inputs.moving_bodies(seed=11), 13, 3)]
+    vec, block = 4, 128
+    pool = lbvp.Pool(storage="f32", cap_bytes=1 << 30, max_slots=3, vec=vec, block=block, chunk_bytes=64 << 20,
+                     max_in_flight=2)
+    pending, slot_of, results, epoch = list(range(len(reqs))), {}, {}, 0
+    while pending or slot_of:
+        for k in list(pending):
+            prob, steps, at = reqs[k]
+            if at > epoch:
+                continue
+            slot = pool.admit(prob, steps)
+            if slot is None:
+                break
+            slot_of[slot] = k
+            pending.remove(k)
+        ran = pool.run_epoch(64)
+        epoch += 1
+        for slot in pool.poll(wait=(ran == 0)):
+            k = slot_of.pop(slot)
+            f, m, first = pool.forces(slot)
+            results[k] = (f, m, first, pool.fields(slot))
+            pool.release(slot)
+        assert epoch < 500
     pool.close()
+    for k, (prob, steps, _) in enumerate(reqs):
+        print(f"moving pool request {k} {prob.nx}x{prob.ny} {steps} steps", flush=True)
+        f, m, first, fields = results[k]
+        a = lbvp.Solver(prob, storage="f32", force_every=1, force_capacity=steps + 1)
+        a.set_launch(vec, block)
+        a.step(steps, keep_fields=True)
+        fa, ma, firsta = a.forces()
+        fl = a.fields()
+        a.close()
+        assert len(m) == steps and first == firsta == 1
+        assert np.array_equal(f, fa) and np.array_equal(m, ma), k
+        for name in fields:
+            assert np.array_equal(fields[name], fl[name]), (k, name)
+
+
+def test_tuner_takes_moving_members(lbvp):
+    stream = torch.cuda.Stream()
+    probs = _mixed_members()
+    members = [lbvp.Solver(q, storage="f32", force_every=1, force_capacity=64, stream=stream) for q in probs]
+    for m in members:
+        m.step(3)
+    before = [m.populations() for m in members]
+    rows, best = lbvp.tune(members, steps=20, fresh=True)
+    assert {(r["vec"], r["block"], r["band"]) for r in rows} == {
+        (v, b, t) for v in (1, 4) for b in (64, 128, 256) for t in ((0,) if v == 1 else (0, 2, 16))}
+    for m, g in zip(members, before):
+        assert m.step_count == 3 and np.array_equal(m.populations(), g)
+    for m in members:
+        m.forces()
+    batch = lbvp.Batch(members, vec=best["vec"], block=best["block"])
+    batch.set_tile_band(best["band"])
+    batch.step(5)
+    batch.close()
+    assert all(m.step_count == 8 for m in members)
+
+
+def test_moving_rejections(lbvp):
+    """At most 8 moving bodies (the pose row holds 8)."""
+    p = inputs.moving_bodies()
+    p.bodies = np.tile(p.bodies[:1], (9, 1))
+    p.mask = p.mask.copy()
+    p.mask[0, :9] = np.arange(1, 10, dtype=np.uint8)
+    with pytest.raises(lbvp.LbvpError) as e:
+        lbvp.Solver(p, storage="f32", force_every=1, force_capacity=64)
+    assert e.value.status == lbvp.E_ARG
+    assert lbvp.lbvp_footprint_bytes(lbvp.params_for(p, "f32", 1, 64)) == 0
+    p.moving = False                    # the same bodies on a fixed mask are fine
+    assert lbvp.lbvp_footprint_bytes(lbvp.params_for(p, "f32", 1, 64)) > 0
+    s = lbvp.Solver(p, storage="f32", force_every=1, force_capacity=64)
+    s.step(3)
+    assert s.step_count == 3
+    s.close()
