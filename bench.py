@@ -29,7 +29,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 METRIC = "MLUPS + % of HBM peak, plain vs batched/FP16; p50/p99 solve latency"
-BYTES_PER_NODE = {"f64": 145, "f32": 73, "f16": 37, "bf16": 37}
+# the nine populations read and written once per step in the storage type; the
+# body-mask byte is added per node where the step reads it (alg_bytes_per_node)
+POP_BYTES = {"f64": 144, "f32": 72, "f16": 36, "bf16": 36}
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_kernel_counters.json")
 # per lattice: populations per node, the sources its step kernel is built from,
 # and the committed counter summary of that kernel
@@ -64,6 +66,41 @@ def measured_traffic(storage: str, nodes: int, lattice: str = "d2q9"):
     if not entry or entry.get("nodes") != nodes:
         return None
     return entry.get("hbm_bytes_per_launch")
+
+
+# the default D2Q9 launch of the 8192 x 4096 domain per storage type (the
+# library's choice, which the GPU tests check)
+DEFAULT_LAUNCH_2D = {"f32": {"vec": 4, "block": 128}, "f64": {"vec": 2, "block": 128},
+                     "f16": {"vec": 4, "block": 256}, "bf16": {"vec": 4, "block": 256}}
+
+
+def tile_shape(nx: int, launch) -> tuple:
+    """(tile_w, tile_rows) of a D2Q9 launch shape (vec nodes per thread, block threads)."""
+    vec, block = launch["vec"], launch["block"]
+    tile_w = min(vec * block, max(vec, 1 << max(nx - 1, 0).bit_length()))
+    return tile_w, vec * block // tile_w
+
+
+def mask_read_fraction(prob, launch) -> float:
+    """Nodes whose mask byte a step reads, over all nodes: the nodes of tiles that
+    hold a solid node (the step kernels skip the mask of every other tile)."""
+    if prob.mask is None or not (prob.mask > 0).any():
+        return 0.0
+    ny, nx = prob.mask.shape
+    tw, tr = tile_shape(nx, launch)
+    tx, ty = -(-nx // tw), -(-ny // tr)
+    pad = np.zeros((ty * tr, tx * tw), dtype=bool)
+    pad[:ny, :nx] = prob.mask > 0
+    has = pad.reshape(ty, tr, tx, tw).any(axis=(1, 3))
+    w = np.minimum(tw, nx - np.arange(tx) * tw)            # real columns per tile column
+    h = np.minimum(tr, ny - np.arange(ty) * tr)            # real rows per tile row
+    return float((has * h[:, None] * w[None, :]).sum()) / (nx * ny)
+
+
+def alg_bytes_per_node(storage: str, prob, launch) -> float:
+    """Algorithmic HBM bytes per node of one step: 18 population accesses in the
+    storage type plus the mask byte where the step reads it."""
+    return POP_BYTES[storage] + mask_read_fraction(prob, launch)
 
 
 def time_gpu(storage: str, steps: int, warmup: int, prob, repeats: int = 1):
@@ -429,7 +466,10 @@ def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 
     drain(members)
     out["steps"] = {"batched": steps, "per_domain": per_domain_steps}
     out["batched_vs_per_domain"] = round(out["batched_MLUPS"] / out["per_domain_MLUPS"], 2)
-    out["hbm_frac_batched"] = round(out["batched_MLUPS"] * 1e6 * BYTES_PER_NODE[storage] / (HBM_PEAK_GBPS * 1e9), 4)
+    launch = {"vec": best["vec"], "block": best["block"]}
+    bpn = sum(alg_bytes_per_node(storage, p, launch) * p.nx * p.ny for p in probs) / nodes
+    out["alg_bytes_per_node"] = round(bpn, 3)
+    out["hbm_frac_batched"] = round(out["batched_MLUPS"] * 1e6 * bpn / (HBM_PEAK_GBPS * 1e9), 4)
     batch.close()
     for m in members:
         m.close()
@@ -630,10 +670,15 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
     copy_bytes read and copy_bytes written."""
     if lattice == "d2q9":
         from paper_1901_08766_amd import inputs
-        nodes = inputs.large_domain().nx * inputs.large_domain().ny
+        prob = inputs.large_domain()
+        nodes = prob.nx * prob.ny
+        # the mask bytes of the tiles holding a solid node, in the default launch
+        # that the profiled command runs
+        mask_bytes = int(round(mask_read_fraction(prob, DEFAULT_LAUNCH_2D[storage]) * nodes))
     else:
         from paper_1901_08766_amd import inputs3
         nodes = int(np.prod(inputs3.SPHERE_SHAPE))
+        mask_bytes = nodes
     out_json = LATTICES[lattice]["counters"]
     pop_bytes = LATTICES[lattice]["q"] * STORAGE_BYTES[storage]
     copy_kib = copy_bytes / 1024.0
@@ -643,7 +688,7 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
     wk = _counter_mean(step_write, "WRITE_SIZE", kernel_part)
     fetch_b = fk * f_cal * 1024.0
     write_b = wk * w_cal * 1024.0
-    alg_read = pop_bytes * nodes + nodes   # every population once, one mask byte
+    alg_read = pop_bytes * nodes + mask_bytes   # every population once, the mask where it is read
     alg_write = pop_bytes * nodes
     entry = {"nodes": nodes, "fetch_kib_raw": round(fk, 1), "write_kib_raw": round(wk, 1),
              "fetch_calibration": round(f_cal, 5), "write_calibration": round(w_cal, 5),
@@ -686,11 +731,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--storage", default="f32", choices=sorted(BYTES_PER_NODE))
+    ap.add_argument("--storage", default="f32", choices=sorted(POP_BYTES))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--variants", default="f16,bf16,f64",
                     help="other storage types to time as extra fields ('' for none)")
+    ap.add_argument("--moving-storages", default="f32,f16",
+                    help="storage types to time on the large domain with moving masks ('' for none)")
     ap.add_argument("--ensemble-steps", type=int, default=300,
                     help="batched steps of the 256-domain ensemble comparison (0: skip it)")
     ap.add_argument("--ensemble-storages", default="f32,f16")
@@ -774,20 +821,36 @@ def main():
     if not ok:
         raise SystemExit("non-finite mass during the timed run")
     mlups = nodes / (ms * 1e-3) / 1e6
-    alg_bytes = BYTES_PER_NODE[a.storage] * nodes
+    bpn = alg_bytes_per_node(a.storage, prob, launch)
+    alg_bytes = bpn * nodes
     achieved = alg_bytes / (ms * 1e-3) / 1e9
-    extra = {}
+    extra, moving_res = {}, {}
     for v in [s for s in a.variants.split(",") if s and s != a.storage]:
         # median of 5 repeats of the requested steps (the first absorbs the
         # clock ramp after the set-up of the variant's context)
         vms, vok, vlaunch, vruns = time_gpu(v, a.steps, a.warmup, prob, repeats=5)
-        vb = BYTES_PER_NODE[v] * nodes / (vms * 1e-3) / 1e9
-        extra[v] = {"MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
+        vbpn = alg_bytes_per_node(v, prob, vlaunch)
+        vb = vbpn * nodes / (vms * 1e-3) / 1e9
+        extra[v] = {"alg_bytes_per_node": round(vbpn, 3), "MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
                     "ms_per_step_runs": [round(x, 4) for x in vruns],
                     "timing": f"median of 5 repeats of {a.steps} steps after {a.warmup} + 100 untimed steps",
                     "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4), "finite": vok,
                     "launch": vlaunch, "traffic": measured_traffic(v, nodes)}
         print(f"# {v}: {extra[v]}", file=sys.stderr, flush=True)
+    if a.moving_storages:
+        # the same domain with its masks following the bodies (a cylinder crossing
+        # the stream, the airfoil pitching, the rotating pair turning their masks)
+        mprob = inputs.large_domain(moving=True)
+        for v in [s for s in a.moving_storages.split(",") if s]:
+            vms, vok, vlaunch, vruns = time_gpu(v, a.steps, a.warmup, mprob, repeats=5)
+            vbpn = alg_bytes_per_node(v, mprob, vlaunch)
+            vb = vbpn * nodes / (vms * 1e-3) / 1e9
+            fixed = ms if v == a.storage else extra.get(v, {}).get("ms_per_step")
+            moving_res[v] = {"alg_bytes_per_node": round(vbpn, 3), "MLUPS": round(nodes / (vms * 1e-3) / 1e6, 1), "ms_per_step": round(vms, 4),
+                             "ms_per_step_runs": [round(x, 4) for x in vruns], "finite": vok, "launch": vlaunch,
+                             "achieved_GBps": round(vb, 1), "hbm_frac": round(vb / HBM_PEAK_GBPS, 4),
+                             "time_vs_fixed_mask": round(vms / fixed, 4) if fixed else None}
+            print(f"# moving {v}: {moving_res[v]}", file=sys.stderr, flush=True)
     traffic = measured_traffic(a.storage, nodes)
     out = {
         "metric": METRIC,
@@ -807,10 +870,16 @@ def main():
                    "nx": prob.nx, "ny": prob.ny, "storage": a.storage, "layout": "two-lattice pull",
                    "force_every": 1},
         "launch": launch,
+        "alg_bytes_per_node": round(bpn, 4),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic},
         "variants": extra,
+        "moving_bodies": {"workload": f"the same {prob.nx}x{prob.ny} domain with time-dependent masks: the "
+                                      "upstream tandem cylinder crossing at 0.1 U, the airfoil pitching "
+                                      "(trailing edge 0.3 U), the rotating pair turning their masks",
+                          "timing": f"median of 5 repeats of {a.steps} steps, default launch",
+                          **moving_res} if moving_res else None,
         "copy": {"GBps": round(copy_gbps, 1), "step_frac_of_copy": round(achieved / copy_gbps, 4),
                  "kernel": "device copy, one 16-byte non-temporal load and store per thread (lbvp_device_copy), 2.4 GB each way"},
     }

@@ -418,6 +418,16 @@ int lbvp_ref_step_nodes(const ref_ctx *c, const double *g, int64_t n_nodes, cons
 
 int64_t lbvp_ref_step_count(const ref_ctx *c) { return c->step; }
 
+/* The populations (lbvp_ref_write_populations) are those of time level `step`:
+ * the next step, whole or sampled, computes level step + 1 (which is where
+ * moving bodies stand). */
+int lbvp_ref_set_step_count(ref_ctx *c, int64_t step)
+{
+    if (step < 0) return 1;
+    c->step = step;
+    return 0;
+}
+
 void lbvp_ref_read_fields(const ref_ctx *c, double *rho, double *ux, double *uy, double *fx, double *fy)
 {
     double *dst[5] = {rho, ux, uy, fx, fy};

@@ -68,6 +68,7 @@ def lib():
         L.lbvp_ref_step_nodes.argtypes = [C.c_void_p, dp, C.c_int64, ip, ip, dp, dp]
         L.lbvp_ref_step_count.restype = C.c_int64
         L.lbvp_ref_step_count.argtypes = [C.c_void_p]
+        L.lbvp_ref_set_step_count.argtypes = [C.c_void_p, C.c_int64]
         L.lbvp_ref_read_fields.argtypes = [C.c_void_p] + [C.c_void_p] * 5
         L.lbvp_ref_read_populations.argtypes = [C.c_void_p, dp]
         L.lbvp_ref_write_populations.argtypes = [C.c_void_p, dp]
@@ -205,6 +206,11 @@ class RefSolver:
     @property
     def step_count(self) -> int:
         return lib().lbvp_ref_step_count(self._h)
+
+    def set_step_count(self, step: int):
+        """The state now held (set_populations) is that of time level `step`."""
+        if lib().lbvp_ref_set_step_count(self._h, int(step)):
+            raise ValueError("step count < 0")
 
     def fields(self):
         out = [np.zeros((self.ny, self.nx)) for _ in range(5)]

@@ -453,6 +453,12 @@ std::vector<char> body_table_bytes(const lbvp_body* bodies, int32_t n, int32_t m
 
 // The (tile, body) reduction tables for the current tiling and mask: a slot per
 // body present in each tile, numbered in tile order, and each body's slots.
+// Moving bodies: with a pose window on the device (time levels pose_first ..
+// pose_first + POSE_ROWS - 1), a tile lists body b when b's radius about one of
+// the window's centres can reach it: the centres move on a line, so their box
+// widened by the radius and two nodes holds every such tile (the kernels' own
+// per-tile test, with the radius alone, is tighter); before any window, every
+// body in every tile.
 lbvp_status build_tile_tables(lbvp_ctx* c)
 {
     const lbvp_params& p = c->p;
@@ -463,11 +469,33 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
     std::vector<int32_t> tile_ptr((size_t)l.n_tiles + 1, 0), slot_body;
     std::vector<std::vector<int32_t>> per_body((size_t)nb);
     std::vector<uint8_t> seen((size_t)nb + 1, 0);
+    const bool windowed = c->moving() && c->pose_first >= 0;
+    std::vector<std::array<int32_t, 4>> reach_box((size_t)nb);   // tile columns and rows, inclusive
+    if (windowed) {
+        const int32_t tiles_y = l.n_tiles / l.tiles_x;
+        const double ta = (double)c->pose_first, tb = (double)(c->pose_first + POSE_ROWS - 1);
+        auto span = [](double lo, double hi, int32_t size, int32_t count, int32_t* first, int32_t* last) {
+            *first = (int32_t)std::max(0.0, std::floor(lo / size));
+            *last = (int32_t)std::min((double)count - 1.0, std::floor(hi / size));
+        };
+        for (int32_t b = 0; b < nb; ++b) {
+            const lbvp_body& B = c->bodies_host[b];
+            const double xa = B.cx + B.vx * ta, xb = B.cx + B.vx * tb;
+            const double ya = B.cy + B.vy * ta, yb = B.cy + B.vy * tb;
+            const double r = std::sqrt(c->mov_r2[b]) + 2.0;
+            auto& q = reach_box[b];
+            span(std::min(xa, xb) - r, std::max(xa, xb) + r, l.tile_w, l.tiles_x, &q[0], &q[1]);
+            span(std::min(ya, yb) - r, std::max(ya, yb) + r, l.tile_rows, tiles_y, &q[2], &q[3]);
+        }
+    }
     for (int32_t t = 0; t < l.n_tiles; ++t) {
         tile_ptr[t] = (int32_t)slot_body.size();
         if (nb == 0) continue;
-        if (c->moving()) {   // dense: a slot for every body in every tile, in body order
+        if (c->moving()) {   // in body order
+            const int32_t tx = t % l.tiles_x, ty = t / l.tiles_x;
             for (int32_t b = 1; b <= nb; ++b) {
+                const auto& q = reach_box[b - 1];
+                if (windowed && (tx < q[0] || tx > q[1] || ty < q[2] || ty > q[3])) continue;
                 per_body[b - 1].push_back((int32_t)slot_body.size());
                 slot_body.push_back(b);
             }
@@ -600,7 +628,11 @@ lbvp_status pose_window(lbvp_ctx* c, int64_t next, int64_t n)
                                hipMemcpyHostToDevice, c->stream));
     LBVP_HIP(c, launch_set_i64(c->at<int64_t>(c->L.pose_base), 0, c->stream));
     c->pose_first = next;
-    return LBVP_OK;
+    // the force slots of the window's reach (after the previous run's last
+    // record was summed: same stream)
+    const lbvp_status st = build_tile_tables(c);
+    if (st != LBVP_OK) c->pose_first = -1;
+    return st;
 }
 
 // n steps from the current state, one launch each, then the standalone sum of

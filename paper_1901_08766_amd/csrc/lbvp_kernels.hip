@@ -76,6 +76,7 @@ struct BodySource {
     bool uniform;
     BodyRow<R> row;
     const double* pose;   // moving bodies: the poses at this step's time level, else null
+    uint32_t near;        // moving bodies whose reach meets the tile (bit b - 1 for body b)
 };
 
 // Volume penalization of a solid node (eqs. d-V, force-density): U_O = V +
@@ -224,11 +225,13 @@ __device__ __forceinline__ NodeResult<R> collide_node_lowp(R (&f)[9], int body, 
 // nearest to R(-th) (x - c(t)) + c(0), the node carried back by the body's
 // rigid motion; the first such body in order wins. Evaluated in FP64 one
 // operation per statement (no fused multiply-adds), so that membership does
-// not depend on the storage type. Nodes outside a body's radius skip it.
+// not depend on the storage type. Only the bodies in `near` are tried (the
+// tile's, see tile_near_bodies); nodes outside a body's radius skip it.
 template <typename R>
-__device__ __forceinline__ int moving_body(const StepArgs<R>& a, const double* row, int i, int j)
+__device__ __forceinline__ int moving_body(const StepArgs<R>& a, const double* row, uint32_t near, int i, int j)
 {
-    for (int b = 0; b < a.n_moving; ++b) {
+    for (uint32_t bits = near; bits; bits &= bits - 1) {
+        const int b = __builtin_ctz(bits);
         const double* m = row + b * POSE_STRIDE;
         const double dx = (double)i - m[2];
         const double dy = (double)j - m[3];
@@ -249,6 +252,26 @@ __device__ __forceinline__ int moving_body(const StepArgs<R>& a, const double* r
         if (a.mask[(int64_t)fy * a.pitch + (int64_t)fx] == b + 1) return b + 1;
     }
     return 0;
+}
+
+// The moving bodies whose radius reaches the rectangle [x0, x1] x [y0, y1] (a
+// tile), as bits. Skipping the others for the tile's nodes changes nothing:
+// rounding is monotone, so a node's FP64 squared distance to a centre, computed
+// as in moving_body, is never below the rectangle's computed the same way.
+template <typename R>
+__device__ __forceinline__ uint32_t tile_near_bodies(const StepArgs<R>& a, const double* row, double x0, double x1,
+                                                     double y0, double y1)
+{
+    uint32_t near = 0;
+    for (int b = 0; b < a.n_moving; ++b) {
+        const double* m = row + b * POSE_STRIDE;
+        const double ex = m[2] < x0 ? x0 - m[2] : (m[2] > x1 ? m[2] - x1 : 0.0);
+        const double ey = m[3] < y0 ? y0 - m[3] : (m[3] > y1 ? m[3] - y1 : 0.0);
+        const double ex2 = ex * ex;
+        const double ey2 = ey * ey;
+        if (!(ex2 + ey2 > m[6])) near |= 1u << b;
+    }
+    return near;
 }
 
 // D2Q9 directions (eq. D2Q9) and the opposite map (Sec. 2.1: f_{-1} = f_3).
@@ -318,10 +341,28 @@ __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, 
         const int s0 = f.body_slot_ptr[b], s1 = f.body_slot_ptr[b + 1];
         for (int v = (int)threadIdx.x; v < FIN_LANES; v += (int)blockDim.x) {
             double x = 0.0, y = 0.0;
-            for (int k = s0 + v; k < s1; k += FIN_LANES) {
-                const int s = f.body_slots[k];
-                x += sf[2 * s];
-                y += sf[2 * s + 1];
+            int k = s0 + v;
+            // four slots' loads in flight at a time, added in the same order
+            for (; k + 3 * FIN_LANES < s1; k += 4 * FIN_LANES) {
+                int sl[4];
+                double px[4], py[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) sl[u] = f.body_slots[k + u * FIN_LANES];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    px[u] = sf[2 * sl[u]];
+                    py[u] = sf[2 * sl[u] + 1];
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    x += px[u];
+                    y += py[u];
+                }
+            }
+            for (; k < s1; k += FIN_LANES) {
+                const int sl = f.body_slots[k];
+                x += sf[2 * sl];
+                y += sf[2 * sl + 1];
             }
             sx[v] = x;
             sy[v] = y;
@@ -354,14 +395,16 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     BodySource<R> bs;
     bs.uniform = false;
     bs.pose = nullptr;
+    bs.near = 0;
     if constexpr (MOVING) {      // the poses at this step's time level (a domain with moving bodies)
         if (a.n_moving > 0) bs.pose = a.pose + (*a.pose_base + pose_k) * (int64_t)(MAX_MOVING * POSE_STRIDE);
     }
-    if constexpr (RECORD) {
+    {
         s0 = a.tile_slot_ptr[t];
         s1 = a.tile_slot_ptr[t + 1];
-        // the slots list every body with a node in the tile: with one, its row
-        // serves every solid node of the tile (read here, before any store)
+        // the slots list every body with a node in the tile: with none, the
+        // tile's mask is not read at all; with one, its row serves every solid
+        // node of the tile (read here, before any store)
         if (s1 - s0 == 1) {
             bs.uniform = true;
             bs.row = body_row(a.bodies + BODY_STRIDE * a.slot_body[s0]);
@@ -375,6 +418,13 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     const int lane = (int)(threadIdx.x & 63);
     const bool act = i0 < a.nx && ty * a.tile_rows + lr < a.ny;   // owns at least one real node
     const int n_own = act ? min(V, a.nx - i0) : 0;
+    if constexpr (MOVING) {
+        if (bs.pose) {   // once per tile: most tiles meet no moving body
+            const double x0 = (double)(tx * a.tile_w), y0 = (double)(ty * a.tile_rows);
+            bs.near = __builtin_amdgcn_readfirstlane(
+                tile_near_bodies(a, bs.pose, x0, x0 + (double)(a.tile_w - 1), y0, y0 + (double)(a.tile_rows - 1)));
+        }
+    }
 
     const int jm = (j == 0) ? a.ny - 1 : j - 1;     // rows are periodic
     const int jp = (j == a.ny - 1) ? 0 : j + 1;
@@ -429,9 +479,12 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         }
         if (MOVING && bs.pose) {
 #pragma unroll
-            for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, bs.pose, i0 + k, j) : 0;
-        } else {
+            for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, bs.pose, bs.near, i0 + k, j) : 0;
+        } else if (s1 > s0) {
             load_mask<V>(a.mask + r0 + il, body);
+        } else {
+#pragma unroll
+            for (int k = 0; k < V; ++k) body[k] = 0;
         }
     } else {
 #pragma unroll
@@ -664,7 +717,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         if (s1 > s0 && act) {
             if (MOVING && bs.pose) {
 #pragma unroll
-                for (int k = 0; k < V; ++k) bid[k] = (k < n_own) ? moving_body(a, bs.pose, i0 + k, j) : 0;
+                for (int k = 0; k < V; ++k) bid[k] = (k < n_own) ? moving_body(a, bs.pose, bs.near, i0 + k, j) : 0;
             } else {
                 load_mask<V>(a.mask + r0 + i0, bid);
             }
@@ -679,19 +732,13 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
             const int c1 = min(s1, c0 + per_pass);
             for (int s = c0; s < c1; ++s) {
                 const int b = a.slot_body[s];
-                bool skip = false;
-                if (MOVING && bs.pose) {
-                    // slots are dense (every tile, every body): a body whose radius
-                    // misses this tile's rectangle adds nothing (uniform across the block)
-                    const double* m = bs.pose + (b - 1) * POSE_STRIDE;
-                    const double x0 = (double)(tx * a.tile_w), x1 = x0 + (double)(a.tile_w - 1);
-                    const double y0 = (double)(ty * a.tile_rows), y1 = y0 + (double)(a.tile_rows - 1);
-                    const double ex = m[2] < x0 ? x0 - m[2] : (m[2] > x1 ? m[2] - x1 : 0.0);
-                    const double ey = m[3] < y0 ? y0 - m[3] : (m[3] > y1 ? m[3] - y1 : 0.0);
-                    skip = ex * ex + ey * ey > m[6];
-                }
-                double px = 0.0, py = 0.0;
+                // slots of moving bodies are dense (every tile, every body): a body
+                // whose radius misses this tile adds zero, without the wave sums
+                // (uniform across the block)
+                const bool skip = MOVING && bs.pose && !((bs.near >> (b - 1)) & 1u);
+                double wx = 0.0, wy = 0.0;
                 if (!skip) {
+                    double px = 0.0, py = 0.0;
 #pragma unroll
                     for (int k = 0; k < V; ++k) {
                         if (k < n_own && bid[k] == b) {
@@ -699,9 +746,9 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                             py -= (double)fv[(V + k) * a.block + (int)threadIdx.x];
                         }
                     }
+                    wx = wave_sum_lane63(px);
+                    wy = wave_sum_lane63(py);
                 }
-                const double wx = wave_sum_lane63(px);
-                const double wy = wave_sum_lane63(py);
                 if (lane == 63) {
                     lds[2 * ((s - c0) * nw + wid)] = wx;
                     lds[2 * ((s - c0) * nw + wid) + 1] = wy;

@@ -217,7 +217,8 @@ def cylinder(nx: int = 1024, ny: int = 512, d: float = 40.0, cx: float = 256.0, 
 
 
 def large_domain(scale: int = 1, u: float = 0.04, re: float = 200.0, magic_lambda: float = 0.25,
-                 eta: float = 1e-4, seed=3, noise: bool = True, steps: Optional[int] = None) -> Problem:
+                 eta: float = 1e-4, seed=3, noise: bool = True, steps: Optional[int] = None,
+                 moving: bool = False) -> Problem:
     """Large single domain (8192 x 4096 at scale 1) holding two counter-rotating
     cylinders (Sec. 3.4), a tandem pair (Sec. 3.3.1) and a NACA-0012 airfoil
     (Sec. 3.5). All lengths are divided by ``scale``; U and Re are kept.
@@ -226,6 +227,11 @@ def large_domain(scale: int = 1, u: float = 0.04, re: float = 200.0, magic_lambd
     (counter-clockwise), surface speed U, gap-side surfaces moving upstream;
     3 tandem upstream, 4 tandem downstream (centre spacing 2D); 5 the airfoil,
     chord 5D, 5 degrees nose-up about its quarter chord.
+
+    ``moving``: the mask follows the bodies (a time-dependent chi): the upstream
+    tandem cylinder crosses the stream at 0.1 U and the airfoil keeps pitching
+    nose-up (clockwise) about its quarter chord, its trailing edge at 0.3 U; the rotating
+    cylinders turn their masks with their surfaces.
     """
     s = float(scale)
     nx, ny = 8192 // scale, 4096 // scale
@@ -249,14 +255,18 @@ def large_domain(scale: int = 1, u: float = 0.04, re: float = 200.0, magic_lambd
         [tan_x1, tan_y, 0.0, 0.0, 0.0],
         [pivot[0], pivot[1], 0.0, 0.0, 0.0],
     ])
+    if moving:
+        bodies[2, 3] = 0.1 * u
+        bodies[4, 4] = -0.3 * u / (0.75 * chord)
     rho, ux, uy = seeded_inflow_init(mask, bodies, u, 1e-3 if noise else 0.0, seed)
     nu = viscosity_from_re(u, d, re)
     if steps is None:
         steps = 50_000 // scale
-    return Problem(name=f"large{nx}x{ny}", nx=nx, ny=ny, tau_plus=tau_plus_from_viscosity(nu),
+    return Problem(name=f"large{nx}x{ny}" + ("-moving" if moving else ""), nx=nx, ny=ny,
+                   tau_plus=tau_plus_from_viscosity(nu),
                    magic_lambda=magic_lambda, eta=eta, bc=(INFLOW_EQ, OUTFLOW, PERIODIC, PERIODIC),
                    rho_in=1.0, u_in=(u, 0.0), mask=mask, bodies=bodies, rho_init=rho,
-                   ux_init=ux, uy_init=uy, steps=steps, u_ref=u, l_ref=d)
+                   ux_init=ux, uy_init=uy, steps=steps, u_ref=u, l_ref=d, moving=moving)
 
 
 ENSEMBLE_SIZES = ((128, 128), (256, 128), (512, 256), (1024, 512))

@@ -297,3 +297,62 @@ def test_moving_rejections(lbvp):
     s.step(3)
     assert s.step_count == 3
     s.close()
+
+
+def _box(x0, x1, y0, y1):
+    ys, xs = np.meshgrid(np.arange(y0, y1), np.arange(x0, x1), indexing="ij")
+    return xs.ravel(), ys.ravel()
+
+
+def test_fp32_full_size_moving_sampled(lbvp, oracle):
+    """The 8192 x 4096 domain with its masks following the bodies (a cylinder
+    crossing the stream, the airfoil pitching, the rotating pair turning their
+    masks), in the default launch the benchmark times: after 300 GPU steps the
+    oracle, set to that time level, advances the GPU's state by one step at every
+    node of boxes around the moving bodies, along the sides and at random nodes;
+    that must equal the GPU's next state to FP32 rounding, and the recorded
+    forces of the crossing cylinder and of the airfoil the oracle's node sums."""
+    prob = inputs.large_domain(moving=True)
+    k = 300
+    gpu = lbvp.Solver(prob, storage="f32", force_every=1, force_capacity=k + 16)
+    print(f"case {prob.name} f32 launch={gpu.launch} band={gpu.tile_band} steps={k}", flush=True)
+    gpu.step(k)
+    gpu.forces()
+    gk = gpu.populations()
+    gpu.step(1, keep_fields=True)
+    gf, _, first = gpu.forces()
+    assert first == k + 1
+    g1 = gpu.populations()
+    fl = gpu.fields()
+    gpu.close()
+    nx, ny = prob.nx, prob.ny
+    boxes = {3: _box(1180, 1380, 800, 1010), 5: _box(985, 1815, 1950, 2150)}
+    rims = [_box(1190, 1370, 3230, 3410), _box(1190, 1370, 2990, 3170)]
+    rng = np.random.Generator(np.random.PCG64(97))
+    xs = np.concatenate([boxes[3][0], boxes[5][0]] + [r[0] for r in rims] +
+                        [np.zeros(64, int), np.full(64, nx - 1), rng.integers(0, nx, 4096)])
+    ys = np.concatenate([boxes[3][1], boxes[5][1]] + [r[1] for r in rims] +
+                        [rng.integers(0, ny, 64), rng.integers(0, ny, 64), rng.integers(0, ny, 4096)])
+    ref = oracle.RefSolver(prob)
+    ref.set_step_count(k)
+    gout, rfl = ref.step_nodes(gk, xs, ys)
+    err = np.abs(g1[:, ys, xs].T - gout).max()
+    print(f"moving full size: {len(xs)} sampled nodes, population error {err:.2e}", flush=True)
+    assert err <= 1e-6
+    for q, key in enumerate(("rho", "ux", "uy", "fx", "fy")):
+        assert np.abs(fl[key][ys, xs] - rfl[:, q]).max() <= 2e-6, key
+    off = 0
+    for b in (3, 5):
+        bx, by = boxes[b]
+        now = np.array([ref.body_at(int(i), int(j), k + 1) for i, j in zip(bx, by)])
+        sel = now == b
+        moved = int(np.count_nonzero(sel != (prob.mask[by, bx] == b)))
+        part = rfl[off:off + len(bx)]
+        fx, fy = -part[sel, 3].sum(), -part[sel, 4].sum()
+        mag = np.abs(part[sel, 3:5]).sum()
+        print(f"body {b}: {int(sel.sum())} nodes at level {k + 1}, {moved} changed since level 0; "
+              f"force ({gf[0, b - 1, 0]:.6e}, {gf[0, b - 1, 1]:.6e}) oracle ({fx:.6e}, {fy:.6e})", flush=True)
+        assert moved > 100
+        assert abs(gf[0, b - 1, 0] - fx) <= 1e-5 * mag and abs(gf[0, b - 1, 1] - fy) <= 1e-5 * mag
+        off += len(bx)
+    ref.close()

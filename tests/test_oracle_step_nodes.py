@@ -56,6 +56,37 @@ def test_step_nodes_equals_the_whole_step(oracle, name, make, pre):
     s.close()
 
 
+def test_resumed_at_a_time_level_equals_the_straight_run(oracle):
+    """A second context given the first one's populations at time level k and
+    told it stands at k (set_step_count) continues the moving-mask run exactly:
+    whole steps, sampled steps and the recorded forces."""
+    p = inputs.moving_bodies(nx=120, ny=80, seed=12, bc=IO, u_in=0.03)
+    a = oracle.RefSolver(p)
+    a.step(37)
+    g = a.populations()
+    b = oracle.RefSolver(p)
+    b.set_populations(g)
+    b.set_step_count(37)
+    assert b.step_count == 37
+    xs, ys = _all_nodes_2d(p.nx, p.ny)
+    ga, fa = a.step_nodes(g, xs, ys)
+    gb, fb = b.step_nodes(g, xs, ys)
+    assert np.array_equal(ga, gb) and np.array_equal(fa, fb)
+    # and not what a context at level 0 computes from the same populations
+    c = oracle.RefSolver(p)
+    gc, _ = c.step_nodes(g, xs, ys)
+    assert not np.array_equal(gc, ga)
+    c.close()
+    ra, ma = a.step(5, record=True)
+    rb, mb = b.step(5, record=True)
+    assert np.array_equal(ra, rb) and np.array_equal(ma, mb)
+    assert np.array_equal(a.populations(), b.populations())
+    with pytest.raises(ValueError):
+        b.set_step_count(-1)
+    a.close()
+    b.close()
+
+
 def test_step_nodes_of_a_subset_in_any_order(oracle):
     p = inputs.random_state_problem(29, 11, seed=34, n_disks=3, bc=IO)
     s = oracle.RefSolver(p)
