@@ -370,6 +370,7 @@ void fill_step_args(lbvp_ctx* c, StepArgs<R>& a)
     a.plane = L.plane;
     a.lstride = L.lstride;
     a.plane_f = L.plane_f;
+    a.off32 = (uint64_t)p.ny * (uint64_t)L.lstride * storage_bytes(p.storage) <= 0xFFFFFFFFull ? 1 : 0;
     a.rho0 = (R)p.rho0;
     a.om_p = (R)(1.0 / p.tau_plus);
     a.om_m = (R)(1.0 / c->tau_minus);
@@ -878,6 +879,8 @@ lbvp_status batch_run(lbvp_batch* b, int64_t step0, int64_t k0, int64_t n, bool 
     L.tile_domain = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_domain);
     L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_tile_start);
     L.args = b->dev;
+    L.off32 = 1;
+    for (const lbvp_ctx* c : b->members) L.off32 &= c->a32.off32;   // off32 does not depend on the precision
     bool pending = false;
     int32_t pending_buf = 0;
     for (int64_t k = k0; k < k0 + n; ++k) {

@@ -58,6 +58,16 @@ __device__ __forceinline__ void enc2(float a, float b, S* out)
 template <typename S> struct Arith { using R = float; };
 template <> struct Arith<double> { using R = double; };
 
+// base + elem elements, the element offset taken as a 32-bit byte offset (the
+// caller guarantees it fits): the address is a uniform base plus a zero-extended
+// 32-bit lane offset, the form of the scalar-base global access.
+template <typename T>
+__device__ __forceinline__ T* at_off32(T* base, uint32_t elem)
+{
+    using B = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + elem * (uint32_t)sizeof(T));
+}
+
 // V consecutive elements moved as one aligned access of V * sizeof(S) bytes.
 template <typename S, int V>
 __device__ __forceinline__ void load_vec(const S* p, S (&out)[V])

@@ -63,6 +63,7 @@ struct StepArgs {
     int32_t west, east;
     int32_t part_buf;   // partial buffer a recording step writes
     int32_t fin_buf;    // partial buffer whose record a leading block of the launch sums, or -1
+    int32_t off32;      // a lattice spans fewer than 2^32 bytes: per-lane offsets fit 32 bits
     int64_t pitch;      // elements per row of one population, of the mask and of a field
     int64_t plane;      // elements between the rows of populations q and q + 1 (= pitch)
     int64_t lstride;    // elements between lattice rows j and j + 1 (= 9 pitch)
@@ -118,6 +119,7 @@ struct BatchLaunch {
     int32_t n_fin;                  // leading blocks that sum the fin_buf records: n_domains
                                     // rounded up to a multiple of 8, or 0 if fin_buf < 0
     int32_t pose_k;                 // this launch's step within the run (moving bodies)
+    int32_t off32;                  // every member's StepArgs::off32
     const int32_t* tile_domain;     // [total_tiles] domain of each tile
     const int32_t* tile_start;      // [n_domains] first tile of each domain
     const void* args;               // StepArgs<R>[n_domains]

@@ -386,7 +386,10 @@ __device__ __forceinline__ void finalize_record(const FinalizeArgs& f, int buf, 
 // consecutive nodes per thread. part_buf: the partial buffer this step's record
 // writes (the previous record is summed by leading blocks of the same launch).
 // lds: the kernel's 2 FIN_LANES doubles.
-template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false>
+// OFF32 (2-byte storage, vector pull form, a lattice under 4 GiB): the main
+// loads and stores address a uniform population-row base plus a 32-bit per-lane
+// byte offset, which the scalar-base addressing mode takes directly.
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false, bool OFF32 = false>
 __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<typename Arith<S>::R>& a, int t,
                                           int part_buf, double* lds, int pose_k = 0)
 {
@@ -466,7 +469,11 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
                 load_vec<S, V>(src + q * P + l0 + il, raw);
             } else {
                 const int pq = (MODE == AA_PUSH) ? OPP[q] : q;
-                if constexpr (kShifted) {
+                if constexpr (OFF32) {
+                    static_assert(!kShifted && MODE == PULL, "the 32-bit form is the lane-shuffle pull form");
+                    load_vec<S, V>(at_off32(src + pq * P, (uint32_t)row_idx[q] * (uint32_t)a.lstride + (uint32_t)il),
+                                   raw);
+                } else if constexpr (kShifted) {
                     if (EXQ[q] == 1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il - 1), raw);
                     else if (EXQ[q] == -1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il + 1), raw);
                     else load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
@@ -611,7 +618,12 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
         // own node: plane q (pull) or plane opp(q) (AA local)
         if (n_own == V) {
 #pragma unroll
-            for (int q = 0; q < 9; ++q) store_vec<S, V>(dst + (MODE == PULL ? q : OPP[q]) * P + l0 + i0, out[q]);
+            for (int q = 0; q < 9; ++q) {
+                if constexpr (OFF32)
+                    store_vec<S, V>(at_off32(dst + q * P, (uint32_t)j * (uint32_t)a.lstride + (uint32_t)i0), out[q]);
+                else
+                    store_vec<S, V>(dst + (MODE == PULL ? q : OPP[q]) * P + l0 + i0, out[q]);
+            }
         } else if (n_own > 0) {  // ragged end of a row
 #pragma unroll
             for (int k = 0; k < V; ++k)
@@ -770,7 +782,7 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
 }
 
 // Two lattices: source and destination never alias.
-template <typename S, int V, bool RECORD, bool FIELDS, bool MOVING = false>
+template <typename S, int V, bool RECORD, bool FIELDS, bool MOVING = false, bool OFF32 = false>
 __global__ void __launch_bounds__(256)
 k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S>::R> a)
 {
@@ -783,7 +795,7 @@ k_step(const S* __restrict__ src, S* __restrict__ dst, StepArgs<typename Arith<S
     }
     const int t = xcd_tile(a.tiles_per_xcd, a.band_log2, lead);
     if (t >= a.n_tiles) return;  // whole block
-    step_body<S, V, PULL, RECORD, FIELDS, MOVING>(src, dst, a, t, a.part_buf, lds, a.pose_k);
+    step_body<S, V, PULL, RECORD, FIELDS, MOVING, OFF32>(src, dst, a, t, a.part_buf, lds, a.pose_k);
 }
 
 // One lattice, read and written in place (no restrict).
@@ -804,7 +816,7 @@ __global__ void __launch_bounds__(256) k_step_aa(S* lat, StepArgs<typename Arith
 // Many domains in one launch: block -> (domain, tile) through the tile map;
 // every domain's arguments (geometry, parameters, lattices) live in device
 // memory. All domains take the same step kind, record flag and partial buffers.
-template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false>
+template <typename S, int V, int MODE, bool RECORD, bool FIELDS, bool MOVING = false, bool OFF32 = false>
 __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
 {
     using R = typename Arith<S>::R;
@@ -825,8 +837,8 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
     const int cur = a.cur ^ b.flip;
     S* lat_cur = static_cast<S*>(cur ? a.lat1 : a.lat0);
     S* lat_next = static_cast<S*>(cur ? a.lat0 : a.lat1);
-    step_body<S, V, MODE, RECORD, FIELDS, MOVING>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf, lds,
-                                                  b.pose_k);
+    step_body<S, V, MODE, RECORD, FIELDS, MOVING, OFF32>(lat_cur, MODE == PULL ? lat_next : lat_cur, a, t, b.part_buf,
+                                                         lds, b.pose_k);
 }
 
 // The last record of an lbvp_step call, summed on its own.
@@ -1006,6 +1018,18 @@ hipError_t step_v(int mode, bool record, bool fields, const S* in, S* out, const
     const dim3 grid((unsigned)(a.tiles_per_xcd * N_XCD + (a.fin_buf >= 0 ? N_XCD : 0))), block((unsigned)a.block);
     const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, a.block);
     if (mode == PULL) {
+        if constexpr (sizeof(S) == 2 && V > 1) {
+            if (a.off32) {
+                if (record) {
+                    if (fields) hipLaunchKernelGGL((k_step<S, V, true, true, MOVING, true>), grid, block, lds, s, in, out, a);
+                    else hipLaunchKernelGGL((k_step<S, V, true, false, MOVING, true>), grid, block, lds, s, in, out, a);
+                } else {
+                    if (fields) hipLaunchKernelGGL((k_step<S, V, false, true, MOVING, true>), grid, block, 0, s, in, out, a);
+                    else hipLaunchKernelGGL((k_step<S, V, false, false, MOVING, true>), grid, block, 0, s, in, out, a);
+                }
+                return hipGetLastError();
+            }
+        }
         if (record) {
             if (fields) hipLaunchKernelGGL((k_step<S, V, true, true, MOVING>), grid, block, lds, s, in, out, a);
             else hipLaunchKernelGGL((k_step<S, V, true, false, MOVING>), grid, block, lds, s, in, out, a);
@@ -1078,6 +1102,18 @@ hipError_t batch_mode(bool record, bool fields, const BatchLaunch& b, int32_t bl
 {
     const dim3 grid((unsigned)(b.tiles_per_xcd * N_XCD + b.n_fin)), blk((unsigned)block);
     const size_t lds = record_lds_bytes<typename Arith<S>::R>(V, block);
+    if constexpr (sizeof(S) == 2 && V > 1 && MODE == PULL) {
+        if (b.off32) {
+            if (record) {
+                if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true, MOVING, true>), grid, blk, lds, s, b);
+                else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false, MOVING, true>), grid, blk, lds, s, b);
+            } else {
+                if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, true, MOVING, true>), grid, blk, 0, s, b);
+                else hipLaunchKernelGGL((k_step_batch<S, V, MODE, false, false, MOVING, true>), grid, blk, 0, s, b);
+            }
+            return hipGetLastError();
+        }
+    }
     if (record) {
         if (fields) hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, true, MOVING>), grid, blk, lds, s, b);
         else hipLaunchKernelGGL((k_step_batch<S, V, MODE, true, false, MOVING>), grid, blk, lds, s, b);

@@ -81,6 +81,61 @@ def test_fp32_maximum_size_2d(lbvp, oracle):
     torch.cuda.empty_cache()
 
 
+W9 = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+
+
+def test_fp16_lattice_beyond_4gib_2d(lbvp, oracle):
+    """2-byte storage past 4 GiB per lattice (16384 x 16384, 4.8 GB each): the
+    vector kernels address such a lattice with 64-bit offsets (smaller ones take
+    32-bit lane offsets from a scalar base). After a few steps the oracle
+    advances the GPU's decoded state by one step on row bands (the first, last and
+    middle rows, and the rows of the far-corner body); the stored populations
+    must lie within FP16 rounding of the exact step, w (|h_ref| u + 2e-6) with
+    u = 2^-11, plus the inflow column's input rounding carried through the
+    collision (gain < 8), and the FP32 fields to 2e-6 (plus the entering
+    populations' rounding in the inflow column)."""
+    prob = inputs.huge_domain(nx=16384, ny=16384)
+    nx, ny = prob.nx, prob.ny
+    assert ny * nx * 9 * 2 > 2 ** 32
+    gpu = lbvp.Solver(prob, storage="f16", force_every=1, force_capacity=64)
+    print(f"case {prob.name} f16 launch={gpu.launch} band={gpu.tile_band} device bytes={gpu.footprint}", flush=True)
+    lo2, hi2 = _body_span((prob.mask == 2).any(axis=1))
+    bands = [(ny - 1, 3), (ny // 2 - 1, 3), (lo2 - 1, hi2 - lo2 + 3)]
+    gpu.step(12)
+    gpu.forces()
+    g12 = [_rows(lambda a, n: gpu.populations(a, n), lo, n, ny) for lo, n in bands]
+    gpu.step(1, keep_fields=True)
+    gpu.forces()
+    u = 2.0 ** -11
+    f_in = oracle.feq(prob.rho_in, *prob.u_in)
+    h_in = np.abs(f_in / W9 - prob.rho0).max()
+    ex = oracle.lattice()[0]
+    s_in = u * np.abs(f_in - W9 * prob.rho0)[ex == 1].sum()
+    rng = np.random.Generator(np.random.PCG64(11))
+    for (lo, n), g0 in zip(bands, g12):
+        band = inputs.rows_band(prob, lo, n)
+        ref = oracle.RefSolver(band)
+        inner = np.arange(1, n - 1)
+        g13 = _rows(lambda a, m: gpu.populations(a, m), lo + 1, n - 2, ny)
+        fl = _rows(lambda a, m: _stack(gpu.fields(a, m)), lo + 1, n - 2, ny)
+        ys_s, xs_s = np.nonzero(band.mask[1:n - 1])
+        xs = np.concatenate([np.array([0, 1, nx - 2, nx - 1] * len(inner)), rng.integers(0, nx, 256), xs_s])
+        ys = np.concatenate([np.repeat(inner - 1, 4), rng.integers(0, n - 2, 256), ys_s])
+        gout, rfl = ref.step_nodes(g0, xs, ys + 1)
+        ref.close()
+        h_ref = gout / W9 - prob.rho0
+        bound = W9 * (np.abs(h_ref) * u + 2e-6 + np.where(xs == 0, 8.0 * u * h_in, 0.0)[:, None])
+        err = np.abs(g13[:, ys, xs].T - gout)
+        print(f"band {lo}+{n}: worst population error / bound {float((err / bound).max()):.3f}", flush=True)
+        assert np.all(err <= bound), (lo, n)
+        field_tol = 2e-6 + np.where(xs == 0, 2.0 * s_in, 0.0)
+        for q, k in enumerate(FIELDS2):
+            assert np.all(np.abs(fl[q][ys, xs] - rfl[:, q]) <= field_tol), (lo, n, k)
+    gpu.close()
+    del gpu
+    torch.cuda.empty_cache()
+
+
 def test_fp32_maximum_size_3d(lbvp3, ref3):
     prob = inputs3.huge_domain3()
     nx, ny, nz = prob.nx, prob.ny, prob.nz
