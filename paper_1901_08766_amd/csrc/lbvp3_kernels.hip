@@ -562,12 +562,24 @@ __global__ void __launch_bounds__(256) k_step3_batch(Batch3Launch b)
     }
     const int g = xcd_tile(b.tiles_per_xcd, b.band_log2, b.n_fin);
     if (g >= b.total_tiles) return;   // whole block
+#if defined(__HIP_DEVICE_COMPILE__)
+    // the tile map and the members do not change during a launch: read through
+    // the constant address space (scalar loads no store of the step can alias),
+    // the member copied once, up front
+    using CI = const __attribute__((address_space(4))) int32_t;
+    using CM = const __attribute__((address_space(4))) Member3<R>;
+    const int d = ((CI*)b.tile_domain)[g];
+    const Member3<R> md = ((CM*)m)[d];
+    const int t = g - ((CI*)b.tile_start)[d];
+#else
     const int d = b.tile_domain[g];
     const Member3<R>& md = m[d];
+    const int t = g - b.tile_start[d];
+#endif
     const int cur = md.cur ^ b.flip;
     const S* src = static_cast<const S*>(cur ? md.lat1 : md.lat0);
     S* dst = static_cast<S*>(cur ? md.lat0 : md.lat1);
-    step3_body<S, V, RECORD, FIELDS>(src, dst, md.a, g - b.tile_start[d], b.part_buf, lds);
+    step3_body<S, V, RECORD, FIELDS>(src, dst, md.a, t, b.part_buf, lds);
 }
 
 // The last record of an lbvp3_batch_step call: one block per member.

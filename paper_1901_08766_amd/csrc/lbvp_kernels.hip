@@ -831,9 +831,21 @@ __global__ void __launch_bounds__(256) k_step_batch(BatchLaunch b)
     }
     const int g = xcd_tile(b.tiles_per_xcd, b.band_log2, b.n_fin);
     if (g >= b.total_tiles) return;  // whole block
+#if defined(__HIP_DEVICE_COMPILE__)
+    // the tile map and the members' arguments do not change during a launch:
+    // read through the constant address space they are scalar loads that no
+    // store of the step can alias, and the arguments are copied once, up front
+    // (through a generic reference every later use reloaded them)
+    using CI = const __attribute__((address_space(4))) int32_t;
+    using CA = const __attribute__((address_space(4))) StepArgs<R>;
+    const int d = ((CI*)b.tile_domain)[g];
+    const StepArgs<R> a = ((CA*)args)[d];
+    const int t = g - ((CI*)b.tile_start)[d];
+#else
     const int d = b.tile_domain[g];
     const StepArgs<R>& a = args[d];
     const int t = g - b.tile_start[d];
+#endif
     const int cur = a.cur ^ b.flip;
     S* lat_cur = static_cast<S*>(cur ? a.lat1 : a.lat0);
     S* lat_next = static_cast<S*>(cur ? a.lat0 : a.lat1);
