@@ -52,7 +52,7 @@ def kernel_source_hash(lattice: str = "d2q9") -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(storage: str, nodes: int, lattice: str = "d2q9"):
+def measured_traffic(storage: str, nodes: int, lattice: str = "d2q9", key: str = None):
     """HBM bytes per step-kernel launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
     try:
@@ -62,7 +62,7 @@ def measured_traffic(storage: str, nodes: int, lattice: str = "d2q9"):
         return None
     if c.get("kernel_source_hash") != kernel_source_hash(lattice):
         return None
-    entry = c.get("per_storage", {}).get(storage)
+    entry = c.get("per_storage", {}).get(key or storage)
     if not entry or entry.get("nodes") != nodes:
         return None
     return entry.get("hbm_bytes_per_launch")
@@ -477,6 +477,38 @@ def time_ensemble(storage: str, steps: int, per_domain_steps: int, n_dom: int = 
     return out
 
 
+def profile_ensemble(storage: str, launch, steps: int, warmup: int):
+    """Only the batched 256-domain ensemble in one given launch shape (vec, block,
+    band): warmup steps, then `steps` timed ones (for kernel traces and counters,
+    without the tuner's and the per-domain runs' launches)."""
+    import torch
+    from paper_1901_08766_amd import inputs, lbvp
+
+    probs = inputs.ensemble(n=256)
+    nodes = sum(p.nx * p.ny for p in probs)
+    stream = torch.cuda.Stream()
+    members = [lbvp.Solver(p, storage=storage, force_every=1, force_capacity=steps + warmup + 16, stream=stream)
+               for p in probs]
+    vec, block, band = launch
+    batch = lbvp.Batch(members, vec=vec, block=block)
+    batch.set_tile_band(band)
+    batch.step(warmup)
+    stream.synchronize()
+    for m in members:
+        m.forces()
+    ms = _timed(stream, lambda: batch.step(steps))
+    bpn = sum(alg_bytes_per_node(storage, p, {"vec": vec, "block": block}) * p.nx * p.ny for p in probs) / nodes
+    out = {"ensemble_profile": storage, "launch": list(launch), "nodes": nodes, "steps": steps,
+           "ms_per_step": round(ms / steps, 4), "MLUPS": round(nodes * steps / ms / 1e3, 1),
+           "alg_bytes_per_node": round(bpn, 3),
+           "hbm_frac": round(nodes * steps / ms * 1e3 * bpn / (HBM_PEAK_GBPS * 1e9), 4),
+           "traffic": measured_traffic(storage, nodes, key="ensemble_" + storage)}
+    batch.close()
+    for m in members:
+        m.close()
+    return out
+
+
 def run_serving(storage: str, rate: float, n_req: int, seed: int = 5, max_slots: int = 256,
                 max_epoch_steps: int = 256, tune_sample: int = 32):
     """Poisson arrivals of cylinder and airfoil solves through the native pool;
@@ -664,11 +696,20 @@ def _counter_mean(db: str, counter: str, name_part: str) -> float:
 
 
 def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_write: str, copy_bytes: int,
-                       storage: str, kernel_part: str, out_md: str, command: str, lattice: str = "d2q9"):
+                       storage: str, kernel_part: str, out_md: str, command: str, lattice: str = "d2q9",
+                       ensemble_launch=None):
     """HBM bytes per step-kernel launch from FETCH_SIZE / WRITE_SIZE (KiB per
     dispatch), each scaled by what the counter reads for a plain device copy of
-    copy_bytes read and copy_bytes written."""
-    if lattice == "d2q9":
+    copy_bytes read and copy_bytes written. ensemble_launch: the counters are of
+    the batched 256-domain ensemble in that launch shape (entry ensemble_<storage>)."""
+    key = storage
+    if lattice == "d2q9" and ensemble_launch is not None:
+        from paper_1901_08766_amd import inputs
+        probs = inputs.ensemble(n=256)
+        nodes = sum(p.nx * p.ny for p in probs)
+        mask_bytes = int(round(sum(mask_read_fraction(p, ensemble_launch) * p.nx * p.ny for p in probs)))
+        key = "ensemble_" + storage
+    elif lattice == "d2q9":
         from paper_1901_08766_amd import inputs
         prob = inputs.large_domain()
         nodes = prob.nx * prob.ny
@@ -709,7 +750,7 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
         data = {"kernel_source_hash": kernel_source_hash(lattice), "per_storage": {}}
     data.pop("kernel", None)
     data.pop("command", None)
-    data.setdefault("per_storage", {})[storage] = entry
+    data.setdefault("per_storage", {})[key] = entry
     with open(out_json, "w") as f:
         json.dump(data, f, indent=1)
     md = ["# HBM traffic of the step kernel (rocprofv3 PMC)", "", "Command:", "", "```", command, "```", "",
@@ -759,6 +800,11 @@ def main():
     ap.add_argument("--serve-storage", default="f16")
     ap.add_argument("--serve-sweep", default="",
                     help="only run the serving stream at these comma-separated rates (req/s)")
+    ap.add_argument("--ensemble-profile", default="", metavar="STORAGE",
+                    help="only run the batched 256-domain ensemble in --ensemble-launch for --steps steps")
+    ap.add_argument("--ensemble-launch", default="8,64,16", help="vec,block,band of --ensemble-profile")
+    ap.add_argument("--counters-ensemble", action="store_true",
+                    help="--summarize-counters describes the ensemble profile in --ensemble-launch")
     ap.add_argument("--precision-study", action="store_true",
                     help="only run FP32/FP16/BF16 against FP64 on the large domain (1k/5k/50k steps)")
     ap.add_argument("--steady-wake", action="store_true",
@@ -778,9 +824,14 @@ def main():
     if a.summarize_trace:
         summarize_trace(*a.summarize_trace)
         return
+    ens_launch = tuple(int(x) for x in a.ensemble_launch.split(","))
     if a.summarize_counters:
         sf, sw, cf, cw, cb, kern, md, cmd = a.summarize_counters
-        summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, md, cmd, a.lattice)
+        summarize_counters(sf, sw, cf, cw, int(cb), a.storage, kern, md, cmd, a.lattice,
+                           {"vec": ens_launch[0], "block": ens_launch[1]} if a.counters_ensemble else None)
+        return
+    if a.ensemble_profile:
+        print(json.dumps(profile_ensemble(a.ensemble_profile, ens_launch, a.steps, a.warmup)), flush=True)
         return
     if a.slabs:
         print(json.dumps(time_slabs(a.slabs, storage=a.storage)), flush=True)
