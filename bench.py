@@ -83,14 +83,16 @@ def tile_shape(nx: int, launch) -> tuple:
 
 def mask_read_fraction(prob, launch) -> float:
     """Nodes whose mask byte a step reads, over all nodes: the nodes of tiles that
-    hold a solid node (the step kernels skip the mask of every other tile)."""
+    hold a solid node (the step kernels skip the mask of every other tile). A 3-D
+    mask [nz][ny][nx] is tiled as its nz ny lattice rows."""
     if prob.mask is None or not (prob.mask > 0).any():
         return 0.0
-    ny, nx = prob.mask.shape
+    mask = prob.mask.reshape(-1, prob.mask.shape[-1])
+    ny, nx = mask.shape
     tw, tr = tile_shape(nx, launch)
     tx, ty = -(-nx // tw), -(-ny // tr)
     pad = np.zeros((ty * tr, tx * tw), dtype=bool)
-    pad[:ny, :nx] = prob.mask > 0
+    pad[:ny, :nx] = mask > 0
     has = pad.reshape(ty, tr, tx, tw).any(axis=(1, 3))
     w = np.minimum(tw, nx - np.arange(tx) * tw)            # real columns per tile column
     h = np.minimum(tr, ny - np.arange(ty) * tr)            # real rows per tile row
@@ -143,7 +145,16 @@ def time_gpu(storage: str, steps: int, warmup: int, prob, repeats: int = 1):
     return float(np.median(runs)), ok, launch, runs
 
 
-BYTES_PER_NODE_3D = {"f64": 305, "f32": 153, "f16": 77, "bf16": 77}
+POP_BYTES_3D = {"f64": 304, "f32": 152, "f16": 76, "bf16": 76}
+# the default D3Q19 launch of the sphere domain per storage type
+DEFAULT_LAUNCH_3D = {"f64": {"vec": 1, "block": 128}, "f32": {"vec": 1, "block": 256},
+                     "f16": {"vec": 4, "block": 256}, "bf16": {"vec": 4, "block": 256}}
+
+
+def alg_bytes_per_node3(storage: str, prob, launch) -> float:
+    """D3Q19: 38 population accesses in the storage type plus the mask byte where
+    the step reads it."""
+    return POP_BYTES_3D[storage] + mask_read_fraction(prob, launch)
 
 
 def time_d3q19(storages, steps: int, warmup: int):
@@ -163,8 +174,10 @@ def time_d3q19(storages, steps: int, warmup: int):
         s.forces()
         ms = _timed(s.stream, lambda: s.step(steps)) / steps
         _, mass, _ = s.forces()
-        gbps = BYTES_PER_NODE_3D[st] * n / (ms * 1e-3) / 1e9
+        bpn = alg_bytes_per_node3(st, prob, {"vec": s.launch[0], "block": s.launch[1]})
+        gbps = bpn * n / (ms * 1e-3) / 1e9
         out["per_storage"][st] = {"launch": list(s.launch), "tile_band": s.tile_band, "ms_per_step": round(ms, 4),
+                                  "alg_bytes_per_node": round(bpn, 3),
                                   "MLUPS": round(n / (ms * 1e-3) / 1e6, 1), "achieved_GBps": round(gbps, 1),
                                   "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
                                   "traffic": measured_traffic(st, n, "d3q19"),
@@ -718,8 +731,9 @@ def summarize_counters(step_fetch: str, step_write: str, copy_fetch: str, copy_w
         mask_bytes = int(round(mask_read_fraction(prob, DEFAULT_LAUNCH_2D[storage]) * nodes))
     else:
         from paper_1901_08766_amd import inputs3
+        prob = inputs3.sphere()
         nodes = int(np.prod(inputs3.SPHERE_SHAPE))
-        mask_bytes = nodes
+        mask_bytes = int(round(mask_read_fraction(prob, DEFAULT_LAUNCH_3D[storage]) * nodes))
     out_json = LATTICES[lattice]["counters"]
     pop_bytes = LATTICES[lattice]["q"] * STORAGE_BYTES[storage]
     copy_kib = copy_bytes / 1024.0

@@ -215,12 +215,10 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     const int64_t r0 = (int64_t)row * a.pitch;       // mask and fields
 
     // this tile's (tile, body) force slots: loaded first, so that waiting for them
-    // never waits for the stores (a vector-memory wait covers every earlier access)
-    int s0 = 0, s1 = 0;
-    if constexpr (RECORD) {
-        s0 = a.tile_slot_ptr[t];
-        s1 = a.tile_slot_ptr[t + 1];
-    }
+    // never waits for the stores (a vector-memory wait covers every earlier
+    // access); a tile without slots holds no solid node and reads no mask
+    const int s0 = a.tile_slot_ptr[t];
+    const int s1 = a.tile_slot_ptr[t + 1];
     // Dword-or-wider elements (and single nodes) fetch the x-shifted directions
     // as one vector access one element off alignment. 2-byte vectors load aligned
     // and take the missing end element from the neighbouring lane (lanes that
@@ -246,7 +244,12 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
 #pragma unroll
             for (int e = 0; e < V; ++e) v[q][e] = as_lv<LV>(raw[e]);
         }
-        load_mask<V>(a.mask + r0 + i0, body);
+        if (s1 > s0) {
+            load_mask<V>(a.mask + r0 + i0, body);
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) body[e] = 0;
+        }
         if constexpr (kShifted) {
             if (i0 == 0) {   // the west side: column -1 lies outside
 #pragma unroll

@@ -43,3 +43,20 @@ def test_no_bodies_reads_no_mask(bench):
     p = inputs.random_state_problem(64, 32, seed=3, n_disks=0)
     assert bench.mask_read_fraction(p, {"vec": 4, "block": 128}) == 0.0
     assert bench.alg_bytes_per_node("f16", p, {"vec": 4, "block": 128}) == 36
+
+
+def test_mask_fraction_3d_rows(bench):
+    """A 3-D mask is tiled as its nz ny lattice rows (row = z ny + y)."""
+    from paper_1901_08766_amd import inputs3
+    p = inputs3.random_state_problem3(37, 11, 6, seed=5, n_spheres=2)
+    launch = {"vec": 4, "block": 64}
+    tw, tr = bench.tile_shape(p.nx, launch)
+    rows = p.mask.reshape(-1, p.nx)
+    count = 0
+    for r0 in range(0, rows.shape[0], tr):
+        for i0 in range(0, p.nx, tw):
+            tile = rows[r0:r0 + tr, i0:i0 + tw]
+            if (tile > 0).any():
+                count += tile.size
+    assert bench.mask_read_fraction(p, launch) == pytest.approx(count / rows.size, abs=0, rel=1e-15)
+    assert bench.alg_bytes_per_node3("f16", p, launch) == 76 + count / rows.size
