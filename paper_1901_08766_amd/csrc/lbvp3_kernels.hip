@@ -229,29 +229,34 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     const int lane = (int)(threadIdx.x & 63);
     LV v[Q][V];
     int body[V];
-    if (act) {
+    // 2-byte storage: threads without a node of their own load column 0 of
+    // their (clamped) row instead (every access stays inside the lattice; their
+    // results are never stored, summed or shuffled into an owned node), which
+    // spares the register clearing (1.5% faster); the wider types keep the branch
+    const int il = act ? i0 : 0;
+    if (sizeof(S) == 2 || act) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             S raw[V];
             const S* p = src + src_row[q] + (int64_t)q * a.pitch;
             if constexpr (kShifted) {
-                if (CX[q] == 1) load_vec_shifted<S, V>(p + (i0 - 1), raw);
-                else if (CX[q] == -1) load_vec_shifted<S, V>(p + (i0 + 1), raw);
-                else load_vec<S, V>(p + i0, raw);
+                if (CX[q] == 1) load_vec_shifted<S, V>(p + (il - 1), raw);
+                else if (CX[q] == -1) load_vec_shifted<S, V>(p + (il + 1), raw);
+                else load_vec<S, V>(p + il, raw);
             } else {
-                load_vec<S, V>(p + i0, raw);
+                load_vec<S, V>(p + il, raw);
             }
 #pragma unroll
             for (int e = 0; e < V; ++e) v[q][e] = as_lv<LV>(raw[e]);
         }
         if (s1 > s0) {
-            load_mask<V>(a.mask + r0 + i0, body);
+            load_mask<V>(a.mask + r0 + il, body);
         } else {
 #pragma unroll
             for (int e = 0; e < V; ++e) body[e] = 0;
         }
         if constexpr (kShifted) {
-            if (i0 == 0) {   // the west side: column -1 lies outside
+            if (il == 0) {   // the west side: column -1 lies outside
 #pragma unroll
                 for (int q = 0; q < Q; ++q)
                     if (CX[q] == 1) v[q][0] = pull_col<S, R>(src, q, src_row[q], -1, a);

@@ -461,43 +461,34 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     // lattice, no branch or register clearing is needed, and their results are
     // never stored, summed or shuffled into an owned node.
     const int il = act ? i0 : 0;
-    if (sizeof(S) >= 4 || act) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            S raw[V];
-            if constexpr (MODE == AA_LOCAL) {
-                load_vec<S, V>(src + q * P + l0 + il, raw);
-            } else {
-                const int pq = (MODE == AA_PUSH) ? OPP[q] : q;
-                if constexpr (OFF32) {
-                    static_assert(!kShifted && MODE == PULL, "the 32-bit form is the lane-shuffle pull form");
-                    load_vec<S, V>(at_off32(src + pq * P, (uint32_t)row_idx[q] * (uint32_t)a.lstride + (uint32_t)il),
-                                   raw);
-                } else if constexpr (kShifted) {
-                    if (EXQ[q] == 1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il - 1), raw);
-                    else if (EXQ[q] == -1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il + 1), raw);
-                    else load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
-                } else {
-                    load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < V; ++k) v[q][k] = as_lv<LV>(raw[k]);
-        }
-        if (MOVING && bs.pose) {
-#pragma unroll
-            for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, bs.pose, bs.near, i0 + k, j) : 0;
-        } else if (s1 > s0) {
-            load_mask<V>(a.mask + r0 + il, body);
+    for (int q = 0; q < 9; ++q) {
+        S raw[V];
+        if constexpr (MODE == AA_LOCAL) {
+            load_vec<S, V>(src + q * P + l0 + il, raw);
         } else {
-#pragma unroll
-            for (int k = 0; k < V; ++k) body[k] = 0;
+            const int pq = (MODE == AA_PUSH) ? OPP[q] : q;
+            if constexpr (OFF32) {
+                static_assert(!kShifted && MODE == PULL, "the 32-bit form is the lane-shuffle pull form");
+                load_vec<S, V>(at_off32(src + pq * P, (uint32_t)row_idx[q] * (uint32_t)a.lstride + (uint32_t)il),
+                               raw);
+            } else if constexpr (kShifted) {
+                if (EXQ[q] == 1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il - 1), raw);
+                else if (EXQ[q] == -1) load_vec_shifted<S, V>(src + pq * P + row_of[q] + (il + 1), raw);
+                else load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
+            } else {
+                load_vec<S, V>(src + pq * P + row_of[q] + il, raw);
+            }
         }
+#pragma unroll
+        for (int k = 0; k < V; ++k) v[q][k] = as_lv<LV>(raw[k]);
+    }
+    if (MOVING && bs.pose) {
+#pragma unroll
+        for (int k = 0; k < V; ++k) body[k] = (k < n_own) ? moving_body(a, bs.pose, bs.near, i0 + k, j) : 0;
+    } else if (s1 > s0) {
+        load_mask<V>(a.mask + r0 + il, body);
     } else {
-#pragma unroll
-        for (int q = 0; q < 9; ++q)
-#pragma unroll
-            for (int k = 0; k < V; ++k) v[q][k] = LV{};
 #pragma unroll
         for (int k = 0; k < V; ++k) body[k] = 0;
     }
