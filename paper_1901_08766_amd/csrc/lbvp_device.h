@@ -68,6 +68,19 @@ __device__ __forceinline__ T* at_off32(T* base, uint32_t elem)
     return reinterpret_cast<T*>(reinterpret_cast<B*>(base) + elem * (uint32_t)sizeof(T));
 }
 
+// The wavefront's values moved one lane up (lane l gets lane l - 1) or down
+// (lane l gets lane l + 1) by a DPP wavefront shift, a VALU move rather than a
+// trip through the LDS crossbar; the end lane gets 0 (callers load lanes 0 and
+// 63's end elements themselves).
+__device__ __forceinline__ float wave_shift_up1(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float wave_shift_down1(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x130, 0xf, 0xf, false));
+}
+
 // V consecutive elements moved as one aligned access of V * sizeof(S) bytes.
 template <typename S, int V>
 __device__ __forceinline__ void load_vec(const S* p, S (&out)[V])

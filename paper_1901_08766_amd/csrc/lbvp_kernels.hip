@@ -498,8 +498,8 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     if constexpr (!kShifted) {
 #pragma unroll
         for (int m = 0; m < 3; ++m) {
-            left[m] = __shfl_up(dec(v[EXP[m]][V - 1]), 1, 64);
-            right[m] = __shfl_down(dec(v[EXM[m]][0]), 1, 64);
+            left[m] = wave_shift_up1(dec(v[EXP[m]][V - 1]));
+            right[m] = wave_shift_down1(dec(v[EXM[m]][0]));
         }
         // lanes that start a wavefront or a tile row load the end element
         // themselves: a plain load inside the domain, the side resolution only
