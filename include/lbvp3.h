@@ -173,8 +173,11 @@ lbvp_status lbvp3_load_state(lbvp3_ctx* ctx, const void* buf, size_t size);
  * (borrowed; they must outlive the batch; same storage type, stream, force_every
  * and step count), vec / block as in lbvp3_set_launch (0: member 0's), applied
  * to every member. lbvp3_batch_step: every member advances n_steps (flags as
- * lbvp3_step); each member's populations, fields and force and mass records are
- * bitwise those of the member stepped alone with the same launch shape.
+ * lbvp3_step: with LBVP_GRAPH each run of up to 512 batched steps is captured
+ * once per distinct launch sequence and replayed, bitwise equal to the plain
+ * call; it needs a stream other than the null stream); each member's
+ * populations, fields and force and mass records are bitwise those of the
+ * member stepped alone with the same launch shape.
  * Asynchronous, apart from waiting for the batch's previous steps. E_STATE if a
  * member was stepped alone or given another launch shape since, or a member's
  * records would overflow its ring. The batch's tile band (lbvp3_batch_set_tile_band,

@@ -239,6 +239,8 @@ struct lbvp3_batch {
     char* dev = nullptr;             // owned: [member images | tile_domain | tile_start]
     size_t member_bytes = 0, off_domain = 0, off_start = 0;
     std::vector<char> image;         // host image of the member block, as last uploaded
+    lbvp_host::GraphCache graphs;    // captured chunks of batched steps (LBVP_GRAPH)
+    int64_t gen = 0;                 // bumped when something a captured launch bakes in changes
     std::string err;
 
     lbvp_status fail(lbvp_status s, const std::string& m)
@@ -253,6 +255,7 @@ struct lbvp3_batch {
     }
     ~lbvp3_batch()
     {
+        graphs.clear(stream);
         if (dev) {
             (void)hipStreamSynchronize(stream);
             (void)hipFree(dev);
@@ -1029,7 +1032,8 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
 {
     if (!b) return LBVP_E_ARG;
     if (n_steps < 0) return b->fail(LBVP_E_ARG, "n_steps < 0");
-    if (flags & ~LBVP_KEEP_FIELDS) return b->fail(LBVP_E_ARG, "unknown step flag (batches take LBVP_KEEP_FIELDS only)");
+    if (flags & ~KNOWN_STEP_FLAGS) return b->fail(LBVP_E_ARG, "unknown step flag");
+    if ((flags & LBVP_GRAPH) && !b->stream) return b->fail(LBVP_E_ARG, "LBVP_GRAPH needs a stream other than the null stream");
     if (n_steps == 0) return LBVP_OK;
     lbvp3_ctx* c0 = b->members[0];
     const int64_t fe = c0->p.force_every;
@@ -1065,10 +1069,13 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
     L.tile_start = reinterpret_cast<const int32_t*>(b->dev + b->off_start);
     L.members = b->dev;
     L.n_members = n;
-    for (int64_t k = 0; k < n_steps; ++k) {
+    // steps k0 .. k0 + n - 1 of the call (the members' parity flips with k),
+    // then the run's last record summed in one launch
+    auto run = [&](int64_t k0, int64_t n_run, bool keep_last) -> lbvp_status {
+    for (int64_t k = k0; k < k0 + n_run; ++k) {
         const int64_t next = c0->step + 1;
         const bool record = fe > 0 && next % fe == 0;
-        const bool keep_here = keep && k == n_steps - 1;
+        const bool keep_here = keep_last && k == k0 + n_run - 1;
         const int32_t part_buf = (int32_t)(c0->rec_head & 1);
         L.flip = (int32_t)(k & 1);
         L.part_buf = part_buf;
@@ -1087,11 +1094,84 @@ lbvp_status lbvp3_batch_step(lbvp3_batch* b, int64_t n_steps, uint32_t flags)
             c->step = next;
         }
     }
-    if (c0->pending) {   // the last record of the call, every member's in one launch
+    if (c0->pending) {   // the last record of the run, every member's in one launch
         L.fin_buf = c0->pending_buf;
         e = launch_finalize3_members(b->storage, L, b->stream);
         if (e != hipSuccess) return b->hip_fail(e, "finalize kernel launch");
         for (lbvp3_ctx* c : b->members) c->pending = false;
+    }
+    return LBVP_OK;
+    };
+    if (!(flags & LBVP_GRAPH)) return run(0, n_steps, keep);
+    // through graphs: runs of up to GRAPH_CHUNK steps, each captured once per
+    // distinct launch sequence (length, parity within the call, record phase and
+    // buffer) and replayed; the member block was uploaded above, outside any
+    // capture, and is read by the replayed kernels
+    for (int64_t done = 0; done < n_steps;) {
+        const int64_t n_run = std::min(GRAPH_CHUNK, n_steps - done);
+        const bool keep_here = keep && done + n_run == n_steps;
+        lbvp_host::GraphKey key;   // every run starts with its records summed
+        key.n = n_run;
+        key.keep = keep_here;
+        key.cur = (int32_t)(done & 1);
+        key.phase = fe > 0 ? c0->step % fe : 0;
+        key.rec = (int32_t)(c0->rec_head & 1);
+        key.gen = b->gen;
+        hipGraphExec_t x = b->graphs.find(key);
+        if (x) {
+            e = hipGraphLaunch(x, b->stream);
+            if (e != hipSuccess) return b->hip_fail(e, "hipGraphLaunch");
+            // the members' bookkeeping exactly as the captured launches advanced it
+            const int64_t step0 = c0->step;
+            const int64_t recs = fe > 0 ? (step0 + n_run) / fe - step0 / fe : 0;
+            for (lbvp3_ctx* c : b->members) {
+                c->cur = (c->cur + (int)(n_run & 1)) & 1;
+                c->step = step0 + n_run;
+                c->rec_head += recs;
+                c->pending = false;
+                if (recs > 0) c->pending_buf = (int32_t)((c->rec_head - 1) & 1);
+                if (keep_here) c->fields_valid = true;
+            }
+        } else {
+            struct Saved { int cur; int64_t step, head; bool pending, fields; int32_t buf; };
+            std::vector<Saved> saved;
+            for (lbvp3_ctx* c : b->members)
+                saved.push_back({c->cur, c->step, c->rec_head, c->pending, c->fields_valid, c->pending_buf});
+            auto restore = [&]() {
+                for (size_t i = 0; i < b->members.size(); ++i) {
+                    lbvp3_ctx* c = b->members[i];
+                    c->cur = saved[i].cur;
+                    c->step = saved[i].step;
+                    c->rec_head = saved[i].head;
+                    c->pending = saved[i].pending;
+                    c->fields_valid = saved[i].fields;
+                    c->pending_buf = saved[i].buf;
+                }
+            };
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return b->hip_fail(e, "hipStreamBeginCapture");
+            const lbvp_status st = run(done, n_run, keep_here);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(b->stream, &g);
+            if (st != LBVP_OK || e != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                restore();
+                return st != LBVP_OK ? st : b->hip_fail(e, "hipStreamEndCapture");
+            }
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                restore();
+                return b->hip_fail(e, "hipGraphInstantiate");
+            }
+            b->graphs.put(key, x, b->stream);
+            e = hipGraphLaunch(x, b->stream);
+            if (e != hipSuccess) {
+                restore();
+                return b->hip_fail(e, "hipGraphLaunch");
+            }
+        }
+        done += n_run;
     }
     return LBVP_OK;
 }
@@ -1101,6 +1181,10 @@ lbvp_status lbvp3_batch_set_tile_band(lbvp3_batch* b, int32_t band)
     if (!b) return LBVP_E_ARG;
     if (band < 0 || band > MAX_TILE_BAND || (band & (band - 1)) != 0)
         return b->fail(LBVP_E_ARG, "band must be 0 or a power of two up to 65536");
+    if (band != b->band) {   // the band is baked into captured launches
+        b->graphs.clear(b->stream);
+        b->gen += 1;
+    }
     b->band = band;
     return LBVP_OK;
 }

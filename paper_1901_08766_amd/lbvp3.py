@@ -371,8 +371,8 @@ class Batch3:
         self.solvers = list(solvers)
         self.handle = lbvp3_batch_create([s.ctx for s in self.solvers], vec, block)
 
-    def step(self, n: int, keep_fields: bool = False):
-        lbvp3_batch_step(self.handle, n, KEEP_FIELDS if keep_fields else 0)
+    def step(self, n: int, keep_fields: bool = False, graph: bool = False):
+        lbvp3_batch_step(self.handle, n, (KEEP_FIELDS if keep_fields else 0) | (GRAPH if graph else 0))
 
     @property
     def tile_band(self) -> int:

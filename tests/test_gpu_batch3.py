@@ -205,3 +205,44 @@ def test_tuner(lbvp3):
     assert e.value.status == lbvp3.E_ARG
     for s in members + [other]:
         s.close()
+
+
+@pytest.mark.parametrize("storage,launch,force_every", [("f32", (1, 128), 1), ("f16", (4, 64), 3), ("f64", (2, 128), 2)])
+def test_batch_graph_replays_equal_plain_batch(lbvp3, storage, launch, force_every):
+    """LBVP_GRAPH on batches: calls longer than one captured chunk (600 steps:
+    512 + 88), calls that replay a captured chunk at other parities and record
+    phases, interleaved with plain calls and host reads; a new tile band drops
+    the graphs. Every member ends bitwise where the same calls without graphs
+    leave it (populations, fields, every force and mass record)."""
+    probs = _members()[:4]
+    calls = [(600, False, True), (7, False, True), (7, True, True), (5, False, False), (7, False, True),
+             (3, True, True), ("band", 8), (7, False, True), (2, True, True)]
+    outs = []
+    for use_graph in (False, True):
+        stream = torch.cuda.Stream()
+        ms = [lbvp3.Solver3(p, storage=storage, force_every=force_every, force_capacity=1024, stream=stream)
+              for p in probs]
+        batch = lbvp3.Batch3(ms, *launch)
+        recs = [[] for _ in ms]
+        for item in calls:
+            if item[0] == "band":
+                batch.set_tile_band(item[1])
+                continue
+            n, keep, graphed = item
+            print(f"graph={use_graph} {storage} n={n} keep={keep}", flush=True)
+            batch.step(n, keep_fields=keep, graph=use_graph and graphed)
+            for r, m in zip(recs, ms):
+                r.append(m.forces())
+        outs.append(([m.populations() for m in ms], [m.fields() for m in ms], recs, [m.step_count for m in ms]))
+        batch.close()
+        for m in ms:
+            m.close()
+    (pa, fa, ra, sa), (pb, fb, rb, sb) = outs
+    assert sa == sb
+    for k in range(len(probs)):
+        assert np.array_equal(pa[k], pb[k]), k
+        for name in fa[k]:
+            assert np.array_equal(fa[k][name], fb[k][name]), (k, name)
+        for (f1, m1, s1), (f2, m2, s2) in zip(ra[k], rb[k]):
+            assert s1 == s2 and np.array_equal(f1, f2) and np.array_equal(m1, m2), k
+
