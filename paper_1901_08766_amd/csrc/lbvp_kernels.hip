@@ -441,18 +441,21 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     const int64_t P = a.plane;
 
     // Source plane of direction q: the pull and the AA local step read plane q,
-    // the AA push step the neighbour's opposite slot. Dword-or-wider elements
-    // (and single nodes) take the x-shifted directions as single accesses one
-    // element off alignment (columns i0 - 1 .. or i0 + 1 ..; both stay inside
-    // the allocation: population 0 of row 0 is never shifted left, the last
-    // population row (8 of row ny - 1) is never shifted right, and every other
-    // population row is preceded and followed by another). FP16/BF16 vectors load aligned and shift
-    // through lane shuffles (pull only).
-    constexpr bool kShifted = sizeof(S) >= 4 || V == 1;
+    // the AA push step the neighbour's opposite slot. FP32 vectors, single
+    // nodes and the AA steps take the x-shifted directions as single accesses
+    // one element off alignment (columns i0 - 1 .. or i0 + 1 ..; both stay
+    // inside the allocation: population 0 of row 0 is never shifted left, the
+    // last population row (8 of row ny - 1) is never shifted right, and every
+    // other population row is preceded and followed by another). FP64 and
+    // FP16/BF16 vectors of the pull step load aligned and shift through lane
+    // moves (FP64: 0.787 -> 0.783 ms and no line-straddling reads; FP32 measured
+    // the same either way).
+    constexpr bool kShifted = sizeof(S) == 4 || V == 1 || MODE != PULL;
     static_assert(MODE == PULL || kShifted, "the AA pattern needs dword-or-wider elements or one node per thread");
-    // The lane-shuffle form (2-byte types, V > 1) keeps the loaded values in the
-    // storage type and decodes each node's nine just before its collision, so
-    // that the packed loads, not 9 V decoded floats, stay live across the tile.
+    // The lane-shuffle form (FP64 and 2-byte types, V > 1, pull) keeps the
+    // loaded values in the storage type and decodes each node's nine just before
+    // its collision, so that the packed loads, not 9 V decoded floats, stay live
+    // across the tile.
     using LV = typename std::conditional<kShifted, R, S>::type;
     LV v[9][V];
     int body[V];
