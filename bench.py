@@ -74,10 +74,15 @@ DEFAULT_LAUNCH_2D = {"f32": {"vec": 4, "block": 128}, "f64": {"vec": 2, "block":
                      "f16": {"vec": 4, "block": 256}, "bf16": {"vec": 4, "block": 256}}
 
 
-def tile_shape(nx: int, launch) -> tuple:
-    """(tile_w, tile_rows) of a D2Q9 launch shape (vec nodes per thread, block threads)."""
+def tile_shape(nx: int, launch, d3q19: bool = False) -> tuple:
+    """(tile_w, tile_rows) of a launch shape (vec nodes per thread, block threads):
+    on a narrow grid a D2Q9 tile row is nx rounded up to a power of two, a D3Q19
+    one nx rounded up to vec."""
     vec, block = launch["vec"], launch["block"]
-    tile_w = min(vec * block, max(vec, 1 << max(nx - 1, 0).bit_length()))
+    if d3q19:
+        tile_w = min(vec * block, -(-max(nx, 1) // vec) * vec)
+    else:
+        tile_w = min(vec * block, max(vec, 1 << max(nx - 1, 0).bit_length()))
     return tile_w, vec * block // tile_w
 
 
@@ -89,7 +94,7 @@ def mask_read_fraction(prob, launch) -> float:
         return 0.0
     mask = prob.mask.reshape(-1, prob.mask.shape[-1])
     ny, nx = mask.shape
-    tw, tr = tile_shape(nx, launch)
+    tw, tr = tile_shape(nx, launch, d3q19=prob.mask.ndim == 3)
     tx, ty = -(-nx // tw), -(-ny // tr)
     pad = np.zeros((ty * tr, tx * tw), dtype=bool)
     pad[:ny, :nx] = mask > 0

@@ -52,21 +52,17 @@ int32_t band_log2(int32_t band)
     return k;
 }
 
-int32_t pow2_ceil(int32_t v)
-{
-    int32_t p = 1;
-    while (p < v) p <<= 1;
-    return p;
-}
-
-// A tile is tile_rows lattice rows of tile_w nodes (vec * block nodes): full
-// rows of vec * block nodes on wide grids, several shorter rows on narrow ones.
+// A tile is tile_rows lattice rows of tile_w nodes: full rows of vec * block
+// nodes on wide grids; on narrow ones, as many whole rows of nx nodes (rounded
+// up to vec) as a block holds, the block's remaining threads idle (a 96- or
+// 160-node row then idles 6% of a 512-node block, not the 25% or 37.5% of rows
+// padded to a power of two).
 Launch3 make_launch(int32_t nx, int64_t rows, int32_t vec, int32_t block)
 {
     Launch3 l;
     l.vec = vec;
     l.block = block;
-    l.tile_w = std::min(vec * block, std::max(vec, pow2_ceil(nx)));
+    l.tile_w = std::min(vec * block, (std::max(nx, 1) + vec - 1) / vec * vec);
     l.tile_rows = vec * block / l.tile_w;
     l.tiles_x = (nx + l.tile_w - 1) / l.tile_w;
     l.n_tiles = (int32_t)(l.tiles_x * ((rows + l.tile_rows - 1) / l.tile_rows));

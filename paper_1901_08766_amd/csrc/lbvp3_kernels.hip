@@ -198,7 +198,7 @@ __device__ __forceinline__ void step3_body(const S* __restrict__ src, S* __restr
     const int row = min(row_u, n_rows - 1);          // rows past the grid idle (clamped for addressing)
     const int k = row / a.ny, j = row - k * a.ny;
     const int i0 = tx * a.tile_w + lc * V;
-    const bool act = i0 < a.nx && row_u < n_rows;
+    const bool act = i0 < a.nx && row_u < n_rows && lr < a.tile_rows;   // threads past the tile's rows idle
     const int n_own = act ? min(V, a.nx - i0) : 0;
 
     const int jm = (j == 0) ? a.ny - 1 : j - 1, jp = (j == a.ny - 1) ? 0 : j + 1;   // y and z periodic

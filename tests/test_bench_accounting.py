@@ -1,6 +1,7 @@
 """The benchmark's algorithmic byte count (host only): the mask byte is counted
 for exactly the nodes of tiles that hold a solid node, with the tiling the
-library's launch shapes make (tile width a power of two up to vec x block)."""
+library's launch shapes make (D2Q9 tile width a power of two up to vec x
+block, D3Q19 nx rounded up to vec)."""
 import importlib.util
 import os
 
@@ -45,12 +46,17 @@ def test_no_bodies_reads_no_mask(bench):
     assert bench.alg_bytes_per_node("f16", p, {"vec": 4, "block": 128}) == 36
 
 
-def test_mask_fraction_3d_rows(bench):
-    """A 3-D mask is tiled as its nz ny lattice rows (row = z ny + y)."""
+@pytest.mark.parametrize("nx,launch,shape", [(37, (4, 64), (40, 6)), (96, (4, 128), (96, 5)),
+                                             (160, (4, 256), (160, 6)), (130, (1, 64), (64, 1)),
+                                             (3, (4, 64), (4, 64))])
+def test_mask_fraction_3d_rows(bench, nx, launch, shape):
+    """A 3-D mask is tiled as its nz ny lattice rows (row = z ny + y), a narrow
+    grid's tile holding as many whole rows of nx rounded up to vec as fit."""
     from paper_1901_08766_amd import inputs3
-    p = inputs3.random_state_problem3(37, 11, 6, seed=5, n_spheres=2)
-    launch = {"vec": 4, "block": 64}
-    tw, tr = bench.tile_shape(p.nx, launch)
+    p = inputs3.random_state_problem3(nx, 11, 6, seed=5, n_spheres=2)
+    launch = {"vec": launch[0], "block": launch[1]}
+    tw, tr = bench.tile_shape(p.nx, launch, d3q19=True)
+    assert (tw, tr) == shape
     rows = p.mask.reshape(-1, p.nx)
     count = 0
     for r0 in range(0, rows.shape[0], tr):
