@@ -153,7 +153,7 @@ def time_gpu(storage: str, steps: int, warmup: int, prob, repeats: int = 1):
 POP_BYTES_3D = {"f64": 304, "f32": 152, "f16": 76, "bf16": 76}
 # the default D3Q19 launch of the sphere domain per storage type
 DEFAULT_LAUNCH_3D = {"f64": {"vec": 1, "block": 128}, "f32": {"vec": 1, "block": 256},
-                     "f16": {"vec": 4, "block": 256}, "bf16": {"vec": 4, "block": 256}}
+                     "f16": {"vec": 4, "block": 128}, "bf16": {"vec": 4, "block": 128}}
 
 
 def alg_bytes_per_node3(storage: str, prob, launch) -> float:

@@ -74,21 +74,22 @@ Launch3 make_launch(int32_t nx, int64_t rows, int32_t vec, int32_t block)
 // (256-thread blocks) and FP64 (128): the 19 loads of a node already keep enough
 // bytes in flight, and the narrow form keeps ~70 VGPRs and 7 waves per SIMD,
 // against ~150 VGPRs and 3 waves for 16-byte vectors. The 2-byte types take four
-// nodes per thread (8-byte loads, lane shuffles) in 256-thread blocks, 7% ahead
+// nodes per thread (8-byte loads, lane shuffles) in 128-thread blocks, 7% ahead
 // of single 2-byte elements. Tiles go to the XCDs in bands (lbvp3_set_tile_band):
 // 128 tiles (a quarter plane there) for FP32 and FP64, 0.874 and 1.736 ms per
-// step against 0.890 and 1.758 with one eighth per XCD; 2 tiles for the 2-byte
-// types, 0.490 ms against 0.514. Grids too small to fill the chip: one node per
+// step against 0.890 and 1.758 with one eighth per XCD; 4 tiles for the 2-byte
+// types, 0.445 ms against 0.468 with one eighth per XCD and 0.458 for bands of
+// 2 tiles of 256-thread blocks. Grids too small to fill the chip: one node per
 // thread, 64-thread blocks, one eighth per XCD.
 Launch3 default_launch(const lbvp3_params& p)
 {
     const int64_t rows = (int64_t)p.ny * p.nz, n = rows * p.nx;
     const bool two_byte = p.storage == LBVP_F16_DEV || p.storage == LBVP_BF16_DEV;
     const int32_t vec = two_byte && n / (64 * 4) >= 8 * 1024 ? 4 : 1;
-    const int32_t wide = p.storage == LBVP_F64 ? 128 : 256;
+    const int32_t wide = (p.storage == LBVP_F64 || two_byte) ? 128 : 256;
     const bool large = n / (64 * vec) >= 4096;
     Launch3 l = make_launch(p.nx, rows, vec, large ? wide : 64);
-    if (large) l.band = two_byte ? 2 : 128;
+    if (large) l.band = two_byte ? 4 : 128;
     return l;
 }
 

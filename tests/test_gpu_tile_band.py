@@ -63,7 +63,7 @@ def test_default_launches_take_bands(lbvp, lbvp3):
     assert (s.launch, s.tile_band) == ((4, 128), 0)
     s.close()
     s3 = lbvp3.Solver3(inputs3.random_state_problem3(256, 128, 64, seed=1, n_spheres=1), storage="f16", force_every=0)
-    assert (s3.launch, s3.tile_band) == ((4, 256), 2)
+    assert (s3.launch, s3.tile_band) == ((4, 128), 4)
     s3.close()
     s = lbvp.Solver(inputs.random_state_problem(64, 40, seed=3, n_disks=1), storage="f32")
     assert s.tile_band == 0 and s.launch[0] == 1
