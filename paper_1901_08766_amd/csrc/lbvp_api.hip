@@ -303,6 +303,9 @@ struct lbvp_ctx {
     std::vector<uint8_t> mask_host;         // [ny][nx], kept to rebuild the tile tables
     std::vector<lbvp_body> bodies_host;
     std::vector<double> mov_r2;             // moving bodies: squared reach about the centre
+    // moving bodies: each body's mask rows as (row, first column, last column),
+    // the span between its first and last node of the row
+    std::vector<std::vector<std::array<int32_t, 3>>> mov_runs;
     std::vector<double> pose_host;          // moving bodies: the uploaded pose table
     int64_t pose_first = -1;                // its first time level (-1: none)
     uint64_t gen = 0;                       // kernel-argument generation (graph keys)
@@ -455,11 +458,17 @@ std::vector<char> body_table_bytes(const lbvp_body* bodies, int32_t n, int32_t m
 // The (tile, body) reduction tables for the current tiling and mask: a slot per
 // body present in each tile, numbered in tile order, and each body's slots.
 // Moving bodies: with a pose window on the device (time levels pose_first ..
-// pose_first + POSE_ROWS - 1), a tile lists body b when b's radius about one of
-// the window's centres can reach it: the centres move on a line, so their box
-// widened by the radius and two nodes holds every such tile (the kernels' own
-// per-tile test, with the radius alone, is tighter); before any window, every
-// body in every tile.
+// pose_first + POSE_ROWS - 1), a tile lists body b when one of b's nodes can lie
+// in it at one of the window's time levels; before any window, every body in
+// every tile. The kernels test only the bodies a tile lists. A node x belongs to
+// b at time t when R(-theta) (x - c(t)) + c0 rounds to a node y of b's mask:
+// then x lies within 1/sqrt(2) of c(t) + R(theta) d, d = y - c0. Over the
+// window c(t) stays in the box of its two ends, and R(theta) d within |d| |dtheta|
+// of its value at the first level; the points d of one mask row's span between
+// its first and last node rotate onto the segment between the rotated ends. So
+// each row span, its ends rotated to the first level, boxed, widened by the
+// centre's path, |d|max |dtheta|, 1/sqrt(2) and two nodes, holds every tile
+// its nodes reach.
 lbvp_status build_tile_tables(lbvp_ctx* c)
 {
     const lbvp_params& p = c->p;
@@ -471,8 +480,9 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
     std::vector<std::vector<int32_t>> per_body((size_t)nb);
     std::vector<uint8_t> seen((size_t)nb + 1, 0);
     const bool windowed = c->moving() && c->pose_first >= 0;
-    std::vector<std::array<int32_t, 4>> reach_box((size_t)nb);   // tile columns and rows, inclusive
+    std::vector<uint8_t> reach;   // windowed: bit b - 1 of tile t when body b can reach t
     if (windowed) {
+        reach.assign((size_t)l.n_tiles, 0);
         const int32_t tiles_y = l.n_tiles / l.tiles_x;
         const double ta = (double)c->pose_first, tb = (double)(c->pose_first + POSE_ROWS - 1);
         auto span = [](double lo, double hi, int32_t size, int32_t count, int32_t* first, int32_t* last) {
@@ -483,20 +493,30 @@ lbvp_status build_tile_tables(lbvp_ctx* c)
             const lbvp_body& B = c->bodies_host[b];
             const double xa = B.cx + B.vx * ta, xb = B.cx + B.vx * tb;
             const double ya = B.cy + B.vy * ta, yb = B.cy + B.vy * tb;
-            const double r = std::sqrt(c->mov_r2[b]) + 2.0;
-            auto& q = reach_box[b];
-            span(std::min(xa, xb) - r, std::max(xa, xb) + r, l.tile_w, l.tiles_x, &q[0], &q[1]);
-            span(std::min(ya, yb) - r, std::max(ya, yb) + r, l.tile_rows, tiles_y, &q[2], &q[3]);
+            const double th = B.omega * ta, dth = std::fabs(B.omega) * (tb - ta);
+            const double co = std::cos(th), si = std::sin(th);
+            for (const auto& run : c->mov_runs[b]) {
+                const double dy = run[0] - B.cy, dx0 = run[1] - B.cx, dx1 = run[2] - B.cx;
+                const double px0 = co * dx0 - si * dy, py0 = si * dx0 + co * dy;
+                const double px1 = co * dx1 - si * dy, py1 = si * dx1 + co * dy;
+                const double rho = std::sqrt(std::max(dx0 * dx0, dx1 * dx1) + dy * dy);
+                const double w = rho * dth + 0.7072 + 2.0;
+                int32_t c0, c1, r0, r1;
+                span(std::min(xa, xb) + std::min(px0, px1) - w, std::max(xa, xb) + std::max(px0, px1) + w,
+                     l.tile_w, l.tiles_x, &c0, &c1);
+                span(std::min(ya, yb) + std::min(py0, py1) - w, std::max(ya, yb) + std::max(py0, py1) + w,
+                     l.tile_rows, tiles_y, &r0, &r1);
+                for (int32_t ty = r0; ty <= r1; ++ty)
+                    for (int32_t tx = c0; tx <= c1; ++tx) reach[(size_t)ty * l.tiles_x + tx] |= (uint8_t)(1u << b);
+            }
         }
     }
     for (int32_t t = 0; t < l.n_tiles; ++t) {
         tile_ptr[t] = (int32_t)slot_body.size();
         if (nb == 0) continue;
         if (c->moving()) {   // in body order
-            const int32_t tx = t % l.tiles_x, ty = t / l.tiles_x;
             for (int32_t b = 1; b <= nb; ++b) {
-                const auto& q = reach_box[b - 1];
-                if (windowed && (tx < q[0] || tx > q[1] || ty < q[2] || ty > q[3])) continue;
+                if (windowed && !((reach[t] >> (b - 1)) & 1u)) continue;
                 per_body[b - 1].push_back((int32_t)slot_body.size());
                 slot_body.push_back(b);
             }
@@ -1266,17 +1286,25 @@ lbvp_status lbvp_set_mask(lbvp_ctx* c, const uint8_t* body_id, int32_t n_bodies,
     c->mask_host.assign(body_id, body_id + n);
     c->bodies_host.assign(bodies, bodies + n_bodies);
     c->mov_r2.assign((size_t)n_bodies, 0.0);
+    c->mov_runs.assign((size_t)n_bodies, {});
     c->pose_first = -1;   // the poses follow the new bodies
     c->a64.n_moving = c->a32.n_moving = c->moving() ? n_bodies : 0;
     if (c->moving()) {   // reach of each body about its centre: farthest node + 1
         std::vector<double> rmax((size_t)n_bodies, 0.0);
-        for (int32_t j = 0; j < p.ny; ++j)
+        std::vector<std::array<int32_t, 2>> span((size_t)n_bodies);
+        for (int32_t j = 0; j < p.ny; ++j) {
+            for (auto& q : span) q = {INT32_MAX, -1};
             for (int32_t i = 0; i < p.nx; ++i) {
                 const int b = body_id[(int64_t)j * p.nx + i];
                 if (!b) continue;
                 const double dx = i - bodies[b - 1].cx, dy = j - bodies[b - 1].cy;
                 rmax[b - 1] = std::max(rmax[b - 1], std::sqrt(dx * dx + dy * dy));
+                span[b - 1][0] = std::min(span[b - 1][0], i);
+                span[b - 1][1] = i;
             }
+            for (int32_t b = 0; b < n_bodies; ++b)
+                if (span[b][1] >= 0) c->mov_runs[b].push_back({j, span[b][0], span[b][1]});
+        }
         for (int32_t b = 0; b < n_bodies; ++b) c->mov_r2[b] = (rmax[b] + 1.0) * (rmax[b] + 1.0);
     }
     c->n_bodies = n_bodies;

@@ -423,9 +423,16 @@ __device__ __forceinline__ void step_body(const S* src, S* dst, const StepArgs<t
     const int n_own = act ? min(V, a.nx - i0) : 0;
     if constexpr (MOVING) {
         if (bs.pose) {   // once per tile: most tiles meet no moving body
-            const double x0 = (double)(tx * a.tile_w), y0 = (double)(ty * a.tile_rows);
-            bs.near = __builtin_amdgcn_readfirstlane(
-                tile_near_bodies(a, bs.pose, x0, x0 + (double)(a.tile_w - 1), y0, y0 + (double)(a.tile_rows - 1)));
+            // only the bodies the tile's slots list can reach it during the
+            // pose window (none for most tiles); of those, the ones whose
+            // radius about this step's centre meets the tile
+            uint32_t listed = 0;
+            for (int s = s0; s < s1; ++s) listed |= 1u << (a.slot_body[s] - 1);
+            if (listed) {
+                const double x0 = (double)(tx * a.tile_w), y0 = (double)(ty * a.tile_rows);
+                bs.near = listed & __builtin_amdgcn_readfirstlane(tile_near_bodies(
+                                       a, bs.pose, x0, x0 + (double)(a.tile_w - 1), y0, y0 + (double)(a.tile_rows - 1)));
+            }
         }
     }
 

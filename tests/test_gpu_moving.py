@@ -304,16 +304,20 @@ def _box(x0, x1, y0, y1):
     return xs.ravel(), ys.ravel()
 
 
-def test_fp32_full_size_moving_sampled(lbvp, oracle):
+@pytest.mark.parametrize("k", [300, 1020], ids=["step301", "step1021"])
+def test_fp32_full_size_moving_sampled(lbvp, oracle, k):
     """The 8192 x 4096 domain with its masks following the bodies (a cylinder
     crossing the stream, the airfoil pitching, the rotating pair turning their
-    masks), in the default launch the benchmark times: after 300 GPU steps the
+    masks), in the default launch the benchmark times: after k GPU steps the
     oracle, set to that time level, advances the GPU's state by one step at every
     node of boxes around the moving bodies, along the sides and at random nodes;
     that must equal the GPU's next state to FP32 rounding, and the recorded
-    forces of the crossing cylinder and of the airfoil the oracle's node sums."""
+    forces of the crossing cylinder and of the airfoil the oracle's node sums.
+    Level 1021 lies near the end of the first pose table (levels 0 to 1023),
+    where the bodies have turned and moved farthest from their poses at its
+    first level: the tiles each tile table lists for a body must still hold all
+    of its nodes."""
     prob = inputs.large_domain(moving=True)
-    k = 300
     gpu = lbvp.Solver(prob, storage="f32", force_every=1, force_capacity=k + 16)
     print(f"case {prob.name} f32 launch={gpu.launch} band={gpu.tile_band} steps={k}", flush=True)
     gpu.step(k)
