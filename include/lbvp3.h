@@ -192,7 +192,7 @@ lbvp_status lbvp3_batch_destroy(lbvp3_batch* batch);
 const char* lbvp3_batch_last_error(const lbvp3_batch* batch);
 
 /* Tuner: times the step for every launch shape built for the members' storage
- * (vec x block as in lbvp3_set_launch) and tile bands 0, 2 and 16, on scratch
+ * (vec x block as in lbvp3_set_launch) and tile bands 0, 2, 4 and 16, on scratch
  * contexts made from the members' parameters, masks and bodies at rest (the
  * members themselves are not stepped; the scratch contexts need as much device
  * memory again). One member runs alone, several as one batch, as lbvp3_step and

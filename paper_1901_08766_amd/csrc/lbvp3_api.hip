@@ -1283,7 +1283,7 @@ lbvp_status lbvp3_tune(lbvp3_ctx* const* members, int32_t n, int32_t steps, uint
         for (int32_t vec : {1, 2, 4, 8}) {
             if (!vec_supported(c0->p.storage, vec)) continue;
             for (int32_t block : BLOCKS)
-                for (int32_t band : {0, 2, 16}) {
+                for (int32_t band : {0, 2, 4, 16}) {
                     lbvp3_batch* b = nullptr;
                     std::string why;
                     for (lbvp3_ctx* s : sc.ctx) {
